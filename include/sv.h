@@ -1,0 +1,255 @@
+/*
+ * sv.h -- C ABI of the MI355X (gfx950) state-vector library `libsv.so`.
+ *
+ * Scope: the dense state-vector hot path of the paper's simulator -- apply
+ * layers of (parameterised) gates to a 2^n-amplitude state and reduce Pauli
+ * expectation values -- plus adjoint gradients, terminal sampling and a
+ * ragged multi-circuit batch.  The paper's backend contract names the
+ * operations (Appendix A.5: zeros_state, apply_unitary, expectation_sv,
+ * measure_probs, sample, cast, to_numpy); the circuit model is the paper's
+ * typed operation with targets first, then controls and optional control
+ * states (Section 4.2); fusion width follows the paper's `fuse` option
+ * (Section 4.3: 0 disables fusion, a positive width must be at least 2).
+ *
+ * Conventions
+ *   - Qubit q is bit q of the basis index (little-endian).
+ *   - A k-target gate's local matrix index is j = sum_i bit(targets[i]) 2^i.
+ *   - Rotations are exp(-i theta P / 2) (paper Section 9.1).
+ *   - The state is two planes (re, im) of 2^n elements each, FP64 for
+ *     SV_C128 and FP32 for SV_C64 (paper Section 5.2: paired real tensors;
+ *     matrices are always built in FP64 and narrowed at the boundary).
+ *
+ * Ownership and memory
+ *   - State planes and the workspace are DEVICE memory owned by the caller
+ *     (e.g. torch tensors).  A handle borrows them until sv_free and never
+ *     frees them.  Host arrays (ops, params, terms) are read during the call
+ *     and not kept.  Output arrays are caller-owned HOST memory unless the
+ *     function name ends in _device.
+ *
+ * Synchronisation
+ *   - Every call enqueues work on the handle's HIP stream.  sv_apply_layer
+ *     and sv_reset return without waiting.  Calls that return host values
+ *     (expect, adjoint, sample, copy) wait for that stream.
+ *
+ * Errors
+ *   - Every call returns an sv_status.  All argument checks run before any
+ *     device work is enqueued (nothing is narrowed or defaulted silently);
+ *     on error the state is unchanged and sv_last_error() describes it.
+ */
+#ifndef LIBSV_PUBLIC_SV_H_
+#define LIBSV_PUBLIC_SV_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct sv_state sv_state;
+
+typedef enum { SV_C128 = 0, SV_C64 = 1 } sv_dtype;
+
+typedef enum {
+  SV_OK = 0,
+  SV_EINVAL = -1,        /* bad qubit, duplicate qubit, bad width, mask >= 2^n ... */
+  SV_EDTYPE = -2,        /* unsupported dtype */
+  SV_EUNBOUND = -3,      /* parameter index out of range or non-finite parameter */
+  SV_ENOMEM = -4,        /* workspace too small / allocation failed */
+  SV_EUNSUPPORTED = -5,  /* valid request this path does not implement */
+  SV_EDEVICE = -6        /* a HIP runtime call failed */
+} sv_status;
+
+/* Gate kinds (paper Section 4.2 gate table).  Controlled gates are a base
+ * kind plus controls: CX = SV_X with one control, CZ = SV_Z with one control,
+ * Toffoli = SV_X with two controls, CP = SV_P with one control, etc. */
+typedef enum {
+  SV_I = 0, SV_X, SV_Y, SV_Z, SV_H, SV_S, SV_SDG, SV_T, SV_TDG, SV_SX,
+  SV_RX, SV_RY, SV_RZ,     /* exp(-i theta P/2), 1 parameter */
+  SV_P,                    /* diag(1, e^{i lambda}), 1 parameter */
+  SV_U2,                   /* U3(pi/2, phi, lambda), 2 parameters */
+  SV_U3,                   /* [[c, -e^{il}s], [e^{if}s, e^{i(f+l)}c]], 3 parameters */
+  SV_SWAP,                 /* 2 targets */
+  SV_RXX, SV_RYY, SV_RZZ,  /* exp(-i theta P(x)P/2), 2 targets, 1 parameter */
+  SV_GIVENS,               /* rotation [[c,-s],[s,c]] on local |1>,|2>, 2 targets */
+  SV_DEXC,                 /* rotation [[c,-s],[s,c]] on local |3>,|12>, 4 targets */
+  SV_UNITARY,              /* user matrix on 1..5 targets */
+  SV_NKINDS
+} sv_gate_kind;
+
+#define SV_MAX_TARGETS 5
+#define SV_MAX_CONTROLS 5
+
+/* One typed operation (paper Section 4.2 circuit model). */
+typedef struct {
+  int32_t kind;                        /* sv_gate_kind */
+  int32_t n_targets;                   /* must equal the kind's arity (1..5 for SV_UNITARY) */
+  int32_t targets[SV_MAX_TARGETS];     /* targets first */
+  int32_t n_controls;                  /* 0..SV_MAX_CONTROLS */
+  int32_t controls[SV_MAX_CONTROLS];
+  uint32_t control_states;             /* bit i = 1: control i fires on |1>; 0: on |0> */
+  int32_t param_index[3];              /* into params[]; unused slots ignored */
+  const double *matrix;                /* SV_UNITARY only: HOST row-major 2^k x 2^k,
+                                          interleaved (re, im) complex128 */
+} sv_op;
+
+/* One Pauli term (paper Section 4.4 Pauli action): x_mask marks X or Y,
+ * z_mask marks Z or Y (a Y is a bit set in both). */
+typedef struct {
+  uint64_t x_mask;
+  uint64_t z_mask;
+  double coeff;
+} sv_pauli_term;
+
+/* Special fuse_width values (besides 0 and 2..5, the paper's semantics). */
+#define SV_FUSE_AUTO (-1)   /* LDS tile clustering: many <=5-qubit blocks per sweep */
+
+/* Workspace flags. */
+#define SV_WS_ADJOINT 1u    /* room for the adjoint's second state and partial sums */
+
+/* Bytes of device workspace a handle needs.  Always >= the forward path's
+ * needs; SV_WS_ADJOINT adds a second state (lambda) and gradient partials. */
+size_t sv_workspace_bytes(int32_t n_qubits, sv_dtype dtype, uint32_t flags);
+
+/* Wrap caller-owned device planes re/im (2^n elements each, 256-byte aligned)
+ * and workspace into a handle, bound to `hip_stream` (NULL = default stream),
+ * and set the state to |0...0>.  Errors: SV_EINVAL (n outside 1..34, null or
+ * misaligned planes), SV_EDTYPE, SV_ENOMEM (ws_bytes < sv_workspace_bytes). */
+sv_status sv_alloc(int32_t n_qubits, sv_dtype dtype, void *re, void *im, void *workspace,
+                   size_t ws_bytes, void *hip_stream, sv_state **out);
+
+/* Release the handle (never the borrowed memory). */
+sv_status sv_free(sv_state *st);
+
+/* Re-bind the handle to another stream. */
+sv_status sv_set_stream(sv_state *st, void *hip_stream);
+
+/* State <- |0...0> (async). */
+sv_status sv_reset(sv_state *st);
+
+/* Apply ops[0..n_ops) in order (paper Section 5.3 gate application:
+ * gather the amplitudes that differ only on the targets, multiply, scatter),
+ * binding parameters from params[0..n_params).  fuse_width: 0 = one sweep per
+ * gate; 2..5 = greedy in-order blocks of at most that many qubits, one sweep
+ * per block (paper Section 4.3 `fuse`); SV_FUSE_AUTO = LDS-tiled clusters of
+ * <=5-qubit blocks.  Async on the handle's stream.  Errors: SV_EINVAL (qubit
+ * out of range, repeated qubit, bad arity/kind/width), SV_EUNBOUND (parameter
+ * index out of range or a non-finite parameter), SV_ENOMEM. */
+sv_status sv_apply_layer(sv_state *st, const sv_op *ops, int32_t n_ops, const double *params,
+                         int32_t n_params, int32_t fuse_width);
+
+/* <P_j> for every term (paper Section 4.4, matrix-free Pauli action) and
+ * sum_j coeff_j <P_j>.  Either output may be NULL.  Accumulates in FP64 for
+ * both dtypes.  Waits for the stream.  Errors: SV_EINVAL (mask >= 2^n). */
+sv_status sv_expect_pauli(sv_state *st, const sv_pauli_term *terms, int32_t n_terms,
+                          double *out_terms, double *out_sum);
+
+/* Adjoint gradient of E(theta) = <0|U^dag(theta) H U(theta)|0> (paper
+ * Section 4.2 objective).  On entry *st holds the INITIAL state (normally
+ * |0...0>); on return it holds U(theta)|initial>.  grad has n_params entries
+ * (a parameter read by several gates sums their contributions).  n_evals
+ * (may be NULL) receives 1 (one forward and one backward pass).  Needs a
+ * workspace allocated with SV_WS_ADJOINT.  Errors: as sv_apply_layer, plus
+ * SV_EUNSUPPORTED for parameterised kinds without a single-angle generator
+ * (controlled U2/U3, user matrices carry no parameters), SV_ENOMEM. */
+sv_status sv_adjoint_grad(sv_state *st, const sv_op *ops, int32_t n_ops, const double *params,
+                          int32_t n_params, const sv_pauli_term *terms, int32_t n_terms,
+                          double *energy, double *grad, int32_t *n_evals);
+
+/* As sv_adjoint_grad but asynchronous: energy then grad (1 + n_params FP64)
+ * are written to DEVICE memory d_out on the handle's stream. */
+sv_status sv_adjoint_grad_device(sv_state *st, const sv_op *ops, int32_t n_ops,
+                                 const double *params, int32_t n_params,
+                                 const sv_pauli_term *terms, int32_t n_terms, double *d_out);
+
+/* Terminal Z-basis sampling (paper Section 5.3 measurement path) by a fixed
+ * order of floating-point operations, so equal states give equal bits:
+ * p_b = fma(x,x,y*y) in FP64; chunk sums over 2^min(n,10) indices by pairwise
+ * tree; sequential prefix over chunks; u_s = (splitmix64(seed, s) >> 11) 2^-53;
+ * inverse-CDF search with a strict '>' (see DESIGN notes for the fallbacks).
+ * out[s] packs bit qubits[i] of the drawn index into bit i.  Waits. */
+sv_status sv_sample(sv_state *st, uint64_t seed, int64_t shots, const int32_t *qubits,
+                    int32_t n_measured, uint64_t *out);
+
+/* Copy amplitudes [offset, offset+count) of both planes to HOST buffers of
+ * the state's element type (the paper's explicit to_numpy exit).  Waits. */
+sv_status sv_copy_to_host(const sv_state *st, void *re, void *im, uint64_t offset,
+                          uint64_t count);
+
+/* Copy HOST amplitudes into [offset, offset+count) (checkpoint reload).  Waits. */
+sv_status sv_copy_from_host(sv_state *st, const void *re, const void *im, uint64_t offset,
+                            uint64_t count);
+
+/* Thread-local message of the last failing call on this thread. */
+const char *sv_last_error(void);
+
+/* ------------------------------------------------------------ batching
+ * A ragged batch of independent circuits (paper Section 4.1 batched state
+ * vector, generalised to mixed qubit counts), run as ONE persistent launch
+ * over a device work queue of (circuit, sweep, tile-range) units.  The plan
+ * is built once per batch structure; sv_batch_run may be captured in a HIP
+ * graph by the caller; parameters are read from device memory so replays
+ * with new angles need no re-plan. */
+typedef struct sv_batch sv_batch;
+
+typedef struct {
+  int32_t n_qubits;
+  int32_t n_ops;
+  const sv_op *ops;
+  int32_t n_params;         /* parameters of this circuit (its own index space) */
+  int32_t n_terms;          /* observable: sum of Pauli terms, reported per circuit */
+  const sv_pauli_term *terms;
+} sv_circuit_desc;
+
+/* Plan a batch.  tile_bits / low_bits = 0 take defaults.  Device buffers are
+ * allocated by the library (hipMalloc) at plan time and freed by
+ * sv_batch_free.  Errors: SV_EINVAL, SV_EUNBOUND, SV_ENOMEM, SV_EUNSUPPORTED. */
+sv_status sv_batch_plan(const sv_circuit_desc *circuits, int32_t n_circuits, sv_dtype dtype,
+                        int32_t tile_bits, int32_t low_bits, sv_batch **out);
+
+/* Device pointer of the concatenated parameter vector (circuit c's params
+ * start at param_offset(c)); the caller writes new angles there. */
+double *sv_batch_params_device(sv_batch *b);
+int64_t sv_batch_param_offset(const sv_batch *b, int32_t circuit);
+
+/* Enqueue the whole batch on `hip_stream`: reset queue counters, build gate
+ * coefficients from the device parameters, run the persistent kernel, leave
+ * per-circuit observables in the device array returned by
+ * sv_batch_results_device (n_circuits FP64).  Async; capturable. */
+sv_status sv_batch_run(sv_batch *b, void *hip_stream);
+double *sv_batch_results_device(sv_batch *b);
+
+/* After the stream has finished: nonzero if a unit's bounded dependency wait
+ * expired (the results are then invalid). */
+sv_status sv_batch_check(sv_batch *b, void *hip_stream);
+
+/* Device pointers to circuit c's state planes (for parity tests). */
+sv_status sv_batch_state(sv_batch *b, int32_t circuit, void **re, void **im);
+
+/* Statistics: number of work units, total sweeps, total gate-amplitude updates. */
+sv_status sv_batch_stats(const sv_batch *b, int64_t *units, int64_t *sweeps, double *updates);
+
+sv_status sv_batch_free(sv_batch *b);
+
+/* ------------------------------------------------------- plan inspection
+ * Number of full-state sweeps and register blocks sv_apply_layer would use
+ * for this circuit with these settings (host-only; for tests and tuning). */
+sv_status sv_plan_stats(int32_t n_qubits, const sv_op *ops, int32_t n_ops, int32_t fuse_width,
+                        int32_t tile_bits, int32_t low_bits, int32_t *n_sweeps,
+                        int32_t *n_blocks);
+
+/* Tuning knobs used by SV_FUSE_AUTO for a handle (0 = default). */
+sv_status sv_set_tiling(sv_state *st, int32_t tile_bits, int32_t low_bits);
+
+/* Greedy in-order fusion (paper Section 9.2 ablation planner): block id per
+ * op into block_of (host array of n_ops), returns the block count in *n_blocks. */
+sv_status sv_fuse_blocks(const sv_op *ops, int32_t n_ops, int32_t width, int32_t *block_of,
+                         int32_t *n_blocks);
+
+/* Library build identification (gfx target, compile flags). */
+const char *sv_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,1545 @@
+// Host runtime of libsv: argument validation, circuit lowering, the sweep /
+// stage planner, plan cache, kernel launches and the C ABI of include/sv.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "sv.h"
+#include "sv_internal.h"
+#include "sv_launch.h"
+
+// ------------------------------------------------------------------ errors
+
+static thread_local std::string g_err;
+
+static sv_status fail(sv_status st, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return st;
+}
+
+#define HIPCHK(expr)                                                                  \
+  do {                                                                                \
+    hipError_t e_ = (expr);                                                           \
+    if (e_ != hipSuccess)                                                             \
+      return fail(SV_EDEVICE, "%s failed: %s", #expr, hipGetErrorString(e_));         \
+  } while (0)
+
+extern "C" const char *sv_last_error(void) { return g_err.c_str(); }
+
+extern "C" const char *sv_version(void) {
+  return "libsv gfx950 (tile sweeps M<=14, register blocks R<=5, FP64/FP32 planes)";
+}
+
+// ------------------------------------------------------------- device info
+
+struct DevInfo {
+  int cus = 0;
+};
+static std::mutex g_dev_mu;
+static std::unordered_map<int, DevInfo> g_dev;
+
+static sv_status device_info(DevInfo &out) {
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(g_dev_mu);
+  auto it = g_dev.find(dev);
+  if (it == g_dev.end()) {
+    DevInfo di;
+    HIPCHK(hipDeviceGetAttribute(&di.cus, hipDeviceAttributeMultiprocessorCount, dev));
+    it = g_dev.emplace(dev, di).first;
+  }
+  out = it->second;
+  return SV_OK;
+}
+
+// --------------------------------------------------------------- lowering
+
+static int arity_of(int kind) {
+  switch (kind) {
+    case SV_SWAP: case SV_RXX: case SV_RYY: case SV_RZZ: case SV_GIVENS: return 2;
+    case SV_DEXC: return 4;
+    case SV_UNITARY: return -1;
+    default: return 1;
+  }
+}
+
+static int nparams_of(int kind) {
+  switch (kind) {
+    case SV_RX: case SV_RY: case SV_RZ: case SV_P: case SV_RXX: case SV_RYY: case SV_RZZ:
+    case SV_GIVENS: case SV_DEXC:
+      return 1;
+    case SV_U2: return 2;
+    case SV_U3: return 3;
+    default: return 0;
+  }
+}
+
+// Kernel-side kind ids (sv_kernels.hip gate_local) equal sv_gate_kind values.
+
+struct GateRec {
+  int kind = 0;
+  int nt = 0;
+  int t[5] = {0, 0, 0, 0, 0};
+  int nc = 0;
+  int c[5] = {0, 0, 0, 0, 0};
+  uint32_t cs = 0;
+  int pidx[3] = {-1, -1, -1};
+  uint64_t qmask = 0;        // targets | controls
+  int mo = MO_NOP;
+  int coef_kind = 0;         // kind used to build the coefficients
+  int fmt = 0;               // CF_* (0 = none)
+  int ncoef = 0;             // doubles
+  int user_mat = -1;         // index of the user matrix (SV_UNITARY)
+  bool dagger = false;
+  // adjoint gradient micro-op (before the gate)
+  bool grad = false;
+  int gparam = -1;
+  uint64_t gx = 0, gz = 0;   // generator masks (global qubits)
+  double galpha = 1.0, gbeta = 0.0;
+  double cost = 0.0;         // VALU ops per amplitude (rough)
+};
+
+static sv_status validate_op(const sv_op &op, int idx, int n, int n_params) {
+  if (op.kind < 0 || op.kind >= SV_NKINDS) return fail(SV_EINVAL, "op %d: bad kind %d", idx, op.kind);
+  int ar = arity_of(op.kind);
+  if (op.kind == SV_UNITARY) {
+    if (op.n_targets < 1 || op.n_targets > 3)
+      return fail(SV_EUNSUPPORTED, "op %d: user matrices on 1..3 targets are supported (got %d)",
+                  idx, op.n_targets);
+    if (!op.matrix) return fail(SV_EINVAL, "op %d: unitary without matrix", idx);
+  } else if (op.n_targets != ar) {
+    return fail(SV_EINVAL, "op %d: kind %d takes %d targets, got %d", idx, op.kind, ar, op.n_targets);
+  }
+  if (op.n_controls < 0 || op.n_controls > SV_MAX_CONTROLS)
+    return fail(SV_EINVAL, "op %d: bad control count %d", idx, op.n_controls);
+  uint64_t seen = 0;
+  for (int i = 0; i < op.n_targets + op.n_controls; i++) {
+    int q = i < op.n_targets ? op.targets[i] : op.controls[i - op.n_targets];
+    if (q < 0 || q >= n) return fail(SV_EINVAL, "op %d: qubit %d out of range [0,%d)", idx, q, n);
+    if (seen & (1ull << q)) return fail(SV_EINVAL, "op %d: qubit %d repeated", idx, q);
+    seen |= 1ull << q;
+  }
+  if (op.n_controls < 32 && (op.control_states >> op.n_controls) != 0)
+    return fail(SV_EINVAL, "op %d: control_states has bits beyond n_controls", idx);
+  for (int i = 0; i < nparams_of(op.kind); i++)
+    if (op.param_index[i] < 0 || op.param_index[i] >= n_params)
+      return fail(SV_EUNBOUND, "op %d: parameter index %d unbound (n_params=%d)", idx,
+                  op.param_index[i], n_params);
+  if ((int)__builtin_popcountll(seen) > SVI_RMAX)
+    return fail(SV_EUNSUPPORTED, "op %d: acts on %d qubits (max %d incl. controls)", idx,
+                (int)__builtin_popcountll(seen), SVI_RMAX);
+  return SV_OK;
+}
+
+static void set_mo(GateRec &g) {
+  switch (g.kind) {
+    case SV_X: g.mo = MO_X; g.cost = 1; break;
+    case SV_Z: g.mo = MO_NEG; g.cost = 1; break;
+    case SV_Y: case SV_SX: case SV_RX: case SV_U2: case SV_U3:
+      g.mo = MO_U; g.fmt = CF_U2X2; g.ncoef = 8; g.cost = 8; break;
+    case SV_H: case SV_RY: g.mo = MO_R; g.fmt = CF_R2X2; g.ncoef = 4; g.cost = 4; break;
+    case SV_S: case SV_SDG: case SV_T: case SV_TDG: case SV_RZ: case SV_P:
+      g.mo = MO_P; g.fmt = CF_DIAG; g.ncoef = 4; g.cost = 4; break;
+    case SV_RZZ: g.mo = MO_P; g.fmt = CF_DIAG; g.ncoef = 4; g.coef_kind = SV_RZ; g.cost = 4; break;
+    case SV_SWAP: g.mo = MO_SWAP; g.cost = 1; break;
+    case SV_RXX: case SV_RYY: g.mo = MO_Q; g.fmt = CF_Q4X4; g.ncoef = 32; g.cost = 16; break;
+    case SV_GIVENS: case SV_DEXC:
+      g.mo = MO_2L; g.fmt = CF_R2X2; g.ncoef = 4; g.coef_kind = SV_RY; g.cost = 2; break;
+    case SV_UNITARY:
+      if (g.nt == 1) { g.mo = MO_U; g.ncoef = 8; g.cost = 8; }
+      else if (g.nt == 2) { g.mo = MO_Q; g.ncoef = 32; g.cost = 16; }
+      else { g.mo = MO_DENSE; g.ncoef = 2 * 64; g.cost = 32; }
+      g.fmt = CF_COPY;
+      break;
+    default: g.mo = MO_NOP; break;
+  }
+  if (g.coef_kind == 0) g.coef_kind = g.kind;
+}
+
+static GateRec lower_one(const sv_op &op, int user_mat) {
+  GateRec g;
+  g.kind = op.kind;
+  g.nt = op.n_targets;
+  for (int i = 0; i < g.nt; i++) { g.t[i] = op.targets[i]; g.qmask |= 1ull << g.t[i]; }
+  g.nc = op.n_controls;
+  for (int i = 0; i < g.nc; i++) { g.c[i] = op.controls[i]; g.qmask |= 1ull << g.c[i]; }
+  g.cs = op.control_states;
+  for (int i = 0; i < nparams_of(op.kind); i++) g.pidx[i] = op.param_index[i];
+  g.user_mat = op.kind == SV_UNITARY ? user_mat : -1;
+  set_mo(g);
+  return g;
+}
+
+// Generator of a single-angle gate exp(-i theta G / 2): G = alpha P + beta I.
+static bool generator_of(const GateRec &g, uint64_t &x, uint64_t &z, double &alpha, double &beta) {
+  alpha = 1.0; beta = 0.0; x = z = 0;
+  uint64_t b0 = 1ull << g.t[0];
+  uint64_t b01 = g.nt >= 2 ? (b0 | (1ull << g.t[1])) : b0;
+  switch (g.kind) {
+    case SV_RX: x = b0; return true;
+    case SV_RY: x = z = b0; return true;
+    case SV_RZ: z = b0; return true;
+    case SV_P: z = b0; beta = -1.0; return true;   // diag(1, e^{i l}) = exp(-i l (Z - I)/2)
+    case SV_RXX: x = b01; return true;
+    case SV_RYY: x = z = b01; return true;
+    case SV_RZZ: z = b01; return true;
+    default: return false;
+  }
+}
+
+// --------------------------------------------------------------- planner
+
+struct StageP {
+  std::vector<int> recs;      // indices into the record list, program order
+  int gq[SVI_RMAX];           // tile-local position of group bit i
+  bool dense = false;
+};
+
+struct SweepP {
+  int m = 0, c = 0, nh = 0;
+  int hb[SVI_MMAX] = {0};
+  std::vector<StageP> stages;
+};
+
+struct Tiling {
+  int M = 13, c = 3, R = 5;
+};
+
+static int popc(uint64_t v) { return __builtin_popcountll(v); }
+
+// Records of `cand` (program order, not yet done) that can run inside qubit set T:
+// a record is taken iff its qubits lie in T and no earlier untaken record shares a
+// qubit with it.  Records flagged in `veto` block like untaken ones.
+static int closure(const std::vector<GateRec> &recs, const std::vector<int> &cand,
+                   const std::vector<char> &done, uint64_t T, std::vector<int> *take,
+                   const std::vector<char> *veto = nullptr, double cost_cap = 1e300) {
+  uint64_t blocked = 0;
+  int cnt = 0;
+  double cost = 0.0;
+  for (int r : cand) {
+    if (done[r]) continue;
+    const uint64_t q = recs[r].qmask;
+    const bool vetoed = veto && (*veto)[r];
+    if (!vetoed && (q & ~T) == 0 && (q & blocked) == 0 && cost + recs[r].cost <= cost_cap) {
+      cnt++;
+      cost += recs[r].cost;
+      if (take) take->push_back(r);
+    } else {
+      blocked |= q;
+      if ((blocked & T) == T) break;
+    }
+  }
+  return cnt;
+}
+
+// Qubits of the earliest pending record that is blocked w.r.t. T (tie-break).
+static uint64_t first_blocked_qubits(const std::vector<GateRec> &recs, const std::vector<int> &cand,
+                                     const std::vector<char> &done, uint64_t T) {
+  uint64_t blocked = 0;
+  for (int r : cand) {
+    if (done[r]) continue;
+    const uint64_t q = recs[r].qmask;
+    if ((q & ~T) == 0 && (q & blocked) == 0) continue;
+    return q & ~T ? (q & ~T) : q;
+  }
+  (void)blocked;
+  return 0;
+}
+
+static int tile_pos(const SweepP &sw, int q) {
+  if (q < sw.c) return q;
+  for (int k = 0; k < sw.nh; k++)
+    if (sw.hb[k] == q) return sw.c + k;
+  return -1;
+}
+
+static void set_tile(SweepP &sw, int n, uint64_t T, int c) {
+  sw.c = c;
+  sw.nh = 0;
+  for (int q = c; q < n; q++)
+    if (T & (1ull << q)) sw.hb[sw.nh++] = q;
+  sw.m = c + sw.nh;
+}
+
+// Split one sweep's records into register stages of <= R qubits.
+static void plan_stages(const std::vector<GateRec> &recs, const std::vector<int> &take, SweepP &sw,
+                        int R, int n) {
+  std::vector<char> done(recs.size(), 0);
+  std::vector<char> veto(recs.size(), 0);
+  for (int r : take)
+    if (recs[r].mo == MO_DENSE) veto[r] = 1;
+  uint64_t Ttile = 0;
+  for (int q = 0; q < sw.c; q++) Ttile |= 1ull << q;
+  for (int k = 0; k < sw.nh; k++) Ttile |= 1ull << sw.hb[k];
+  size_t left = take.size();
+  const int mm = std::max(sw.m, R);
+  while (left) {
+    int first = -1;
+    for (int r : take)
+      if (!done[r]) { first = r; break; }
+    StageP st;
+    std::vector<int> grp;   // qubits (global) in group order
+    if (recs[first].mo == MO_DENSE) {
+      st.dense = true;
+      st.recs.push_back(first);
+      done[first] = 1;
+      left--;
+      for (int i = 0; i < recs[first].nt; i++) grp.push_back(recs[first].t[i]);
+      for (int i = 0; i < recs[first].nc; i++) grp.push_back(recs[first].c[i]);
+    } else {
+      uint64_t S = recs[first].qmask;
+      while (popc(S) < R) {
+        int best = -1, bestv = closure(recs, take, done, S, nullptr, &veto);
+        for (int q = 0; q < n; q++) {
+          if (!(Ttile & (1ull << q)) || (S & (1ull << q))) continue;
+          int v = closure(recs, take, done, S | (1ull << q), nullptr, &veto);
+          if (v > bestv) { bestv = v; best = q; }
+        }
+        if (best < 0) {
+          uint64_t fq = first_blocked_qubits(recs, take, done, S) & Ttile & ~S;
+          // only grow by a record we can actually take later
+          if (fq && popc(S | fq) <= R) {
+            S |= fq;
+            continue;
+          }
+          break;
+        }
+        S |= 1ull << best;
+      }
+      std::vector<int> got;
+      closure(recs, take, done, S, &got, &veto);
+      for (int r : got) { done[r] = 1; left--; }
+      st.recs = got;
+      for (int q = 0; q < n; q++)
+        if (S & (1ull << q)) grp.push_back(q);
+    }
+    // group bit -> tile-local position; pad with the highest unused positions
+    int used = 0;
+    for (size_t i = 0; i < grp.size(); i++) st.gq[i] = tile_pos(sw, grp[i]);
+    used = (int)grp.size();
+    uint64_t taken = 0;
+    for (int i = 0; i < used; i++) taken |= 1ull << st.gq[i];
+    for (int p = mm - 1; p >= 0 && used < R; p--)
+      if (!(taken & (1ull << p))) { st.gq[used++] = p; taken |= 1ull << p; }
+    sw.stages.push_back(st);
+  }
+}
+
+// AUTO planner: DAG-aware tile clustering.
+static void plan_auto(const std::vector<GateRec> &recs, int n, const Tiling &tl,
+                      std::vector<SweepP> &out, double cost_cap) {
+  const int M = std::min(tl.M, n);
+  const int c = std::min(tl.c, n);
+  std::vector<int> cand(recs.size());
+  for (size_t i = 0; i < recs.size(); i++) cand[i] = (int)i;
+  std::vector<char> done(recs.size(), 0);
+  size_t left = recs.size();
+  uint64_t low = c >= 64 ? ~0ull : ((1ull << c) - 1);
+  size_t start = 0;
+  while (left) {
+    while (start < cand.size() && done[cand[start]]) start++;
+    std::vector<int> sub(cand.begin() + start, cand.end());
+    uint64_t T = low;
+    if (n <= M) {
+      T = n >= 64 ? ~0ull : ((1ull << n) - 1);
+    } else {
+      for (int step = c; step < M; step++) {
+        int best = -1, bestv = closure(recs, sub, done, T, nullptr, nullptr, cost_cap);
+        for (int q = c; q < n; q++) {
+          if (T & (1ull << q)) continue;
+          int v = closure(recs, sub, done, T | (1ull << q), nullptr, nullptr, cost_cap);
+          if (v > bestv) { bestv = v; best = q; }
+        }
+        if (best < 0) {
+          uint64_t fq = first_blocked_qubits(recs, sub, done, T) & ~T;
+          if (!fq) break;
+          // lowest qubit of the earliest blocked record
+          best = __builtin_ctzll(fq);
+        }
+        T |= 1ull << best;
+      }
+      // fill the tile to M qubits (larger tiles cost nothing extra)
+      for (int q = c; q < n && popc(T) < M; q++) T |= 1ull << q;
+    }
+    std::vector<int> take;
+    closure(recs, sub, done, T, &take, nullptr, cost_cap);
+    if (take.empty()) {
+      // cost cap smaller than one record: take the first pending record alone
+      take.push_back(sub[0]);
+    }
+    SweepP sw;
+    set_tile(sw, n, T, c);
+    plan_stages(recs, take, sw, tl.R, n);
+    for (int r : take) { done[r] = 1; left--; }
+    out.push_back(std::move(sw));
+  }
+}
+
+// Paper-style fusion: greedy in-order blocks of <= width qubits, one sweep per block.
+static int fuse_greedy(const std::vector<GateRec> &recs, int width, std::vector<int> &block_of) {
+  uint64_t open = 0;
+  int nb = 0;
+  block_of.resize(recs.size());
+  for (size_t i = 0; i < recs.size(); i++) {
+    const uint64_t q = recs[i].qmask;
+    if (open && popc(open | q) > width) open = 0;
+    if (!open) nb++;
+    open |= q;
+    block_of[i] = nb - 1;
+  }
+  return nb;
+}
+
+static void plan_fused(const std::vector<GateRec> &recs, int n, const Tiling &tl, int width,
+                       std::vector<SweepP> &out) {
+  std::vector<int> block_of;
+  int nb = fuse_greedy(recs, width, block_of);
+  const int M = std::min(tl.M, n);
+  const int c = std::min(tl.c, n);
+  size_t i = 0;
+  for (int b = 0; b < nb; b++) {
+    std::vector<int> take;
+    uint64_t Q = 0;
+    while (i < recs.size() && block_of[i] == b) { take.push_back((int)i); Q |= recs[i].qmask; i++; }
+    uint64_t T = (c >= 64 ? ~0ull : ((1ull << c) - 1)) | Q;
+    for (int q = c; q < n && popc(T) < M; q++) T |= 1ull << q;
+    SweepP sw;
+    set_tile(sw, n, T, c);
+    plan_stages(recs, take, sw, tl.R, n);
+    out.push_back(std::move(sw));
+  }
+}
+
+// --------------------------------------------------------- plan material
+
+struct Step {
+  int kind = 0;              // 0 = tile sweep, 1 = single-gate kernel
+  SweepArgs sa{};            // tile sweep (pointers patched at launch)
+  GateArgsHost ga{};         // single gate
+  int gate_coef = -1;
+};
+
+struct Plan {
+  int n = 0;
+  bool dbl = true;
+  int M = 13, R = 5, NS = 1;
+  std::vector<Step> steps;
+  std::vector<StageDesc> stages;
+  std::vector<MicroOp> ops;
+  std::vector<CoefDesc> coefs;
+  int ncoef = 0;
+  std::vector<double> constants;     // appended after the user parameters
+  int n_user_params = 0;
+  int n_user_mats = 0;
+  std::vector<int> mat_dim;          // per user matrix: doubles
+  int nstatic = 0;
+  // adjoint
+  int n_gslots = 0;
+  std::vector<int> slot_param;
+  std::vector<int32_t> grad_rowptr, grad_slots;
+  // device buffers
+  void *d_buf = nullptr;
+  size_t d_bytes = 0;
+  StageDesc *d_stages = nullptr;
+  MicroOp *d_ops = nullptr;
+  CoefDesc *d_coefdesc = nullptr;
+  double *d_coef = nullptr;
+  double *d_params = nullptr;        // user params + constants
+  double *d_statics = nullptr;
+  int32_t *d_rowptr = nullptr, *d_gslots = nullptr;
+  int n_sweeps = 0, n_blocks = 0;
+  ~Plan() {
+    if (d_buf) (void)hipFree(d_buf);
+  }
+};
+
+static void add_coef(Plan &P, GateRec &g, int &coef_off) {
+  coef_off = -1;
+  if (g.ncoef == 0) return;
+  CoefDesc cd{};
+  cd.kind = g.coef_kind;
+  cd.fmt = g.fmt | (g.dagger ? CF_DAGGER : 0);
+  for (int k = 0; k < 3; k++) cd.pidx[k] = g.pidx[k];
+  cd.dst = P.ncoef;
+  if (g.fmt == CF_COPY) {
+    int off = 0;
+    for (int k = 0; k < g.user_mat; k++) off += P.mat_dim[k];
+    cd.src = off;
+    cd.len = g.ncoef;
+  }
+  P.coefs.push_back(cd);
+  coef_off = P.ncoef;
+  P.ncoef += g.ncoef;
+}
+
+static uint16_t spread_local(int j, const int *gq, int R) {
+  int o = 0;
+  for (int i = 0; i < R; i++)
+    if ((j >> i) & 1) o |= 1 << gq[i];
+  return (uint16_t)o;
+}
+
+static int perm_apply(const MicroOp &op, int j) {
+  if (((uint32_t)j & op.cm) != op.cv) return j;
+  if (op.type == MO_X) return j ^ (1 << op.t0);
+  if (op.type == MO_SWAP) {
+    int a = (j >> op.t0) & 1, b = (j >> op.t1) & 1;
+    return a != b ? (j ^ (1 << op.t0) ^ (1 << op.t1)) : j;
+  }
+  return j;
+}
+
+// Emit the device descriptors of one tile sweep.
+static void emit_sweep(Plan &P, std::vector<GateRec> &recs, const SweepP &sw, int n, int R,
+                       int flags, int gslot_base, int &gslots_used) {
+  Step s;
+  s.kind = 0;
+  SweepArgs &a = s.sa;
+  std::memset(&a, 0, sizeof a);
+  a.n = n;
+  a.m = sw.m;
+  a.c = sw.c;
+  a.nh = sw.nh;
+  for (int k = 0; k < SVI_MMAX; k++) a.hb[k] = k < sw.nh ? sw.hb[k] : 0;
+  a.flags = flags;
+  a.ntiles = (int64_t)1 << (n - sw.m);
+  a.stage_begin = (int)P.stages.size();
+  a.gslot_begin = gslot_base;
+  int gs = 0;
+  for (const StageP &st : sw.stages) {
+    // group bits: qubit of tile position st.gq[i]
+    auto local_of = [&](int q) {
+      int p = tile_pos(sw, q);
+      for (int i = 0; i < R; i++)
+        if (st.gq[i] == p) return i;
+      return -1;
+    };
+    std::vector<MicroOp> mops;
+    for (int r : st.recs) {
+      GateRec &g = recs[r];
+      uint32_t cm = 0, cv = 0;
+      for (int i = 0; i < g.nc; i++) {
+        int l = local_of(g.c[i]);
+        cm |= 1u << l;
+        if ((g.cs >> i) & 1u) cv |= 1u << l;
+      }
+      if (g.grad) {
+        MicroOp go{};
+        go.type = MO_GRAD;
+        uint32_t xl = 0, zl = 0;
+        for (int q = 0; q < n; q++) {
+          if ((g.gx >> q) & 1) xl |= 1u << local_of(q);
+          if ((g.gz >> q) & 1) zl |= 1u << local_of(q);
+        }
+        go.mask = xl;
+        go.gz = zl;
+        go.cm = cm;
+        go.cv = cv;
+        go.galpha = g.galpha;
+        go.gbeta = g.gbeta;
+        go.coef = gs;
+        P.slot_param.push_back(g.gparam);
+        gs++;
+        mops.push_back(go);
+      }
+      MicroOp op{};
+      op.type = g.mo;
+      op.cm = cm;
+      op.cv = cv;
+      int coff = -1;
+      add_coef(P, g, coff);
+      op.coef = coff < 0 ? 0 : coff;
+      switch (g.mo) {
+        case MO_U: case MO_R: case MO_X: op.t0 = local_of(g.t[0]); break;
+        case MO_P: {
+          uint32_t mk = 0;
+          for (int i = 0; i < g.nt; i++) mk |= 1u << local_of(g.t[i]);
+          op.mask = mk;
+          break;
+        }
+        case MO_NEG: {
+          int l = local_of(g.t[0]);
+          op.cm |= 1u << l;
+          op.cv |= 1u << l;
+          break;
+        }
+        case MO_SWAP: case MO_Q: op.t0 = local_of(g.t[0]); op.t1 = local_of(g.t[1]); break;
+        case MO_2L: {
+          uint32_t tm = 0;
+          for (int i = 0; i < g.nt; i++) tm |= 1u << local_of(g.t[i]);
+          uint32_t pa, pb;
+          if (g.nt == 2) { pa = 1u << local_of(g.t[0]); pb = 1u << local_of(g.t[1]); }
+          else {
+            pa = (1u << local_of(g.t[0])) | (1u << local_of(g.t[1]));
+            pb = (1u << local_of(g.t[2])) | (1u << local_of(g.t[3]));
+          }
+          op.mask = tm;
+          op.gz = pa;
+          op.t1 = (int)(pa ^ pb);
+          break;
+        }
+        case MO_DENSE: op.mask = g.nt; break;   // targets are group bits 0..k-1
+        default: break;
+      }
+      if (op.type != MO_NOP) mops.push_back(op);
+    }
+    // fold leading / trailing permutations into the LDS offsets
+    size_t lead = 0;
+    while (lead < mops.size() && (mops[lead].type == MO_X || mops[lead].type == MO_SWAP)) lead++;
+    size_t trail = mops.size();
+    if (lead < mops.size())
+      while (trail > lead && (mops[trail - 1].type == MO_X || mops[trail - 1].type == MO_SWAP)) trail--;
+    StageDesc sd;
+    std::memset(&sd, 0, sizeof sd);
+    int sorted[SVI_RMAX];
+    for (int i = 0; i < R; i++) sorted[i] = st.gq[i];
+    std::sort(sorted, sorted + R);
+    for (int i = 0; i < SVI_RMAX; i++) sd.sbits[i] = i < R ? sorted[i] : 0;
+    for (int j = 0; j < (1 << R); j++) {
+      int jl = j;
+      for (size_t k = lead; k-- > 0;) jl = perm_apply(mops[k], jl);
+      sd.ld_off[j] = spread_local(jl, st.gq, R);
+      int js = j;
+      for (size_t k = trail; k < mops.size(); k++) js = perm_apply(mops[k], js);
+      sd.st_off[j] = spread_local(js, st.gq, R);
+    }
+    sd.op_begin = (int)P.ops.size();
+    for (size_t k = lead; k < trail; k++) P.ops.push_back(mops[k]);
+    sd.op_end = (int)P.ops.size();
+    P.stages.push_back(sd);
+    P.n_blocks++;
+  }
+  a.stage_end = (int)P.stages.size();
+  a.n_gslots = gs;
+  gslots_used = gs;
+  P.steps.push_back(s);
+  P.n_sweeps++;
+}
+
+static void emit_gate(Plan &P, GateRec &g, int n) {
+  Step s;
+  s.kind = 1;
+  GateArgsHost &a = s.ga;
+  std::memset(&a, 0, sizeof a);
+  a.type = g.mo;
+  a.t0 = g.t[0];
+  a.t1 = g.nt > 1 ? g.t[1] : 0;
+  int pos[16], np = 0;
+  uint64_t cval = 0;
+  for (int i = 0; i < g.nc; i++) {
+    pos[np++] = g.c[i];
+    if ((g.cs >> i) & 1u) cval |= 1ull << g.c[i];
+  }
+  if (g.mo == MO_P) {
+    for (int i = 0; i < g.nt; i++) a.pmask |= 1ull << g.t[i];
+  } else if (g.mo == MO_NEG) {
+    pos[np++] = g.t[0];
+    cval |= 1ull << g.t[0];
+  } else {
+    for (int i = 0; i < g.nt; i++) pos[np++] = g.t[i];
+  }
+  std::sort(pos, pos + np);
+  a.npos = np;
+  for (int i = 0; i < np; i++) a.pos[i] = pos[i];
+  a.cval = cval;
+  a.nitems = (int64_t)1 << (n - np);
+  int coff = -1;
+  add_coef(P, g, coff);
+  s.gate_coef = coff;
+  P.steps.push_back(s);
+  P.n_sweeps++;
+  P.n_blocks++;
+}
+
+static sv_status upload_plan(Plan &P) {
+  // layout: stages | ops | coefdesc | coef | params | statics | rowptr | gslots
+  auto align = [](size_t v) { return (v + 255) & ~(size_t)255; };
+  size_t o_st = 0;
+  size_t o_ops = align(o_st + P.stages.size() * sizeof(StageDesc));
+  size_t o_cd = align(o_ops + P.ops.size() * sizeof(MicroOp));
+  size_t o_cf = align(o_cd + P.coefs.size() * sizeof(CoefDesc));
+  size_t o_pa = align(o_cf + (size_t)std::max(P.ncoef, 1) * 8);
+  size_t npar = (size_t)P.n_user_params + P.constants.size();
+  size_t o_stc = align(o_pa + std::max<size_t>(npar, 1) * 8);
+  size_t o_rp = align(o_stc + (size_t)std::max(P.nstatic, 1) * 8);
+  size_t o_gs = align(o_rp + (P.grad_rowptr.size() + 1) * 4);
+  size_t total = align(o_gs + (P.grad_slots.size() + 1) * 4);
+  HIPCHK(hipMalloc(&P.d_buf, total));
+  P.d_bytes = total;
+  char *b = (char *)P.d_buf;
+  P.d_stages = (StageDesc *)(b + o_st);
+  P.d_ops = (MicroOp *)(b + o_ops);
+  P.d_coefdesc = (CoefDesc *)(b + o_cd);
+  P.d_coef = (double *)(b + o_cf);
+  P.d_params = (double *)(b + o_pa);
+  P.d_statics = (double *)(b + o_stc);
+  P.d_rowptr = (int32_t *)(b + o_rp);
+  P.d_gslots = (int32_t *)(b + o_gs);
+  if (!P.stages.empty())
+    HIPCHK(hipMemcpy(P.d_stages, P.stages.data(), P.stages.size() * sizeof(StageDesc), hipMemcpyHostToDevice));
+  if (!P.ops.empty())
+    HIPCHK(hipMemcpy(P.d_ops, P.ops.data(), P.ops.size() * sizeof(MicroOp), hipMemcpyHostToDevice));
+  if (!P.coefs.empty())
+    HIPCHK(hipMemcpy(P.d_coefdesc, P.coefs.data(), P.coefs.size() * sizeof(CoefDesc), hipMemcpyHostToDevice));
+  if (!P.constants.empty())
+    HIPCHK(hipMemcpy(P.d_params + P.n_user_params, P.constants.data(), P.constants.size() * 8, hipMemcpyHostToDevice));
+  if (!P.grad_rowptr.empty())
+    HIPCHK(hipMemcpy(P.d_rowptr, P.grad_rowptr.data(), P.grad_rowptr.size() * 4, hipMemcpyHostToDevice));
+  if (!P.grad_slots.empty())
+    HIPCHK(hipMemcpy(P.d_gslots, P.grad_slots.data(), P.grad_slots.size() * 4, hipMemcpyHostToDevice));
+  return SV_OK;
+}
+
+// ---------------------------------------------------------------- handle
+
+struct sv_state {
+  int n = 0;
+  sv_dtype dtype = SV_C128;
+  void *re = nullptr, *im = nullptr;
+  void *ws = nullptr;
+  size_t ws_bytes = 0;
+  hipStream_t stream = nullptr;
+  Tiling tiling;
+  int dev = 0;
+  std::unordered_map<std::string, std::unique_ptr<Plan>> plans;
+  // growable scratch (partials)
+  void *scratch = nullptr;
+  size_t scratch_bytes = 0;
+  ~sv_state() {
+    if (scratch) (void)hipFree(scratch);
+  }
+};
+
+static size_t elem_size(sv_dtype d) { return d == SV_C128 ? 8 : 4; }
+
+static int sample_K(int n) { int cb = n < 10 ? n : 10; return (int)(((int64_t)1 << n) >> cb); }
+
+extern "C" size_t sv_workspace_bytes(int32_t n, sv_dtype dtype, uint32_t flags) {
+  if (n < 1 || n > 34 || (dtype != SV_C128 && dtype != SV_C64)) return 0;
+  size_t K = (size_t)sample_K(n);
+  size_t b = ((2 * K + 1) * 8 + 255) & ~(size_t)255;
+  if (flags & SV_WS_ADJOINT) b += 4 * ((size_t)1 << n) * elem_size(dtype);
+  return b + 256;
+}
+
+static void ws_layout(const sv_state *st, double **S, double **P, void **lre, void **lim, void **wre,
+                      void **wim) {
+  size_t K = (size_t)sample_K(st->n);
+  char *b = (char *)st->ws;
+  *S = (double *)b;
+  *P = (double *)(b + K * 8);
+  size_t off = ((2 * K + 1) * 8 + 255) & ~(size_t)255;
+  size_t plane = ((size_t)1 << st->n) * elem_size(st->dtype);
+  *lre = b + off;
+  *lim = b + off + plane;
+  *wre = b + off + 2 * plane;
+  *wim = b + off + 3 * plane;
+}
+
+static sv_status ensure_scratch(sv_state *st, size_t bytes) {
+  if (st->scratch_bytes >= bytes) return SV_OK;
+  if (st->scratch) {
+    HIPCHK(hipStreamSynchronize(st->stream));
+    HIPCHK(hipFree(st->scratch));
+    st->scratch = nullptr;
+  }
+  size_t b = std::max(bytes, (size_t)1 << 20);
+  HIPCHK(hipMalloc(&st->scratch, b));
+  st->scratch_bytes = b;
+  return SV_OK;
+}
+
+static Tiling default_tiling(int n, sv_dtype dt, int NS) {
+  Tiling t;
+  if (dt == SV_C128) {
+    if (NS == 2) { t.M = 12; t.R = 4; t.c = 3; }
+    else { t.M = 13; t.R = 5; t.c = 3; }
+  } else {
+    if (NS == 2) { t.M = 13; t.R = 4; t.c = 3; }
+    else { t.M = 14; t.R = 5; t.c = 3; }
+  }
+  (void)n;
+  return t;
+}
+
+extern "C" sv_status sv_alloc(int32_t n, sv_dtype dtype, void *re, void *im, void *ws,
+                              size_t ws_bytes, void *stream, sv_state **out) {
+  if (!out) return fail(SV_EINVAL, "null output handle");
+  *out = nullptr;
+  if (dtype != SV_C128 && dtype != SV_C64) return fail(SV_EDTYPE, "unsupported dtype %d", (int)dtype);
+  if (n < 1 || n > 34) return fail(SV_EINVAL, "n_qubits %d outside 1..34", n);
+  if (!re || !im) return fail(SV_EINVAL, "null state plane");
+  if (((uintptr_t)re & 15) || ((uintptr_t)im & 15)) return fail(SV_EINVAL, "state planes must be 16-byte aligned");
+  size_t need = sv_workspace_bytes(n, dtype, 0);
+  if (!ws || ws_bytes < need)
+    return fail(SV_ENOMEM, "workspace %zu bytes < required %zu", ws_bytes, need);
+  if ((uintptr_t)ws & 255) return fail(SV_EINVAL, "workspace must be 256-byte aligned");
+  DevInfo di;
+  sv_status s = device_info(di);
+  if (s) return s;
+  sv_state *st = new sv_state;
+  st->n = n;
+  st->dtype = dtype;
+  st->re = re;
+  st->im = im;
+  st->ws = ws;
+  st->ws_bytes = ws_bytes;
+  st->stream = (hipStream_t)stream;
+  st->tiling = default_tiling(n, dtype, 1);
+  (void)hipGetDevice(&st->dev);
+  hipError_t e = svk_launch_init_zero(dtype == SV_C128, re, im, (int64_t)1 << n, st->stream);
+  if (e != hipSuccess) {
+    delete st;
+    return fail(SV_EDEVICE, "init kernel: %s", hipGetErrorString(e));
+  }
+  *out = st;
+  return SV_OK;
+}
+
+extern "C" sv_status sv_free(sv_state *st) {
+  if (!st) return SV_OK;
+  if (st->stream || true) (void)hipStreamSynchronize(st->stream);
+  delete st;
+  return SV_OK;
+}
+
+extern "C" sv_status sv_set_stream(sv_state *st, void *stream) {
+  if (!st) return fail(SV_EINVAL, "null handle");
+  st->stream = (hipStream_t)stream;
+  return SV_OK;
+}
+
+extern "C" sv_status sv_set_tiling(sv_state *st, int32_t tile_bits, int32_t low_bits) {
+  if (!st) return fail(SV_EINVAL, "null handle");
+  Tiling t = default_tiling(st->n, st->dtype, 1);
+  if (tile_bits) t.M = tile_bits;
+  if (low_bits) t.c = low_bits;
+  if (!svk_has_sweep(st->dtype == SV_C128, t.M, t.R, 1)) {
+    // try the other register width
+    int altR = t.R == 5 ? 4 : 5;
+    if (svk_has_sweep(st->dtype == SV_C128, t.M, altR, 1)) t.R = altR;
+    else return fail(SV_EINVAL, "no kernel for tile_bits=%d", t.M);
+  }
+  if (t.c < 1 || t.c > t.M - t.R + 1) return fail(SV_EINVAL, "low_bits %d out of range", t.c);
+  st->tiling = t;
+  st->plans.clear();
+  return SV_OK;
+}
+
+extern "C" sv_status sv_reset(sv_state *st) {
+  if (!st) return fail(SV_EINVAL, "null handle");
+  hipError_t e = svk_launch_init_zero(st->dtype == SV_C128, st->re, st->im, (int64_t)1 << st->n, st->stream);
+  if (e != hipSuccess) return fail(SV_EDEVICE, "init kernel: %s", hipGetErrorString(e));
+  return SV_OK;
+}
+
+// --------------------------------------------------------- plan building
+
+static sv_status validate_circuit(int n, const sv_op *ops, int n_ops, const double *params,
+                                  int n_params) {
+  if (n_ops < 0) return fail(SV_EINVAL, "negative n_ops");
+  if (n_ops > 0 && !ops) return fail(SV_EINVAL, "null ops");
+  if (n_params < 0) return fail(SV_EINVAL, "negative n_params");
+  if (n_params > 0 && !params) return fail(SV_EUNBOUND, "null params with n_params=%d", n_params);
+  for (int i = 0; i < n_ops; i++) {
+    sv_status s = validate_op(ops[i], i, n, n_params);
+    if (s) return s;
+  }
+  for (int p = 0; p < n_params; p++)
+    if (!std::isfinite(params[p])) return fail(SV_EUNBOUND, "parameter %d is not finite", p);
+  return SV_OK;
+}
+
+static std::string plan_key(int mode, int n, const Tiling &tl, bool dbl, const sv_op *ops, int n_ops,
+                            int n_params) {
+  std::string k;
+  k.reserve(64 + (size_t)n_ops * 24);
+  char buf[96];
+  snprintf(buf, sizeof buf, "%d|%d|%d,%d,%d|%d|%d|", mode, n, tl.M, tl.c, tl.R, (int)dbl, n_params);
+  k += buf;
+  for (int i = 0; i < n_ops; i++) {
+    const sv_op &o = ops[i];
+    int v[16] = {o.kind, o.n_targets, o.targets[0], o.targets[1], o.targets[2], o.targets[3],
+                 o.targets[4], o.n_controls, o.controls[0], o.controls[1], o.controls[2],
+                 o.controls[3], o.controls[4], (int)o.control_states, o.param_index[0],
+                 o.param_index[1]};
+    for (int j = o.n_targets; j < 5; j++) v[2 + j] = 0;
+    for (int j = o.n_controls; j < 5; j++) v[8 + j] = 0;
+    int np = nparams_of(o.kind);
+    if (np < 1) v[14] = 0;
+    if (np < 2) v[15] = 0;
+    k.append((const char *)v, sizeof v);
+    int p2 = np >= 3 ? o.param_index[2] : 0;
+    k.append((const char *)&p2, sizeof p2);
+  }
+  return k;
+}
+
+static void collect_user_mats(Plan &P, const sv_op *ops, int n_ops) {
+  P.mat_dim.clear();
+  for (int i = 0; i < n_ops; i++)
+    if (ops[i].kind == SV_UNITARY) {
+      int d = 1 << ops[i].n_targets;
+      P.mat_dim.push_back(2 * d * d);
+    }
+  P.n_user_mats = (int)P.mat_dim.size();
+  P.nstatic = 0;
+  for (int v : P.mat_dim) P.nstatic += v;
+}
+
+// mode: 0 = one sweep per gate, 2..5 = paper fusion width, -1 = AUTO
+static sv_status build_forward_plan(int mode, int n, bool dbl, const Tiling &tl, const sv_op *ops,
+                                    int n_ops, int n_params, Plan &P) {
+  P.n = n;
+  P.dbl = dbl;
+  P.M = tl.M;
+  P.R = tl.R;
+  P.NS = 1;
+  P.n_user_params = n_params;
+  collect_user_mats(P, ops, n_ops);
+  std::vector<GateRec> recs;
+  int um = 0;
+  for (int i = 0; i < n_ops; i++) {
+    GateRec g = lower_one(ops[i], ops[i].kind == SV_UNITARY ? um : -1);
+    if (ops[i].kind == SV_UNITARY) um++;
+    if (g.mo == MO_NOP) continue;
+    recs.push_back(g);
+  }
+  if (mode == 0) {
+    for (GateRec &g : recs) {
+      if (g.mo == MO_2L || g.mo == MO_DENSE) {
+        SweepP sw;
+        const int M = std::min(tl.M, n), c = std::min(tl.c, n);
+        uint64_t T = (c >= 64 ? ~0ull : ((1ull << c) - 1)) | g.qmask;
+        for (int q = c; q < n && popc(T) < M; q++) T |= 1ull << q;
+        set_tile(sw, n, T, c);
+        std::vector<GateRec> one{g};
+        plan_stages(one, std::vector<int>{0}, sw, tl.R, n);
+        int used = 0;
+        emit_sweep(P, one, sw, n, tl.R, 0, 0, used);
+      } else {
+        emit_gate(P, g, n);
+      }
+    }
+  } else {
+    std::vector<SweepP> sweeps;
+    if (mode < 0) plan_auto(recs, n, tl, sweeps, 1e300);
+    else plan_fused(recs, n, tl, mode, sweeps);
+    for (const SweepP &sw : sweeps) {
+      int used = 0;
+      emit_sweep(P, recs, sw, n, tl.R, 0, 0, used);
+    }
+  }
+  return SV_OK;
+}
+
+// Backward program of the adjoint: gates in reverse, each daggered, with a
+// gradient micro-op before every parameterised rotation.
+static sv_status build_adjoint_plan(int n, bool dbl, const Tiling &tl, const sv_op *ops, int n_ops,
+                                    int n_params, Plan &P) {
+  P.n = n;
+  P.dbl = dbl;
+  P.M = tl.M;
+  P.R = tl.R;
+  P.NS = 2;
+  P.n_user_params = n_params;
+  collect_user_mats(P, ops, n_ops);
+  std::vector<GateRec> recs;
+  int um_total = P.n_user_mats;
+  int um = um_total;
+  for (int i = n_ops - 1; i >= 0; i--) {
+    const sv_op &op = ops[i];
+    if (op.kind == SV_UNITARY) um--;
+    GateRec g = lower_one(op, op.kind == SV_UNITARY ? um : -1);
+    if (g.mo == MO_NOP) continue;
+    if (op.kind == SV_U2 || op.kind == SV_U3) {
+      if (op.n_controls)
+        return fail(SV_EUNSUPPORTED, "op %d: adjoint of controlled U2/U3 is not supported", i);
+      // U3(t,f,l) = e^{i(f+l)/2} RZ(f) RY(t) RZ(l); reversed: RZ(f)^dag, RY(t)^dag, RZ(l)^dag
+      int pt, pf, pl;
+      if (op.kind == SV_U3) { pt = op.param_index[0]; pf = op.param_index[1]; pl = op.param_index[2]; }
+      else {
+        P.constants.push_back(1.57079632679489661923);
+        pt = n_params + (int)P.constants.size() - 1;
+        pf = op.param_index[0];
+        pl = op.param_index[1];
+      }
+      const int kinds[3] = {SV_RZ, SV_RY, SV_RZ};
+      const int pids[3] = {pf, pt, pl};
+      for (int k = 0; k < 3; k++) {
+        sv_op sub{};
+        sub.kind = kinds[k];
+        sub.n_targets = 1;
+        sub.targets[0] = op.targets[0];
+        sub.param_index[0] = pids[k];
+        GateRec s = lower_one(sub, -1);
+        s.dagger = true;
+        bool trainable = !(op.kind == SV_U2 && k == 1);
+        if (trainable) {
+          s.grad = true;
+          s.gparam = pids[k];
+          generator_of(s, s.gx, s.gz, s.galpha, s.gbeta);
+          s.cost += 8;
+        }
+        recs.push_back(s);
+      }
+      continue;
+    }
+    g.dagger = true;
+    if (nparams_of(op.kind) > 0) {
+      if (!generator_of(g, g.gx, g.gz, g.galpha, g.gbeta))
+        return fail(SV_EUNSUPPORTED, "op %d: adjoint gradient of kind %d is not supported", i, op.kind);
+      g.grad = true;
+      g.gparam = op.param_index[0];
+      g.cost += 8;
+    }
+    recs.push_back(g);
+  }
+  std::vector<SweepP> sweeps;
+  plan_auto(recs, n, tl, sweeps, 1e300);
+  // cap gradient slots per sweep by splitting sweeps whose stages exceed the limit
+  int gbase = 0;
+  for (const SweepP &sw0 : sweeps) {
+    // count grads per stage; split stage list into chunks with <= SVI_GSLOTS_MAX grads
+    SweepP cur = sw0;
+    cur.stages.clear();
+    int cnt = 0;
+    auto flush = [&]() {
+      if (cur.stages.empty()) return;
+      int used = 0;
+      emit_sweep(P, recs, cur, n, tl.R, 0, gbase, used);
+      gbase += used;
+      cur.stages.clear();
+      cnt = 0;
+    };
+    for (const StageP &st : sw0.stages) {
+      int g = 0;
+      for (int r : st.recs) g += recs[r].grad ? 1 : 0;
+      if (cnt + g > SVI_GSLOTS_MAX) flush();
+      cur.stages.push_back(st);
+      cnt += g;
+    }
+    flush();
+  }
+  P.n_gslots = gbase;
+  // CSR: parameter -> slots in ascending slot order
+  int np = n_params + (int)P.constants.size();
+  std::vector<std::vector<int>> rows(np);
+  for (int s = 0; s < P.n_gslots; s++) rows[P.slot_param[s]].push_back(s);
+  P.grad_rowptr.assign(n_params + 1, 0);
+  P.grad_slots.clear();
+  for (int p = 0; p < n_params; p++) {
+    for (int s : rows[p]) P.grad_slots.push_back(s);
+    P.grad_rowptr[p + 1] = (int32_t)P.grad_slots.size();
+  }
+  return SV_OK;
+}
+
+static sv_status get_plan(sv_state *st, int mode, const Tiling &tl, const sv_op *ops, int n_ops,
+                          int n_params, bool adjoint, Plan **out) {
+  std::string key = (adjoint ? "A" : "F") + plan_key(mode, st->n, tl, st->dtype == SV_C128, ops, n_ops, n_params);
+  auto it = st->plans.find(key);
+  if (it != st->plans.end()) {
+    *out = it->second.get();
+    return SV_OK;
+  }
+  std::unique_ptr<Plan> P(new Plan);
+  sv_status s = adjoint ? build_adjoint_plan(st->n, st->dtype == SV_C128, tl, ops, n_ops, n_params, *P)
+                        : build_forward_plan(mode, st->n, st->dtype == SV_C128, tl, ops, n_ops, n_params, *P);
+  if (s) return s;
+  s = upload_plan(*P);
+  if (s) return s;
+  if (st->plans.size() > 64) st->plans.clear();
+  *out = P.get();
+  st->plans.emplace(key, std::move(P));
+  return SV_OK;
+}
+
+static sv_status upload_call_data(sv_state *st, Plan &P, const sv_op *ops, int n_ops,
+                                  const double *params, int n_params) {
+  if (n_params > 0)
+    HIPCHK(hipMemcpyAsync(P.d_params, params, (size_t)n_params * 8, hipMemcpyHostToDevice, st->stream));
+  if (P.nstatic > 0) {
+    std::vector<double> stat(P.nstatic);
+    int off = 0;
+    for (int i = 0; i < n_ops; i++)
+      if (ops[i].kind == SV_UNITARY) {
+        int d = 1 << ops[i].n_targets;
+        std::memcpy(&stat[off], ops[i].matrix, sizeof(double) * 2 * d * d);
+        off += 2 * d * d;
+      }
+    HIPCHK(hipMemcpyAsync(P.d_statics, stat.data(), (size_t)P.nstatic * 8, hipMemcpyHostToDevice, st->stream));
+    // the host vector dies at return: make the copy complete first
+    HIPCHK(hipStreamSynchronize(st->stream));
+  }
+  hipError_t e = svk_launch_coefs(P.d_coefdesc, (int)P.coefs.size(), P.d_params, P.d_statics, P.d_coef, st->stream);
+  if (e != hipSuccess) return fail(SV_EDEVICE, "coefficient kernel: %s", hipGetErrorString(e));
+  return SV_OK;
+}
+
+static sv_status run_steps(sv_state *st, Plan &P, void *re, void *im, void *re2, void *im2,
+                           double *gpart, int grid_override) {
+  DevInfo di;
+  sv_status s = device_info(di);
+  if (s) return s;
+  const bool dbl = st->dtype == SV_C128;
+  int occ = svk_sweep_occupancy(dbl, P.M, P.R, P.NS);
+  for (Step &stp : P.steps) {
+    if (stp.kind == 0) {
+      SweepArgs a = stp.sa;
+      a.re = re; a.im = im; a.re2 = re2; a.im2 = im2;
+      a.stages = P.d_stages;
+      a.ops = P.d_ops;
+      a.coef = P.d_coef;
+      a.gpart = gpart;
+      int64_t g = (int64_t)di.cus * occ;
+      if (grid_override > 0) g = grid_override;
+      if (g > a.ntiles) g = a.ntiles;
+      hipError_t e = svk_launch_sweep(dbl, P.M, P.R, P.NS, a, (int)g, st->stream);
+      if (e != hipSuccess) return fail(SV_EDEVICE, "sweep kernel: %s", hipGetErrorString(e));
+    } else {
+      GateArgsHost a = stp.ga;
+      a.re = re; a.im = im;
+      a.coef = P.d_coef + (stp.gate_coef < 0 ? 0 : stp.gate_coef);
+      hipError_t e = svk_launch_gate(dbl, a, st->stream);
+      if (e != hipSuccess) return fail(SV_EDEVICE, "gate kernel: %s", hipGetErrorString(e));
+    }
+  }
+  return SV_OK;
+}
+
+extern "C" sv_status sv_apply_layer(sv_state *st, const sv_op *ops, int32_t n_ops,
+                                    const double *params, int32_t n_params, int32_t fuse_width) {
+  if (!st) return fail(SV_EINVAL, "null handle");
+  if (!(fuse_width == 0 || fuse_width == SV_FUSE_AUTO || (fuse_width >= 2 && fuse_width <= 5)))
+    return fail(SV_EINVAL, "fuse_width %d: must be 0, 2..5 or SV_FUSE_AUTO", fuse_width);
+  sv_status s = validate_circuit(st->n, ops, n_ops, params, n_params);
+  if (s) return s;
+  if (n_ops == 0) return SV_OK;
+  Tiling tl = st->tiling;
+  if (fuse_width >= 2) {
+    // fused blocks need a register group as wide as the block
+    if (fuse_width > tl.R) {
+      if (svk_has_sweep(st->dtype == SV_C128, tl.M, 5, 1)) tl.R = 5;
+      else if (svk_has_sweep(st->dtype == SV_C128, 13, 5, 1)) { tl.M = 13; tl.R = 5; }
+    }
+  }
+  Plan *P = nullptr;
+  s = get_plan(st, fuse_width, tl, ops, n_ops, n_params, false, &P);
+  if (s) return s;
+  s = upload_call_data(st, *P, ops, n_ops, params, n_params);
+  if (s) return s;
+  return run_steps(st, *P, st->re, st->im, nullptr, nullptr, nullptr, 0);
+}
+
+// ------------------------------------------------------- Pauli reductions
+
+struct PauliPlan {
+  std::vector<PauliTermDev> terms;    // reordered by pass
+  struct Pass { int m, c, nh; int hb[SVI_MMAX]; int t0, t1; };
+  std::vector<Pass> passes;
+};
+
+static void plan_pauli(int n, const sv_pauli_term *terms, int nt, PauliPlan &pp) {
+  const int M = std::min(13, n);
+  const int c = std::min(3, n);
+  const uint64_t low = (1ull << c) - 1;
+  struct Open { uint64_t U; std::vector<int> ids; };
+  std::vector<Open> open;
+  for (int j = 0; j < nt; j++) {
+    uint64_t xh = terms[j].x_mask & ~low;
+    bool placed = false;
+    for (Open &o : open) {
+      if ((int)o.ids.size() >= SVI_PTERMS_MAX) continue;
+      if (popc(o.U | xh) <= M - c) { o.U |= xh; o.ids.push_back(j); placed = true; break; }
+    }
+    if (!placed) open.push_back(Open{xh, {j}});
+  }
+  for (Open &o : open) {
+    PauliPlan::Pass ps{};
+    uint64_t T = low | o.U;
+    for (int q = c; q < n && popc(T) < M; q++) T |= 1ull << q;
+    ps.c = c;
+    ps.nh = 0;
+    for (int q = c; q < n; q++)
+      if (T & (1ull << q)) ps.hb[ps.nh++] = q;
+    ps.m = c + ps.nh;
+    ps.t0 = (int)pp.terms.size();
+    for (int j : o.ids) {
+      PauliTermDev d{};
+      d.x = terms[j].x_mask;
+      d.z = terms[j].z_mask;
+      d.c = terms[j].coeff;
+      d.term = j;
+      pp.terms.push_back(d);
+    }
+    ps.t1 = (int)pp.terms.size();
+    pp.passes.push_back(ps);
+  }
+}
+
+// Runs the Pauli passes; term values land in device array `d_terms` (original order).
+static sv_status run_pauli(sv_state *st, const sv_pauli_term *terms, int nt, void *re, void *im,
+                           void *lre, void *lim, double **d_terms_out) {
+  PauliPlan pp;
+  plan_pauli(st->n, terms, nt, pp);
+  DevInfo di;
+  sv_status s = device_info(di);
+  if (s) return s;
+  const bool dbl = st->dtype == SV_C128;
+  int occ = svk_pauli_occupancy(dbl);
+  int64_t grid_max = (int64_t)di.cus * occ;
+  // scratch: terms | partials | reduced (by pass order) | reduced (original order)
+  size_t nterm = pp.terms.size();
+  size_t need = 256 + nterm * sizeof(PauliTermDev) + nterm * grid_max * 8 + 2 * (nterm + 1) * 8 + 1024;
+  s = ensure_scratch(st, need);
+  if (s) return s;
+  char *b = (char *)st->scratch;
+  PauliTermDev *d_terms = (PauliTermDev *)b;
+  double *d_part = (double *)(b + ((nterm * sizeof(PauliTermDev) + 255) & ~(size_t)255));
+  double *d_red = d_part + nterm * grid_max;
+  double *d_vals = d_red + nterm + 1;
+  if (nterm)
+    HIPCHK(hipMemcpyAsync(d_terms, pp.terms.data(), nterm * sizeof(PauliTermDev), hipMemcpyHostToDevice, st->stream));
+  if (lre && nterm == 0) {
+    size_t bytes = ((size_t)1 << st->n) * elem_size(st->dtype);
+    HIPCHK(hipMemsetAsync(lre, 0, bytes, st->stream));
+    HIPCHK(hipMemsetAsync(lim, 0, bytes, st->stream));
+  }
+  for (size_t p = 0; p < pp.passes.size(); p++) {
+    const PauliPlan::Pass &ps = pp.passes[p];
+    PauliPassArgs a{};
+    a.re = re; a.im = im; a.lre = lre; a.lim = lim;
+    a.terms = d_terms;
+    a.n = st->n; a.m = ps.m; a.c = ps.c; a.nh = ps.nh;
+    for (int k = 0; k < SVI_MMAX; k++) a.hb[k] = k < ps.nh ? ps.hb[k] : 0;
+    a.t_begin = ps.t0; a.t_end = ps.t1;
+    a.accumulate = p > 0;
+    a.ntiles = (int64_t)1 << (st->n - ps.m);
+    int64_t g = std::min<int64_t>(grid_max, a.ntiles);
+    a.part = d_part + (size_t)ps.t0 * g;
+    hipError_t e = svk_launch_pauli(dbl, 13, a, (int)g, st->stream);
+    if (e != hipSuccess) return fail(SV_EDEVICE, "pauli kernel: %s", hipGetErrorString(e));
+    e = svk_launch_reduce_rows(a.part, ps.t1 - ps.t0, (int)g, d_red + ps.t0, st->stream);
+    if (e != hipSuccess) return fail(SV_EDEVICE, "reduce kernel: %s", hipGetErrorString(e));
+  }
+  // d_red is in pass order; return it with the permutation on the host side
+  *d_terms_out = d_red;
+  (void)d_vals;
+  return SV_OK;
+}
+
+static void pauli_order(int n, const sv_pauli_term *terms, int nt, std::vector<int> &order) {
+  PauliPlan pp;
+  plan_pauli(n, terms, nt, pp);
+  order.clear();
+  for (auto &t : pp.terms) order.push_back(t.term);
+}
+
+static sv_status validate_terms(int n, const sv_pauli_term *terms, int nt) {
+  if (nt < 0) return fail(SV_EINVAL, "negative n_terms");
+  if (nt > 0 && !terms) return fail(SV_EINVAL, "null terms");
+  for (int j = 0; j < nt; j++) {
+    if (n < 64 && ((terms[j].x_mask | terms[j].z_mask) >> n))
+      return fail(SV_EINVAL, "term %d: mask beyond %d qubits", j, n);
+    if (!std::isfinite(terms[j].coeff)) return fail(SV_EINVAL, "term %d: non-finite coefficient", j);
+  }
+  return SV_OK;
+}
+
+extern "C" sv_status sv_expect_pauli(sv_state *st, const sv_pauli_term *terms, int32_t n_terms,
+                                     double *out_terms, double *out_sum) {
+  if (!st) return fail(SV_EINVAL, "null handle");
+  sv_status s = validate_terms(st->n, terms, n_terms);
+  if (s) return s;
+  if (n_terms == 0) {
+    if (out_sum) *out_sum = 0.0;
+    return SV_OK;
+  }
+  double *d_red = nullptr;
+  s = run_pauli(st, terms, n_terms, st->re, st->im, nullptr, nullptr, &d_red);
+  if (s) return s;
+  std::vector<double> red(n_terms);
+  HIPCHK(hipMemcpyAsync(red.data(), d_red, n_terms * 8, hipMemcpyDeviceToHost, st->stream));
+  HIPCHK(hipStreamSynchronize(st->stream));
+  std::vector<int> order;
+  pauli_order(st->n, terms, n_terms, order);
+  std::vector<double> vals(n_terms);
+  for (int k = 0; k < n_terms; k++) vals[order[k]] = red[k];
+  if (out_terms)
+    for (int j = 0; j < n_terms; j++) out_terms[j] = vals[j];
+  if (out_sum) {
+    double e = 0.0;
+    for (int j = 0; j < n_terms; j++) e += terms[j].coeff * vals[j];
+    *out_sum = e;
+  }
+  return SV_OK;
+}
+
+// ----------------------------------------------------------------- adjoint
+
+static sv_status adjoint_enqueue(sv_state *st, const sv_op *ops, int n_ops, const double *params,
+                                 int n_params, const sv_pauli_term *terms, int n_terms,
+                                 double **d_terms, double **d_grad, Plan **bwd_out) {
+  if (!st) return fail(SV_EINVAL, "null handle");
+  sv_status s = validate_circuit(st->n, ops, n_ops, params, n_params);
+  if (s) return s;
+  s = validate_terms(st->n, terms, n_terms);
+  if (s) return s;
+  if (st->ws_bytes < sv_workspace_bytes(st->n, st->dtype, SV_WS_ADJOINT))
+    return fail(SV_ENOMEM, "workspace too small for the adjoint (%zu < %zu)", st->ws_bytes,
+                sv_workspace_bytes(st->n, st->dtype, SV_WS_ADJOINT));
+  Tiling tf = st->tiling;
+  Tiling tb = default_tiling(st->n, st->dtype, 2);
+  Plan *F = nullptr, *B = nullptr;
+  if (n_ops > 0) {
+    s = get_plan(st, SV_FUSE_AUTO, tf, ops, n_ops, n_params, false, &F);
+    if (s) return s;
+  }
+  s = get_plan(st, SV_FUSE_AUTO, tb, ops, n_ops, n_params, true, &B);
+  if (s) return s;
+  double *S, *Pp;
+  void *lre, *lim, *wre, *wim;
+  ws_layout(st, &S, &Pp, &lre, &lim, &wre, &wim);
+  // forward on the caller's planes
+  if (F) {
+    s = upload_call_data(st, *F, ops, n_ops, params, n_params);
+    if (s) return s;
+    s = run_steps(st, *F, st->re, st->im, nullptr, nullptr, nullptr, 0);
+    if (s) return s;
+  }
+  // lambda = H psi and <P_j> on the final state
+  double *d_red = nullptr;
+  s = run_pauli(st, terms, n_terms, st->re, st->im, lre, lim, &d_red);
+  if (s) return s;
+  // working copy of psi for the backward sweep
+  size_t plane = ((size_t)1 << st->n) * elem_size(st->dtype);
+  HIPCHK(hipMemcpyAsync(wre, st->re, plane, hipMemcpyDeviceToDevice, st->stream));
+  HIPCHK(hipMemcpyAsync(wim, st->im, plane, hipMemcpyDeviceToDevice, st->stream));
+  // backward sweeps
+  DevInfo di;
+  s = device_info(di);
+  if (s) return s;
+  int occ = svk_sweep_occupancy(st->dtype == SV_C128, B->M, B->R, 2);
+  int64_t grid = (int64_t)di.cus * occ;
+  int64_t maxtiles = (int64_t)1 << (st->n - std::min(B->M, st->n));
+  if (grid > maxtiles) grid = maxtiles;
+  // scratch after the Pauli area: partials [slots][grid] | slot sums | grad
+  size_t pauli_bytes = 256 + (size_t)n_terms * sizeof(PauliTermDev) + (size_t)n_terms * di.cus *
+                       svk_pauli_occupancy(st->dtype == SV_C128) * 8 + 2 * ((size_t)n_terms + 1) * 8 + 1024;
+  pauli_bytes = (pauli_bytes + 255) & ~(size_t)255;
+  size_t need = pauli_bytes + (size_t)B->n_gslots * grid * 8 + (size_t)B->n_gslots * 8 +
+                ((size_t)n_params + 1) * 8 + 1024;
+  if (need > st->scratch_bytes) {
+    // growing would free the Pauli results: re-run them after growing
+    s = ensure_scratch(st, need);
+    if (s) return s;
+    s = run_pauli(st, terms, n_terms, st->re, st->im, lre, lim, &d_red);
+    if (s) return s;
+  }
+  char *b = (char *)st->scratch + pauli_bytes;
+  double *gpart = (double *)b;
+  double *slot_sum = gpart + (size_t)B->n_gslots * grid;
+  double *grad = slot_sum + B->n_gslots;
+  s = upload_call_data(st, *B, ops, n_ops, params, n_params);
+  if (s) return s;
+  s = run_steps(st, *B, wre, wim, lre, lim, gpart, (int)grid);
+  if (s) return s;
+  hipError_t e = svk_launch_reduce_rows(gpart, B->n_gslots, (int)grid, slot_sum, st->stream);
+  if (e != hipSuccess) return fail(SV_EDEVICE, "reduce: %s", hipGetErrorString(e));
+  e = svk_launch_gather_grad(slot_sum, B->d_rowptr, B->d_gslots, n_params, grad, st->stream);
+  if (e != hipSuccess) return fail(SV_EDEVICE, "gather: %s", hipGetErrorString(e));
+  *d_terms = d_red;
+  *d_grad = grad;
+  *bwd_out = B;
+  return SV_OK;
+}
+
+extern "C" sv_status sv_adjoint_grad(sv_state *st, const sv_op *ops, int32_t n_ops,
+                                     const double *params, int32_t n_params,
+                                     const sv_pauli_term *terms, int32_t n_terms, double *energy,
+                                     double *grad, int32_t *n_evals) {
+  double *d_terms = nullptr, *d_grad = nullptr;
+  Plan *B = nullptr;
+  sv_status s = adjoint_enqueue(st, ops, n_ops, params, n_params, terms, n_terms, &d_terms, &d_grad, &B);
+  if (s) return s;
+  std::vector<double> red(std::max(n_terms, 1));
+  if (n_terms)
+    HIPCHK(hipMemcpyAsync(red.data(), d_terms, n_terms * 8, hipMemcpyDeviceToHost, st->stream));
+  if (grad && n_params)
+    HIPCHK(hipMemcpyAsync(grad, d_grad, n_params * 8, hipMemcpyDeviceToHost, st->stream));
+  HIPCHK(hipStreamSynchronize(st->stream));
+  std::vector<int> order;
+  pauli_order(st->n, terms, n_terms, order);
+  std::vector<double> vals(std::max(n_terms, 1));
+  for (int k = 0; k < n_terms; k++) vals[order[k]] = red[k];
+  double e = 0.0;
+  for (int j = 0; j < n_terms; j++) e += terms[j].coeff * vals[j];
+  if (energy) *energy = e;
+  if (n_evals) *n_evals = 1;
+  return SV_OK;
+}
+
+extern "C" sv_status sv_adjoint_grad_device(sv_state *st, const sv_op *ops, int32_t n_ops,
+                                            const double *params, int32_t n_params,
+                                            const sv_pauli_term *terms, int32_t n_terms,
+                                            double *d_out) {
+  if (!d_out) return fail(SV_EINVAL, "null output");
+  double *d_terms = nullptr, *d_grad = nullptr;
+  Plan *B = nullptr;
+  sv_status s = adjoint_enqueue(st, ops, n_ops, params, n_params, terms, n_terms, &d_terms, &d_grad, &B);
+  if (s) return s;
+  // energy in original term order: coefficients permuted to pass order
+  std::vector<int> order;
+  pauli_order(st->n, terms, n_terms, order);
+  if (n_terms) {
+    std::vector<double> cperm(n_terms);
+    for (int k = 0; k < n_terms; k++) cperm[k] = terms[order[k]].coeff;
+    // place the permuted coefficients right after the gradient
+    double *d_c = d_grad + n_params;
+    HIPCHK(hipMemcpyAsync(d_c, cperm.data(), n_terms * 8, hipMemcpyHostToDevice, st->stream));
+    HIPCHK(hipStreamSynchronize(st->stream));
+    hipError_t e = svk_launch_energy(d_terms, d_c, n_terms, d_out, st->stream);
+    if (e != hipSuccess) return fail(SV_EDEVICE, "energy: %s", hipGetErrorString(e));
+  } else {
+    HIPCHK(hipMemsetAsync(d_out, 0, 8, st->stream));
+  }
+  if (n_params)
+    HIPCHK(hipMemcpyAsync(d_out + 1, d_grad, n_params * 8, hipMemcpyDeviceToDevice, st->stream));
+  return SV_OK;
+}
+
+// ---------------------------------------------------------------- sampling
+
+extern "C" sv_status sv_sample(sv_state *st, uint64_t seed, int64_t shots, const int32_t *qubits,
+                               int32_t n_measured, uint64_t *out) {
+  if (!st) return fail(SV_EINVAL, "null handle");
+  if (shots < 0) return fail(SV_EINVAL, "negative shots");
+  if (n_measured < 0 || n_measured > 64) return fail(SV_EINVAL, "n_measured %d outside 0..64", n_measured);
+  if (n_measured > 0 && !qubits) return fail(SV_EINVAL, "null qubits");
+  for (int i = 0; i < n_measured; i++)
+    if (qubits[i] < 0 || qubits[i] >= st->n) return fail(SV_EINVAL, "measured qubit %d out of range", qubits[i]);
+  if (shots > 0 && !out) return fail(SV_EINVAL, "null output");
+  if (shots == 0) return SV_OK;
+  double *S, *P;
+  void *a, *b, *c, *d;
+  ws_layout(st, &S, &P, &a, &b, &c, &d);
+  sv_status s = ensure_scratch(st, (size_t)shots * 8 + 1024);
+  if (s) return s;
+  uint64_t *d_out = (uint64_t *)st->scratch;
+  hipError_t e = svk_launch_sampling(st->dtype == SV_C128, st->re, st->im, st->n, S, P, seed, shots,
+                                     qubits, n_measured, d_out, st->stream);
+  if (e != hipSuccess) return fail(SV_EDEVICE, "sampling: %s", hipGetErrorString(e));
+  HIPCHK(hipMemcpyAsync(out, d_out, (size_t)shots * 8, hipMemcpyDeviceToHost, st->stream));
+  HIPCHK(hipStreamSynchronize(st->stream));
+  return SV_OK;
+}
+
+// ------------------------------------------------------------ host copies
+
+extern "C" sv_status sv_copy_to_host(const sv_state *st, void *re, void *im, uint64_t offset,
+                                     uint64_t count) {
+  if (!st) return fail(SV_EINVAL, "null handle");
+  uint64_t N = 1ull << st->n;
+  if (offset > N || count > N - offset) return fail(SV_EINVAL, "range [%llu,+%llu) beyond 2^n",
+                                                   (unsigned long long)offset, (unsigned long long)count);
+  size_t es = elem_size(st->dtype);
+  if (re) HIPCHK(hipMemcpyAsync(re, (char *)st->re + offset * es, count * es, hipMemcpyDeviceToHost, st->stream));
+  if (im) HIPCHK(hipMemcpyAsync(im, (char *)st->im + offset * es, count * es, hipMemcpyDeviceToHost, st->stream));
+  HIPCHK(hipStreamSynchronize(st->stream));
+  return SV_OK;
+}
+
+extern "C" sv_status sv_copy_from_host(sv_state *st, const void *re, const void *im, uint64_t offset,
+                                       uint64_t count) {
+  if (!st) return fail(SV_EINVAL, "null handle");
+  uint64_t N = 1ull << st->n;
+  if (offset > N || count > N - offset) return fail(SV_EINVAL, "range beyond 2^n");
+  if (!re || !im) return fail(SV_EINVAL, "null host plane");
+  size_t es = elem_size(st->dtype);
+  HIPCHK(hipMemcpyAsync((char *)st->re + offset * es, re, count * es, hipMemcpyHostToDevice, st->stream));
+  HIPCHK(hipMemcpyAsync((char *)st->im + offset * es, im, count * es, hipMemcpyHostToDevice, st->stream));
+  HIPCHK(hipStreamSynchronize(st->stream));
+  return SV_OK;
+}
+
+// ------------------------------------------------------- host-only helpers
+
+static sv_status lower_all(int n, const sv_op *ops, int n_ops, std::vector<GateRec> &recs) {
+  int np = 0;
+  for (int i = 0; i < n_ops; i++)
+    for (int k = 0; k < nparams_of(ops[i].kind); k++) np = std::max(np, ops[i].param_index[k] + 1);
+  sv_status s = validate_circuit(n, ops, n_ops, nullptr, 0);
+  if (s && s != SV_EUNBOUND) return s;
+  for (int i = 0; i < n_ops; i++) {
+    sv_status v = validate_op(ops[i], i, n, np);
+    if (v) return v;
+  }
+  int um = 0;
+  for (int i = 0; i < n_ops; i++) {
+    GateRec g = lower_one(ops[i], ops[i].kind == SV_UNITARY ? um : -1);
+    if (ops[i].kind == SV_UNITARY) um++;
+    recs.push_back(g);
+  }
+  return SV_OK;
+}
+
+extern "C" sv_status sv_fuse_blocks(const sv_op *ops, int32_t n_ops, int32_t width, int32_t *block_of,
+                                    int32_t *n_blocks) {
+  if (width < 2 || width > 64) return fail(SV_EINVAL, "width %d", width);
+  if (n_ops < 0 || (n_ops && (!ops || !block_of)) || !n_blocks) return fail(SV_EINVAL, "bad arguments");
+  std::vector<GateRec> recs;
+  sv_status s = lower_all(64, ops, n_ops, recs);
+  if (s) return s;
+  std::vector<int> bo;
+  *n_blocks = fuse_greedy(recs, width, bo);
+  for (int i = 0; i < n_ops; i++) block_of[i] = bo[i];
+  return SV_OK;
+}
+
+extern "C" sv_status sv_plan_stats(int32_t n, const sv_op *ops, int32_t n_ops, int32_t fuse_width,
+                                   int32_t tile_bits, int32_t low_bits, int32_t *n_sweeps,
+                                   int32_t *n_blocks) {
+  if (n < 1 || n > 34) return fail(SV_EINVAL, "n %d", n);
+  if (!(fuse_width == 0 || fuse_width == SV_FUSE_AUTO || (fuse_width >= 2 && fuse_width <= 5)))
+    return fail(SV_EINVAL, "fuse_width %d", fuse_width);
+  std::vector<GateRec> recs;
+  sv_status s = lower_all(n, ops, n_ops, recs);
+  if (s) return s;
+  Tiling tl = default_tiling(n, SV_C128, 1);
+  if (tile_bits) tl.M = tile_bits;
+  if (low_bits) tl.c = low_bits;
+  if (fuse_width > tl.R) tl.R = 5;
+  std::vector<GateRec> live;
+  for (auto &g : recs)
+    if (g.mo != MO_NOP) live.push_back(g);
+  std::vector<SweepP> sweeps;
+  int blocks = 0;
+  if (fuse_width == 0) {
+    if (n_sweeps) *n_sweeps = (int)live.size();
+    if (n_blocks) *n_blocks = (int)live.size();
+    return SV_OK;
+  } else if (fuse_width < 0) {
+    plan_auto(live, n, tl, sweeps, 1e300);
+  } else {
+    plan_fused(live, n, tl, fuse_width, sweeps);
+  }
+  for (auto &sw : sweeps) blocks += (int)sw.stages.size();
+  if (n_sweeps) *n_sweeps = (int)sweeps.size();
+  if (n_blocks) *n_blocks = blocks;
+  return SV_OK;
+}

@@ -1,0 +1,41 @@
+// Host-side entry points of the kernels in sv_kernels.hip (internal).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "sv_internal.h"
+
+struct GateArgsHost {
+  void *re, *im;
+  const double *coef;
+  int32_t type;
+  int32_t t0, t1;
+  int32_t npos;
+  int32_t pos[SVI_RMAX + 5];
+  uint64_t cval;
+  uint64_t pmask;
+  int64_t nitems;
+};
+
+hipError_t svk_launch_sweep(int dbl, int M, int R, int NS, const SweepArgs &a, int grid,
+                            hipStream_t s);
+int svk_sweep_occupancy(int dbl, int M, int R, int NS);
+int svk_has_sweep(int dbl, int M, int R, int NS);
+hipError_t svk_launch_gate(int dbl, const GateArgsHost &a, hipStream_t s);
+hipError_t svk_launch_init_zero(int dbl, void *re, void *im, int64_t n, hipStream_t s);
+hipError_t svk_launch_coefs(const CoefDesc *d, int nd, const double *params,
+                            const double *statics, double *coef, hipStream_t s);
+hipError_t svk_launch_pauli(int dbl, int M, const PauliPassArgs &a, int grid, hipStream_t s);
+int svk_pauli_occupancy(int dbl);
+hipError_t svk_launch_reduce_rows(const double *part, int nslots, int np, double *out,
+                                  hipStream_t s);
+hipError_t svk_launch_gather_grad(const double *slot_sum, const int32_t *row_ptr,
+                                  const int32_t *slots, int np, double *grad, hipStream_t s);
+hipError_t svk_launch_energy(const double *terms, const double *coef, int nt, double *out,
+                             hipStream_t s);
+hipError_t svk_launch_sampling(int dbl, const void *re, const void *im, int n, double *S,
+                               double *P, uint64_t seed, int64_t shots, const int32_t *qubits,
+                               int nq, uint64_t *out, hipStream_t s);
+
+#define SVI_GSLOTS_MAX 256
+#define SVI_PTERMS_MAX 64

@@ -230,9 +230,11 @@ def serving_trace(rate: float, count: int = 2000, seed: int = 0, n_lo: int = 10,
 
 
 def random_circuit(n: int, depth: int, seed: int = 0, kinds: Optional[Sequence[str]] = None,
-                   max_controls: int = 2, allow_unitary: bool = True) -> Circuit:
+                   max_controls: int = 2, allow_unitary: bool = True,
+                   max_qubits: int = 5) -> Circuit:
     """Random circuit over the whole vocabulary, with random target/control
-    orderings and random control states; every op gets fresh parameters."""
+    orderings and random control states; every op gets fresh parameters.
+    Each op touches at most `max_qubits` qubits (targets + controls)."""
     rng = np.random.default_rng(seed)
     if kinds is None:
         kinds = [k for k in GATES if k != "unitary" or allow_unitary]
@@ -247,7 +249,7 @@ def random_circuit(n: int, depth: int, seed: int = 0, kinds: Optional[Sequence[s
             continue
         perm = rng.permutation(n)
         targets = tuple(int(q) for q in perm[:nt])
-        nc = int(rng.integers(0, min(max_controls, n - nt) + 1))
+        nc = int(rng.integers(0, max(0, min(max_controls, n - nt, max_qubits - nt)) + 1))
         controls = tuple(int(q) for q in perm[nt:nt + nc])
         cstate = int(rng.integers(0, 1 << nc)) if nc else None
         pidx = []

@@ -1,0 +1,293 @@
+"""ctypes binding of libsv.so (include/sv.h).  Argument marshalling only:
+every step of the path runs in the HIP library; torch supplies device memory
+and the stream.  Importing this module loads the library and raises if it is
+missing -- there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional, Sequence, Tuple
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libsv.so")
+
+SV_C128, SV_C64 = 0, 1
+SV_FUSE_AUTO = -1
+SV_WS_ADJOINT = 1
+STATUS = {0: "SV_OK", -1: "SV_EINVAL", -2: "SV_EDTYPE", -3: "SV_EUNBOUND", -4: "SV_ENOMEM",
+          -5: "SV_EUNSUPPORTED", -6: "SV_EDEVICE"}
+
+KINDS = ["i", "x", "y", "z", "h", "s", "sdg", "t", "tdg", "sx", "rx", "ry", "rz", "p", "u2",
+         "u3", "swap", "rxx", "ryy", "rzz", "givens", "dexc", "unitary"]
+KIND_ID = {k: i for i, k in enumerate(KINDS)}
+
+
+class SvError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class SvOp(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("n_targets", C.c_int32), ("targets", C.c_int32 * 5),
+                ("n_controls", C.c_int32), ("controls", C.c_int32 * 5),
+                ("control_states", C.c_uint32), ("param_index", C.c_int32 * 3),
+                ("matrix", C.POINTER(C.c_double))]
+
+
+class SvPauliTerm(C.Structure):
+    _fields_ = [("x_mask", C.c_uint64), ("z_mask", C.c_uint64), ("coeff", C.c_double)]
+
+
+class SvCircuitDesc(C.Structure):
+    _fields_ = [("n_qubits", C.c_int32), ("n_ops", C.c_int32), ("ops", C.POINTER(SvOp)),
+                ("n_params", C.c_int32), ("n_terms", C.c_int32),
+                ("terms", C.POINTER(SvPauliTerm))]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"HIP library missing: {LIB_PATH}; run `python -m paper_2608_09733_amd.build`")
+    L = C.CDLL(LIB_PATH)
+    vp, dp, u64p = C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_uint64)
+    opp, tp = C.POINTER(SvOp), C.POINTER(SvPauliTerm)
+    i32, i64, u64 = C.c_int32, C.c_int64, C.c_uint64
+    sig = {
+        "sv_workspace_bytes": (C.c_size_t, [i32, C.c_int, C.c_uint32]),
+        "sv_alloc": (C.c_int, [i32, C.c_int, vp, vp, vp, C.c_size_t, vp, C.POINTER(vp)]),
+        "sv_free": (C.c_int, [vp]),
+        "sv_set_stream": (C.c_int, [vp, vp]),
+        "sv_reset": (C.c_int, [vp]),
+        "sv_apply_layer": (C.c_int, [vp, opp, i32, dp, i32, i32]),
+        "sv_expect_pauli": (C.c_int, [vp, tp, i32, dp, dp]),
+        "sv_adjoint_grad": (C.c_int, [vp, opp, i32, dp, i32, tp, i32, dp, dp, C.POINTER(i32)]),
+        "sv_adjoint_grad_device": (C.c_int, [vp, opp, i32, dp, i32, tp, i32, vp]),
+        "sv_sample": (C.c_int, [vp, u64, i64, C.POINTER(i32), i32, u64p]),
+        "sv_copy_to_host": (C.c_int, [vp, vp, vp, u64, u64]),
+        "sv_copy_from_host": (C.c_int, [vp, vp, vp, u64, u64]),
+        "sv_last_error": (C.c_char_p, []),
+        "sv_plan_stats": (C.c_int, [i32, opp, i32, i32, i32, i32, C.POINTER(i32), C.POINTER(i32)]),
+        "sv_set_tiling": (C.c_int, [vp, i32, i32]),
+        "sv_fuse_blocks": (C.c_int, [opp, i32, i32, C.POINTER(i32), C.POINTER(i32)]),
+        "sv_version": (C.c_char_p, []),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(L, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = L
+    return L
+
+
+def _check(st: int):
+    if st != 0:
+        raise SvError(st, lib().sv_last_error().decode())
+
+
+class OpArray:
+    """sv_op records for a gate list (objects with .kind .targets .controls
+    .control_states .params .matrix); keeps user matrices alive."""
+
+    def __init__(self, ops: Sequence):
+        self.n = len(ops)
+        self.arr = (SvOp * max(1, self.n))()
+        self.keep = []
+        for i, op in enumerate(ops):
+            r = self.arr[i]
+            r.kind = KIND_ID[op.kind]
+            r.n_targets = len(op.targets)
+            for j, q in enumerate(op.targets):
+                r.targets[j] = int(q)
+            r.n_controls = len(op.controls)
+            for j, q in enumerate(op.controls):
+                r.controls[j] = int(q)
+            r.control_states = int(op.control_states)
+            for j in range(3):
+                r.param_index[j] = int(op.params[j]) if j < len(op.params) else -1
+            if op.kind == "unitary":
+                m = np.ascontiguousarray(np.asarray(op.matrix, dtype=np.complex128))
+                flat = np.ascontiguousarray(m.reshape(-1).view(np.float64))
+                self.keep.append(flat)
+                r.matrix = flat.ctypes.data_as(C.POINTER(C.c_double))
+
+    def ptr(self):
+        return C.cast(self.arr, C.POINTER(SvOp))
+
+
+class TermArray:
+    def __init__(self, ham):
+        self.n = len(ham)
+        self.arr = (SvPauliTerm * max(1, self.n))()
+        for j in range(self.n):
+            self.arr[j].x_mask = int(ham.x[j])
+            self.arr[j].z_mask = int(ham.z[j])
+            self.arr[j].coeff = float(ham.c[j])
+
+    def ptr(self):
+        return C.cast(self.arr, C.POINTER(SvPauliTerm))
+
+
+def _params_ptr(params) -> Tuple[np.ndarray, int]:
+    p = np.ascontiguousarray(np.asarray(params, dtype=np.float64))
+    n = int(p.size)
+    if n == 0:
+        p = np.zeros(1)
+    return p, n
+
+
+def _stream_ptr(stream) -> Optional[int]:
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return int(stream.cuda_stream) or None
+
+
+class State:
+    """A 2^n-amplitude state held as two torch device planes (FP64 or FP32)."""
+
+    def __init__(self, n: int, dtype: str = "c128", adjoint: bool = False, device: str = "cuda",
+                 stream=None):
+        import torch
+        L = lib()
+        self.n = int(n)
+        self.dtype = dtype
+        self.code = SV_C128 if dtype == "c128" else SV_C64
+        tdt = torch.float64 if dtype == "c128" else torch.float32
+        self.np_dtype = np.float64 if dtype == "c128" else np.float32
+        N = 1 << self.n
+        self.re = torch.empty(N, dtype=tdt, device=device)
+        self.im = torch.empty(N, dtype=tdt, device=device)
+        wsb = int(L.sv_workspace_bytes(self.n, self.code, SV_WS_ADJOINT if adjoint else 0))
+        if wsb == 0:
+            raise SvError(-1, f"bad state size n={n} dtype={dtype}")
+        self.ws = torch.empty(wsb + 256, dtype=torch.uint8, device=device)
+        base = self.ws.data_ptr()
+        off = (-base) % 256
+        self.stream = stream
+        h = C.c_void_p()
+        _check(L.sv_alloc(self.n, self.code, C.c_void_p(self.re.data_ptr()),
+                          C.c_void_p(self.im.data_ptr()), C.c_void_p(base + off), wsb,
+                          C.c_void_p(_stream_ptr(stream)), C.byref(h)))
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().sv_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_stream(self, stream):
+        self.stream = stream
+        _check(lib().sv_set_stream(self.h, C.c_void_p(_stream_ptr(stream))))
+
+    def set_tiling(self, tile_bits: int = 0, low_bits: int = 0):
+        _check(lib().sv_set_tiling(self.h, tile_bits, low_bits))
+
+    def reset(self):
+        _check(lib().sv_reset(self.h))
+
+    def apply(self, ops, params, fuse: int = SV_FUSE_AUTO, op_array: Optional[OpArray] = None):
+        oa = op_array or OpArray(ops)
+        p, npar = _params_ptr(params)
+        _check(lib().sv_apply_layer(self.h, oa.ptr(), oa.n, p.ctypes.data_as(C.POINTER(C.c_double)),
+                                    npar, int(fuse)))
+
+    def run(self, circ, fuse: int = SV_FUSE_AUTO):
+        self.reset()
+        self.apply(circ.ops, circ.params, fuse)
+
+    def expect(self, ham) -> Tuple[np.ndarray, float]:
+        ta = TermArray(ham)
+        out = np.zeros(max(1, ta.n))
+        tot = C.c_double(0.0)
+        _check(lib().sv_expect_pauli(self.h, ta.ptr(), ta.n,
+                                     out.ctypes.data_as(C.POINTER(C.c_double)), C.byref(tot)))
+        return out[:ta.n], float(tot.value)
+
+    def adjoint_grad(self, ops, params, ham, op_array: Optional[OpArray] = None
+                     ) -> Tuple[float, np.ndarray]:
+        oa = op_array or OpArray(ops)
+        ta = TermArray(ham)
+        p, npar = _params_ptr(params)
+        g = np.zeros(max(1, npar))
+        e = C.c_double(0.0)
+        ne = C.c_int32(0)
+        _check(lib().sv_adjoint_grad(self.h, oa.ptr(), oa.n, p.ctypes.data_as(C.POINTER(C.c_double)),
+                                     npar, ta.ptr(), ta.n, C.byref(e),
+                                     g.ctypes.data_as(C.POINTER(C.c_double)), C.byref(ne)))
+        return float(e.value), g[:npar]
+
+    def adjoint_grad_device(self, ops, params, ham, out_tensor, op_array=None):
+        oa = op_array or OpArray(ops)
+        ta = TermArray(ham)
+        p, npar = _params_ptr(params)
+        _check(lib().sv_adjoint_grad_device(self.h, oa.ptr(), oa.n,
+                                            p.ctypes.data_as(C.POINTER(C.c_double)), npar,
+                                            ta.ptr(), ta.n, C.c_void_p(out_tensor.data_ptr())))
+
+    def sample(self, seed: int, shots: int, qubits: Sequence[int]) -> np.ndarray:
+        q = np.ascontiguousarray(np.asarray(list(qubits), dtype=np.int32))
+        nq = int(q.size)
+        if nq == 0:
+            q = np.zeros(1, dtype=np.int32)
+        out = np.zeros(max(1, shots), dtype=np.uint64)
+        _check(lib().sv_sample(self.h, C.c_uint64(seed), int(shots),
+                               q.ctypes.data_as(C.POINTER(C.c_int32)), nq,
+                               out.ctypes.data_as(C.POINTER(C.c_uint64))))
+        return out[:shots]
+
+    def planes(self, offset: int = 0, count: Optional[int] = None) -> Tuple[np.ndarray, np.ndarray]:
+        N = 1 << self.n
+        if count is None:
+            count = N - offset
+        re = np.empty(count, dtype=self.np_dtype)
+        im = np.empty(count, dtype=self.np_dtype)
+        _check(lib().sv_copy_to_host(self.h, C.c_void_p(re.ctypes.data), C.c_void_p(im.ctypes.data),
+                                     offset, count))
+        return re, im
+
+    def to_numpy(self) -> np.ndarray:
+        re, im = self.planes()
+        return re.astype(np.float64) + 1j * im.astype(np.float64)
+
+    def set_planes(self, re: np.ndarray, im: np.ndarray, offset: int = 0):
+        re = np.ascontiguousarray(re, dtype=self.np_dtype)
+        im = np.ascontiguousarray(im, dtype=self.np_dtype)
+        _check(lib().sv_copy_from_host(self.h, C.c_void_p(re.ctypes.data), C.c_void_p(im.ctypes.data),
+                                       offset, int(re.size)))
+
+
+def plan_stats(n: int, ops, fuse: int = SV_FUSE_AUTO, tile_bits: int = 0, low_bits: int = 0
+               ) -> Tuple[int, int]:
+    oa = OpArray(ops)
+    s = C.c_int32(0)
+    b = C.c_int32(0)
+    _check(lib().sv_plan_stats(n, oa.ptr(), oa.n, fuse, tile_bits, low_bits, C.byref(s), C.byref(b)))
+    return int(s.value), int(b.value)
+
+
+def fuse_blocks(ops, width: int) -> Tuple[int, np.ndarray]:
+    oa = OpArray(ops)
+    out = np.zeros(max(1, oa.n), dtype=np.int32)
+    nb = C.c_int32(0)
+    _check(lib().sv_fuse_blocks(oa.ptr(), oa.n, width, out.ctypes.data_as(C.POINTER(C.c_int32)),
+                                C.byref(nb)))
+    return int(nb.value), out[:oa.n]
+
+
+def version() -> str:
+    return lib().sv_version().decode()

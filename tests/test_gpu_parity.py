@@ -1,0 +1,269 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle.
+
+Bars (FP64): max-abs <= 1e-12 per amplitude, expectation values and
+gradients; complex64: <= 1e-5 per amplitude.  Every case prints its name
+before it touches the GPU.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2608_09733_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-12
+TOL32 = 1e-5
+
+
+@pytest.fixture(scope="module")
+def sv():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2608_09733_amd import sv as _sv
+    _sv.lib()
+    return _sv
+
+
+def _say(*a):
+    print("[case]", *a, flush=True)
+
+
+def _forward(sv, circ, fuse, dtype="c128", tiling=None):
+    st = sv.State(circ.n, dtype)
+    if tiling:
+        st.set_tiling(*tiling)
+    st.apply(circ.ops, circ.params, fuse=fuse)
+    out = st.to_numpy()
+    st.close()
+    return out
+
+
+FUSES = [0, 2, 3, 5, -1]
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 5, 6, 8])
+@pytest.mark.parametrize("fuse", FUSES)
+def test_random_circuits_all_kinds(sv, n, fuse):
+    for seed in range(3):
+        circ = I.random_circuit(n, 40, seed=100 * n + seed, max_controls=min(2, n - 1))
+        _say("random", n, fuse, seed)
+        psi = _forward(sv, circ, fuse)
+        ref = O.run_circuit(circ)
+        assert np.max(np.abs(psi - ref)) <= TOL, (n, fuse, seed)
+
+
+@pytest.mark.parametrize("n", [14, 16])
+@pytest.mark.parametrize("fuse", [0, 4, -1])
+def test_random_circuits_multi_tile(sv, n, fuse):
+    circ = I.random_circuit(n, 60, seed=7 + n, max_controls=2)
+    _say("random multi-tile", n, fuse)
+    psi = _forward(sv, circ, fuse)
+    ref = O.run_circuit(circ)
+    assert np.max(np.abs(psi - ref)) <= TOL
+
+
+@pytest.mark.parametrize("fuse", FUSES)
+def test_config1_layered_12q(sv, fuse):
+    circ = I.layered(12, 20, seed=0)
+    _say("cfg1", fuse)
+    st = sv.State(12, "c128")
+    st.apply(circ.ops, circ.params, fuse=fuse)
+    psi = st.to_numpy()
+    ref = O.run_circuit(circ)
+    assert np.max(np.abs(psi - ref)) <= TOL
+    ham = I.hamiltonian(12, [("Z", [q], 1.0) for q in range(12)])
+    z, _ = st.expect(ham)
+    zr, _, _ = O.expect(12, ref, ham)
+    assert np.max(np.abs(z - zr)) <= TOL
+    st.close()
+
+
+@pytest.mark.parametrize("n,L", [(15, 3), (18, 4), (20, 2)])
+@pytest.mark.parametrize("tiling", [(13, 3), (12, 3), (13, 4), (12, 4), (11, 5)])
+def test_layered_tilings(sv, n, L, tiling):
+    circ = I.layered(n, L, seed=n)
+    _say("layered tiling", n, L, tiling)
+    psi = _forward(sv, circ, -1, tiling=tiling)
+    ref = O.run_circuit(circ)
+    assert np.max(np.abs(psi - ref)) <= TOL
+
+
+def test_hea_and_qft_and_ghz(sv):
+    for circ in [I.hea(14, 3, seed=1), I.qft(12), I.ghz(17)]:
+        _say("family", circ.n, len(circ.ops))
+        for fuse in [0, -1]:
+            psi = _forward(sv, circ, fuse)
+            ref = O.run_circuit(circ)
+            assert np.max(np.abs(psi - ref)) <= TOL
+
+
+@pytest.mark.parametrize("n", [3, 10, 15])
+def test_expectation_random_terms(sv, n):
+    circ = I.random_circuit(n, 40, seed=n)
+    ham = I.random_hamiltonian(n, 30, seed=n)
+    _say("expect", n)
+    st = sv.State(n)
+    st.apply(circ.ops, circ.params, fuse=-1)
+    t, e = st.expect(ham)
+    ref = O.run_circuit(circ)
+    tr, er, _ = O.expect(n, ref, ham)
+    assert np.max(np.abs(t - tr)) <= TOL and abs(e - er) <= TOL
+    st.close()
+
+
+def test_expectation_tfim_many_passes(sv):
+    n = 20
+    circ = I.layered(n, 2, seed=3)
+    ham = I.tfim(n)
+    _say("expect tfim", n)
+    st = sv.State(n)
+    st.apply(circ.ops, circ.params, fuse=-1)
+    t, e = st.expect(ham)
+    ref = O.run_circuit(circ)
+    tr, er, _ = O.expect(n, ref, ham)
+    assert np.max(np.abs(t - tr)) <= TOL and abs(e - er) <= TOL
+    st.close()
+
+
+@pytest.mark.parametrize("n,L,seed", [(6, 3, 0), (12, 3, 1), (16, 2, 2)])
+def test_adjoint_hea_tfim(sv, n, L, seed):
+    circ = I.hea(n, L, seed=seed)
+    ham = I.tfim(n)
+    _say("adjoint hea", n, L, seed)
+    st = sv.State(n, adjoint=True)
+    e, g = st.adjoint_grad(circ.ops, circ.params, ham)
+    er, gr = O.adjoint_grad(circ, ham)
+    assert abs(e - er) <= TOL
+    assert np.max(np.abs(g - gr)) <= TOL
+    # the state holds U|0> on return
+    psi = st.to_numpy()
+    assert np.max(np.abs(psi - O.run_circuit(circ))) <= TOL
+    st.close()
+
+
+def test_adjoint_general_generators(sv):
+    n = 7
+    kinds = ["rx", "ry", "rz", "p", "rxx", "ryy", "rzz", "u3", "u2", "h", "x", "swap", "s", "t"]
+    for seed in range(4):
+        circ = I.random_circuit(n, 50, seed=300 + seed, kinds=kinds, max_controls=2)
+        # controlled U2/U3 have no single-angle generator: drop their controls
+        ops = [I.Op(o.kind, o.targets, () if o.kind in ("u2", "u3") else o.controls,
+                    None if o.kind in ("u2", "u3") else o.cstate, o.params) for o in circ.ops]
+        circ = I.Circuit(n, ops, circ.params)
+        ham = I.random_hamiltonian(n, 8, seed=seed)
+        _say("adjoint general", seed)
+        st = sv.State(n, adjoint=True)
+        e, g = st.adjoint_grad(circ.ops, circ.params, ham)
+        er, gr = O.adjoint_grad(circ, ham)
+        assert abs(e - er) <= TOL
+        assert np.max(np.abs(g - gr)) <= 1e-11
+        st.close()
+
+
+def test_adjoint_config3_zero_angle_closed_form(sv):
+    # 20-qubit HEA, 10 layers, 400 parameters, TFIM h = 0.7: at all-zero angles
+    # E = n - 1, dE/dtheta(RY) = 0.7, dE/dphi(RZ) = 0.
+    n, L = 20, 10
+    circ = I.hea(n, L)
+    p = np.zeros(circ.n_params)
+    _say("cfg3 zero angles")
+    st = sv.State(n, adjoint=True)
+    e, g = st.adjoint_grad(circ.ops, p, I.tfim(n))
+    assert abs(e - 19.0) <= TOL
+    assert np.max(np.abs(g[0::2] - 0.7)) <= TOL
+    assert np.max(np.abs(g[1::2])) <= TOL
+    st.close()
+
+
+def test_adjoint_config3_vs_oracle(sv):
+    n, L = 20, 10
+    circ = I.hea(n, L, seed=0)
+    ham = I.tfim(n)
+    _say("cfg3 random angles")
+    st = sv.State(n, adjoint=True)
+    e, g = st.adjoint_grad(circ.ops, circ.params, ham)
+    er, gr = O.adjoint_grad(circ, ham)
+    assert abs(e - er) <= TOL
+    assert np.max(np.abs(g - gr)) <= TOL
+    st.close()
+
+
+@pytest.mark.parametrize("n", [3, 9, 12, 16])
+def test_sampling_bit_exact(sv, n):
+    circ = I.layered(n, 3, seed=n)
+    _say("sample", n)
+    st = sv.State(n)
+    st.apply(circ.ops, circ.params, fuse=-1)
+    qubits = list(range(n))[::-1]
+    got = st.sample(seed=12345, shots=10000, qubits=qubits)
+    # contract A: the specification applied to the GPU's own state
+    psi_gpu = st.to_numpy()
+    a = O.sample(n, psi_gpu, 12345, 10000, qubits)
+    assert np.array_equal(got, a)
+    # contract B: the oracle's state gives the same draws on this seed
+    b = O.sample(n, O.run_circuit(circ), 12345, 10000, qubits)
+    assert np.array_equal(got, b)
+    st.close()
+
+
+@pytest.mark.parametrize("n", [4, 12, 17])
+def test_complex64_forward(sv, n):
+    circ = I.layered(n, 6, seed=n)
+    _say("c64", n)
+    psi = _forward(sv, circ, -1, dtype="c64")
+    ref = O.run_circuit(circ)
+    err = float(np.max(np.abs(psi - ref)))
+    print(f"complex64 n={n}: max|err| = {err:.3e}", flush=True)
+    assert err <= TOL32
+
+
+def test_complex64_adjoint(sv):
+    n = 10
+    circ = I.hea(n, 3, seed=4)
+    ham = I.tfim(n)
+    _say("c64 adjoint")
+    st = sv.State(n, "c64", adjoint=True)
+    e, g = st.adjoint_grad(circ.ops, circ.params, ham)
+    er, gr = O.adjoint_grad(circ, ham)
+    assert abs(e - er) <= 1e-4 and np.max(np.abs(g - gr)) <= 1e-4
+    st.close()
+
+
+def test_determinism_bitwise(sv):
+    circ = I.hea(16, 3, seed=9)
+    ham = I.tfim(16)
+    _say("determinism")
+    outs = []
+    for _ in range(2):
+        st = sv.State(16, adjoint=True)
+        e, g = st.adjoint_grad(circ.ops, circ.params, ham)
+        outs.append((e, g.copy(), st.to_numpy()))
+        st.close()
+    assert outs[0][0] == outs[1][0]
+    assert np.array_equal(outs[0][1], outs[1][1])
+    assert np.array_equal(outs[0][2], outs[1][2])
+
+
+def test_errors_rejected_before_device_work(sv):
+    st = sv.State(4)
+    before = st.to_numpy()
+    bad = [I.Op("x", (5,))]
+    with pytest.raises(sv.SvError) as ei:
+        st.apply(bad, [], fuse=-1)
+    assert ei.value.status == -1
+    with pytest.raises(sv.SvError) as ei:
+        st.apply([I.Op("ry", (0,), params=(3,))], [0.1], fuse=-1)
+    assert ei.value.status == -3
+    with pytest.raises(sv.SvError) as ei:
+        st.apply([I.Op("ry", (0,), params=(0,))], [math.nan], fuse=-1)
+    assert ei.value.status == -3
+    with pytest.raises(sv.SvError):
+        st.apply([I.Op("ry", (0,), params=(0,))], [0.1], fuse=1)
+    with pytest.raises(sv.SvError) as ei:
+        st.adjoint_grad([I.Op("ry", (0,), params=(0,))], [0.1], I.tfim(4))
+    assert ei.value.status == -4   # workspace without adjoint room
+    assert np.array_equal(before, st.to_numpy())
+    st.close()

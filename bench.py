@@ -1,0 +1,217 @@
+#!/usr/bin/env python3
+"""Benchmark of the state-vector hot path on one MI355X.
+
+Headline workload: the 30-qubit layered circuit (20 layers of RY, RZ on every
+qubit followed by the CNOT ladder 0->1 ... 28->29; 1780 gates, 1200 angles
+uniform in [0, 2pi) from seed 0) applied to |0...0> in FP64 split planes
+(16 GiB), then <Z_i> for every qubit.  One step = reset + all sweeps + one
+Pauli pass; the state is resident in HBM throughout.
+
+value = amplitude-gate updates per second = 1780 * 2^30 * steps / time.
+
+Also reported: the roofline of the dominant kernel (tile sweep) from HIP
+events around each sweep launch, the oracle's CPU rate on a bounded sample of
+the same workload, and extras (paper-style width-5 fusion plan, complex64).
+
+    python bench.py [--gpus 1] [--steps 5] [--warmup 2] [--no-cpu] [--no-extras]
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published
+METRIC = "amplitude-gate updates/s + % HBM roofline (30q); served req/s, p99 latency"
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(circ, budget_s: float):
+    """The oracle (plain C, OpenMP over amplitude groups) applying the first gates of
+    the same 30-qubit circuit until `budget_s` of CPU work; returns updates/s."""
+    import ctypes as C
+    import numpy as np
+    from oracle import oracle as O
+    n = circ.n
+    N = 1 << n
+    t_alloc = time.time()
+    buf = np.zeros(2 * N, dtype=np.float64)
+    buf[0] = 1.0
+    log(f"cpu_baseline: allocated {buf.nbytes / 2**30:.1f} GiB in {time.time() - t_alloc:.1f}s")
+    L = O.lib()
+    p = np.ascontiguousarray(circ.params, dtype=np.float64)
+    dp = p.ctypes.data_as(C.POINTER(C.c_double))
+    bp = buf.ctypes.data_as(C.POINTER(C.c_double))
+    done = 0
+    t0 = time.time()
+    while done < len(circ.ops) and time.time() - t0 < budget_s:
+        oa = O.OpArray([circ.ops[done]])
+        rc = L.orc_apply(n, bp, oa.ptr(), 1, dp)
+        if rc != 0:
+            raise RuntimeError("oracle failed")
+        done += 1
+    el = time.time() - t0
+    rate = done * float(N) / el
+    del buf
+    return {"value": rate, "unit": "updates/s", "cores": O.threads(), "kind": "oracle",
+            "sample": f"first {done} of {len(circ.ops)} gates of the same 30-qubit circuit, "
+                      f"{el:.1f} s wall, plain C FP64 gate-by-gate"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--n", type=int, default=30)
+    ap.add_argument("--layers", type=int, default=20)
+    ap.add_argument("--tile", type=int, default=0)
+    ap.add_argument("--low", type=int, default=0)
+    ap.add_argument("--group", type=int, default=0)
+    ap.add_argument("--fuse", type=int, default=-1)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--cpu-budget", type=float, default=15.0)
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py: this build runs on one GPU only (the state-vector path is measured on "
+              "one MI355X); --gpus must be 1", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_2608_09733_amd import inputs as I
+    from paper_2608_09733_amd import sv
+
+    torch.cuda.set_device(0)
+    n, L = args.n, args.layers
+    circ = I.layered(n, L, seed=0)
+    gates = len(circ.ops)
+    zs = I.hamiltonian(n, [("Z", [q], 1.0) for q in range(n)])
+    oa = sv.OpArray(circ.ops)
+    sweeps, blocks = sv.plan_stats(n, circ.ops, args.fuse, args.tile, args.low, args.group)
+    log(f"workload n={n} L={L} gates={gates} plan fuse={args.fuse}: {sweeps} sweeps, {blocks} blocks")
+
+    st = sv.State(n, "c128")
+    if args.tile or args.low or args.group:
+        st.set_tiling(args.tile, args.low, args.group)
+
+    def step():
+        st.reset()
+        st.apply(None, circ.params, fuse=args.fuse, op_array=oa)
+        return st.expect(zs)
+
+    for w in range(args.warmup):
+        step()
+        log(f"warmup {w} done")
+    torch.cuda.synchronize()
+    st.timing(True)
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.time()
+    ev0.record()
+    for k in range(args.steps):
+        z, _ = step()
+        log(f"step {k} done")
+    ev1.record()
+    torch.cuda.synchronize()
+    wall = time.time() - t0
+    gpu_ms = ev0.elapsed_time(ev1)
+    sweep_ms, launches, sweep_bytes = st.timing_read()
+    st.timing(False)
+    ms_per_step = gpu_ms / args.steps
+    value = gates * float(1 << n) * args.steps / (gpu_ms / 1e3)
+    avg_launch_ms = sweep_ms / max(1, launches)
+    bytes_per_launch = sweep_bytes / max(1, launches)
+    achieved = bytes_per_launch / (avg_launch_ms / 1e3) / 1e9
+    log(f"GPU {ms_per_step:.2f} ms/step ({wall / args.steps * 1e3:.2f} wall), {value:.4e} updates/s, "
+        f"sweep avg {avg_launch_ms:.3f} ms over {launches} launches -> {achieved:.0f} GB/s")
+
+    result = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "amplitude-gate updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"layered RY/RZ + CNOT-ladder circuit, {n} qubits, {L} layers, "
+                               f"{gates} gates, angles U[0,2pi) seed 0, from |0..0>, then <Z_i> "
+                               f"for all i", "n_qubits": n, "layers": L, "gates": gates,
+                   "plan": "tile clusters (SV_FUSE_AUTO)" if args.fuse == -1 else f"fuse={args.fuse}",
+                   "sweeps": sweeps, "register_blocks": blocks,
+                   "state_bytes": 16 * (1 << n)},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "k_sweep<double,13,5,1> (tile sweep)",
+                     "bytes_per_launch": bytes_per_launch, "avg_launch_ms": avg_launch_ms,
+                     "launches": launches},
+    }
+    extras = {}
+    # whole-path HBM efficiency: counted sweep bytes / step time
+    extras["path_hbm_gbs"] = (sweep_bytes / args.steps) / (ms_per_step / 1e3) / 1e9
+    if not args.no_extras and args.fuse == -1:
+        # paper-style fusion (greedy in-order blocks of <= 5 qubits, one sweep each)
+        s5, _ = sv.plan_stats(n, circ.ops, 5)
+        st.reset()
+        st.apply(None, circ.params, fuse=5, op_array=oa)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        st.reset()
+        e0.record()
+        st.apply(None, circ.params, fuse=5, op_array=oa)
+        e1.record()
+        torch.cuda.synchronize()
+        t5 = e0.elapsed_time(e1)
+        extras["fuse5_plan"] = {"sweeps": s5, "ms": t5,
+                                "updates_per_s": gates * float(1 << n) / (t5 / 1e3),
+                                "hbm_gbs": s5 * 32.0 * (1 << n) / (t5 / 1e3) / 1e9}
+        log(f"fuse=5: {s5} sweeps, {t5:.1f} ms")
+        # complex64 variant: same circuit in FP32 planes; error vs the FP64 result
+        ref_re, ref_im = st.planes(0, 1 << 16)
+        st.reset()
+        st.apply(None, circ.params, fuse=-1, op_array=oa)
+        ref_re, ref_im = st.planes(0, 1 << 16)
+        s32 = sv.State(n, "c64")
+        s32.apply(None, circ.params, fuse=-1, op_array=oa)
+        torch.cuda.synchronize()
+        e0.record()
+        s32.reset()
+        s32.apply(None, circ.params, fuse=-1, op_array=oa)
+        e1.record()
+        torch.cuda.synchronize()
+        t32 = e0.elapsed_time(e1)
+        r32, i32 = s32.planes(0, 1 << 16)
+        err = float(np.max(np.abs((r32.astype(np.float64) - ref_re) + 1j * (i32.astype(np.float64) - ref_im))))
+        extras["complex64"] = {"ms": t32, "updates_per_s": gates * float(1 << n) / (t32 / 1e3),
+                               "max_abs_err_vs_fp64_first_65536_amps": err}
+        log(f"complex64: {t32:.1f} ms, max err {err:.2e}")
+        s32.close()
+        del s32
+    st.close()
+    del st
+    torch.cuda.empty_cache()
+    if not args.no_cpu:
+        result["cpu_baseline"] = cpu_baseline(circ, args.cpu_budget)
+        log(f"cpu_baseline {result['cpu_baseline']['value']:.3e} updates/s on "
+            f"{result['cpu_baseline']['cores']} threads")
+    result["extras"] = extras
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -235,16 +235,27 @@ sv_status sv_batch_free(sv_batch *b);
  * Number of full-state sweeps and register blocks sv_apply_layer would use
  * for this circuit with these settings (host-only; for tests and tuning). */
 sv_status sv_plan_stats(int32_t n_qubits, const sv_op *ops, int32_t n_ops, int32_t fuse_width,
-                        int32_t tile_bits, int32_t low_bits, int32_t *n_sweeps,
-                        int32_t *n_blocks);
+                        int32_t tile_bits, int32_t low_bits, int32_t group_bits,
+                        int32_t *n_sweeps, int32_t *n_blocks);
 
-/* Tuning knobs used by SV_FUSE_AUTO for a handle (0 = default). */
-sv_status sv_set_tiling(sv_state *st, int32_t tile_bits, int32_t low_bits);
+/* Tiling used by SV_FUSE_AUTO for a handle (0 = keep the default): tile_bits =
+ * qubits per LDS tile, low_bits = contiguous low qubits in every tile (rows of
+ * 2^low_bits elements in HBM), group_bits = qubits per register block.  A
+ * combination without a compiled kernel is SV_EINVAL. */
+sv_status sv_set_tiling(sv_state *st, int32_t tile_bits, int32_t low_bits, int32_t group_bits);
 
 /* Greedy in-order fusion (paper Section 9.2 ablation planner): block id per
  * op into block_of (host array of n_ops), returns the block count in *n_blocks. */
 sv_status sv_fuse_blocks(const sv_op *ops, int32_t n_ops, int32_t width, int32_t *block_of,
                          int32_t *n_blocks);
+
+/* Kernel-time instrumentation (for benchmarks).  While enabled, every tile
+ * sweep launched for this handle is bracketed by HIP events recorded on the
+ * handle's stream.  sv_timing_read waits for the stream and returns the summed
+ * event time of those launches in milliseconds, their count, and their
+ * algorithmic HBM bytes (read + write of both planes), then clears the log. */
+sv_status sv_timing_enable(sv_state *st, int32_t on);
+sv_status sv_timing_read(sv_state *st, double *sweep_ms, int64_t *launches, double *bytes);
 
 /* Library build identification (gfx target, compile flags). */
 const char *sv_version(void);

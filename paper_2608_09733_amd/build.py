@@ -9,6 +9,7 @@ hipcc flags:
       compile-time slot indices into dynamic ones and demotes groups to scratch)
 """
 import os
+import re
 import subprocess
 import sys
 
@@ -36,27 +37,49 @@ def _run(cmd, verbose):
         print(out)
 
 
-def build(verbose: bool = False) -> str:
+def variants():
+    """(T, M, R, NS) entries of SVI_VARIANTS in sv_variants.h."""
+    txt = open(os.path.join(CSRC, "sv_variants.h")).read()
+    return re.findall(r"X\((double|float),\s*(\d+),\s*(\d+),\s*(\d+)\)", txt)
+
+
+def build(verbose: bool = False, jobs: int = 0) -> str:
     objdir = os.path.join(HERE, "_build")
     os.makedirs(objdir, exist_ok=True)
-    objs = []
-    procs = []
+    jobs = jobs or min(16, os.cpu_count() or 4)
+    todo = []
     for src in ["sv_kernels.hip", "sv_host.cpp"]:
         obj = os.path.join(objdir, src + ".o")
         cmd = [HIPCC] + COMMON + ["-c", os.path.join(CSRC, src), "-o", obj]
         if src.endswith(".cpp"):
             cmd = [HIPCC, "-x", "hip"] + COMMON + ["-c", os.path.join(CSRC, src), "-o", obj]
-        if verbose:
-            print(" ".join(cmd), flush=True)
-        procs.append((cmd, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT,
-                                            text=True)))
-        objs.append(obj)
-    for cmd, p in procs:
+        todo.append((cmd, obj))
+    for t, m, r, ns in variants():
+        obj = os.path.join(objdir, f"sweep_{t}_{m}_{r}_{ns}.o")
+        cmd = [HIPCC] + COMMON + [f"-DSVI_VT={t}", f"-DSVI_VM={m}", f"-DSVI_VR={r}",
+                                  f"-DSVI_VNS={ns}", "-c",
+                                  os.path.join(CSRC, "sv_sweep_variant.hip"), "-o", obj]
+        todo.append((cmd, obj))
+    objs = [o for _, o in todo]
+    running = []
+    while todo or running:
+        while todo and len(running) < jobs:
+            cmd, _ = todo.pop(0)
+            if verbose:
+                print(" ".join(cmd), flush=True)
+            running.append((cmd, subprocess.Popen(cmd, stdout=subprocess.PIPE,
+                                                  stderr=subprocess.STDOUT, text=True)))
+        cmd, p = running.pop(0)
         out, _ = p.communicate()
         out = "\n".join(l for l in out.splitlines() if "packed-fp32-ops" not in l)
         if p.returncode != 0:
+            for _, q in running:
+                q.kill()
             raise RuntimeError(f"build failed: {' '.join(cmd)}\n{out}")
     tmp = LIB + ".tmp"
+    for f in os.listdir(objdir):
+        if f.endswith(".o") and os.path.join(objdir, f) not in objs:
+            os.remove(os.path.join(objdir, f))
     _run([HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp] + objs, verbose)
     os.replace(tmp, LIB)
     return LIB

@@ -1,0 +1,741 @@
+#pragma once
+// gfx950 kernels of the state-vector library.
+//
+// State layout in HBM: two planes (re, im) of 2^n elements (double for
+// complex128, float for complex64).  Gate action follows the paper's gather /
+// multiply / scatter over the amplitudes that differ only on the targets
+// (Section 5.3), but indices are computed by bit insertion instead of an index
+// table, and many gates are applied per HBM round trip (see sv_internal.h).
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "sv_internal.h"
+
+namespace svk {
+
+template <typename T> struct C2T;
+template <> struct C2T<double> { using type = double2; };
+template <> struct C2T<float> { using type = float2; };
+
+template <typename T> struct V4T;   // 16-byte global vector of T
+template <> struct V4T<double> { using type = double2; static constexpr int N = 2; };
+template <> struct V4T<float> { using type = float4; static constexpr int N = 4; };
+
+template <typename T>
+__device__ __forceinline__ int swz(int i) {
+  return svi_swz(i, sizeof(T) == 8 ? 3 : 4);
+}
+
+// Insert a zero bit at each position of pos[0..np) (ascending).
+__device__ __forceinline__ uint64_t insert_zeros64(uint64_t x, const int32_t *pos, int np) {
+  for (int k = 0; k < np; k++) {
+    const int p = pos[k];
+    const uint64_t lo = x & ((1ull << p) - 1ull);
+    x = ((x >> p) << (p + 1)) | lo;
+  }
+  return x;
+}
+
+__device__ __forceinline__ int insert_zeros32(int x, const int32_t *pos, int np) {
+  for (int k = 0; k < np; k++) {
+    const int p = pos[k];
+    const int lo = x & ((1 << p) - 1);
+    x = ((x >> p) << (p + 1)) | lo;
+  }
+  return x;
+}
+
+// Global offset of tile row r: bit k of r goes to qubit hb[k].
+__device__ __forceinline__ uint64_t spread_row(int r, const int32_t *hb, int nh) {
+  uint64_t o = 0;
+  for (int k = 0; k < nh; k++) o |= (uint64_t)((r >> k) & 1) << hb[k];
+  return o;
+}
+
+// Base index of tile `tile`: zeros inserted at the tile's qubits (0..c-1 and hb).
+__device__ __forceinline__ uint64_t tile_base(int64_t tile, int c, const int32_t *hb, int nh) {
+  uint64_t x = (uint64_t)tile << c;
+  return insert_zeros64(x, hb, nh);
+}
+
+// ------------------------------------------------------------ micro-ops
+// All group arrays are indexed with compile-time indices only.
+
+template <typename T, int R, int TB>
+__device__ __forceinline__ void mo_u(T *re, T *im, const double *cf, uint32_t cm, uint32_t cv) {
+  const T a0r = (T)cf[0], a0i = (T)cf[1], a1r = (T)cf[2], a1i = (T)cf[3];
+  const T b0r = (T)cf[4], b0i = (T)cf[5], b1r = (T)cf[6], b1i = (T)cf[7];
+  if (cm == 0) {
+#pragma unroll
+    for (int j = 0; j < (1 << R); j++) {
+      if (j & (1 << TB)) continue;
+      const int k = j | (1 << TB);
+      const T xr = re[j], xi = im[j], yr = re[k], yi = im[k];
+      re[j] = a0r * xr - a0i * xi + a1r * yr - a1i * yi;
+      im[j] = a0r * xi + a0i * xr + a1r * yi + a1i * yr;
+      re[k] = b0r * xr - b0i * xi + b1r * yr - b1i * yi;
+      im[k] = b0r * xi + b0i * xr + b1r * yi + b1i * yr;
+    }
+  } else {
+#pragma unroll
+    for (int j = 0; j < (1 << R); j++) {
+      if (j & (1 << TB)) continue;
+      if ((j & cm) != cv) continue;
+      const int k = j | (1 << TB);
+      const T xr = re[j], xi = im[j], yr = re[k], yi = im[k];
+      re[j] = a0r * xr - a0i * xi + a1r * yr - a1i * yi;
+      im[j] = a0r * xi + a0i * xr + a1r * yi + a1i * yr;
+      re[k] = b0r * xr - b0i * xi + b1r * yr - b1i * yi;
+      im[k] = b0r * xi + b0i * xr + b1r * yi + b1i * yr;
+    }
+  }
+}
+
+template <typename T, int R, int TB>
+__device__ __forceinline__ void mo_r(T *re, T *im, const double *cf, uint32_t cm, uint32_t cv) {
+  const T r00 = (T)cf[0], r01 = (T)cf[1], r10 = (T)cf[2], r11 = (T)cf[3];
+  if (cm == 0) {
+#pragma unroll
+    for (int j = 0; j < (1 << R); j++) {
+      if (j & (1 << TB)) continue;
+      const int k = j | (1 << TB);
+      const T xr = re[j], xi = im[j], yr = re[k], yi = im[k];
+      re[j] = r00 * xr + r01 * yr;
+      im[j] = r00 * xi + r01 * yi;
+      re[k] = r10 * xr + r11 * yr;
+      im[k] = r10 * xi + r11 * yi;
+    }
+  } else {
+#pragma unroll
+    for (int j = 0; j < (1 << R); j++) {
+      if (j & (1 << TB)) continue;
+      if ((j & cm) != cv) continue;
+      const int k = j | (1 << TB);
+      const T xr = re[j], xi = im[j], yr = re[k], yi = im[k];
+      re[j] = r00 * xr + r01 * yr;
+      im[j] = r00 * xi + r01 * yi;
+      re[k] = r10 * xr + r11 * yr;
+      im[k] = r10 * xi + r11 * yi;
+    }
+  }
+}
+
+template <typename T, int R>
+__device__ __forceinline__ void mo_p(T *re, T *im, const double *cf, uint32_t mask, uint32_t cm,
+                                     uint32_t cv) {
+  const T d0r = (T)cf[0], d0i = (T)cf[1], d1r = (T)cf[2], d1i = (T)cf[3];
+#pragma unroll
+  for (int j = 0; j < (1 << R); j++) {
+    if ((j & cm) != cv) continue;
+    const bool odd = __builtin_popcount((uint32_t)j & mask) & 1;
+    const T dr = odd ? d1r : d0r;
+    const T di = odd ? d1i : d0i;
+    const T xr = re[j], xi = im[j];
+    re[j] = xr * dr - xi * di;
+    im[j] = xr * di + xi * dr;
+  }
+}
+
+template <typename T, int R, int TB>
+__device__ __forceinline__ void mo_x(T *re, T *im, uint32_t cm, uint32_t cv) {
+#pragma unroll
+  for (int j = 0; j < (1 << R); j++) {
+    if (j & (1 << TB)) continue;
+    if ((j & cm) != cv) continue;
+    const int k = j | (1 << TB);
+    T t = re[j]; re[j] = re[k]; re[k] = t;
+    t = im[j]; im[j] = im[k]; im[k] = t;
+  }
+}
+
+template <typename T, int R, int A, int B>
+__device__ __forceinline__ void mo_swap(T *re, T *im, uint32_t cm, uint32_t cv) {
+#pragma unroll
+  for (int j = 0; j < (1 << R); j++) {
+    if (!((j >> A) & 1) || ((j >> B) & 1)) continue;
+    if ((j & cm) != cv) continue;
+    const int k = j ^ (1 << A) ^ (1 << B);
+    T t = re[j]; re[j] = re[k]; re[k] = t;
+    t = im[j]; im[j] = im[k]; im[k] = t;
+  }
+}
+
+template <typename T, int R>
+__device__ __forceinline__ void mo_neg(T *re, T *im, uint32_t cm, uint32_t cv) {
+#pragma unroll
+  for (int j = 0; j < (1 << R); j++) {
+    if ((j & cm) != cv) continue;
+    re[j] = -re[j];
+    im[j] = -im[j];
+  }
+}
+
+// 4x4 on (bit A = low local bit, bit B = high local bit).
+template <typename T, int R, int A, int B>
+__device__ __forceinline__ void mo_q(T *re, T *im, const double *cf, uint32_t cm, uint32_t cv) {
+  T u[32];
+#pragma unroll
+  for (int q = 0; q < 32; q++) u[q] = (T)cf[q];
+#pragma unroll
+  for (int j = 0; j < (1 << R); j++) {
+    if ((j >> A) & 1) continue;
+    if ((j >> B) & 1) continue;
+    if ((j & cm) != cv) continue;
+    constexpr int a1 = 1 << A, b1 = 1 << B;
+    const T x0r = re[j], x0i = im[j], x1r = re[j | a1], x1i = im[j | a1];
+    const T x2r = re[j | b1], x2i = im[j | b1], x3r = re[j | a1 | b1], x3i = im[j | a1 | b1];
+#define SVI_ROW(r, dst)                                                                   \
+    {                                                                                     \
+      const T ar = u[8 * r + 0] * x0r - u[8 * r + 1] * x0i + u[8 * r + 2] * x1r -         \
+                   u[8 * r + 3] * x1i + u[8 * r + 4] * x2r - u[8 * r + 5] * x2i +         \
+                   u[8 * r + 6] * x3r - u[8 * r + 7] * x3i;                               \
+      const T ai = u[8 * r + 0] * x0i + u[8 * r + 1] * x0r + u[8 * r + 2] * x1i +         \
+                   u[8 * r + 3] * x1r + u[8 * r + 4] * x2i + u[8 * r + 5] * x2r +         \
+                   u[8 * r + 6] * x3i + u[8 * r + 7] * x3r;                               \
+      re[dst] = ar;                                                                       \
+      im[dst] = ai;                                                                       \
+    }
+    SVI_ROW(0, j) SVI_ROW(1, j | a1) SVI_ROW(2, j | b1) SVI_ROW(3, j | a1 | b1)
+#undef SVI_ROW
+  }
+}
+
+// Real rotation between the two local patterns of a two-level subspace:
+// for every j with (j & tm) == pa, partner k = j ^ XM:
+//   (x_j, x_k) <- (r00 x_j + r01 x_k, r10 x_j + r11 x_k).
+template <typename T, int R, int XM>
+__device__ __forceinline__ void mo_2l(T *re, T *im, const double *cf, uint32_t tm, uint32_t pa,
+                                      uint32_t cm, uint32_t cv) {
+  const T r00 = (T)cf[0], r01 = (T)cf[1], r10 = (T)cf[2], r11 = (T)cf[3];
+#pragma unroll
+  for (int j = 0; j < (1 << R); j++) {
+    if (((uint32_t)j & tm) != pa) continue;
+    if ((j & cm) != cv) continue;
+    const int k = j ^ XM;
+    const T xr = re[j], xi = im[j], yr = re[k], yi = im[k];
+    re[j] = r00 * xr + r01 * yr;
+    im[j] = r00 * xi + r01 * yi;
+    re[k] = r10 * xr + r11 * yr;
+    im[k] = r10 * xi + r11 * yi;
+  }
+}
+
+// 2^K x 2^K on group bits 0..K-1.
+template <typename T, int R, int K>
+__device__ __forceinline__ void mo_dense(T *re, T *im, const double *cf, uint32_t cm,
+                                         uint32_t cv) {
+  constexpr int D = 1 << K;
+#pragma clang loop unroll(full)
+  for (int o = 0; o < (1 << (R - K)); o++) {
+    const int base = o << K;
+    if ((base & cm) != cv) continue;
+    T xr[D], xi[D];
+#pragma unroll
+    for (int q = 0; q < D; q++) { xr[q] = re[base + q]; xi[q] = im[base + q]; }
+#pragma unroll
+    for (int r = 0; r < D; r++) {
+      T ar = 0, ai = 0;
+#pragma unroll
+      for (int q = 0; q < D; q++) {
+        const T ur = (T)cf[(r * D + q) * 2], ui = (T)cf[(r * D + q) * 2 + 1];
+        ar += ur * xr[q] - ui * xi[q];
+        ai += ur * xi[q] + ui * xr[q];
+      }
+      re[base + r] = ar;
+      im[base + r] = ai;
+    }
+  }
+}
+
+template <typename T, int R>
+__device__ __forceinline__ void mo_diagt(T *re, T *im, const double *cf) {
+#pragma unroll
+  for (int j = 0; j < (1 << R); j++) {
+    const T dr = (T)cf[2 * j], di = (T)cf[2 * j + 1];
+    const T xr = re[j], xi = im[j];
+    re[j] = xr * dr - xi * di;
+    im[j] = xr * di + xi * dr;
+  }
+}
+
+// Im <lam| G |psi> over one group, G = alpha * (Pauli string x,z) + beta * I
+// on the control subspace.  XM is the compile-time x-mask (group bits).
+template <typename T, int R, int XM>
+__device__ __forceinline__ double mo_grad(const T *pr, const T *pi, const T *lr, const T *li,
+                                          uint32_t z, uint32_t cm, uint32_t cv, double alpha,
+                                          double beta) {
+  const int ny = __builtin_popcount((uint32_t)XM & z) & 3;
+  double acc = 0.0;
+#pragma unroll
+  for (int j = 0; j < (1 << R); j++) {
+    if ((j & cm) != cv) continue;
+    const int k = j ^ XM;
+    // (P psi)_j = i^ny (-1)^{popcount(k & z)} psi_k
+    const bool neg = __builtin_popcount((uint32_t)k & z) & 1;
+    double wr = (double)pr[k], wi = (double)pi[k];
+    double tr, ti;
+    switch (ny) {
+      case 0: tr = wr; ti = wi; break;
+      case 1: tr = -wi; ti = wr; break;
+      case 2: tr = -wr; ti = -wi; break;
+      default: tr = wi; ti = -wr; break;
+    }
+    if (neg) { tr = -tr; ti = -ti; }
+    const double gr = alpha * tr + beta * (double)pr[j];
+    const double gi = alpha * ti + beta * (double)pi[j];
+    // Im(conj(l) * g) = lr*gi - li*gr
+    acc += (double)lr[j] * gi - (double)li[j] * gr;
+  }
+  return acc;
+}
+
+// Fast-Givens rotation on group bit TB (record {form, k, scale, 0}, form 0 or
+// 1; the scale is applied separately).  Gentleman's scaled rotation: each
+// output is one FMA with a +-1 coefficient on one input.
+template <typename T, int R, int TB>
+__device__ __forceinline__ void mo_fastr(T *re, T *im, const double *cf) {
+  const int form = (int)cf[0];
+  const T k = (T)cf[1];
+#define SVI_FR(XR, XI, YR, YI)                                   \
+  _Pragma("unroll") for (int j = 0; j < (1 << R); j++) {         \
+    if (j & (1 << TB)) continue;                                 \
+    const int l = j | (1 << TB);                                 \
+    const T xr = re[j], xi = im[j], yr = re[l], yi = im[l];      \
+    re[j] = XR; im[j] = XI; re[l] = YR; im[l] = YI;              \
+  }
+  if (form == 0) {
+    SVI_FR(xr - k * yr, xi - k * yi, k * xr + yr, k * xi + yi)
+  } else {
+    SVI_FR(k * xr - yr, k * xi - yi, xr + k * yr, xi + k * yi)
+  }
+#undef SVI_FR
+}
+
+// Static Kronecker stage: s * D_after * (R~_{R-1} (x) ... (x) R~_0) * D_before.
+template <typename T, int R>
+__device__ __forceinline__ void kron_stage(T *re, T *im, const double *cf, uint32_t rmask,
+                                           int dflags) {
+  constexpr int G = 1 << R;
+  const double *tb = cf + 4 * R;
+  const double *ta = tb + 2 * G;
+  if (dflags & 1) mo_diagt<T, R>(re, im, tb);
+  if (rmask & 1u) mo_fastr<T, R, 0>(re, im, cf + 0);
+  if (rmask & 2u) mo_fastr<T, R, 1>(re, im, cf + 4);
+  if constexpr (R > 2) { if (rmask & 4u) mo_fastr<T, R, 2>(re, im, cf + 8); }
+  if constexpr (R > 3) { if (rmask & 8u) mo_fastr<T, R, 3>(re, im, cf + 12); }
+  if constexpr (R > 4) { if (rmask & 16u) mo_fastr<T, R, 4>(re, im, cf + 16); }
+  if (dflags & 2) mo_diagt<T, R>(re, im, ta);
+  if (dflags & 4) {
+    const T sc = (T)ta[2 * G];
+#pragma unroll
+    for (int j = 0; j < G; j++) { re[j] *= sc; im[j] *= sc; }
+  }
+}
+
+#define SVI_T5(F, t, ...)                                   \
+  switch (t) {                                              \
+    case 0: F<T, R, 0>(__VA_ARGS__); break;                 \
+    case 1: F<T, R, 1>(__VA_ARGS__); break;                 \
+    case 2: if constexpr (R > 2) F<T, R, 2>(__VA_ARGS__); break; \
+    case 3: if constexpr (R > 3) F<T, R, 3>(__VA_ARGS__); break; \
+    case 4: if constexpr (R > 4) F<T, R, 4>(__VA_ARGS__); break; \
+    default: break;                                         \
+  }
+
+template <typename T, int R>
+__device__ __forceinline__ void dispatch_swap(int a, int b, T *re, T *im, uint32_t cm, uint32_t cv) {
+#define SVI_SW(A, B) if (a == A && b == B) { if constexpr (A < R && B < R) mo_swap<T, R, A, B>(re, im, cm, cv); return; }
+  SVI_SW(0, 1) SVI_SW(0, 2) SVI_SW(0, 3) SVI_SW(0, 4) SVI_SW(1, 0) SVI_SW(1, 2) SVI_SW(1, 3)
+  SVI_SW(1, 4) SVI_SW(2, 0) SVI_SW(2, 1) SVI_SW(2, 3) SVI_SW(2, 4) SVI_SW(3, 0) SVI_SW(3, 1)
+  SVI_SW(3, 2) SVI_SW(3, 4) SVI_SW(4, 0) SVI_SW(4, 1) SVI_SW(4, 2) SVI_SW(4, 3)
+#undef SVI_SW
+}
+
+template <typename T, int R>
+__device__ __forceinline__ void dispatch_q(int a, int b, T *re, T *im, const double *cf,
+                                           uint32_t cm, uint32_t cv) {
+#define SVI_Q(A, B) if (a == A && b == B) { if constexpr (A < R && B < R) mo_q<T, R, A, B>(re, im, cf, cm, cv); return; }
+  SVI_Q(0, 1) SVI_Q(0, 2) SVI_Q(0, 3) SVI_Q(0, 4) SVI_Q(1, 0) SVI_Q(1, 2) SVI_Q(1, 3)
+  SVI_Q(1, 4) SVI_Q(2, 0) SVI_Q(2, 1) SVI_Q(2, 3) SVI_Q(2, 4) SVI_Q(3, 0) SVI_Q(3, 1)
+  SVI_Q(3, 2) SVI_Q(3, 4) SVI_Q(4, 0) SVI_Q(4, 1) SVI_Q(4, 2) SVI_Q(4, 3)
+#undef SVI_Q
+}
+
+template <typename T, int R>
+__device__ __forceinline__ void apply_op(const MicroOp &op, T *re, T *im, const double *coef) {
+  const double *cf = coef + op.coef;
+  switch (op.type) {
+    case MO_U: SVI_T5(mo_u, op.t0, re, im, cf, op.cm, op.cv) break;
+    case MO_R: SVI_T5(mo_r, op.t0, re, im, cf, op.cm, op.cv) break;
+    case MO_P: mo_p<T, R>(re, im, cf, op.mask, op.cm, op.cv); break;
+    case MO_X:
+      switch (op.t0) {
+        case 0: mo_x<T, R, 0>(re, im, op.cm, op.cv); break;
+        case 1: mo_x<T, R, 1>(re, im, op.cm, op.cv); break;
+        case 2: if constexpr (R > 2) mo_x<T, R, 2>(re, im, op.cm, op.cv); break;
+        case 3: if constexpr (R > 3) mo_x<T, R, 3>(re, im, op.cm, op.cv); break;
+        case 4: if constexpr (R > 4) mo_x<T, R, 4>(re, im, op.cm, op.cv); break;
+        default: break;
+      }
+      break;
+    case MO_SWAP: dispatch_swap<T, R>(op.t0, op.t1, re, im, op.cm, op.cv); break;
+    case MO_NEG: mo_neg<T, R>(re, im, op.cm, op.cv); break;
+    case MO_Q: dispatch_q<T, R>(op.t0, op.t1, re, im, cf, op.cm, op.cv); break;
+    case MO_DENSE:
+      switch (op.mask) {
+        case 1: mo_dense<T, R, 1>(re, im, cf, op.cm, op.cv); break;
+        case 2: mo_dense<T, R, 2>(re, im, cf, op.cm, op.cv); break;
+        case 3: if constexpr (R >= 3) mo_dense<T, R, 3>(re, im, cf, op.cm, op.cv); break;
+        default: break;
+      }
+      break;
+    case MO_DIAGT: mo_diagt<T, R>(re, im, cf); break;
+    case MO_2L:
+      switch (op.t1) {
+#define SVI_L(XV) case XV: if constexpr (XV < (1 << R)) mo_2l<T, R, XV>(re, im, cf, op.mask, op.gz, op.cm, op.cv); break;
+        SVI_L(1) SVI_L(2) SVI_L(3) SVI_L(4) SVI_L(5) SVI_L(6) SVI_L(7) SVI_L(8) SVI_L(9) SVI_L(10)
+        SVI_L(11) SVI_L(12) SVI_L(13) SVI_L(14) SVI_L(15) SVI_L(16) SVI_L(17) SVI_L(18) SVI_L(19)
+        SVI_L(20) SVI_L(21) SVI_L(22) SVI_L(23) SVI_L(24) SVI_L(25) SVI_L(26) SVI_L(27) SVI_L(28)
+        SVI_L(29) SVI_L(30) SVI_L(31)
+#undef SVI_L
+        default: break;
+      }
+      break;
+    default: break;
+  }
+}
+
+template <typename T, int R>
+__device__ __forceinline__ double grad_op(const MicroOp &op, const T *pr, const T *pi, const T *lr,
+                                          const T *li) {
+  // op.mask = x-mask (0, one bit, or two bits) over group bits.
+  const uint32_t x = op.mask;
+  switch (x) {
+#define SVI_G(XV) case XV: if constexpr (XV < (1 << R)) return mo_grad<T, R, XV>(pr, pi, lr, li, op.gz, op.cm, op.cv, op.galpha, op.gbeta); break;
+    SVI_G(0) SVI_G(1) SVI_G(2) SVI_G(3) SVI_G(4) SVI_G(5) SVI_G(6) SVI_G(7) SVI_G(8) SVI_G(9)
+    SVI_G(10) SVI_G(11) SVI_G(12) SVI_G(13) SVI_G(14) SVI_G(15) SVI_G(16) SVI_G(17) SVI_G(18)
+    SVI_G(19) SVI_G(20) SVI_G(21) SVI_G(22) SVI_G(23) SVI_G(24) SVI_G(25) SVI_G(26) SVI_G(27)
+    SVI_G(28) SVI_G(29) SVI_G(30) SVI_G(31)
+#undef SVI_G
+    default: break;
+  }
+  return 0.0;
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// ------------------------------------------------------------ tile sweep
+// One persistent workgroup loops over tiles.  NS = 1 (forward) or 2 (adjoint:
+// state 0 = psi, state 1 = lambda, micro-ops applied to both, MO_GRAD
+// accumulates gradient partials).
+
+#define SVI_GSLOTS 256
+
+template <typename T, int M, int R, int NS>
+__global__ void __launch_bounds__(1 << (M - R)) k_sweep(SweepArgs a) {
+  constexpr int NT = 1 << (M - R);
+  constexpr int G = 1 << R;
+  constexpr int VN = V4T<T>::N;
+  constexpr int LV = VN == 2 ? 1 : 2;
+  constexpr int NIT = (1 << M) / (VN * NT);   // vector loads per thread per plane (full tile)
+  constexpr int NWAVE = (NT + 63) / 64;
+  using C2 = typename C2T<T>::type;
+  using V4 = typename V4T<T>::type;
+  __shared__ C2 lds[NS][1 << M];
+  __shared__ double wsum[NS == 2 ? NWAVE : 1][NS == 2 ? SVI_GSLOTS : 1];
+  __shared__ double gacc[NS == 2 ? SVI_GSLOTS : 1];
+  __shared__ int32_t hb_s[SVI_MMAX];
+
+  const int tid = threadIdx.x;
+  const int m = a.m, c = a.c, nh = a.nh;
+  const int mm = m > R ? m : R;              // tile bits including phantom padding
+  const int ntile_el = 1 << m;               // real amplitudes per tile
+  const int ngroups = 1 << (mm - R);
+  const bool vec = c >= LV;                  // rows hold whole 16-byte vectors
+
+  if (tid < SVI_MMAX) hb_s[tid] = a.hb[tid < nh ? tid : 0];
+  if constexpr (NS == 2) {
+    for (int s = tid; s < SVI_GSLOTS; s += NT) gacc[s] = 0.0;
+  }
+  __syncthreads();
+
+  // Row offsets of this thread's elements, the same for every tile.
+  uint64_t roff[NIT];
+#pragma unroll
+  for (int k = 0; k < NIT; k++) {
+    const int i = (tid + k * NT) * (vec ? VN : 1);
+    roff[k] = spread_row(i >> c, hb_s, nh) + (uint64_t)(i & ((1 << c) - 1));
+  }
+
+  const int tsw = swz<T>(tid * VN);          // swizzled slot of this thread's first element
+  T *const pre0 = (T *)a.re, *const pim0 = (T *)a.im;
+  T *const pre1 = (T *)a.re2, *const pim1 = (T *)a.im2;
+
+  for (int64_t tile = blockIdx.x; tile < a.ntiles; tile += gridDim.x) {
+    const uint64_t base = tile_base(tile, c, hb_s, nh);
+    // ---- load tile (rows of 2^c contiguous amplitudes) into LDS
+    if (mm > m) {
+      for (int i = tid; i < (1 << mm); i += NT) {
+        lds[0][swz<T>(i)] = C2{0, 0};
+        if constexpr (NS == 2) lds[1][swz<T>(i)] = C2{0, 0};
+      }
+      __syncthreads();
+    }
+#pragma unroll
+    for (int s = 0; s < NS; s++) {
+      const T *pr = s == 0 ? pre0 : pre1;
+      const T *pi = s == 0 ? pim0 : pim1;
+      if (s == 0 && (a.flags & SW_INIT_ZERO)) {
+        for (int i = tid; i < ntile_el; i += NT) {
+          const T v = (base == 0 && i == 0) ? (T)1 : (T)0;
+          lds[0][swz<T>(i)] = C2{v, 0};
+        }
+      } else if (vec) {
+#pragma unroll
+        for (int k = 0; k < NIT; k++) {
+          const int i = (tid + k * NT) * VN;
+          if (i < ntile_el) {
+            const uint64_t g = base + roff[k];
+            const V4 vr = *(const V4 *)(pr + g);
+            const V4 vi = *(const V4 *)(pi + g);
+            const int si = tsw ^ swz<T>(k * NT * VN);
+            if constexpr (VN == 2) {
+              lds[s][si] = C2{vr.x, vi.x};
+              lds[s][si ^ 1] = C2{vr.y, vi.y};
+            } else {
+              lds[s][si] = C2{vr.x, vi.x};
+              lds[s][si ^ 1] = C2{vr.y, vi.y};
+              lds[s][si ^ 2] = C2{vr.z, vi.z};
+              lds[s][si ^ 3] = C2{vr.w, vi.w};
+            }
+          }
+        }
+      } else {
+        for (int i = tid; i < ntile_el; i += NT) {
+          const uint64_t g = base + spread_row(i >> c, hb_s, nh) + (uint64_t)(i & ((1 << c) - 1));
+          lds[s][swz<T>(i)] = C2{pr[g], pi[g]};
+        }
+      }
+    }
+    __syncthreads();
+
+    // ---- stages
+    for (int st = a.stage_begin; st < a.stage_end; st++) {
+      const StageDesc &sd = a.stages[st];
+      // Every thread runs the stage (keeps wave shuffles uniform).  Threads
+      // beyond the tile's groups work on LDS slots above 2^mm, which are
+      // never written back.
+      const bool active = tid < ngroups;
+      const int gbs = swz<T>(insert_zeros32(tid, sd.sbits, R)) * (int)sizeof(C2);
+      T re[NS][G], im[NS][G];
+#pragma unroll
+      for (int s = 0; s < NS; s++) {
+        const char *lb = (const char *)lds[s];
+#pragma unroll
+        for (int j = 0; j < G; j++) {
+          const C2 v = *(const C2 *)(lb + (gbs ^ sd.ld_off[j]));
+          re[s][j] = v.x;
+          im[s][j] = v.y;
+        }
+      }
+      if (sd.kind == ST_KRON) {
+        kron_stage<T, R>(re[0], im[0], a.coef + sd.kcoef, sd.rmask, sd.dflags);
+        if constexpr (NS == 2) kron_stage<T, R>(re[1], im[1], a.coef + sd.kcoef, sd.rmask, sd.dflags);
+      } else
+      for (int o = sd.op_begin; o < sd.op_end; o++) {
+        const MicroOp op = a.ops[o];
+        if constexpr (NS == 2) {
+          if (op.type == MO_GRAD) {
+            double v = active ? grad_op<T, R>(op, re[0], im[0], re[1], im[1]) : 0.0;
+            v = wave_sum(v);
+            if ((tid & 63) == 0) wsum[tid >> 6][op.coef] = v;
+            continue;
+          }
+        }
+        apply_op<T, R>(op, re[0], im[0], a.coef);
+        if constexpr (NS == 2) apply_op<T, R>(op, re[1], im[1], a.coef);
+      }
+#pragma unroll
+      for (int s = 0; s < NS; s++) {
+        char *lb = (char *)lds[s];
+#pragma unroll
+        for (int j = 0; j < G; j++) *(C2 *)(lb + (gbs ^ sd.st_off[j])) = C2{re[s][j], im[s][j]};
+      }
+      __syncthreads();
+    }
+
+    if constexpr (NS == 2) {
+      // fold this tile's per-wave sums into the workgroup accumulators
+      for (int s = tid; s < a.n_gslots; s += NT) {
+        double v = 0.0;
+        for (int w = 0; w < NWAVE; w++) v += wsum[w][s];
+        gacc[s] += v;
+      }
+    }
+
+    // ---- store tile
+#pragma unroll
+    for (int s = 0; s < NS; s++) {
+      T *pr = s == 0 ? pre0 : pre1;
+      T *pi = s == 0 ? pim0 : pim1;
+      if (vec) {
+#pragma unroll
+        for (int k = 0; k < NIT; k++) {
+          const int i = (tid + k * NT) * VN;
+          if (i < ntile_el) {
+            const uint64_t g = base + roff[k];
+            const int si = tsw ^ swz<T>(k * NT * VN);
+            V4 vr, vi;
+            if constexpr (VN == 2) {
+              const C2 p0 = lds[s][si], p1 = lds[s][si ^ 1];
+              vr = V4{p0.x, p1.x};
+              vi = V4{p0.y, p1.y};
+            } else {
+              const C2 p0 = lds[s][si], p1 = lds[s][si ^ 1];
+              const C2 p2 = lds[s][si ^ 2], p3 = lds[s][si ^ 3];
+              vr = V4{p0.x, p1.x, p2.x, p3.x};
+              vi = V4{p0.y, p1.y, p2.y, p3.y};
+            }
+            *(V4 *)(pr + g) = vr;
+            *(V4 *)(pi + g) = vi;
+          }
+        }
+      } else {
+        for (int i = tid; i < ntile_el; i += NT) {
+          const uint64_t g = base + spread_row(i >> c, hb_s, nh) + (uint64_t)(i & ((1 << c) - 1));
+          const C2 p = lds[s][swz<T>(i)];
+          pr[g] = p.x;
+          pi[g] = p.y;
+        }
+      }
+    }
+    __syncthreads();
+  }
+
+  if constexpr (NS == 2) {
+    for (int s = tid; s < a.n_gslots; s += NT)
+      a.gpart[(int64_t)(a.gslot_begin + s) * gridDim.x + blockIdx.x] = gacc[s];
+  }
+}
+
+
+// ------------------------------------------------- Kronecker-only sweep
+// Lean variant for sweeps whose every stage is a Kronecker stage.  Stage
+// descriptors and coefficients are uniform and read with scalar loads; LDS
+// holds only the tile, and the code holds only the static stage body, so the
+// register groups stay in VGPRs with no interpreter paths competing for them.
+
+template <typename T, int M, int R>
+__global__ void __launch_bounds__(1 << (M - R)) k_sweep_kron(SweepArgs a) {
+  constexpr int NT = 1 << (M - R);
+  constexpr int G = 1 << R;
+  constexpr int VN = V4T<T>::N;
+  constexpr int NIT = (1 << M) / (VN * NT);
+  using C2 = typename C2T<T>::type;
+  using V4 = typename V4T<T>::type;
+  __shared__ C2 lds[1 << M];
+  __shared__ int32_t hb_s[SVI_MMAX];
+
+  const int tid = threadIdx.x;
+  const int m = a.m, c = a.c, nh = a.nh;
+  const int ntile_el = 1 << m;
+  const bool vec = c >= (VN == 2 ? 1 : 2);
+  const StageDesc *__restrict__ stages = a.stages + a.stage_begin;
+  const int nst = a.stage_end - a.stage_begin;
+  const double *__restrict__ coef = a.coef;
+
+  if (tid < SVI_MMAX) hb_s[tid] = a.hb[tid < nh ? tid : 0];
+  __syncthreads();
+
+  uint64_t roff[NIT];
+#pragma unroll
+  for (int k = 0; k < NIT; k++) {
+    const int i = (tid + k * NT) * (vec ? VN : 1);
+    roff[k] = spread_row(i >> c, hb_s, nh) + (uint64_t)(i & ((1 << c) - 1));
+  }
+  const int tsw = swz<T>(tid * VN);
+  T *const pre = (T *)a.re, *const pim = (T *)a.im;
+  char *const lb = (char *)lds;
+
+  for (int64_t tile = blockIdx.x; tile < a.ntiles; tile += gridDim.x) {
+    const uint64_t base = tile_base(tile, c, hb_s, nh);
+    if (vec) {
+#pragma unroll
+      for (int k = 0; k < NIT; k++) {
+        const int i = (tid + k * NT) * VN;
+        if (i < ntile_el) {
+          const uint64_t g = base + roff[k];
+          const V4 vr = *(const V4 *)(pre + g);
+          const V4 vi = *(const V4 *)(pim + g);
+          const int si = tsw ^ swz<T>(k * NT * VN);
+          if constexpr (VN == 2) {
+            lds[si] = C2{vr.x, vi.x};
+            lds[si ^ 1] = C2{vr.y, vi.y};
+          } else {
+            lds[si] = C2{vr.x, vi.x};
+            lds[si ^ 1] = C2{vr.y, vi.y};
+            lds[si ^ 2] = C2{vr.z, vi.z};
+            lds[si ^ 3] = C2{vr.w, vi.w};
+          }
+        }
+      }
+    } else {
+      for (int i = tid; i < ntile_el; i += NT) {
+        const uint64_t g = base + spread_row(i >> c, hb_s, nh) + (uint64_t)(i & ((1 << c) - 1));
+        lds[swz<T>(i)] = C2{pre[g], pim[g]};
+      }
+    }
+    __syncthreads();
+    for (int st = 0; st < nst; st++) {
+      const StageDesc &sd = stages[st];
+      const int gbs = swz<T>(insert_zeros32(tid, sd.sbits, R)) * (int)sizeof(C2);
+      T re[G], im[G];
+#pragma unroll
+      for (int j = 0; j < G; j++) {
+        const C2 v = *(const C2 *)(lb + (gbs ^ sd.ld_off[j]));
+        re[j] = v.x;
+        im[j] = v.y;
+      }
+      kron_stage<T, R>(re, im, coef + sd.kcoef, sd.rmask, sd.dflags);
+#pragma unroll
+      for (int j = 0; j < G; j++) *(C2 *)(lb + (gbs ^ sd.st_off[j])) = C2{re[j], im[j]};
+      __syncthreads();
+    }
+    if (vec) {
+#pragma unroll
+      for (int k = 0; k < NIT; k++) {
+        const int i = (tid + k * NT) * VN;
+        if (i < ntile_el) {
+          const uint64_t g = base + roff[k];
+          const int si = tsw ^ swz<T>(k * NT * VN);
+          V4 vr, vi;
+          if constexpr (VN == 2) {
+            const C2 p0 = lds[si], p1 = lds[si ^ 1];
+            vr = V4{p0.x, p1.x};
+            vi = V4{p0.y, p1.y};
+          } else {
+            const C2 p0 = lds[si], p1 = lds[si ^ 1], p2 = lds[si ^ 2], p3 = lds[si ^ 3];
+            vr = V4{p0.x, p1.x, p2.x, p3.x};
+            vi = V4{p0.y, p1.y, p2.y, p3.y};
+          }
+          *(V4 *)(pre + g) = vr;
+          *(V4 *)(pim + g) = vi;
+        }
+      }
+    } else {
+      for (int i = tid; i < ntile_el; i += NT) {
+        const uint64_t g = base + spread_row(i >> c, hb_s, nh) + (uint64_t)(i & ((1 << c) - 1));
+        const C2 p = lds[swz<T>(i)];
+        pre[g] = p.x;
+        pim[g] = p.y;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+}  // namespace svk

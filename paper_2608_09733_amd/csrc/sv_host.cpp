@@ -207,7 +207,58 @@ struct StageP {
   std::vector<int> recs;      // indices into the record list, program order
   int gq[SVI_RMAX];           // tile-local position of group bit i
   bool dense = false;
+  bool kron = false;          // canonical Kronecker stage
+  std::vector<int> lead, dbefore, rops, dafter, trail;   // kron: records by role
 };
+
+// Records a Kronecker stage can hold: uncontrolled RY rotations, diagonal
+// gates (any controls) and permutations (any controls).
+static bool kron_eligible(const GateRec &g) {
+  if (g.grad) return false;
+  if (g.mo == MO_R) return g.nc == 0 && g.nt == 1 && g.kind == SV_RY;
+  return g.mo == MO_P || g.mo == MO_NEG || g.mo == MO_X || g.mo == MO_SWAP;
+}
+
+// Closure of records that fit  P_trail * D_after * (x) R * D_before * P_lead  inside S.
+static int closure_kron(const std::vector<GateRec> &recs, const std::vector<int> &cand,
+                        const std::vector<char> &done, uint64_t S, StageP *st) {
+  uint64_t blocked = 0, rq = 0, dA = 0, pq = 0;
+  bool leading = true;
+  int cnt = 0;
+  for (int r : cand) {
+    if (done[r]) continue;
+    const GateRec &g = recs[r];
+    const uint64_t q = g.qmask;
+    bool ok = (q & ~S) == 0 && (q & blocked) == 0 && kron_eligible(g);
+    int role = -1;   // 0 lead, 1 dbefore, 2 r, 3 dafter, 4 trail
+    if (ok) {
+      if (g.mo == MO_X || g.mo == MO_SWAP) {
+        role = leading ? 0 : 4;
+        if (!leading) pq |= q;
+      } else if (g.mo == MO_P || g.mo == MO_NEG) {
+        if (q & pq) ok = false;
+        else if (q & rq) { role = 3; dA |= q; }
+        else role = 1;
+      } else {
+        if (q & (rq | dA | pq)) ok = false;
+        else { role = 2; rq |= q; }
+      }
+    }
+    if (ok) {
+      if (role != 0) leading = false;
+      cnt++;
+      if (st) {
+        st->recs.push_back(r);
+        std::vector<int> *dst[5] = {&st->lead, &st->dbefore, &st->rops, &st->dafter, &st->trail};
+        dst[role]->push_back(r);
+      }
+    } else {
+      blocked |= q;
+      if ((blocked & S) == S) break;
+    }
+  }
+  return cnt;
+}
 
 struct SweepP {
   int m = 0, c = 0, nh = 0;
@@ -277,7 +328,7 @@ static void set_tile(SweepP &sw, int n, uint64_t T, int c) {
 
 // Split one sweep's records into register stages of <= R qubits.
 static void plan_stages(const std::vector<GateRec> &recs, const std::vector<int> &take, SweepP &sw,
-                        int R, int n) {
+                        int R, int n, bool allow_kron = false) {
   std::vector<char> done(recs.size(), 0);
   std::vector<char> veto(recs.size(), 0);
   for (int r : take)
@@ -293,7 +344,24 @@ static void plan_stages(const std::vector<GateRec> &recs, const std::vector<int>
       if (!done[r]) { first = r; break; }
     StageP st;
     std::vector<int> grp;   // qubits (global) in group order
-    if (recs[first].mo == MO_DENSE) {
+    if (allow_kron && kron_eligible(recs[first])) {
+      uint64_t S = recs[first].qmask;
+      while (popc(S) < R) {
+        int best = -1, bestv = closure_kron(recs, take, done, S, nullptr);
+        for (int q = 0; q < n; q++) {
+          if (!(Ttile & (1ull << q)) || (S & (1ull << q))) continue;
+          int v = closure_kron(recs, take, done, S | (1ull << q), nullptr);
+          if (v > bestv) { bestv = v; best = q; }
+        }
+        if (best < 0) break;
+        S |= 1ull << best;
+      }
+      st.kron = true;
+      closure_kron(recs, take, done, S, &st);
+      for (int r : st.recs) { done[r] = 1; left--; }
+      for (int q = 0; q < n; q++)
+        if (S & (1ull << q)) grp.push_back(q);
+    } else if (recs[first].mo == MO_DENSE) {
       st.dense = true;
       st.recs.push_back(first);
       done[first] = 1;
@@ -341,7 +409,7 @@ static void plan_stages(const std::vector<GateRec> &recs, const std::vector<int>
 
 // AUTO planner: DAG-aware tile clustering.
 static void plan_auto(const std::vector<GateRec> &recs, int n, const Tiling &tl,
-                      std::vector<SweepP> &out, double cost_cap) {
+                      std::vector<SweepP> &out, double cost_cap, bool kron = false) {
   const int M = std::min(tl.M, n);
   const int c = std::min(tl.c, n);
   std::vector<int> cand(recs.size());
@@ -383,7 +451,7 @@ static void plan_auto(const std::vector<GateRec> &recs, int n, const Tiling &tl,
     }
     SweepP sw;
     set_tile(sw, n, T, c);
-    plan_stages(recs, take, sw, tl.R, n);
+    plan_stages(recs, take, sw, tl.R, n, kron);
     for (int r : take) { done[r] = 1; left--; }
     out.push_back(std::move(sw));
   }
@@ -405,7 +473,7 @@ static int fuse_greedy(const std::vector<GateRec> &recs, int width, std::vector<
 }
 
 static void plan_fused(const std::vector<GateRec> &recs, int n, const Tiling &tl, int width,
-                       std::vector<SweepP> &out) {
+                       std::vector<SweepP> &out, bool kron = false) {
   std::vector<int> block_of;
   int nb = fuse_greedy(recs, width, block_of);
   const int M = std::min(tl.M, n);
@@ -419,7 +487,7 @@ static void plan_fused(const std::vector<GateRec> &recs, int n, const Tiling &tl
     for (int q = c; q < n && popc(T) < M; q++) T |= 1ull << q;
     SweepP sw;
     set_tile(sw, n, T, c);
-    plan_stages(recs, take, sw, tl.R, n);
+    plan_stages(recs, take, sw, tl.R, n, kron);
     out.push_back(std::move(sw));
   }
 }
@@ -428,6 +496,7 @@ static void plan_fused(const std::vector<GateRec> &recs, int n, const Tiling &tl
 
 struct Step {
   int kind = 0;              // 0 = tile sweep, 1 = single-gate kernel
+  bool all_kron = false;     // every stage is a Kronecker stage (lean kernel)
   SweepArgs sa{};            // tile sweep (pointers patched at launch)
   GateArgsHost ga{};         // single gate
   int gate_coef = -1;
@@ -441,6 +510,7 @@ struct Plan {
   std::vector<StageDesc> stages;
   std::vector<MicroOp> ops;
   std::vector<CoefDesc> coefs;
+  std::vector<TabFactor> factors;
   int ncoef = 0;
   std::vector<double> constants;     // appended after the user parameters
   int n_user_params = 0;
@@ -457,6 +527,7 @@ struct Plan {
   StageDesc *d_stages = nullptr;
   MicroOp *d_ops = nullptr;
   CoefDesc *d_coefdesc = nullptr;
+  TabFactor *d_factors = nullptr;
   double *d_coef = nullptr;
   double *d_params = nullptr;        // user params + constants
   double *d_statics = nullptr;
@@ -506,6 +577,8 @@ static int perm_apply(const MicroOp &op, int j) {
 // Emit the device descriptors of one tile sweep.
 static void emit_sweep(Plan &P, std::vector<GateRec> &recs, const SweepP &sw, int n, int R,
                        int flags, int gslot_base, int &gslots_used) {
+  const int SWB = P.dbl ? 3 : 4;
+  const int EB = P.dbl ? 16 : 8;        // bytes per LDS complex element
   Step s;
   s.kind = 0;
   SweepArgs &a = s.sa;
@@ -561,7 +634,7 @@ static void emit_sweep(Plan &P, std::vector<GateRec> &recs, const SweepP &sw, in
       op.cm = cm;
       op.cv = cv;
       int coff = -1;
-      add_coef(P, g, coff);
+      if (!st.kron) add_coef(P, g, coff);
       op.coef = coff < 0 ? 0 : coff;
       switch (g.mo) {
         case MO_U: case MO_R: case MO_X: op.t0 = local_of(g.t[0]); break;
@@ -595,36 +668,118 @@ static void emit_sweep(Plan &P, std::vector<GateRec> &recs, const SweepP &sw, in
         case MO_DENSE: op.mask = g.nt; break;   // targets are group bits 0..k-1
         default: break;
       }
-      if (op.type != MO_NOP) mops.push_back(op);
+      mops.push_back(op);
     }
-    // fold leading / trailing permutations into the LDS offsets
-    size_t lead = 0;
-    while (lead < mops.size() && (mops[lead].type == MO_X || mops[lead].type == MO_SWAP)) lead++;
-    size_t trail = mops.size();
-    if (lead < mops.size())
-      while (trail > lead && (mops[trail - 1].type == MO_X || mops[trail - 1].type == MO_SWAP)) trail--;
     StageDesc sd;
     std::memset(&sd, 0, sizeof sd);
     int sorted[SVI_RMAX];
     for (int i = 0; i < R; i++) sorted[i] = st.gq[i];
     std::sort(sorted, sorted + R);
     for (int i = 0; i < SVI_RMAX; i++) sd.sbits[i] = i < R ? sorted[i] : 0;
+    std::vector<MicroOp> leadp, trailp, body;
+    if (st.kron) {
+      // mops holds every record's micro-op in stage order; split by role
+      auto mop_of = [&](int r) {
+        for (size_t k = 0; k < st.recs.size(); k++)
+          if (st.recs[k] == r) return mops[k];
+        return MicroOp{};
+      };
+      for (int r : st.lead) leadp.push_back(mop_of(r));
+      for (int r : st.trail) trailp.push_back(mop_of(r));
+      sd.kind = ST_KRON;
+      sd.kcoef = P.ncoef;
+      const int G = 1 << R;
+      P.ncoef += 4 * R + 4 * G + 2;
+      uint32_t rmask = 0;
+      for (int r : st.rops) {
+        GateRec &g = recs[r];
+        int t = local_of(g.t[0]);
+        rmask |= 1u << t;
+        CoefDesc cd{};
+        cd.kind = g.coef_kind;
+        cd.fmt = CF_FASTR | (g.dagger ? CF_DAGGER : 0);
+        for (int k = 0; k < 3; k++) cd.pidx[k] = g.pidx[k];
+        cd.dst = sd.kcoef + 4 * t;
+        P.coefs.push_back(cd);
+      }
+      sd.rmask = rmask;
+      // fast-Givens scales of the stage's real gates (folded into D_after or a scalar)
+      auto push_scales = [&]() {
+        for (int r : st.rops) {
+          TabFactor f{};
+          f.kind = recs[r].coef_kind;
+          f.pidx = recs[r].pidx[0];
+          f.neg = 2;
+          P.factors.push_back(f);
+        }
+      };
+      auto table = [&](const std::vector<int> &rs, int dst, bool scales) {
+        CoefDesc cd{};
+        cd.fmt = CF_TABLE;
+        cd.src = (int)P.factors.size();
+        cd.len = R;
+        cd.dst = dst;
+        if (scales) push_scales();
+        for (int r : rs) {
+          GateRec &g = recs[r];
+          MicroOp m = mop_of(r);
+          TabFactor f{};
+          f.kind = g.coef_kind;
+          f.pidx = g.pidx[0];
+          f.cm = m.cm;
+          f.cv = m.cv;
+          if (g.mo == MO_NEG) f.neg = 1;
+          else f.mask = m.mask;
+          P.factors.push_back(f);
+        }
+        cd.pidx[0] = (int)P.factors.size() - cd.src;
+        P.coefs.push_back(cd);
+      };
+      if (!st.dbefore.empty()) { sd.dflags |= 1; table(st.dbefore, sd.kcoef + 4 * R, false); }
+      if (!st.dafter.empty()) {
+        sd.dflags |= 2;
+        table(st.dafter, sd.kcoef + 4 * R + 2 * G, true);
+      } else if (!st.rops.empty()) {
+        sd.dflags |= 4;
+        CoefDesc cd{};
+        cd.fmt = CF_SCALE;
+        cd.src = (int)P.factors.size();
+        push_scales();
+        cd.pidx[0] = (int)P.factors.size() - cd.src;
+        cd.dst = sd.kcoef + 4 * R + 4 * G;
+        P.coefs.push_back(cd);
+      }
+    } else {
+      // fold leading / trailing permutations into the LDS offsets
+      size_t lead = 0;
+      while (lead < mops.size() && (mops[lead].type == MO_X || mops[lead].type == MO_SWAP)) lead++;
+      size_t trail = mops.size();
+      if (lead < mops.size())
+        while (trail > lead && (mops[trail - 1].type == MO_X || mops[trail - 1].type == MO_SWAP)) trail--;
+      leadp.assign(mops.begin(), mops.begin() + lead);
+      trailp.assign(mops.begin() + trail, mops.end());
+      body.assign(mops.begin() + lead, mops.begin() + trail);
+      sd.kind = ST_OPS;
+    }
     for (int j = 0; j < (1 << R); j++) {
       int jl = j;
-      for (size_t k = lead; k-- > 0;) jl = perm_apply(mops[k], jl);
-      sd.ld_off[j] = spread_local(jl, st.gq, R);
+      for (size_t k = leadp.size(); k-- > 0;) jl = perm_apply(leadp[k], jl);
+      sd.ld_off[j] = svi_swz(spread_local(jl, st.gq, R), SWB) * EB;
       int js = j;
-      for (size_t k = trail; k < mops.size(); k++) js = perm_apply(mops[k], js);
-      sd.st_off[j] = spread_local(js, st.gq, R);
+      for (size_t k = 0; k < trailp.size(); k++) js = perm_apply(trailp[k], js);
+      sd.st_off[j] = svi_swz(spread_local(js, st.gq, R), SWB) * EB;
     }
     sd.op_begin = (int)P.ops.size();
-    for (size_t k = lead; k < trail; k++) P.ops.push_back(mops[k]);
+    for (const MicroOp &m : body) P.ops.push_back(m);
     sd.op_end = (int)P.ops.size();
     P.stages.push_back(sd);
     P.n_blocks++;
   }
   a.stage_end = (int)P.stages.size();
   a.n_gslots = gs;
+  s.all_kron = gs == 0;
+  for (int k = a.stage_begin; k < a.stage_end; k++)
+    if (P.stages[k].kind != ST_KRON) s.all_kron = false;
   gslots_used = gs;
   P.steps.push_back(s);
   P.n_sweeps++;
@@ -671,7 +826,8 @@ static sv_status upload_plan(Plan &P) {
   size_t o_st = 0;
   size_t o_ops = align(o_st + P.stages.size() * sizeof(StageDesc));
   size_t o_cd = align(o_ops + P.ops.size() * sizeof(MicroOp));
-  size_t o_cf = align(o_cd + P.coefs.size() * sizeof(CoefDesc));
+  size_t o_fa = align(o_cd + P.coefs.size() * sizeof(CoefDesc));
+  size_t o_cf = align(o_fa + (P.factors.size() + 1) * sizeof(TabFactor));
   size_t o_pa = align(o_cf + (size_t)std::max(P.ncoef, 1) * 8);
   size_t npar = (size_t)P.n_user_params + P.constants.size();
   size_t o_stc = align(o_pa + std::max<size_t>(npar, 1) * 8);
@@ -685,6 +841,9 @@ static sv_status upload_plan(Plan &P) {
   P.d_ops = (MicroOp *)(b + o_ops);
   P.d_coefdesc = (CoefDesc *)(b + o_cd);
   P.d_coef = (double *)(b + o_cf);
+  P.d_factors = (TabFactor *)(b + o_fa);
+  if (!P.factors.empty())
+    HIPCHK(hipMemcpy(P.d_factors, P.factors.data(), P.factors.size() * sizeof(TabFactor), hipMemcpyHostToDevice));
   P.d_params = (double *)(b + o_pa);
   P.d_statics = (double *)(b + o_stc);
   P.d_rowptr = (int32_t *)(b + o_rp);
@@ -719,10 +878,25 @@ struct sv_state {
   // growable scratch (partials)
   void *scratch = nullptr;
   size_t scratch_bytes = 0;
+  // kernel timing instrumentation
+  bool timing = false;
+  std::vector<hipEvent_t> ev_pool;
+  size_t ev_used = 0;
+  std::vector<double> ev_bytes;      // algorithmic bytes of each timed launch
   ~sv_state() {
     if (scratch) (void)hipFree(scratch);
+    for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
   }
 };
+
+static hipEvent_t next_event(sv_state *st) {
+  if (st->ev_used == st->ev_pool.size()) {
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    st->ev_pool.push_back(e);
+  }
+  return st->ev_pool[st->ev_used++];
+}
 
 static size_t elem_size(sv_dtype d) { return d == SV_C128 ? 8 : 4; }
 
@@ -823,11 +997,17 @@ extern "C" sv_status sv_set_stream(sv_state *st, void *stream) {
   return SV_OK;
 }
 
-extern "C" sv_status sv_set_tiling(sv_state *st, int32_t tile_bits, int32_t low_bits) {
+extern "C" sv_status sv_set_tiling(sv_state *st, int32_t tile_bits, int32_t low_bits,
+                                   int32_t group_bits) {
   if (!st) return fail(SV_EINVAL, "null handle");
   Tiling t = default_tiling(st->n, st->dtype, 1);
   if (tile_bits) t.M = tile_bits;
   if (low_bits) t.c = low_bits;
+  if (group_bits) {
+    if (!svk_has_sweep(st->dtype == SV_C128, t.M, group_bits, 1))
+      return fail(SV_EINVAL, "no kernel for tile_bits=%d group_bits=%d", t.M, group_bits);
+    t.R = group_bits;
+  }
   if (!svk_has_sweep(st->dtype == SV_C128, t.M, t.R, 1)) {
     // try the other register width
     int altR = t.R == 5 ? 4 : 5;
@@ -837,6 +1017,34 @@ extern "C" sv_status sv_set_tiling(sv_state *st, int32_t tile_bits, int32_t low_
   if (t.c < 1 || t.c > t.M - t.R + 1) return fail(SV_EINVAL, "low_bits %d out of range", t.c);
   st->tiling = t;
   st->plans.clear();
+  return SV_OK;
+}
+
+extern "C" sv_status sv_timing_enable(sv_state *st, int32_t on) {
+  if (!st) return fail(SV_EINVAL, "null handle");
+  HIPCHK(hipStreamSynchronize(st->stream));
+  st->timing = on != 0;
+  st->ev_used = 0;
+  st->ev_bytes.clear();
+  return SV_OK;
+}
+
+extern "C" sv_status sv_timing_read(sv_state *st, double *sweep_ms, int64_t *launches,
+                                    double *bytes) {
+  if (!st) return fail(SV_EINVAL, "null handle");
+  HIPCHK(hipStreamSynchronize(st->stream));
+  double ms = 0.0, by = 0.0;
+  for (size_t k = 0; k + 1 < st->ev_used; k += 2) {
+    float t = 0.f;
+    HIPCHK(hipEventElapsedTime(&t, st->ev_pool[k], st->ev_pool[k + 1]));
+    ms += t;
+    by += st->ev_bytes[k / 2];
+  }
+  if (sweep_ms) *sweep_ms = ms;
+  if (launches) *launches = (int64_t)(st->ev_used / 2);
+  if (bytes) *bytes = by;
+  st->ev_used = 0;
+  st->ev_bytes.clear();
   return SV_OK;
 }
 
@@ -937,8 +1145,8 @@ static sv_status build_forward_plan(int mode, int n, bool dbl, const Tiling &tl,
     }
   } else {
     std::vector<SweepP> sweeps;
-    if (mode < 0) plan_auto(recs, n, tl, sweeps, 1e300);
-    else plan_fused(recs, n, tl, mode, sweeps);
+    if (mode < 0) plan_auto(recs, n, tl, sweeps, 1e300, true);
+    else plan_fused(recs, n, tl, mode, sweeps, true);
     for (const SweepP &sw : sweeps) {
       int used = 0;
       emit_sweep(P, recs, sw, n, tl.R, 0, 0, used);
@@ -1086,7 +1294,8 @@ static sv_status upload_call_data(sv_state *st, Plan &P, const sv_op *ops, int n
     // the host vector dies at return: make the copy complete first
     HIPCHK(hipStreamSynchronize(st->stream));
   }
-  hipError_t e = svk_launch_coefs(P.d_coefdesc, (int)P.coefs.size(), P.d_params, P.d_statics, P.d_coef, st->stream);
+  hipError_t e = svk_launch_coefs(P.d_coefdesc, (int)P.coefs.size(), P.d_params, P.d_statics,
+                                  P.d_factors, P.d_coef, st->stream);
   if (e != hipSuccess) return fail(SV_EDEVICE, "coefficient kernel: %s", hipGetErrorString(e));
   return SV_OK;
 }
@@ -1098,6 +1307,7 @@ static sv_status run_steps(sv_state *st, Plan &P, void *re, void *im, void *re2,
   if (s) return s;
   const bool dbl = st->dtype == SV_C128;
   int occ = svk_sweep_occupancy(dbl, P.M, P.R, P.NS);
+  int occk = P.NS == 1 ? svk_sweep_kron_occupancy(dbl, P.M, P.R) : 0;
   for (Step &stp : P.steps) {
     if (stp.kind == 0) {
       SweepArgs a = stp.sa;
@@ -1106,11 +1316,23 @@ static sv_status run_steps(sv_state *st, Plan &P, void *re, void *im, void *re2,
       a.ops = P.d_ops;
       a.coef = P.d_coef;
       a.gpart = gpart;
-      int64_t g = (int64_t)di.cus * occ;
+      const bool lean = stp.all_kron && P.NS == 1 && occk > 0;
+      int64_t g = (int64_t)di.cus * (lean ? occk : occ);
       if (grid_override > 0) g = grid_override;
       if (g > a.ntiles) g = a.ntiles;
-      hipError_t e = svk_launch_sweep(dbl, P.M, P.R, P.NS, a, (int)g, st->stream);
+      hipEvent_t e0 = nullptr, e1 = nullptr;
+      if (st->timing && P.NS == 1) {
+        e0 = next_event(st);
+        e1 = next_event(st);
+        if (e0) (void)hipEventRecord(e0, st->stream);
+      }
+      hipError_t e = lean ? svk_launch_sweep_kron(dbl, P.M, P.R, a, (int)g, st->stream)
+                          : svk_launch_sweep(dbl, P.M, P.R, P.NS, a, (int)g, st->stream);
       if (e != hipSuccess) return fail(SV_EDEVICE, "sweep kernel: %s", hipGetErrorString(e));
+      if (e0 && e1) {
+        (void)hipEventRecord(e1, st->stream);
+        st->ev_bytes.push_back(4.0 * (double)((int64_t)1 << st->n) * (double)elem_size(st->dtype));
+      }
     } else {
       GateArgsHost a = stp.ga;
       a.re = re; a.im = im;
@@ -1512,8 +1734,8 @@ extern "C" sv_status sv_fuse_blocks(const sv_op *ops, int32_t n_ops, int32_t wid
 }
 
 extern "C" sv_status sv_plan_stats(int32_t n, const sv_op *ops, int32_t n_ops, int32_t fuse_width,
-                                   int32_t tile_bits, int32_t low_bits, int32_t *n_sweeps,
-                                   int32_t *n_blocks) {
+                                   int32_t tile_bits, int32_t low_bits, int32_t group_bits,
+                                   int32_t *n_sweeps, int32_t *n_blocks) {
   if (n < 1 || n > 34) return fail(SV_EINVAL, "n %d", n);
   if (!(fuse_width == 0 || fuse_width == SV_FUSE_AUTO || (fuse_width >= 2 && fuse_width <= 5)))
     return fail(SV_EINVAL, "fuse_width %d", fuse_width);
@@ -1523,6 +1745,7 @@ extern "C" sv_status sv_plan_stats(int32_t n, const sv_op *ops, int32_t n_ops, i
   Tiling tl = default_tiling(n, SV_C128, 1);
   if (tile_bits) tl.M = tile_bits;
   if (low_bits) tl.c = low_bits;
+  if (group_bits) tl.R = group_bits;
   if (fuse_width > tl.R) tl.R = 5;
   std::vector<GateRec> live;
   for (auto &g : recs)
@@ -1534,9 +1757,9 @@ extern "C" sv_status sv_plan_stats(int32_t n, const sv_op *ops, int32_t n_ops, i
     if (n_blocks) *n_blocks = (int)live.size();
     return SV_OK;
   } else if (fuse_width < 0) {
-    plan_auto(live, n, tl, sweeps, 1e300);
+    plan_auto(live, n, tl, sweeps, 1e300, true);
   } else {
-    plan_fused(live, n, tl, fuse_width, sweeps);
+    plan_fused(live, n, tl, fuse_width, sweeps, true);
   }
   for (auto &sw : sweeps) blocks += (int)sw.stages.size();
   if (n_sweeps) *n_sweeps = (int)sweeps.size();

@@ -44,13 +44,47 @@ struct MicroOp {
   double galpha, gbeta;// MO_GRAD: G = alpha * PauliString + beta * I (on the control subspace)
 };
 
+// Stage kinds.
+//   ST_OPS:  run the micro-op list [op_begin, op_end) on the group.
+//   ST_KRON: the static form  P * s * D_after * (R~_{R-1} (x) ... (x) R~_0) * D_before
+//            with R~_t a rotation on group bit t (present if bit t of rmask) in
+//            fast-Givens form (one coefficient of each row is +-1, so each
+//            output is one FMA; the factored-out scales multiply into s),
+//            D_* diagonal tables of 2^R complex entries (present per dflags bit
+//            0 / 1), s a real scalar (dflags bit 2; otherwise already folded
+//            into D_after) and P folded into st_off.  Coefficients at kcoef:
+//            [R_0 .. R_{R-1}: 4 doubles each][D_before: 2^(R+1)][D_after: 2^(R+1)][s].
+//            Fast-Givens record of R_t: {form, k, scale, 0} with
+//              form 0: x' = x - k y, y' = k x + y      (|c| >= |s|, k = s/c, scale c)
+//              form 1: x' = k x - y, y' = x + k y      (|s| >  |c|, k = c/s, scale s)
+enum { ST_OPS = 0, ST_KRON = 1 };
+
 struct StageDesc {
-  int32_t sbits[SVI_RMAX];     // tile-local bit positions of the group bits (group bit i)
+  int32_t sbits[SVI_RMAX];     // tile-local bit positions of the group bits, ascending
   int32_t op_begin, op_end;    // micro-ops [op_begin, op_end)
+  int32_t kind;                // ST_OPS / ST_KRON
+  uint32_t rmask;              // ST_KRON: group bits carrying a real 2x2
+  int32_t dflags;              // ST_KRON: 1 = D_before, 2 = D_after
+  int32_t kcoef;               // ST_KRON: coefficient offset (doubles)
   int32_t pad;
-  uint16_t ld_off[SVI_GMAX];   // tile-local offset loaded into slot j
-  uint16_t st_off[SVI_GMAX];   // tile-local offset slot j is stored to
+  int32_t ld_off[SVI_GMAX];    // swizzled tile-local BYTE offset loaded into slot j
+  int32_t st_off[SVI_GMAX];    // swizzled tile-local BYTE offset slot j is stored to
 };
+
+// LDS swizzle of a tile-local element index (B = 3 for 16-byte complex
+// elements, 4 for 8-byte ones): xor the low B bits with a fold of the higher
+// bits.  It is linear over GF(2), so for disjoint bit sets
+// swz(a | b) = swz(a) ^ swz(b), which lets offsets be swizzled ahead of time.
+#if defined(__HIP__)
+#define SVI_HD __host__ __device__
+#else
+#define SVI_HD
+#endif
+static inline SVI_HD int svi_swz(int i, int B) {
+  const int msk = (1 << B) - 1;
+  const int h = (i >> B) ^ (i >> (2 * B)) ^ (i >> (3 * B)) ^ (i >> (4 * B));
+  return i ^ (h & msk);
+}
 
 // Per-sweep launch arguments (passed by value).
 struct SweepArgs {
@@ -81,6 +115,21 @@ enum {
   CF_Q4X4 = 4,     // 32 doubles
   CF_D16 = 5,      // 512 doubles (4-target gate)
   CF_COPY = 6,     // copy `len` doubles from the static (user-matrix) area
+  CF_TABLE = 7,    // diagonal table of 2^len complex entries from factors [src, src+pidx[0])
+  CF_IDENT2 = 8,   // 2x2 real identity (4 doubles)
+  CF_FASTR = 9,    // fast-Givens record {form, k, scale, 0} of a real 1q gate
+  CF_SCALE = 10,   // real scalar: product of the fast-Givens scales of factors [src, +pidx[0])
+};
+
+// One factor of a diagonal table: entry j is multiplied, when (j & cm) == cv,
+// by -1 (neg = 1), by the diagonal entry d0 / d1 of gate `kind` chosen by the
+// parity of j & mask (neg = 0), or -- for every entry -- by the fast-Givens
+// scale of the real 1q gate `kind` (neg = 2).
+struct TabFactor {
+  int32_t kind;
+  int32_t pidx;
+  uint32_t mask, cm, cv;
+  int32_t neg;
 };
 #define CF_DAGGER 0x100
 

@@ -1,579 +1,13 @@
-// gfx950 kernels of the state-vector library.
-//
-// State layout in HBM: two planes (re, im) of 2^n elements (double for
-// complex128, float for complex64).  Gate action follows the paper's gather /
-// multiply / scatter over the amplitudes that differ only on the targets
-// (Section 5.3), but indices are computed by bit insertion instead of an index
-// table, and many gates are applied per HBM round trip (see sv_internal.h).
+// gfx950 kernels of the state-vector library (everything except the tile
+// sweep variants, which live in sv_sweep_variant.hip and are compiled once per
+// variant).
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
-#include "sv_internal.h"
+#include "sv_device.h"
 
 namespace {
-
-template <typename T> struct C2T;
-template <> struct C2T<double> { using type = double2; };
-template <> struct C2T<float> { using type = float2; };
-
-template <typename T> struct V4T;   // 16-byte global vector of T
-template <> struct V4T<double> { using type = double2; static constexpr int N = 2; };
-template <> struct V4T<float> { using type = float4; static constexpr int N = 4; };
-
-// LDS swizzle: xor the low B bits of the element index with a fold of its
-// higher bits, so that lanes whose indices differ only in higher bits land in
-// different banks.  Bijective because the higher bits are unchanged.
-template <typename T>
-__device__ __forceinline__ int swz(int i) {
-  constexpr int B = sizeof(T) == 8 ? 3 : 4;
-  constexpr int MSK = (1 << B) - 1;
-  int h = (i >> B) ^ (i >> (2 * B)) ^ (i >> (3 * B)) ^ (i >> (4 * B));
-  return i ^ (h & MSK);
-}
-
-// Insert a zero bit at each position of pos[0..np) (ascending).
-__device__ __forceinline__ uint64_t insert_zeros64(uint64_t x, const int32_t *pos, int np) {
-  for (int k = 0; k < np; k++) {
-    const int p = pos[k];
-    const uint64_t lo = x & ((1ull << p) - 1ull);
-    x = ((x >> p) << (p + 1)) | lo;
-  }
-  return x;
-}
-
-__device__ __forceinline__ int insert_zeros32(int x, const int32_t *pos, int np) {
-  for (int k = 0; k < np; k++) {
-    const int p = pos[k];
-    const int lo = x & ((1 << p) - 1);
-    x = ((x >> p) << (p + 1)) | lo;
-  }
-  return x;
-}
-
-// Global offset of tile row r: bit k of r goes to qubit hb[k].
-__device__ __forceinline__ uint64_t spread_row(int r, const int32_t *hb, int nh) {
-  uint64_t o = 0;
-  for (int k = 0; k < nh; k++) o |= (uint64_t)((r >> k) & 1) << hb[k];
-  return o;
-}
-
-// Base index of tile `tile`: zeros inserted at the tile's qubits (0..c-1 and hb).
-__device__ __forceinline__ uint64_t tile_base(int64_t tile, int c, const int32_t *hb, int nh) {
-  uint64_t x = (uint64_t)tile << c;
-  return insert_zeros64(x, hb, nh);
-}
-
-// ------------------------------------------------------------ micro-ops
-// All group arrays are indexed with compile-time indices only.
-
-template <typename T, int R, int TB>
-__device__ __forceinline__ void mo_u(T *re, T *im, const double *cf, uint32_t cm, uint32_t cv) {
-  const T a0r = (T)cf[0], a0i = (T)cf[1], a1r = (T)cf[2], a1i = (T)cf[3];
-  const T b0r = (T)cf[4], b0i = (T)cf[5], b1r = (T)cf[6], b1i = (T)cf[7];
-  if (cm == 0) {
-#pragma unroll
-    for (int j = 0; j < (1 << R); j++) {
-      if (j & (1 << TB)) continue;
-      const int k = j | (1 << TB);
-      const T xr = re[j], xi = im[j], yr = re[k], yi = im[k];
-      re[j] = a0r * xr - a0i * xi + a1r * yr - a1i * yi;
-      im[j] = a0r * xi + a0i * xr + a1r * yi + a1i * yr;
-      re[k] = b0r * xr - b0i * xi + b1r * yr - b1i * yi;
-      im[k] = b0r * xi + b0i * xr + b1r * yi + b1i * yr;
-    }
-  } else {
-#pragma unroll
-    for (int j = 0; j < (1 << R); j++) {
-      if (j & (1 << TB)) continue;
-      if ((j & cm) != cv) continue;
-      const int k = j | (1 << TB);
-      const T xr = re[j], xi = im[j], yr = re[k], yi = im[k];
-      re[j] = a0r * xr - a0i * xi + a1r * yr - a1i * yi;
-      im[j] = a0r * xi + a0i * xr + a1r * yi + a1i * yr;
-      re[k] = b0r * xr - b0i * xi + b1r * yr - b1i * yi;
-      im[k] = b0r * xi + b0i * xr + b1r * yi + b1i * yr;
-    }
-  }
-}
-
-template <typename T, int R, int TB>
-__device__ __forceinline__ void mo_r(T *re, T *im, const double *cf, uint32_t cm, uint32_t cv) {
-  const T r00 = (T)cf[0], r01 = (T)cf[1], r10 = (T)cf[2], r11 = (T)cf[3];
-  if (cm == 0) {
-#pragma unroll
-    for (int j = 0; j < (1 << R); j++) {
-      if (j & (1 << TB)) continue;
-      const int k = j | (1 << TB);
-      const T xr = re[j], xi = im[j], yr = re[k], yi = im[k];
-      re[j] = r00 * xr + r01 * yr;
-      im[j] = r00 * xi + r01 * yi;
-      re[k] = r10 * xr + r11 * yr;
-      im[k] = r10 * xi + r11 * yi;
-    }
-  } else {
-#pragma unroll
-    for (int j = 0; j < (1 << R); j++) {
-      if (j & (1 << TB)) continue;
-      if ((j & cm) != cv) continue;
-      const int k = j | (1 << TB);
-      const T xr = re[j], xi = im[j], yr = re[k], yi = im[k];
-      re[j] = r00 * xr + r01 * yr;
-      im[j] = r00 * xi + r01 * yi;
-      re[k] = r10 * xr + r11 * yr;
-      im[k] = r10 * xi + r11 * yi;
-    }
-  }
-}
-
-template <typename T, int R>
-__device__ __forceinline__ void mo_p(T *re, T *im, const double *cf, uint32_t mask, uint32_t cm,
-                                     uint32_t cv) {
-  const T d0r = (T)cf[0], d0i = (T)cf[1], d1r = (T)cf[2], d1i = (T)cf[3];
-#pragma unroll
-  for (int j = 0; j < (1 << R); j++) {
-    if ((j & cm) != cv) continue;
-    const bool odd = __builtin_popcount((uint32_t)j & mask) & 1;
-    const T dr = odd ? d1r : d0r;
-    const T di = odd ? d1i : d0i;
-    const T xr = re[j], xi = im[j];
-    re[j] = xr * dr - xi * di;
-    im[j] = xr * di + xi * dr;
-  }
-}
-
-template <typename T, int R, int TB>
-__device__ __forceinline__ void mo_x(T *re, T *im, uint32_t cm, uint32_t cv) {
-#pragma unroll
-  for (int j = 0; j < (1 << R); j++) {
-    if (j & (1 << TB)) continue;
-    if ((j & cm) != cv) continue;
-    const int k = j | (1 << TB);
-    T t = re[j]; re[j] = re[k]; re[k] = t;
-    t = im[j]; im[j] = im[k]; im[k] = t;
-  }
-}
-
-template <typename T, int R, int A, int B>
-__device__ __forceinline__ void mo_swap(T *re, T *im, uint32_t cm, uint32_t cv) {
-#pragma unroll
-  for (int j = 0; j < (1 << R); j++) {
-    if (!((j >> A) & 1) || ((j >> B) & 1)) continue;
-    if ((j & cm) != cv) continue;
-    const int k = j ^ (1 << A) ^ (1 << B);
-    T t = re[j]; re[j] = re[k]; re[k] = t;
-    t = im[j]; im[j] = im[k]; im[k] = t;
-  }
-}
-
-template <typename T, int R>
-__device__ __forceinline__ void mo_neg(T *re, T *im, uint32_t cm, uint32_t cv) {
-#pragma unroll
-  for (int j = 0; j < (1 << R); j++) {
-    if ((j & cm) != cv) continue;
-    re[j] = -re[j];
-    im[j] = -im[j];
-  }
-}
-
-// 4x4 on (bit A = low local bit, bit B = high local bit).
-template <typename T, int R, int A, int B>
-__device__ __forceinline__ void mo_q(T *re, T *im, const double *cf, uint32_t cm, uint32_t cv) {
-  T u[32];
-#pragma unroll
-  for (int q = 0; q < 32; q++) u[q] = (T)cf[q];
-#pragma unroll
-  for (int j = 0; j < (1 << R); j++) {
-    if ((j >> A) & 1) continue;
-    if ((j >> B) & 1) continue;
-    if ((j & cm) != cv) continue;
-    constexpr int a1 = 1 << A, b1 = 1 << B;
-    const T x0r = re[j], x0i = im[j], x1r = re[j | a1], x1i = im[j | a1];
-    const T x2r = re[j | b1], x2i = im[j | b1], x3r = re[j | a1 | b1], x3i = im[j | a1 | b1];
-#define SVI_ROW(r, dst)                                                                   \
-    {                                                                                     \
-      const T ar = u[8 * r + 0] * x0r - u[8 * r + 1] * x0i + u[8 * r + 2] * x1r -         \
-                   u[8 * r + 3] * x1i + u[8 * r + 4] * x2r - u[8 * r + 5] * x2i +         \
-                   u[8 * r + 6] * x3r - u[8 * r + 7] * x3i;                               \
-      const T ai = u[8 * r + 0] * x0i + u[8 * r + 1] * x0r + u[8 * r + 2] * x1i +         \
-                   u[8 * r + 3] * x1r + u[8 * r + 4] * x2i + u[8 * r + 5] * x2r +         \
-                   u[8 * r + 6] * x3i + u[8 * r + 7] * x3r;                               \
-      re[dst] = ar;                                                                       \
-      im[dst] = ai;                                                                       \
-    }
-    SVI_ROW(0, j) SVI_ROW(1, j | a1) SVI_ROW(2, j | b1) SVI_ROW(3, j | a1 | b1)
-#undef SVI_ROW
-  }
-}
-
-// Real rotation between the two local patterns of a two-level subspace:
-// for every j with (j & tm) == pa, partner k = j ^ XM:
-//   (x_j, x_k) <- (r00 x_j + r01 x_k, r10 x_j + r11 x_k).
-template <typename T, int R, int XM>
-__device__ __forceinline__ void mo_2l(T *re, T *im, const double *cf, uint32_t tm, uint32_t pa,
-                                      uint32_t cm, uint32_t cv) {
-  const T r00 = (T)cf[0], r01 = (T)cf[1], r10 = (T)cf[2], r11 = (T)cf[3];
-#pragma unroll
-  for (int j = 0; j < (1 << R); j++) {
-    if (((uint32_t)j & tm) != pa) continue;
-    if ((j & cm) != cv) continue;
-    const int k = j ^ XM;
-    const T xr = re[j], xi = im[j], yr = re[k], yi = im[k];
-    re[j] = r00 * xr + r01 * yr;
-    im[j] = r00 * xi + r01 * yi;
-    re[k] = r10 * xr + r11 * yr;
-    im[k] = r10 * xi + r11 * yi;
-  }
-}
-
-// 2^K x 2^K on group bits 0..K-1.
-template <typename T, int R, int K>
-__device__ __forceinline__ void mo_dense(T *re, T *im, const double *cf, uint32_t cm,
-                                         uint32_t cv) {
-  constexpr int D = 1 << K;
-#pragma clang loop unroll(full)
-  for (int o = 0; o < (1 << (R - K)); o++) {
-    const int base = o << K;
-    if ((base & cm) != cv) continue;
-    T xr[D], xi[D];
-#pragma unroll
-    for (int q = 0; q < D; q++) { xr[q] = re[base + q]; xi[q] = im[base + q]; }
-#pragma unroll
-    for (int r = 0; r < D; r++) {
-      T ar = 0, ai = 0;
-#pragma unroll
-      for (int q = 0; q < D; q++) {
-        const T ur = (T)cf[(r * D + q) * 2], ui = (T)cf[(r * D + q) * 2 + 1];
-        ar += ur * xr[q] - ui * xi[q];
-        ai += ur * xi[q] + ui * xr[q];
-      }
-      re[base + r] = ar;
-      im[base + r] = ai;
-    }
-  }
-}
-
-template <typename T, int R>
-__device__ __forceinline__ void mo_diagt(T *re, T *im, const double *cf) {
-#pragma unroll
-  for (int j = 0; j < (1 << R); j++) {
-    const T dr = (T)cf[2 * j], di = (T)cf[2 * j + 1];
-    const T xr = re[j], xi = im[j];
-    re[j] = xr * dr - xi * di;
-    im[j] = xr * di + xi * dr;
-  }
-}
-
-// Im <lam| G |psi> over one group, G = alpha * (Pauli string x,z) + beta * I
-// on the control subspace.  XM is the compile-time x-mask (group bits).
-template <typename T, int R, int XM>
-__device__ __forceinline__ double mo_grad(const T *pr, const T *pi, const T *lr, const T *li,
-                                          uint32_t z, uint32_t cm, uint32_t cv, double alpha,
-                                          double beta) {
-  const int ny = __builtin_popcount((uint32_t)XM & z) & 3;
-  double acc = 0.0;
-#pragma unroll
-  for (int j = 0; j < (1 << R); j++) {
-    if ((j & cm) != cv) continue;
-    const int k = j ^ XM;
-    // (P psi)_j = i^ny (-1)^{popcount(k & z)} psi_k
-    const bool neg = __builtin_popcount((uint32_t)k & z) & 1;
-    double wr = (double)pr[k], wi = (double)pi[k];
-    double tr, ti;
-    switch (ny) {
-      case 0: tr = wr; ti = wi; break;
-      case 1: tr = -wi; ti = wr; break;
-      case 2: tr = -wr; ti = -wi; break;
-      default: tr = wi; ti = -wr; break;
-    }
-    if (neg) { tr = -tr; ti = -ti; }
-    const double gr = alpha * tr + beta * (double)pr[j];
-    const double gi = alpha * ti + beta * (double)pi[j];
-    // Im(conj(l) * g) = lr*gi - li*gr
-    acc += (double)lr[j] * gi - (double)li[j] * gr;
-  }
-  return acc;
-}
-
-#define SVI_T5(F, t, ...)                                   \
-  switch (t) {                                              \
-    case 0: F<T, R, 0>(__VA_ARGS__); break;                 \
-    case 1: F<T, R, 1>(__VA_ARGS__); break;                 \
-    case 2: if constexpr (R > 2) F<T, R, 2>(__VA_ARGS__); break; \
-    case 3: if constexpr (R > 3) F<T, R, 3>(__VA_ARGS__); break; \
-    case 4: if constexpr (R > 4) F<T, R, 4>(__VA_ARGS__); break; \
-    default: break;                                         \
-  }
-
-template <typename T, int R>
-__device__ __forceinline__ void dispatch_swap(int a, int b, T *re, T *im, uint32_t cm, uint32_t cv) {
-#define SVI_SW(A, B) if (a == A && b == B) { if constexpr (A < R && B < R) mo_swap<T, R, A, B>(re, im, cm, cv); return; }
-  SVI_SW(0, 1) SVI_SW(0, 2) SVI_SW(0, 3) SVI_SW(0, 4) SVI_SW(1, 0) SVI_SW(1, 2) SVI_SW(1, 3)
-  SVI_SW(1, 4) SVI_SW(2, 0) SVI_SW(2, 1) SVI_SW(2, 3) SVI_SW(2, 4) SVI_SW(3, 0) SVI_SW(3, 1)
-  SVI_SW(3, 2) SVI_SW(3, 4) SVI_SW(4, 0) SVI_SW(4, 1) SVI_SW(4, 2) SVI_SW(4, 3)
-#undef SVI_SW
-}
-
-template <typename T, int R>
-__device__ __forceinline__ void dispatch_q(int a, int b, T *re, T *im, const double *cf,
-                                           uint32_t cm, uint32_t cv) {
-#define SVI_Q(A, B) if (a == A && b == B) { if constexpr (A < R && B < R) mo_q<T, R, A, B>(re, im, cf, cm, cv); return; }
-  SVI_Q(0, 1) SVI_Q(0, 2) SVI_Q(0, 3) SVI_Q(0, 4) SVI_Q(1, 0) SVI_Q(1, 2) SVI_Q(1, 3)
-  SVI_Q(1, 4) SVI_Q(2, 0) SVI_Q(2, 1) SVI_Q(2, 3) SVI_Q(2, 4) SVI_Q(3, 0) SVI_Q(3, 1)
-  SVI_Q(3, 2) SVI_Q(3, 4) SVI_Q(4, 0) SVI_Q(4, 1) SVI_Q(4, 2) SVI_Q(4, 3)
-#undef SVI_Q
-}
-
-template <typename T, int R>
-__device__ __forceinline__ void apply_op(const MicroOp &op, T *re, T *im, const double *coef) {
-  const double *cf = coef + op.coef;
-  switch (op.type) {
-    case MO_U: SVI_T5(mo_u, op.t0, re, im, cf, op.cm, op.cv) break;
-    case MO_R: SVI_T5(mo_r, op.t0, re, im, cf, op.cm, op.cv) break;
-    case MO_P: mo_p<T, R>(re, im, cf, op.mask, op.cm, op.cv); break;
-    case MO_X:
-      switch (op.t0) {
-        case 0: mo_x<T, R, 0>(re, im, op.cm, op.cv); break;
-        case 1: mo_x<T, R, 1>(re, im, op.cm, op.cv); break;
-        case 2: if constexpr (R > 2) mo_x<T, R, 2>(re, im, op.cm, op.cv); break;
-        case 3: if constexpr (R > 3) mo_x<T, R, 3>(re, im, op.cm, op.cv); break;
-        case 4: if constexpr (R > 4) mo_x<T, R, 4>(re, im, op.cm, op.cv); break;
-        default: break;
-      }
-      break;
-    case MO_SWAP: dispatch_swap<T, R>(op.t0, op.t1, re, im, op.cm, op.cv); break;
-    case MO_NEG: mo_neg<T, R>(re, im, op.cm, op.cv); break;
-    case MO_Q: dispatch_q<T, R>(op.t0, op.t1, re, im, cf, op.cm, op.cv); break;
-    case MO_DENSE:
-      switch (op.mask) {
-        case 1: mo_dense<T, R, 1>(re, im, cf, op.cm, op.cv); break;
-        case 2: mo_dense<T, R, 2>(re, im, cf, op.cm, op.cv); break;
-        case 3: if constexpr (R >= 3) mo_dense<T, R, 3>(re, im, cf, op.cm, op.cv); break;
-        default: break;
-      }
-      break;
-    case MO_DIAGT: mo_diagt<T, R>(re, im, cf); break;
-    case MO_2L:
-      switch (op.t1) {
-#define SVI_L(XV) case XV: if constexpr (XV < (1 << R)) mo_2l<T, R, XV>(re, im, cf, op.mask, op.gz, op.cm, op.cv); break;
-        SVI_L(1) SVI_L(2) SVI_L(3) SVI_L(4) SVI_L(5) SVI_L(6) SVI_L(7) SVI_L(8) SVI_L(9) SVI_L(10)
-        SVI_L(11) SVI_L(12) SVI_L(13) SVI_L(14) SVI_L(15) SVI_L(16) SVI_L(17) SVI_L(18) SVI_L(19)
-        SVI_L(20) SVI_L(21) SVI_L(22) SVI_L(23) SVI_L(24) SVI_L(25) SVI_L(26) SVI_L(27) SVI_L(28)
-        SVI_L(29) SVI_L(30) SVI_L(31)
-#undef SVI_L
-        default: break;
-      }
-      break;
-    default: break;
-  }
-}
-
-template <typename T, int R>
-__device__ __forceinline__ double grad_op(const MicroOp &op, const T *pr, const T *pi, const T *lr,
-                                          const T *li) {
-  // op.mask = x-mask (0, one bit, or two bits) over group bits.
-  const uint32_t x = op.mask;
-  switch (x) {
-#define SVI_G(XV) case XV: if constexpr (XV < (1 << R)) return mo_grad<T, R, XV>(pr, pi, lr, li, op.gz, op.cm, op.cv, op.galpha, op.gbeta); break;
-    SVI_G(0) SVI_G(1) SVI_G(2) SVI_G(3) SVI_G(4) SVI_G(5) SVI_G(6) SVI_G(7) SVI_G(8) SVI_G(9)
-    SVI_G(10) SVI_G(11) SVI_G(12) SVI_G(13) SVI_G(14) SVI_G(15) SVI_G(16) SVI_G(17) SVI_G(18)
-    SVI_G(19) SVI_G(20) SVI_G(21) SVI_G(22) SVI_G(23) SVI_G(24) SVI_G(25) SVI_G(26) SVI_G(27)
-    SVI_G(28) SVI_G(29) SVI_G(30) SVI_G(31)
-#undef SVI_G
-    default: break;
-  }
-  return 0.0;
-}
-
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int o = 1; o < 64; o <<= 1) v += __shfl_xor(v, o, 64);
-  return v;
-}
-
-// ------------------------------------------------------------ tile sweep
-// One persistent workgroup loops over tiles.  NS = 1 (forward) or 2 (adjoint:
-// state 0 = psi, state 1 = lambda, micro-ops applied to both, MO_GRAD
-// accumulates gradient partials).
-
-#define SVI_GSLOTS 256
-
-template <typename T, int M, int R, int NS>
-__global__ void __launch_bounds__(1 << (M - R)) k_sweep(SweepArgs a) {
-  constexpr int NT = 1 << (M - R);
-  constexpr int G = 1 << R;
-  constexpr int VN = V4T<T>::N;
-  constexpr int LV = VN == 2 ? 1 : 2;
-  constexpr int NIT = (1 << M) / (VN * NT);   // vector loads per thread per plane (full tile)
-  constexpr int NWAVE = (NT + 63) / 64;
-  using C2 = typename C2T<T>::type;
-  using V4 = typename V4T<T>::type;
-  __shared__ C2 lds[NS][1 << M];
-  __shared__ double wsum[NS == 2 ? NWAVE : 1][NS == 2 ? SVI_GSLOTS : 1];
-  __shared__ double gacc[NS == 2 ? SVI_GSLOTS : 1];
-  __shared__ int32_t hb_s[SVI_MMAX];
-
-  const int tid = threadIdx.x;
-  const int m = a.m, c = a.c, nh = a.nh;
-  const int mm = m > R ? m : R;              // tile bits including phantom padding
-  const int ntile_el = 1 << m;               // real amplitudes per tile
-  const int ngroups = 1 << (mm - R);
-  const bool vec = c >= LV;                  // rows hold whole 16-byte vectors
-
-  if (tid < SVI_MMAX) hb_s[tid] = a.hb[tid < nh ? tid : 0];
-  if constexpr (NS == 2) {
-    for (int s = tid; s < SVI_GSLOTS; s += NT) gacc[s] = 0.0;
-  }
-  __syncthreads();
-
-  // Row offsets of this thread's elements, the same for every tile.
-  uint64_t roff[NIT];
-#pragma unroll
-  for (int k = 0; k < NIT; k++) {
-    const int i = (tid + k * NT) * (vec ? VN : 1);
-    roff[k] = spread_row(i >> c, hb_s, nh) + (uint64_t)(i & ((1 << c) - 1));
-  }
-
-  T *const pre0 = (T *)a.re, *const pim0 = (T *)a.im;
-  T *const pre1 = (T *)a.re2, *const pim1 = (T *)a.im2;
-
-  for (int64_t tile = blockIdx.x; tile < a.ntiles; tile += gridDim.x) {
-    const uint64_t base = tile_base(tile, c, hb_s, nh);
-    // ---- load tile (rows of 2^c contiguous amplitudes) into LDS
-    if (mm > m) {
-      for (int i = tid; i < (1 << mm); i += NT) {
-        lds[0][swz<T>(i)] = C2{0, 0};
-        if constexpr (NS == 2) lds[1][swz<T>(i)] = C2{0, 0};
-      }
-      __syncthreads();
-    }
-#pragma unroll
-    for (int s = 0; s < NS; s++) {
-      const T *pr = s == 0 ? pre0 : pre1;
-      const T *pi = s == 0 ? pim0 : pim1;
-      if (s == 0 && (a.flags & SW_INIT_ZERO)) {
-        for (int i = tid; i < ntile_el; i += NT) {
-          const T v = (base == 0 && i == 0) ? (T)1 : (T)0;
-          lds[0][swz<T>(i)] = C2{v, 0};
-        }
-      } else if (vec) {
-#pragma unroll
-        for (int k = 0; k < NIT; k++) {
-          const int i = (tid + k * NT) * VN;
-          if (i < ntile_el) {
-            const uint64_t g = base + roff[k];
-            const V4 vr = *(const V4 *)(pr + g);
-            const V4 vi = *(const V4 *)(pi + g);
-            if constexpr (VN == 2) {
-              lds[s][swz<T>(i)] = C2{vr.x, vi.x};
-              lds[s][swz<T>(i + 1)] = C2{vr.y, vi.y};
-            } else {
-              lds[s][swz<T>(i)] = C2{vr.x, vi.x};
-              lds[s][swz<T>(i + 1)] = C2{vr.y, vi.y};
-              lds[s][swz<T>(i + 2)] = C2{vr.z, vi.z};
-              lds[s][swz<T>(i + 3)] = C2{vr.w, vi.w};
-            }
-          }
-        }
-      } else {
-        for (int i = tid; i < ntile_el; i += NT) {
-          const uint64_t g = base + spread_row(i >> c, hb_s, nh) + (uint64_t)(i & ((1 << c) - 1));
-          lds[s][swz<T>(i)] = C2{pr[g], pi[g]};
-        }
-      }
-    }
-    __syncthreads();
-
-    // ---- stages
-    for (int st = a.stage_begin; st < a.stage_end; st++) {
-      const StageDesc &sd = a.stages[st];
-      // Every thread runs the stage (keeps wave shuffles uniform).  Threads
-      // beyond the tile's groups work on LDS slots above 2^mm, which are
-      // never written back.
-      const bool active = tid < ngroups;
-      const int gb = insert_zeros32(tid, sd.sbits, R);
-      T re[NS][G], im[NS][G];
-#pragma unroll
-      for (int s = 0; s < NS; s++) {
-#pragma unroll
-        for (int j = 0; j < G; j++) {
-          const C2 v = lds[s][swz<T>(gb + sd.ld_off[j])];
-          re[s][j] = v.x;
-          im[s][j] = v.y;
-        }
-      }
-      for (int o = sd.op_begin; o < sd.op_end; o++) {
-        const MicroOp op = a.ops[o];
-        if constexpr (NS == 2) {
-          if (op.type == MO_GRAD) {
-            double v = active ? grad_op<T, R>(op, re[0], im[0], re[1], im[1]) : 0.0;
-            v = wave_sum(v);
-            if ((tid & 63) == 0) wsum[tid >> 6][op.coef] = v;
-            continue;
-          }
-        }
-        apply_op<T, R>(op, re[0], im[0], a.coef);
-        if constexpr (NS == 2) apply_op<T, R>(op, re[1], im[1], a.coef);
-      }
-#pragma unroll
-      for (int s = 0; s < NS; s++) {
-#pragma unroll
-        for (int j = 0; j < G; j++) lds[s][swz<T>(gb + sd.st_off[j])] = C2{re[s][j], im[s][j]};
-      }
-      __syncthreads();
-    }
-
-    if constexpr (NS == 2) {
-      // fold this tile's per-wave sums into the workgroup accumulators
-      for (int s = tid; s < a.n_gslots; s += NT) {
-        double v = 0.0;
-        for (int w = 0; w < NWAVE; w++) v += wsum[w][s];
-        gacc[s] += v;
-      }
-    }
-
-    // ---- store tile
-#pragma unroll
-    for (int s = 0; s < NS; s++) {
-      T *pr = s == 0 ? pre0 : pre1;
-      T *pi = s == 0 ? pim0 : pim1;
-      if (vec) {
-#pragma unroll
-        for (int k = 0; k < NIT; k++) {
-          const int i = (tid + k * NT) * VN;
-          if (i < ntile_el) {
-            const uint64_t g = base + roff[k];
-            V4 vr, vi;
-            if constexpr (VN == 2) {
-              const C2 p0 = lds[s][swz<T>(i)], p1 = lds[s][swz<T>(i + 1)];
-              vr = V4{p0.x, p1.x};
-              vi = V4{p0.y, p1.y};
-            } else {
-              const C2 p0 = lds[s][swz<T>(i)], p1 = lds[s][swz<T>(i + 1)];
-              const C2 p2 = lds[s][swz<T>(i + 2)], p3 = lds[s][swz<T>(i + 3)];
-              vr = V4{p0.x, p1.x, p2.x, p3.x};
-              vi = V4{p0.y, p1.y, p2.y, p3.y};
-            }
-            *(V4 *)(pr + g) = vr;
-            *(V4 *)(pi + g) = vi;
-          }
-        }
-      } else {
-        for (int i = tid; i < ntile_el; i += NT) {
-          const uint64_t g = base + spread_row(i >> c, hb_s, nh) + (uint64_t)(i & ((1 << c) - 1));
-          const C2 p = lds[s][swz<T>(i)];
-          pr[g] = p.x;
-          pi[g] = p.y;
-        }
-      }
-    }
-    __syncthreads();
-  }
-
-  if constexpr (NS == 2) {
-    for (int s = tid; s < a.n_gslots; s += NT)
-      a.gpart[(int64_t)(a.gslot_begin + s) * gridDim.x + blockIdx.x] = gacc[s];
-  }
-}
+using namespace svk;
 
 // ------------------------------------------------- single-gate sweeps
 // One work item per group of amplitudes that the gate mixes; the control
@@ -722,8 +156,27 @@ __device__ void gate_local(int kind, const double *th, double *m /* interleaved,
   }
 }
 
+// Fast-Givens factorisation of a real orthogonal 2x2 r = [[r0, r1], [r2, r3]]
+// (Gentleman 1973): out = {form, k, scale, 0}, r = scale * (form matrix).
+__device__ void fast_givens(const double *r, double *out) {
+  // rotation [[c,-s],[s,c]] vs reflection [[a,b],[b,-a]]
+  const bool rot = fabs(r[0] - r[3]) + fabs(r[1] + r[2]) <= fabs(r[0] + r[3]) + fabs(r[1] - r[2]);
+  if (rot) {
+    // [[c, -s], [s, c]]
+    const double c = r[0], s = r[2];
+    if (fabs(c) >= fabs(s)) { out[0] = 0; out[1] = s / c; out[2] = c; }
+    else { out[0] = 1; out[1] = c / s; out[2] = s; }
+  } else {
+    // [[a, b], [b, -a]]
+    const double a = r[0], b = r[1];
+    if (fabs(a) >= fabs(b)) { out[0] = 2; out[1] = b / a; out[2] = a; }
+    else { out[0] = 3; out[1] = a / b; out[2] = b; }
+  }
+  out[3] = 0.0;
+}
+
 __global__ void k_build_coefs(const CoefDesc *d, int nd, const double *params, const double *statics,
-                              double *coef) {
+                              const TabFactor *fac, double *coef) {
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nd; i += gridDim.x * blockDim.x) {
     const CoefDesc cd = d[i];
     const int fmt = cd.fmt & 0xff;
@@ -732,7 +185,55 @@ __global__ void k_build_coefs(const CoefDesc *d, int nd, const double *params, c
     for (int k = 0; k < 3; k++)
       if (cd.pidx[k] >= 0) th[k] = params[cd.pidx[k]];
     double *out = coef + cd.dst;
-    if (fmt == CF_U2X2 || fmt == CF_R2X2 || fmt == CF_DIAG) {
+    if (fmt == CF_FASTR) {
+      double m[8];
+      gate_local(cd.kind, th, m);
+      double r[4] = {m[0], m[2], m[4], m[6]};   // real 2x2
+      if (dag) { const double t = r[1]; r[1] = r[2]; r[2] = t; }
+      fast_givens(r, out);
+    } else if (fmt == CF_SCALE) {
+      double sc = 1.0;
+      for (int f = cd.src; f < cd.src + cd.pidx[0]; f++) {
+        const TabFactor tf = fac[f];
+        double m[8], rec[4];
+        double tt[3] = {tf.pidx >= 0 ? params[tf.pidx] : 0.0, 0.0, 0.0};
+        gate_local(tf.kind, tt, m);
+        double r[4] = {m[0], m[2], m[4], m[6]};
+        fast_givens(r, rec);
+        sc *= rec[2];
+      }
+      out[0] = sc;
+    } else if (fmt == CF_IDENT2) {
+      out[0] = 1.0; out[1] = 0.0; out[2] = 0.0; out[3] = 1.0;
+    } else if (fmt == CF_TABLE) {
+      const int G = 1 << cd.len;
+      for (int j = 0; j < G; j++) { out[2 * j] = 1.0; out[2 * j + 1] = 0.0; }
+      for (int f = cd.src; f < cd.src + cd.pidx[0]; f++) {
+        const TabFactor tf = fac[f];
+        double m[8];
+        double tt[3] = {tf.pidx >= 0 ? params[tf.pidx] : 0.0, 0.0, 0.0};
+        gate_local(tf.kind, tt, m);
+        double gsc = 1.0;
+        if (tf.neg == 2) {
+          double r[4] = {m[0], m[2], m[4], m[6]}, rec[4];
+          fast_givens(r, rec);
+          gsc = rec[2];
+        }
+        for (int j = 0; j < G; j++) {
+          if (((uint32_t)j & tf.cm) != tf.cv) continue;
+          double dr, di;
+          if (tf.neg == 2) { dr = gsc; di = 0.0; }
+          else if (tf.neg) { dr = -1.0; di = 0.0; }
+          else if (__builtin_popcount((uint32_t)j & tf.mask) & 1) { dr = m[6]; di = m[7]; }
+          else { dr = m[0]; di = m[1]; }
+          const double xr = out[2 * j], xi = out[2 * j + 1];
+          out[2 * j] = xr * dr - xi * di;
+          out[2 * j + 1] = xr * di + xi * dr;
+        }
+      }
+      if (dag)
+        for (int j = 0; j < G; j++) out[2 * j + 1] = -out[2 * j + 1];
+    } else if (fmt == CF_U2X2 || fmt == CF_R2X2 || fmt == CF_DIAG) {
       double m[8];
       gate_local(cd.kind, th, m);
       if (dag) {
@@ -1078,38 +579,41 @@ __global__ void __launch_bounds__(256) k_sample(SampleArgs a) {
 
 #include "sv_launch.h"
 
-template <typename T, int M, int R, int NS>
-static hipError_t launch_sweep_t(const SweepArgs &a, int grid, hipStream_t s) {
-  hipLaunchKernelGGL((k_sweep<T, M, R, NS>), dim3(grid), dim3(1 << (M - R)), 0, s, a);
-  return hipGetLastError();
+// Sweep variants, one translation unit each (sv_sweep_variant.hip).
+#include "sv_variants.h"
+
+#define X(T, MM, RR, NN)                                                       \
+  hipError_t SVI_VNAME(launch, T, MM, RR, NN)(const SweepArgs &, int, hipStream_t); \
+  int SVI_VNAME(occ, T, MM, RR, NN)();                                            \
+  hipError_t SVI_VNAME(launchk, T, MM, RR, NN)(const SweepArgs &, int, hipStream_t); \
+  int SVI_VNAME(occk, T, MM, RR, NN)();
+SVI_VARIANTS(X)
+#undef X
+
+hipError_t svk_launch_sweep_kron(int dbl, int M, int R, const SweepArgs &a, int grid,
+                                 hipStream_t s) {
+#define X(T, MM, RR, NN)                                                        \
+  if (NN == 1 && (dbl == (sizeof(T) == 8)) && M == MM && R == RR)               \
+    return SVI_VNAME(launchk, T, MM, RR, NN)(a, grid, s);
+  SVI_VARIANTS(X)
+#undef X
+  return hipErrorInvalidValue;
 }
 
-template <typename T, int M, int R, int NS>
-static int occ_sweep_t() {
-  int nb = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_sweep<T, M, R, NS>, 1 << (M - R), 0) !=
-      hipSuccess)
-    return 1;
-  return nb > 0 ? nb : 1;
+int svk_sweep_kron_occupancy(int dbl, int M, int R) {
+#define X(T, MM, RR, NN)                                                        \
+  if (NN == 1 && (dbl == (sizeof(T) == 8)) && M == MM && R == RR)               \
+    return SVI_VNAME(occk, T, MM, RR, NN)();
+  SVI_VARIANTS(X)
+#undef X
+  return 0;
 }
-
-#define SVI_VARIANTS(X)      \
-  X(double, 13, 5, 1)        \
-  X(double, 12, 5, 1)        \
-  X(double, 13, 4, 1)        \
-  X(double, 12, 4, 1)        \
-  X(double, 11, 5, 1)        \
-  X(double, 12, 4, 2)        \
-  X(double, 11, 4, 2)        \
-  X(float, 14, 5, 1)         \
-  X(float, 13, 5, 1)         \
-  X(float, 13, 4, 2)
 
 hipError_t svk_launch_sweep(int dbl, int M, int R, int NS, const SweepArgs &a, int grid,
                             hipStream_t s) {
 #define X(T, MM, RR, NN)                                                        \
   if ((dbl == (sizeof(T) == 8)) && M == MM && R == RR && NS == NN)              \
-    return launch_sweep_t<T, MM, RR, NN>(a, grid, s);
+    return SVI_VNAME(launch, T, MM, RR, NN)(a, grid, s);
   SVI_VARIANTS(X)
 #undef X
   return hipErrorInvalidValue;
@@ -1118,7 +622,7 @@ hipError_t svk_launch_sweep(int dbl, int M, int R, int NS, const SweepArgs &a, i
 int svk_sweep_occupancy(int dbl, int M, int R, int NS) {
 #define X(T, MM, RR, NN)                                                        \
   if ((dbl == (sizeof(T) == 8)) && M == MM && R == RR && NS == NN)              \
-    return occ_sweep_t<T, MM, RR, NN>();
+    return SVI_VNAME(occ, T, MM, RR, NN)();
   SVI_VARIANTS(X)
 #undef X
   return 0;
@@ -1155,10 +659,10 @@ hipError_t svk_launch_init_zero(int dbl, void *re, void *im, int64_t n, hipStrea
 }
 
 hipError_t svk_launch_coefs(const CoefDesc *d, int nd, const double *params, const double *statics,
-                            double *coef, hipStream_t s) {
+                            const TabFactor *fac, double *coef, hipStream_t s) {
   if (nd <= 0) return hipSuccess;
   int grid = (nd + 127) / 128;
-  hipLaunchKernelGGL(k_build_coefs, dim3(grid), dim3(128), 0, s, d, nd, params, statics, coef);
+  hipLaunchKernelGGL(k_build_coefs, dim3(grid), dim3(128), 0, s, d, nd, params, statics, fac, coef);
   return hipGetLastError();
 }
 

@@ -20,11 +20,15 @@ struct GateArgsHost {
 hipError_t svk_launch_sweep(int dbl, int M, int R, int NS, const SweepArgs &a, int grid,
                             hipStream_t s);
 int svk_sweep_occupancy(int dbl, int M, int R, int NS);
+hipError_t svk_launch_sweep_kron(int dbl, int M, int R, const SweepArgs &a, int grid,
+                                 hipStream_t s);
+int svk_sweep_kron_occupancy(int dbl, int M, int R);
 int svk_has_sweep(int dbl, int M, int R, int NS);
 hipError_t svk_launch_gate(int dbl, const GateArgsHost &a, hipStream_t s);
 hipError_t svk_launch_init_zero(int dbl, void *re, void *im, int64_t n, hipStream_t s);
 hipError_t svk_launch_coefs(const CoefDesc *d, int nd, const double *params,
-                            const double *statics, double *coef, hipStream_t s);
+                            const double *statics, const TabFactor *fac, double *coef,
+                            hipStream_t s);
 hipError_t svk_launch_pauli(int dbl, int M, const PauliPassArgs &a, int grid, hipStream_t s);
 int svk_pauli_occupancy(int dbl);
 hipError_t svk_launch_reduce_rows(const double *part, int nslots, int np, double *out,
@@ -39,3 +43,4 @@ hipError_t svk_launch_sampling(int dbl, const void *re, const void *im, int n, d
 
 #define SVI_GSLOTS_MAX 256
 #define SVI_PTERMS_MAX 64
+#define SVI_KMAX_STAGES_HOST 16

@@ -1,0 +1,20 @@
+// The tile-sweep kernel instantiations: (element type, tile bits M, register
+// group bits R, number of states NS).  Each is compiled in its own translation
+// unit (sv_sweep_variant.hip with -DSVI_V=<index>).
+#pragma once
+
+#define SVI_VARIANTS(X)      \
+  X(double, 13, 5, 1)        \
+  X(double, 12, 5, 1)        \
+  X(double, 13, 4, 1)        \
+  X(double, 12, 4, 1)        \
+  X(double, 11, 5, 1)        \
+  X(double, 12, 4, 2)        \
+  X(double, 11, 4, 2)        \
+  X(float, 14, 5, 1)         \
+  X(float, 13, 5, 1)         \
+  X(float, 13, 4, 2)
+
+#define SVI_NVARIANTS 10
+#define SVI_VCAT(a, b, c, d, e, f) svk_##a##_##b##_##c##_##d##_##e##f
+#define SVI_VNAME(what, T, M, R, NS) SVI_VCAT(what, T, M, R, NS, _v)

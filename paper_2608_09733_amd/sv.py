@@ -75,10 +75,13 @@ def lib():
         "sv_copy_to_host": (C.c_int, [vp, vp, vp, u64, u64]),
         "sv_copy_from_host": (C.c_int, [vp, vp, vp, u64, u64]),
         "sv_last_error": (C.c_char_p, []),
-        "sv_plan_stats": (C.c_int, [i32, opp, i32, i32, i32, i32, C.POINTER(i32), C.POINTER(i32)]),
-        "sv_set_tiling": (C.c_int, [vp, i32, i32]),
+        "sv_plan_stats": (C.c_int, [i32, opp, i32, i32, i32, i32, i32, C.POINTER(i32),
+                                    C.POINTER(i32)]),
+        "sv_set_tiling": (C.c_int, [vp, i32, i32, i32]),
         "sv_fuse_blocks": (C.c_int, [opp, i32, i32, C.POINTER(i32), C.POINTER(i32)]),
         "sv_version": (C.c_char_p, []),
+        "sv_timing_enable": (C.c_int, [vp, i32]),
+        "sv_timing_read": (C.c_int, [vp, dp, C.POINTER(i64), dp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -194,11 +197,22 @@ class State:
         self.stream = stream
         _check(lib().sv_set_stream(self.h, C.c_void_p(_stream_ptr(stream))))
 
-    def set_tiling(self, tile_bits: int = 0, low_bits: int = 0):
-        _check(lib().sv_set_tiling(self.h, tile_bits, low_bits))
+    def set_tiling(self, tile_bits: int = 0, low_bits: int = 0, group_bits: int = 0):
+        _check(lib().sv_set_tiling(self.h, tile_bits, low_bits, group_bits))
 
     def reset(self):
         _check(lib().sv_reset(self.h))
+
+    def timing(self, on: bool = True):
+        _check(lib().sv_timing_enable(self.h, 1 if on else 0))
+
+    def timing_read(self) -> Tuple[float, int, float]:
+        """(summed sweep-kernel ms, launches, algorithmic bytes) since the last read."""
+        ms = C.c_double(0.0)
+        n = C.c_int64(0)
+        by = C.c_double(0.0)
+        _check(lib().sv_timing_read(self.h, C.byref(ms), C.byref(n), C.byref(by)))
+        return float(ms.value), int(n.value), float(by.value)
 
     def apply(self, ops, params, fuse: int = SV_FUSE_AUTO, op_array: Optional[OpArray] = None):
         oa = op_array or OpArray(ops)
@@ -271,12 +285,13 @@ class State:
                                        offset, int(re.size)))
 
 
-def plan_stats(n: int, ops, fuse: int = SV_FUSE_AUTO, tile_bits: int = 0, low_bits: int = 0
-               ) -> Tuple[int, int]:
+def plan_stats(n: int, ops, fuse: int = SV_FUSE_AUTO, tile_bits: int = 0, low_bits: int = 0,
+               group_bits: int = 0) -> Tuple[int, int]:
     oa = OpArray(ops)
     s = C.c_int32(0)
     b = C.c_int32(0)
-    _check(lib().sv_plan_stats(n, oa.ptr(), oa.n, fuse, tile_bits, low_bits, C.byref(s), C.byref(b)))
+    _check(lib().sv_plan_stats(n, oa.ptr(), oa.n, fuse, tile_bits, low_bits, group_bits,
+                               C.byref(s), C.byref(b)))
     return int(s.value), int(b.value)
 
 

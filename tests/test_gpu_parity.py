@@ -82,7 +82,8 @@ def test_config1_layered_12q(sv, fuse):
 
 
 @pytest.mark.parametrize("n,L", [(15, 3), (18, 4), (20, 2)])
-@pytest.mark.parametrize("tiling", [(13, 3), (12, 3), (13, 4), (12, 4), (11, 5)])
+@pytest.mark.parametrize("tiling", [(13, 3, 5), (12, 3, 5), (13, 4, 5), (12, 4, 4), (13, 3, 4),
+                                    (11, 5, 5)])
 def test_layered_tilings(sv, n, L, tiling):
     circ = I.layered(n, L, seed=n)
     _say("layered tiling", n, L, tiling)

@@ -156,7 +156,7 @@ def main():
                    "state_bytes": 16 * (1 << n)},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "k_sweep<double,13,5,1> (tile sweep)",
+                     "kernel": "svk::k_sweep_kron<double,13,3> (tile sweep)",
                      "bytes_per_launch": bytes_per_launch, "avg_launch_ms": avg_launch_ms,
                      "launches": launches},
     }

@@ -21,6 +21,25 @@ template <typename T> struct V4T;   // 16-byte global vector of T
 template <> struct V4T<double> { using type = double2; static constexpr int N = 2; };
 template <> struct V4T<float> { using type = float4; static constexpr int N = 4; };
 
+// Read-only views in the constant address space: the data (plan descriptors,
+// coefficients) is written before the kernel and never during it, so loads
+// through these pointers are invariant and go to the scalar cache (SGPRs)
+// when the address is wave-uniform.
+#define SVI_CONST __attribute__((address_space(4)))
+template <typename T>
+__device__ __forceinline__ const SVI_CONST T *cptr(const T *p) {
+  return (const SVI_CONST T *)p;
+}
+
+// Workgroup barrier that orders LDS only: the fences are scoped to the local
+// address space, so outstanding global loads (the next tile's prefetch) are
+// not waited for, unlike __syncthreads().
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 template <typename T>
 __device__ __forceinline__ int swz(int i) {
   return svi_swz(i, sizeof(T) == 8 ? 3 : 4);
@@ -31,6 +50,15 @@ __device__ __forceinline__ uint64_t insert_zeros64(uint64_t x, const int32_t *po
   for (int k = 0; k < np; k++) {
     const int p = pos[k];
     const uint64_t lo = x & ((1ull << p) - 1ull);
+    x = ((x >> p) << (p + 1)) | lo;
+  }
+  return x;
+}
+
+__device__ __forceinline__ int insert_zeros32c(int x, const SVI_CONST int32_t *pos, int np) {
+  for (int k = 0; k < np; k++) {
+    const int p = pos[k];
+    const int lo = x & ((1 << p) - 1);
     x = ((x >> p) << (p + 1)) | lo;
   }
   return x;
@@ -247,8 +275,8 @@ __device__ __forceinline__ void mo_dense(T *re, T *im, const double *cf, uint32_
   }
 }
 
-template <typename T, int R>
-__device__ __forceinline__ void mo_diagt(T *re, T *im, const double *cf) {
+template <typename T, int R, typename CP = const double *>
+__device__ __forceinline__ void mo_diagt(T *re, T *im, CP cf) {
 #pragma unroll
   for (int j = 0; j < (1 << R); j++) {
     const T dr = (T)cf[2 * j], di = (T)cf[2 * j + 1];
@@ -292,8 +320,8 @@ __device__ __forceinline__ double mo_grad(const T *pr, const T *pi, const T *lr,
 // Fast-Givens rotation on group bit TB (record {form, k, scale, 0}, form 0 or
 // 1; the scale is applied separately).  Gentleman's scaled rotation: each
 // output is one FMA with a +-1 coefficient on one input.
-template <typename T, int R, int TB>
-__device__ __forceinline__ void mo_fastr(T *re, T *im, const double *cf) {
+template <typename T, int R, int TB, typename CP>
+__device__ __forceinline__ void mo_fastr(T *re, T *im, CP cf) {
   const int form = (int)cf[0];
   const T k = (T)cf[1];
 #define SVI_FR(XR, XI, YR, YI)                                   \
@@ -312,12 +340,11 @@ __device__ __forceinline__ void mo_fastr(T *re, T *im, const double *cf) {
 }
 
 // Static Kronecker stage: s * D_after * (R~_{R-1} (x) ... (x) R~_0) * D_before.
-template <typename T, int R>
-__device__ __forceinline__ void kron_stage(T *re, T *im, const double *cf, uint32_t rmask,
-                                           int dflags) {
+template <typename T, int R, typename CP>
+__device__ __forceinline__ void kron_stage(T *re, T *im, CP cf, uint32_t rmask, int dflags) {
   constexpr int G = 1 << R;
-  const double *tb = cf + 4 * R;
-  const double *ta = tb + 2 * G;
+  CP tb = cf + 4 * R;
+  CP ta = tb + 2 * G;
   if (dflags & 1) mo_diagt<T, R>(re, im, tb);
   if (rmask & 1u) mo_fastr<T, R, 0>(re, im, cf + 0);
   if (rmask & 2u) mo_fastr<T, R, 1>(re, im, cf + 4);
@@ -525,12 +552,12 @@ __global__ void __launch_bounds__(1 << (M - R)) k_sweep(SweepArgs a) {
 
     // ---- stages
     for (int st = a.stage_begin; st < a.stage_end; st++) {
-      const StageDesc &sd = a.stages[st];
+      const SVI_CONST StageDesc &sd = cptr(a.stages)[st];
       // Every thread runs the stage (keeps wave shuffles uniform).  Threads
       // beyond the tile's groups work on LDS slots above 2^mm, which are
       // never written back.
       const bool active = tid < ngroups;
-      const int gbs = swz<T>(insert_zeros32(tid, sd.sbits, R)) * (int)sizeof(C2);
+      const int gbs = swz<T>(insert_zeros32c(tid, sd.sbits, R)) * (int)sizeof(C2);
       T re[NS][G], im[NS][G];
 #pragma unroll
       for (int s = 0; s < NS; s++) {
@@ -543,8 +570,8 @@ __global__ void __launch_bounds__(1 << (M - R)) k_sweep(SweepArgs a) {
         }
       }
       if (sd.kind == ST_KRON) {
-        kron_stage<T, R>(re[0], im[0], a.coef + sd.kcoef, sd.rmask, sd.dflags);
-        if constexpr (NS == 2) kron_stage<T, R>(re[1], im[1], a.coef + sd.kcoef, sd.rmask, sd.dflags);
+        kron_stage<T, R>(re[0], im[0], cptr(a.coef) + sd.kcoef, sd.rmask, sd.dflags);
+        if constexpr (NS == 2) kron_stage<T, R>(re[1], im[1], cptr(a.coef) + sd.kcoef, sd.rmask, sd.dflags);
       } else
       for (int o = sd.op_begin; o < sd.op_end; o++) {
         const MicroOp op = a.ops[o];
@@ -629,6 +656,15 @@ __global__ void __launch_bounds__(1 << (M - R)) k_sweep(SweepArgs a) {
 // holds only the tile, and the code holds only the static stage body, so the
 // register groups stay in VGPRs with no interpreter paths competing for them.
 
+// Tile order: XCD-aware.  Workgroup b runs on XCD b % 8; in every round the
+// workgroups of one XCD take a contiguous run of tiles, so tiles that share
+// HBM lines and DRAM pages are fetched through the same L2 at the same time.
+__device__ __forceinline__ int64_t tile_of(int64_t round_base, int b, int grid) {
+  const int per = grid >> 3;
+  return grid >= 8 && (grid & 7) == 0 ? round_base + (int64_t)(b & 7) * per + (b >> 3)
+                                      : round_base + b;
+}
+
 template <typename T, int M, int R>
 __global__ void __launch_bounds__(1 << (M - R)) k_sweep_kron(SweepArgs a) {
   constexpr int NT = 1 << (M - R);
@@ -644,9 +680,10 @@ __global__ void __launch_bounds__(1 << (M - R)) k_sweep_kron(SweepArgs a) {
   const int m = a.m, c = a.c, nh = a.nh;
   const int ntile_el = 1 << m;
   const bool vec = c >= (VN == 2 ? 1 : 2);
-  const StageDesc *__restrict__ stages = a.stages + a.stage_begin;
+  const bool init0 = (a.flags & SW_INIT_ZERO) != 0;
+  const SVI_CONST StageDesc *stages = cptr(a.stages + a.stage_begin);
   const int nst = a.stage_end - a.stage_begin;
-  const double *__restrict__ coef = a.coef;
+  const SVI_CONST double *coef = cptr(a.coef);
 
   if (tid < SVI_MMAX) hb_s[tid] = a.hb[tid < nh ? tid : 0];
   __syncthreads();
@@ -661,27 +698,52 @@ __global__ void __launch_bounds__(1 << (M - R)) k_sweep_kron(SweepArgs a) {
   T *const pre = (T *)a.re, *const pim = (T *)a.im;
   char *const lb = (char *)lds;
 
-  for (int64_t tile = blockIdx.x; tile < a.ntiles; tile += gridDim.x) {
+  // Software pipeline: the next tile's HBM loads are issued into registers
+  // before the current tile's stages run, so their latency hides behind the
+  // LDS / VALU work.
+  V4 nr[NIT], ni[NIT];
+  auto fetch = [&](int64_t tile) {
     const uint64_t base = tile_base(tile, c, hb_s, nh);
-    if (vec) {
+#pragma unroll
+    for (int k = 0; k < NIT; k++) {
+      const int i = (tid + k * NT) * VN;
+      if (i < ntile_el) {
+        const uint64_t g = base + roff[k];
+        nr[k] = *(const V4 *)(pre + g);
+        ni[k] = *(const V4 *)(pim + g);
+      }
+    }
+  };
+  const bool pipe = vec && !init0;
+  int64_t r0 = 0;
+  int64_t tile = tile_of(0, blockIdx.x, gridDim.x);
+  if (pipe && tile < a.ntiles) fetch(tile);
+
+  while (tile < a.ntiles) {
+    const uint64_t base = tile_base(tile, c, hb_s, nh);
+    const int64_t next = tile_of(r0 + gridDim.x, blockIdx.x, gridDim.x);
+    // ---- tile into LDS
+    if (pipe) {
 #pragma unroll
       for (int k = 0; k < NIT; k++) {
         const int i = (tid + k * NT) * VN;
         if (i < ntile_el) {
-          const uint64_t g = base + roff[k];
-          const V4 vr = *(const V4 *)(pre + g);
-          const V4 vi = *(const V4 *)(pim + g);
           const int si = tsw ^ swz<T>(k * NT * VN);
           if constexpr (VN == 2) {
-            lds[si] = C2{vr.x, vi.x};
-            lds[si ^ 1] = C2{vr.y, vi.y};
+            lds[si] = C2{nr[k].x, ni[k].x};
+            lds[si ^ 1] = C2{nr[k].y, ni[k].y};
           } else {
-            lds[si] = C2{vr.x, vi.x};
-            lds[si ^ 1] = C2{vr.y, vi.y};
-            lds[si ^ 2] = C2{vr.z, vi.z};
-            lds[si ^ 3] = C2{vr.w, vi.w};
+            lds[si] = C2{nr[k].x, ni[k].x};
+            lds[si ^ 1] = C2{nr[k].y, ni[k].y};
+            lds[si ^ 2] = C2{nr[k].z, ni[k].z};
+            lds[si ^ 3] = C2{nr[k].w, ni[k].w};
           }
         }
+      }
+    } else if (init0) {
+      for (int i = tid; i < ntile_el; i += NT) {
+        const T v = (base == 0 && i == 0) ? (T)1 : (T)0;
+        lds[swz<T>(i)] = C2{v, 0};
       }
     } else {
       for (int i = tid; i < ntile_el; i += NT) {
@@ -689,10 +751,12 @@ __global__ void __launch_bounds__(1 << (M - R)) k_sweep_kron(SweepArgs a) {
         lds[swz<T>(i)] = C2{pre[g], pim[g]};
       }
     }
-    __syncthreads();
+    lds_barrier();
+    if (pipe && next < a.ntiles) fetch(next);
+    // ---- stages
     for (int st = 0; st < nst; st++) {
-      const StageDesc &sd = stages[st];
-      const int gbs = swz<T>(insert_zeros32(tid, sd.sbits, R)) * (int)sizeof(C2);
+      const SVI_CONST StageDesc &sd = stages[st];
+      const int gbs = swz<T>(insert_zeros32c(tid, sd.sbits, R)) * (int)sizeof(C2);
       T re[G], im[G];
 #pragma unroll
       for (int j = 0; j < G; j++) {
@@ -703,8 +767,9 @@ __global__ void __launch_bounds__(1 << (M - R)) k_sweep_kron(SweepArgs a) {
       kron_stage<T, R>(re, im, coef + sd.kcoef, sd.rmask, sd.dflags);
 #pragma unroll
       for (int j = 0; j < G; j++) *(C2 *)(lb + (gbs ^ sd.st_off[j])) = C2{re[j], im[j]};
-      __syncthreads();
+      lds_barrier();
     }
+    // ---- LDS to HBM
     if (vec) {
 #pragma unroll
       for (int k = 0; k < NIT; k++) {
@@ -734,7 +799,9 @@ __global__ void __launch_bounds__(1 << (M - R)) k_sweep_kron(SweepArgs a) {
         pim[g] = p.y;
       }
     }
-    __syncthreads();
+    lds_barrier();
+    r0 += gridDim.x;
+    tile = next;
   }
 }
 

@@ -878,6 +878,8 @@ struct sv_state {
   // growable scratch (partials)
   void *scratch = nullptr;
   size_t scratch_bytes = 0;
+  // |0..0> requested but not yet written: the next sweep synthesises it
+  bool pending_zero = false;
   // kernel timing instrumentation
   bool timing = false;
   std::vector<hipEvent_t> ev_pool;
@@ -940,8 +942,11 @@ static sv_status ensure_scratch(sv_state *st, size_t bytes) {
 static Tiling default_tiling(int n, sv_dtype dt, int NS) {
   Tiling t;
   if (dt == SV_C128) {
+    // forward: 13-qubit tiles, 256-byte rows, 8-amplitude register groups
+    // (1024-thread workgroups, 4 waves per SIMD); measured best on the
+    // 30-qubit layered workload among the compiled tilings
     if (NS == 2) { t.M = 12; t.R = 4; t.c = 3; }
-    else { t.M = 13; t.R = 5; t.c = 3; }
+    else { t.M = 13; t.R = 3; t.c = 5; }
   } else {
     if (NS == 2) { t.M = 13; t.R = 4; t.c = 3; }
     else { t.M = 14; t.R = 5; t.c = 3; }
@@ -975,11 +980,7 @@ extern "C" sv_status sv_alloc(int32_t n, sv_dtype dtype, void *re, void *im, voi
   st->stream = (hipStream_t)stream;
   st->tiling = default_tiling(n, dtype, 1);
   (void)hipGetDevice(&st->dev);
-  hipError_t e = svk_launch_init_zero(dtype == SV_C128, re, im, (int64_t)1 << n, st->stream);
-  if (e != hipSuccess) {
-    delete st;
-    return fail(SV_EDEVICE, "init kernel: %s", hipGetErrorString(e));
-  }
+  st->pending_zero = true;
   *out = st;
   return SV_OK;
 }
@@ -1048,10 +1049,20 @@ extern "C" sv_status sv_timing_read(sv_state *st, double *sweep_ms, int64_t *lau
   return SV_OK;
 }
 
-extern "C" sv_status sv_reset(sv_state *st) {
-  if (!st) return fail(SV_EINVAL, "null handle");
+// Write a pending |0..0> (when the next operation cannot absorb it).
+static sv_status materialize_zero(sv_state *st) {
+  if (!st->pending_zero) return SV_OK;
   hipError_t e = svk_launch_init_zero(st->dtype == SV_C128, st->re, st->im, (int64_t)1 << st->n, st->stream);
   if (e != hipSuccess) return fail(SV_EDEVICE, "init kernel: %s", hipGetErrorString(e));
+  st->pending_zero = false;
+  return SV_OK;
+}
+
+extern "C" sv_status sv_reset(sv_state *st) {
+  if (!st) return fail(SV_EINVAL, "null handle");
+  // Deferred: the first sweep of the next sv_apply_layer synthesises |0..0>
+  // in LDS instead of reading the planes; other readers write it first.
+  st->pending_zero = true;
   return SV_OK;
 }
 
@@ -1300,11 +1311,22 @@ static sv_status upload_call_data(sv_state *st, Plan &P, const sv_op *ops, int n
   return SV_OK;
 }
 
+static sv_status materialize_zero(sv_state *st);
+
 static sv_status run_steps(sv_state *st, Plan &P, void *re, void *im, void *re2, void *im2,
                            double *gpart, int grid_override) {
   DevInfo di;
   sv_status s = device_info(di);
   if (s) return s;
+  // a pending |0..0> on the handle's own planes: the first tile sweep builds it
+  bool fuse_zero = false;
+  if (re == st->re && st->pending_zero) {
+    if (!P.steps.empty() && P.steps[0].kind == 0 && P.NS == 1) fuse_zero = true;
+    else {
+      s = materialize_zero(st);
+      if (s) return s;
+    }
+  }
   const bool dbl = st->dtype == SV_C128;
   int occ = svk_sweep_occupancy(dbl, P.M, P.R, P.NS);
   int occk = P.NS == 1 ? svk_sweep_kron_occupancy(dbl, P.M, P.R) : 0;
@@ -1312,6 +1334,7 @@ static sv_status run_steps(sv_state *st, Plan &P, void *re, void *im, void *re2,
     if (stp.kind == 0) {
       SweepArgs a = stp.sa;
       a.re = re; a.im = im; a.re2 = re2; a.im2 = im2;
+      if (fuse_zero && &stp == &P.steps[0]) a.flags |= SW_INIT_ZERO;
       a.stages = P.d_stages;
       a.ops = P.d_ops;
       a.coef = P.d_coef;
@@ -1329,6 +1352,7 @@ static sv_status run_steps(sv_state *st, Plan &P, void *re, void *im, void *re2,
       hipError_t e = lean ? svk_launch_sweep_kron(dbl, P.M, P.R, a, (int)g, st->stream)
                           : svk_launch_sweep(dbl, P.M, P.R, P.NS, a, (int)g, st->stream);
       if (e != hipSuccess) return fail(SV_EDEVICE, "sweep kernel: %s", hipGetErrorString(e));
+      if (a.flags & SW_INIT_ZERO) st->pending_zero = false;
       if (e0 && e1) {
         (void)hipEventRecord(e1, st->stream);
         st->ev_bytes.push_back(4.0 * (double)((int64_t)1 << st->n) * (double)elem_size(st->dtype));
@@ -1344,6 +1368,16 @@ static sv_status run_steps(sv_state *st, Plan &P, void *re, void *im, void *re2,
   return SV_OK;
 }
 
+// Smallest compiled register-group width >= need (same tile size if possible).
+static sv_status widen_groups(bool dbl, int need, Tiling &tl) {
+  if (need <= tl.R) return SV_OK;
+  for (int R = need; R <= SVI_RMAX; R++)
+    if (svk_has_sweep(dbl, tl.M, R, 1)) { tl.R = R; return SV_OK; }
+  for (int M : {13, 12, 14}) for (int R = need; R <= SVI_RMAX; R++)
+    if (svk_has_sweep(dbl, M, R, 1)) { tl.M = M; tl.R = R; tl.c = std::min(tl.c, M - R); return SV_OK; }
+  return fail(SV_EUNSUPPORTED, "no kernel with %d-qubit register groups", need);
+}
+
 extern "C" sv_status sv_apply_layer(sv_state *st, const sv_op *ops, int32_t n_ops,
                                     const double *params, int32_t n_params, int32_t fuse_width) {
   if (!st) return fail(SV_EINVAL, "null handle");
@@ -1353,13 +1387,12 @@ extern "C" sv_status sv_apply_layer(sv_state *st, const sv_op *ops, int32_t n_op
   if (s) return s;
   if (n_ops == 0) return SV_OK;
   Tiling tl = st->tiling;
-  if (fuse_width >= 2) {
-    // fused blocks need a register group as wide as the block
-    if (fuse_width > tl.R) {
-      if (svk_has_sweep(st->dtype == SV_C128, tl.M, 5, 1)) tl.R = 5;
-      else if (svk_has_sweep(st->dtype == SV_C128, 13, 5, 1)) { tl.M = 13; tl.R = 5; }
-    }
-  }
+  // register groups must be as wide as the widest op (and a fused block)
+  int need = fuse_width >= 2 ? fuse_width : 1;
+  for (int i = 0; i < n_ops; i++)
+    need = std::max(need, ops[i].n_targets + ops[i].n_controls);
+  s = widen_groups(st->dtype == SV_C128, need, tl);
+  if (s) return s;
   Plan *P = nullptr;
   s = get_plan(st, fuse_width, tl, ops, n_ops, n_params, false, &P);
   if (s) return s;
@@ -1371,9 +1404,10 @@ extern "C" sv_status sv_apply_layer(sv_state *st, const sv_op *ops, int32_t n_op
 // ------------------------------------------------------- Pauli reductions
 
 struct PauliPlan {
-  std::vector<PauliTermDev> terms;    // reordered by pass
+  std::vector<PauliTermDev> terms;    // reordered: tiled passes first, then wide terms
   struct Pass { int m, c, nh; int hb[SVI_MMAX]; int t0, t1; };
   std::vector<Pass> passes;
+  int wide_begin = 0;                 // terms[wide_begin..] run untiled (k_pauli_wide)
 };
 
 static void plan_pauli(int n, const sv_pauli_term *terms, int nt, PauliPlan &pp) {
@@ -1382,8 +1416,10 @@ static void plan_pauli(int n, const sv_pauli_term *terms, int nt, PauliPlan &pp)
   const uint64_t low = (1ull << c) - 1;
   struct Open { uint64_t U; std::vector<int> ids; };
   std::vector<Open> open;
+  std::vector<int> wide;
   for (int j = 0; j < nt; j++) {
     uint64_t xh = terms[j].x_mask & ~low;
+    if (popc(xh) > M - c) { wide.push_back(j); continue; }   // cannot fit in any tile
     bool placed = false;
     for (Open &o : open) {
       if ((int)o.ids.size() >= SVI_PTERMS_MAX) continue;
@@ -1412,11 +1448,24 @@ static void plan_pauli(int n, const sv_pauli_term *terms, int nt, PauliPlan &pp)
     ps.t1 = (int)pp.terms.size();
     pp.passes.push_back(ps);
   }
+  pp.wide_begin = (int)pp.terms.size();
+  for (int j : wide) {
+    PauliTermDev d{};
+    d.x = terms[j].x_mask;
+    d.z = terms[j].z_mask;
+    d.c = terms[j].coeff;
+    d.term = j;
+    pp.terms.push_back(d);
+  }
 }
 
 // Runs the Pauli passes; term values land in device array `d_terms` (original order).
 static sv_status run_pauli(sv_state *st, const sv_pauli_term *terms, int nt, void *re, void *im,
                            void *lre, void *lim, double **d_terms_out) {
+  if (re == st->re) {
+    sv_status z = materialize_zero(st);
+    if (z) return z;
+  }
   PauliPlan pp;
   plan_pauli(st->n, terms, nt, pp);
   DevInfo di;
@@ -1452,12 +1501,28 @@ static sv_status run_pauli(sv_state *st, const sv_pauli_term *terms, int nt, voi
     a.t_begin = ps.t0; a.t_end = ps.t1;
     a.accumulate = p > 0;
     a.ntiles = (int64_t)1 << (st->n - ps.m);
+    if (ps.m > 13 || ps.m > st->n) return fail(SV_EINVAL, "internal: Pauli tile of %d bits", ps.m);
     int64_t g = std::min<int64_t>(grid_max, a.ntiles);
     a.part = d_part + (size_t)ps.t0 * g;
     hipError_t e = svk_launch_pauli(dbl, 13, a, (int)g, st->stream);
     if (e != hipSuccess) return fail(SV_EDEVICE, "pauli kernel: %s", hipGetErrorString(e));
     e = svk_launch_reduce_rows(a.part, ps.t1 - ps.t0, (int)g, d_red + ps.t0, st->stream);
     if (e != hipSuccess) return fail(SV_EDEVICE, "reduce kernel: %s", hipGetErrorString(e));
+  }
+  // wide terms: one untiled pass each, after the tiled passes
+  {
+    const int64_t N = (int64_t)1 << st->n;
+    const int gw = (int)std::min<int64_t>(grid_max, (N + 255) / 256);
+    for (size_t k = (size_t)pp.wide_begin; k < nterm; k++) {
+      const PauliTermDev &d = pp.terms[k];
+      double *part = d_part + k * (size_t)grid_max;
+      const bool acc = !pp.passes.empty() || k > (size_t)pp.wide_begin;
+      hipError_t e = svk_launch_pauli_wide(dbl, re, im, lre, lim, d.x, d.z, d.c, N, acc ? 1 : 0,
+                                           part, gw, st->stream);
+      if (e != hipSuccess) return fail(SV_EDEVICE, "pauli wide kernel: %s", hipGetErrorString(e));
+      e = svk_launch_reduce_rows(part, 1, gw, d_red + k, st->stream);
+      if (e != hipSuccess) return fail(SV_EDEVICE, "reduce kernel: %s", hipGetErrorString(e));
+    }
   }
   // d_red is in pass order; return it with the permutation on the host side
   *d_terms_out = d_red;
@@ -1527,6 +1592,13 @@ static sv_status adjoint_enqueue(sv_state *st, const sv_op *ops, int n_ops, cons
                 sv_workspace_bytes(st->n, st->dtype, SV_WS_ADJOINT));
   Tiling tf = st->tiling;
   Tiling tb = default_tiling(st->n, st->dtype, 2);
+  int width = 1;
+  for (int i = 0; i < n_ops; i++) width = std::max(width, ops[i].n_targets + ops[i].n_controls);
+  s = widen_groups(st->dtype == SV_C128, width, tf);
+  if (s) return s;
+  if (width > tb.R)
+    return fail(SV_EUNSUPPORTED, "adjoint: ops on %d qubits exceed the %d-qubit backward groups",
+                width, tb.R);
   Plan *F = nullptr, *B = nullptr;
   if (n_ops > 0) {
     s = get_plan(st, SV_FUSE_AUTO, tf, ops, n_ops, n_params, false, &F);
@@ -1660,7 +1732,9 @@ extern "C" sv_status sv_sample(sv_state *st, uint64_t seed, int64_t shots, const
   double *S, *P;
   void *a, *b, *c, *d;
   ws_layout(st, &S, &P, &a, &b, &c, &d);
-  sv_status s = ensure_scratch(st, (size_t)shots * 8 + 1024);
+  sv_status s = materialize_zero(st);
+  if (s) return s;
+  s = ensure_scratch(st, (size_t)shots * 8 + 1024);
   if (s) return s;
   uint64_t *d_out = (uint64_t *)st->scratch;
   hipError_t e = svk_launch_sampling(st->dtype == SV_C128, st->re, st->im, st->n, S, P, seed, shots,
@@ -1680,6 +1754,8 @@ extern "C" sv_status sv_copy_to_host(const sv_state *st, void *re, void *im, uin
   if (offset > N || count > N - offset) return fail(SV_EINVAL, "range [%llu,+%llu) beyond 2^n",
                                                    (unsigned long long)offset, (unsigned long long)count);
   size_t es = elem_size(st->dtype);
+  sv_status z = materialize_zero(const_cast<sv_state *>(st));
+  if (z) return z;
   if (re) HIPCHK(hipMemcpyAsync(re, (char *)st->re + offset * es, count * es, hipMemcpyDeviceToHost, st->stream));
   if (im) HIPCHK(hipMemcpyAsync(im, (char *)st->im + offset * es, count * es, hipMemcpyDeviceToHost, st->stream));
   HIPCHK(hipStreamSynchronize(st->stream));
@@ -1693,6 +1769,8 @@ extern "C" sv_status sv_copy_from_host(sv_state *st, const void *re, const void 
   if (offset > N || count > N - offset) return fail(SV_EINVAL, "range beyond 2^n");
   if (!re || !im) return fail(SV_EINVAL, "null host plane");
   size_t es = elem_size(st->dtype);
+  sv_status z = materialize_zero(st);
+  if (z) return z;
   HIPCHK(hipMemcpyAsync((char *)st->re + offset * es, re, count * es, hipMemcpyHostToDevice, st->stream));
   HIPCHK(hipMemcpyAsync((char *)st->im + offset * es, im, count * es, hipMemcpyHostToDevice, st->stream));
   HIPCHK(hipStreamSynchronize(st->stream));

@@ -316,7 +316,7 @@ __global__ void k_build_coefs(const CoefDesc *d, int nd, const double *params, c
 template <typename T, int M>
 __global__ void __launch_bounds__(256) k_pauli(PauliPassArgs a) {
   constexpr int NT = 256;
-  constexpr int EPT = (1 << M) / NT;   // elements per thread
+  constexpr int EPT = (1 << M) / NT;   // elements per thread: i = tid + k * NT
   constexpr int NWAVE = NT / 64;
   using C2 = typename C2T<T>::type;
   __shared__ C2 lds[1 << M];
@@ -356,12 +356,58 @@ __global__ void __launch_bounds__(256) k_pauli(PauliPassArgs a) {
       lds[swz<T>(i)] = C2{pre[g], pim[g]};
     }
     __syncthreads();
-    T lr[EPT], li[EPT];
+    // |psi|^2 of this thread's elements (0 beyond the tile)
+    double pn[EPT], zs[EPT];
 #pragma unroll
-    for (int k = 0; k < EPT; k++) { lr[k] = 0; li[k] = 0; }
+    for (int k = 0; k < EPT; k++) {
+      const int i = tid + k * NT;
+      double v = 0.0;
+      if (i < nel) {
+        const C2 pb = lds[swz<T>(i)];
+        v = (double)pb.x * (double)pb.x + (double)pb.y * (double)pb.y;
+      }
+      pn[k] = v;
+      zs[k] = 0.0;
+    }
+    // Z-only terms: sign(i) = parity(base & z) ^ parity(tid & z) ^ parity((k*NT) & z)
     for (int t = 0; t < nterm; t++) {
+      if (xl_s[t] != 0) continue;
       const PauliTermDev pt = a.terms[a.t_begin + t];
-      const uint32_t xl = xl_s[t], zl = zl_s[t];
+      const uint32_t zl = zl_s[t];
+      const bool sneg = (__builtin_popcountll(base & pt.z) ^ __builtin_popcount((uint32_t)tid & zl)) & 1;
+      const uint32_t zk = zl / NT;
+      const double cc = sneg ? -pt.c : pt.c;
+      double acc = 0.0;
+#pragma unroll
+      for (int k = 0; k < EPT; k++) {
+        const bool kn = __builtin_popcount((uint32_t)k & zk) & 1;
+        acc = kn ? acc - pn[k] : acc + pn[k];
+        if (lre) zs[k] = kn ? zs[k] - cc : zs[k] + cc;
+      }
+      acc = sneg ? -acc : acc;
+      acc = wave_sum(acc);
+      if ((tid & 63) == 0) wsum[tid >> 6][t] = acc;
+    }
+    // terms with an X / Y part: partner amplitudes from LDS
+    T lr[EPT], li[EPT];
+    if (lre) {
+#pragma unroll
+      for (int k = 0; k < EPT; k++) {
+        const int i = tid + k * NT;
+        lr[k] = 0;
+        li[k] = 0;
+        if (i < nel) {
+          const C2 pb = lds[swz<T>(i)];
+          lr[k] = (T)(zs[k] * (double)pb.x);
+          li[k] = (T)(zs[k] * (double)pb.y);
+        }
+      }
+    }
+    for (int t = 0; t < nterm; t++) {
+      const uint32_t xl = xl_s[t];
+      if (xl == 0) continue;
+      const PauliTermDev pt = a.terms[a.t_begin + t];
+      const uint32_t zl = zl_s[t];
       const int ny = __builtin_popcountll(pt.x & pt.z) & 3;
       const bool bneg = __builtin_popcountll(base & pt.z) & 1;   // non-tile bits' sign
       double acc = 0.0;
@@ -426,6 +472,50 @@ __global__ void __launch_bounds__(256) k_pauli(PauliPassArgs a) {
     __syncthreads();
   }
   for (int t = tid; t < nterm; t += NT) a.part[(int64_t)t * gridDim.x + blockIdx.x] = tacc[t];
+}
+
+// One Pauli term with an arbitrary x-mask, untiled: every work item reads
+// psi_b and psi_{b^x} from HBM.  Used for terms whose X/Y support does not fit
+// in a tile.  Expectation partial sums per workgroup in part[blockIdx];
+// lam_b (+)= c (P psi)_b when lre is set.
+template <typename T>
+__global__ void __launch_bounds__(256) k_pauli_wide(const T *re, const T *im, T *lre, T *lim,
+                                                    uint64_t x, uint64_t z, double cf, int64_t N,
+                                                    int accumulate, double *part) {
+  __shared__ double ws[4];
+  const int ny = __builtin_popcountll(x & z) & 3;
+  double acc = 0.0;
+  for (int64_t b = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; b < N;
+       b += (int64_t)gridDim.x * blockDim.x) {
+    const uint64_t u = (uint64_t)b, p = u ^ x;
+    const double br = (double)re[u], bi = (double)im[u], pr = (double)re[p], pi = (double)im[p];
+    double tr, ti;
+    switch (ny) {
+      case 0: tr = br; ti = bi; break;
+      case 1: tr = -bi; ti = br; break;
+      case 2: tr = -br; ti = -bi; break;
+      default: tr = bi; ti = -br; break;
+    }
+    if (__builtin_popcountll(u & z) & 1) { tr = -tr; ti = -ti; }
+    acc += pr * tr + pi * ti;
+    if (lre) {
+      double vr, vi;
+      switch (ny) {
+        case 0: vr = pr; vi = pi; break;
+        case 1: vr = -pi; vi = pr; break;
+        case 2: vr = -pr; vi = -pi; break;
+        default: vr = pi; vi = -pr; break;
+      }
+      if (__builtin_popcountll(p & z) & 1) { vr = -vr; vi = -vi; }
+      const T ar = (T)(cf * vr), ai = (T)(cf * vi);
+      if (accumulate) { lre[u] += ar; lim[u] += ai; }
+      else { lre[u] = ar; lim[u] = ai; }
+    }
+  }
+  acc = wave_sum(acc);
+  if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) part[blockIdx.x] = ws[0] + ws[1] + ws[2] + ws[3];
 }
 
 // Sum each slot's partials in a fixed order: out[s] = sum_w part[s * np + w].
@@ -670,6 +760,18 @@ hipError_t svk_launch_pauli(int dbl, int M, const PauliPassArgs &a, int grid, hi
   if (dbl && M == 13) hipLaunchKernelGGL((k_pauli<double, 13>), dim3(grid), dim3(256), 0, s, a);
   else if (!dbl && M == 13) hipLaunchKernelGGL((k_pauli<float, 13>), dim3(grid), dim3(256), 0, s, a);
   else return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+hipError_t svk_launch_pauli_wide(int dbl, const void *re, const void *im, void *lre, void *lim,
+                                 uint64_t x, uint64_t z, double c, int64_t N, int accumulate,
+                                 double *part, int grid, hipStream_t s) {
+  if (dbl)
+    hipLaunchKernelGGL(k_pauli_wide<double>, dim3(grid), dim3(256), 0, s, (const double *)re,
+                       (const double *)im, (double *)lre, (double *)lim, x, z, c, N, accumulate, part);
+  else
+    hipLaunchKernelGGL(k_pauli_wide<float>, dim3(grid), dim3(256), 0, s, (const float *)re,
+                       (const float *)im, (float *)lre, (float *)lim, x, z, c, N, accumulate, part);
   return hipGetLastError();
 }
 

@@ -31,6 +31,9 @@ hipError_t svk_launch_coefs(const CoefDesc *d, int nd, const double *params,
                             hipStream_t s);
 hipError_t svk_launch_pauli(int dbl, int M, const PauliPassArgs &a, int grid, hipStream_t s);
 int svk_pauli_occupancy(int dbl);
+hipError_t svk_launch_pauli_wide(int dbl, const void *re, const void *im, void *lre, void *lim,
+                                 uint64_t x, uint64_t z, double c, int64_t N, int accumulate,
+                                 double *part, int grid, hipStream_t s);
 hipError_t svk_launch_reduce_rows(const double *part, int nslots, int np, double *out,
                                   hipStream_t s);
 hipError_t svk_launch_gather_grad(const double *slot_sum, const int32_t *row_ptr,

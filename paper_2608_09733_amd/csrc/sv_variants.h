@@ -8,6 +8,10 @@
   X(double, 12, 5, 1)        \
   X(double, 13, 4, 1)        \
   X(double, 12, 4, 1)        \
+  X(double, 12, 3, 1)        \
+  X(double, 13, 3, 1)        \
+  X(double, 11, 4, 1)        \
+  X(double, 11, 3, 1)        \
   X(double, 11, 5, 1)        \
   X(double, 12, 4, 2)        \
   X(double, 11, 4, 2)        \
@@ -15,6 +19,6 @@
   X(float, 13, 5, 1)         \
   X(float, 13, 4, 2)
 
-#define SVI_NVARIANTS 10
+#define SVI_NVARIANTS 14
 #define SVI_VCAT(a, b, c, d, e, f) svk_##a##_##b##_##c##_##d##_##e##f
 #define SVI_VNAME(what, T, M, R, NS) SVI_VCAT(what, T, M, R, NS, _v)

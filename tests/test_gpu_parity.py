@@ -268,3 +268,42 @@ def test_errors_rejected_before_device_work(sv):
     assert ei.value.status == -4   # workspace without adjoint room
     assert np.array_equal(before, st.to_numpy())
     st.close()
+
+
+def test_reset_is_lazy_and_exact(sv):
+    # sv_reset defers |0..0>: the next sweep synthesises it, other readers write it
+    n = 14
+    circ = I.layered(n, 2, seed=5)
+    st = sv.State(n)
+    st.apply(circ.ops, circ.params, fuse=-1)
+    st.reset()
+    psi0 = st.to_numpy()
+    assert psi0[0] == 1 and np.count_nonzero(psi0) == 1
+    st.apply(circ.ops, circ.params, fuse=-1)
+    st.reset()
+    z, _ = st.expect(I.hamiltonian(n, [("Z", [q], 1.0) for q in range(n)]))
+    assert np.all(z == 1.0)
+    st.reset()
+    st.apply(circ.ops, circ.params, fuse=-1)
+    assert np.max(np.abs(st.to_numpy() - O.run_circuit(circ))) <= TOL
+    st.reset()
+    st.apply(circ.ops, circ.params, fuse=0)     # first step is a gate kernel: materialised
+    assert np.max(np.abs(st.to_numpy() - O.run_circuit(circ))) <= TOL
+    st.close()
+
+
+def test_expectation_z_terms_and_lambda_large(sv):
+    # many Z-only terms (thread/row parity split) and X/Y terms in one pass
+    n = 17
+    circ = I.random_circuit(n, 60, seed=71)
+    ham = I.random_hamiltonian(n, 40, seed=9)
+    zham = I.hamiltonian(n, [("Z" * (q % 5 + 1), list(range(q, q + q % 5 + 1)), 0.1 * q)
+                             for q in range(n - 5)])
+    st = sv.State(n, adjoint=True)
+    st.apply(circ.ops, circ.params, fuse=-1)
+    ref = O.run_circuit(circ)
+    for h in (ham, zham):
+        t, e = st.expect(h)
+        tr, er, _ = O.expect(n, ref, h)
+        assert np.max(np.abs(t - tr)) <= TOL and abs(e - er) <= TOL
+    st.close()

@@ -201,34 +201,69 @@ typedef struct {
   const sv_pauli_term *terms;
 } sv_circuit_desc;
 
-/* Plan a batch.  tile_bits / low_bits = 0 take defaults.  Device buffers are
- * allocated by the library (hipMalloc) at plan time and freed by
- * sv_batch_free.  Errors: SV_EINVAL, SV_EUNBOUND, SV_ENOMEM, SV_EUNSUPPORTED. */
+/* Plan a batch.  Every circuit gets its own tile plan (the planner of
+ * sv_apply_layer with SV_FUSE_AUTO); its state starts at |0..0>.
+ *   tile_bits   qubits per LDS tile (0 = 13, the only compiled value)
+ *   low_bits    contiguous low qubits per tile (0 = 5)
+ *   group_bits  qubits per register group (0 = the narrowest compiled width
+ *               >= 3 that holds the widest op: 3 or 5)
+ * Ops, terms and user matrices are read during the call and not kept (user
+ * matrices are copied: later changes to them are not seen).  All device
+ * memory (states, plan, queue) is allocated here with hipMalloc and released
+ * by sv_batch_free.  Each circuit's observable must have every term's X/Y
+ * support inside one 13-qubit tile (SV_EUNSUPPORTED otherwise).
+ * Errors: SV_EINVAL (bad sizes, qubits, tiling), SV_EUNBOUND (parameter index
+ * >= the circuit's n_params), SV_EDTYPE, SV_EUNSUPPORTED, SV_EDEVICE. */
 sv_status sv_batch_plan(const sv_circuit_desc *circuits, int32_t n_circuits, sv_dtype dtype,
-                        int32_t tile_bits, int32_t low_bits, sv_batch **out);
+                        int32_t tile_bits, int32_t low_bits, int32_t group_bits, sv_batch **out);
 
-/* Device pointer of the concatenated parameter vector (circuit c's params
- * start at param_offset(c)); the caller writes new angles there. */
+/* Copy new angles into the batch: `params` is host memory holding every
+ * circuit's parameters concatenated in circuit order (count = sum of
+ * n_params).  Synchronous.  SV_EUNBOUND on a non-finite value. */
+sv_status sv_batch_upload_params(sv_batch *b, const double *params, int64_t count);
+
+/* Device pointer of the parameter vector; circuit c's parameters start at
+ * element param_offset(c) (param_offset(n_circuits) = total length).  A
+ * caller may write angles there directly, e.g. from another kernel. */
 double *sv_batch_params_device(sv_batch *b);
 int64_t sv_batch_param_offset(const sv_batch *b, int32_t circuit);
 
-/* Enqueue the whole batch on `hip_stream`: reset queue counters, build gate
- * coefficients from the device parameters, run the persistent kernel, leave
- * per-circuit observables in the device array returned by
- * sv_batch_results_device (n_circuits FP64).  Async; capturable. */
+/* Enqueue the whole batch on `hip_stream`: reset the queue (a small kernel,
+ * no memset), build gate coefficients from the device parameters, run the
+ * persistent kernel, reduce each circuit's observable into the device array
+ * returned by sv_batch_results_device (n_circuits FP64, sum_j c_j <P_j>).
+ * Asynchronous; allocates nothing, so the caller may capture it in a graph.
+ * Overlapping runs of one batch race. */
 sv_status sv_batch_run(sv_batch *b, void *hip_stream);
 double *sv_batch_results_device(sv_batch *b);
 
-/* After the stream has finished: nonzero if a unit's bounded dependency wait
- * expired (the results are then invalid). */
+/* Same work as sv_batch_run, as a HIP graph that the library captures on its
+ * first call (on a stream of its own) and launches on `hip_stream`. */
+sv_status sv_batch_graph_launch(sv_batch *b, void *hip_stream);
+
+/* Synchronise `hip_stream`, then SV_EDEVICE if a unit's bounded dependency
+ * wait expired in the last run (its results are then invalid). */
 sv_status sv_batch_check(sv_batch *b, void *hip_stream);
 
-/* Device pointers to circuit c's state planes (for parity tests). */
+/* Polls of a dependency wait before it expires (default 1048576, about a second).  A
+ * negative value skips every dependency wait and flags it as expired, so the
+ * next sv_batch_check reports the error (tests of the error path). */
+sv_status sv_batch_set_spin_limit(sv_batch *b, int32_t polls);
+
+/* Device pointers to circuit c's state planes (valid until sv_batch_free). */
 sv_status sv_batch_state(sv_batch *b, int32_t circuit, void **re, void **im);
 
-/* Statistics: number of work units, total sweeps, total gate-amplitude updates. */
+/* Synchronous copies to host memory, ordered after the work on `hip_stream`:
+ * the n_circuits observables, or circuit c's planes (2^n elements each, FP64
+ * for SV_C128, FP32 for SV_C64). */
+sv_status sv_batch_copy_results(sv_batch *b, double *out, void *hip_stream);
+sv_status sv_batch_copy_state(sv_batch *b, int32_t circuit, void *re, void *im, void *hip_stream);
+
+/* Statistics: work units in the queue, total sweeps, and the sum over
+ * circuits of n_ops * 2^n (gate-amplitude updates). */
 sv_status sv_batch_stats(const sv_batch *b, int64_t *units, int64_t *sweeps, double *updates);
 
+/* Wait for the device, then release the batch and its device memory. */
 sv_status sv_batch_free(sv_batch *b);
 
 /* ------------------------------------------------------- plan inspection

@@ -37,10 +37,20 @@ def _run(cmd, verbose):
         print(out)
 
 
+def _variants_text():
+    return open(os.path.join(CSRC, "sv_variants.h")).read()
+
+
 def variants():
     """(T, M, R, NS) entries of SVI_VARIANTS in sv_variants.h."""
-    txt = open(os.path.join(CSRC, "sv_variants.h")).read()
-    return re.findall(r"X\((double|float),\s*(\d+),\s*(\d+),\s*(\d+)\)", txt)
+    return re.findall(r"X\((double|float),\s*(\d+),\s*(\d+),\s*(\d+)\)", _variants_text())
+
+
+def batch_variants():
+    """(T, M, R) entries of SVB_VARIANTS in sv_variants.h."""
+    txt = _variants_text()
+    txt = txt[txt.index("#define SVB_VARIANTS"):]
+    return re.findall(r"X\((double|float),\s*(\d+),\s*(\d+)\)", txt)
 
 
 def build(verbose: bool = False, jobs: int = 0) -> str:
@@ -60,6 +70,13 @@ def build(verbose: bool = False, jobs: int = 0) -> str:
                                   f"-DSVI_VNS={ns}", "-c",
                                   os.path.join(CSRC, "sv_sweep_variant.hip"), "-o", obj]
         todo.append((cmd, obj))
+    for t, m, r in batch_variants():
+        obj = os.path.join(objdir, f"batch_{t}_{m}_{r}.o")
+        cmd = [HIPCC] + COMMON + [f"-DSVB_VT={t}", f"-DSVB_VM={m}", f"-DSVB_VR={r}", "-c",
+                                  os.path.join(CSRC, "sv_batch_variant.hip"), "-o", obj]
+        todo.append((cmd, obj))
+    # longest jobs first
+    todo.sort(key=lambda j: 0 if "sv_batch_variant" in " ".join(j[0]) else 1)
     objs = [o for _, o in todo]
     running = []
     while todo or running:

@@ -1844,3 +1844,524 @@ extern "C" sv_status sv_plan_stats(int32_t n, const sv_op *ops, int32_t n_ops, i
   if (n_blocks) *n_blocks = blocks;
   return SV_OK;
 }
+
+// ------------------------------------------------------------ ragged batch
+// Host side of the persistent batch launch: every circuit gets its own tile
+// plan (the same planner as sv_apply_layer), the plans are concatenated into
+// one set of device arrays, and the work units of all circuits are queued
+// level by level (sweep 0 of every circuit, then sweep 1, ..., then the Pauli
+// passes), so each unit depends only on units queued before it.
+
+struct sv_batch {
+  int nc = 0;
+  sv_dtype dtype = SV_C128;
+  bool dbl = true;
+  int M = 13, R = 3, c = 5;
+  int grid = 1;
+  int32_t spin_limit = 1 << 20;   // ~1-2 s of polls
+  int ncoefdesc = 0;
+  int nunits = 0;
+  int64_t total_sweeps = 0;
+  double updates = 0.0;
+  std::vector<int> nq;
+  std::vector<int64_t> param_off;    // per circuit; [nc] = total
+  std::vector<int64_t> n_user_params;
+  std::vector<size_t> state_off;     // byte offset of circuit c's re plane (im follows)
+  void *d_state = nullptr;
+  void *d_meta = nullptr;
+  double *d_params = nullptr, *d_coef = nullptr, *d_statics = nullptr, *d_part = nullptr;
+  double *d_results = nullptr, *d_redcoef = nullptr;
+  CoefDesc *d_coefdesc = nullptr;
+  TabFactor *d_factors = nullptr;
+  BatchUnit *d_units = nullptr;
+  SweepArgs *d_sweeps = nullptr;
+  PauliPassArgs *d_passes = nullptr;
+  PauliTermDev *d_terms = nullptr;
+  StageDesc *d_stages = nullptr;
+  MicroOp *d_ops = nullptr;
+  int32_t *d_ctl = nullptr;          // [0] head, [1] err, [2..2+nc) done
+  int32_t *d_redrow = nullptr, *d_redslot = nullptr;
+  hipStream_t cap_stream = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  ~sv_batch() {
+    if (gexec) (void)hipGraphExecDestroy(gexec);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (cap_stream) (void)hipStreamDestroy(cap_stream);
+    if (d_state) (void)hipFree(d_state);
+    if (d_meta) (void)hipFree(d_meta);
+  }
+};
+
+static sv_status batch_validate(const sv_circuit_desc *cs, int nc, int &need) {
+  if (nc < 1) return fail(SV_EINVAL, "a batch needs at least one circuit (got %d)", nc);
+  if (!cs) return fail(SV_EINVAL, "null circuit array");
+  need = 1;
+  for (int k = 0; k < nc; k++) {
+    const sv_circuit_desc &d = cs[k];
+    if (d.n_qubits < 1 || d.n_qubits > 30)
+      return fail(SV_EINVAL, "circuit %d: n_qubits %d outside 1..30", k, d.n_qubits);
+    if (d.n_ops < 0 || (d.n_ops > 0 && !d.ops)) return fail(SV_EINVAL, "circuit %d: bad op list", k);
+    if (d.n_params < 0) return fail(SV_EINVAL, "circuit %d: negative n_params", k);
+    for (int i = 0; i < d.n_ops; i++) {
+      sv_status s = validate_op(d.ops[i], i, d.n_qubits, d.n_params);
+      if (s) return fail(s, "circuit %d: %s", k, std::string(g_err).c_str());
+      need = std::max(need, d.ops[i].n_targets + d.ops[i].n_controls);
+    }
+    sv_status s = validate_terms(d.n_qubits, d.terms, d.n_terms);
+    if (s) return fail(s, "circuit %d: %s", k, std::string(g_err).c_str());
+  }
+  return SV_OK;
+}
+
+extern "C" sv_status sv_batch_plan(const sv_circuit_desc *circuits, int32_t n_circuits,
+                                   sv_dtype dtype, int32_t tile_bits, int32_t low_bits,
+                                   int32_t group_bits, sv_batch **out) {
+  if (!out) return fail(SV_EINVAL, "null output handle");
+  *out = nullptr;
+  if (dtype != SV_C128 && dtype != SV_C64) return fail(SV_EDTYPE, "unsupported dtype %d", (int)dtype);
+  int need = 1;
+  sv_status s = batch_validate(circuits, n_circuits, need);
+  if (s) return s;
+  const bool dbl = dtype == SV_C128;
+  const int M = tile_bits ? tile_bits : 13;
+  int R = group_bits;
+  if (!R) {
+    R = std::max(3, need);
+    while (R <= SVI_RMAX && !svk_has_batch(dbl, M, R)) R++;
+  }
+  if (R < need) return fail(SV_EINVAL, "group_bits %d narrower than the widest op (%d qubits)", R, need);
+  if (R > SVI_RMAX || !svk_has_batch(dbl, M, R))
+    return fail(SV_EINVAL, "no batch kernel for tile_bits %d, group_bits %d, dtype %d", M, R, (int)dtype);
+  const int c = low_bits ? low_bits : 5;
+  if (c < 1 || c > M) return fail(SV_EINVAL, "low_bits %d outside 1..%d", c, M);
+
+  std::unique_ptr<sv_batch> b(new sv_batch);
+  b->nc = n_circuits;
+  b->dtype = dtype;
+  b->dbl = dbl;
+  b->M = M;
+  b->R = R;
+  b->c = c;
+  const size_t es = elem_size(dtype);
+  const Tiling tl{M, c, R};
+
+  // ---- per-circuit plans, merged
+  std::vector<StageDesc> stages;
+  std::vector<MicroOp> ops;
+  std::vector<CoefDesc> coefs;
+  std::vector<TabFactor> factors;
+  std::vector<double> statics, constants_init;
+  std::vector<SweepArgs> sweeps;
+  std::vector<PauliPassArgs> passes;
+  std::vector<PauliTermDev> terms;
+  std::vector<std::vector<std::vector<BatchUnit>>> levels(n_circuits);  // [circ][level] units
+  std::vector<std::vector<std::pair<double, int>>> red(n_circuits);     // (coef, part slot)
+  int64_t ncoef = 0, nparam = 0, npart = 0;
+  size_t state_bytes = 0;
+  b->nq.resize(n_circuits);
+  b->param_off.resize(n_circuits + 1);
+  b->n_user_params.resize(n_circuits);
+  b->state_off.resize(n_circuits);
+  std::vector<std::pair<int, double>> const_init;   // (param slot, value)
+
+  auto tiles_per_unit = [](int64_t ntiles) -> int64_t {
+    return std::max<int64_t>(1, std::min<int64_t>(8, ntiles / 32));
+  };
+
+  for (int k = 0; k < n_circuits; k++) {
+    const sv_circuit_desc &d = circuits[k];
+    const int n = d.n_qubits;
+    b->nq[k] = n;
+    b->state_off[k] = state_bytes;
+    const size_t plane = (((size_t)1 << n) * es + 255) & ~(size_t)255;
+    state_bytes += 2 * plane;
+    Plan P;
+    s = build_forward_plan(-1, n, dbl, tl, d.ops, d.n_ops, d.n_params, P);
+    if (s) return s;
+    if (P.M != M || P.R != R) return fail(SV_EINVAL, "internal: plan tiling mismatch");
+    for (const Step &st : P.steps)
+      if (st.kind != 0) return fail(SV_EUNSUPPORTED, "circuit %d: plan needs a single-gate kernel", k);
+    const int64_t stage_off = (int64_t)stages.size(), op_off = (int64_t)ops.size();
+    const int64_t factor_off = (int64_t)factors.size(), static_off = (int64_t)statics.size();
+    const int64_t coef_off = ncoef;
+    b->param_off[k] = nparam;
+    b->n_user_params[k] = d.n_params;
+    for (size_t j = 0; j < P.constants.size(); j++)
+      const_init.push_back({(int)(nparam + d.n_params + (int64_t)j), P.constants[j]});
+    nparam += d.n_params + (int64_t)P.constants.size();
+    stages.insert(stages.end(), P.stages.begin(), P.stages.end());
+    ops.insert(ops.end(), P.ops.begin(), P.ops.end());
+    for (CoefDesc cd : P.coefs) {
+      const int fmt = cd.fmt & 0xff;
+      cd.dst += (int32_t)coef_off;
+      if (fmt == CF_TABLE || fmt == CF_SCALE) cd.src += (int32_t)factor_off;
+      else if (fmt == CF_COPY) cd.src += (int32_t)static_off;
+      else if (fmt != CF_IDENT2)
+        for (int q = 0; q < 3; q++)
+          if (cd.pidx[q] >= 0) cd.pidx[q] += (int32_t)b->param_off[k];
+      coefs.push_back(cd);
+    }
+    for (TabFactor f : P.factors) {
+      if (f.pidx >= 0) f.pidx += (int32_t)b->param_off[k];
+      factors.push_back(f);
+    }
+    for (int i = 0; i < d.n_ops; i++)
+      if (d.ops[i].kind == SV_UNITARY) {
+        const int dd = 1 << d.ops[i].n_targets;
+        statics.insert(statics.end(), d.ops[i].matrix, d.ops[i].matrix + 2 * dd * dd);
+      }
+    ncoef += P.ncoef;
+
+    // sweeps (an empty circuit still needs one sweep that writes |0..0>)
+    std::vector<SweepArgs> csw;
+    for (const Step &st : P.steps) csw.push_back(st.sa);
+    if (csw.empty()) {
+      SweepArgs z;
+      std::memset(&z, 0, sizeof z);
+      const int m = std::min(M, n), cc = std::min(c, n);
+      z.n = n;
+      z.m = m;
+      z.c = cc;
+      z.nh = m - cc;
+      for (int q = 0; q < z.nh; q++) z.hb[q] = cc + q;
+      z.ntiles = (int64_t)1 << (n - m);
+      csw.push_back(z);
+    }
+    csw[0].flags |= SW_INIT_ZERO;
+    int64_t before = 0;   // units of this circuit in earlier levels
+    for (SweepArgs &a : csw) {
+      a.re = nullptr;     // patched after the device allocation
+      a.im = nullptr;
+      a.stages = (const StageDesc *)(intptr_t)stage_off;   // offsets, patched later
+      a.ops = (const MicroOp *)(intptr_t)op_off;
+      a.coef = (const double *)(intptr_t)coef_off;
+      a.re2 = (void *)(intptr_t)k;                          // circuit id until patched
+      const int idx = (int)sweeps.size();
+      sweeps.push_back(a);
+      std::vector<BatchUnit> lu;
+      const int64_t tpu = tiles_per_unit(a.ntiles);
+      for (int64_t t = 0; t < a.ntiles; t += tpu) {
+        BatchUnit u{};
+        u.kind = UK_SWEEP;
+        u.circ = k;
+        u.arg = idx;
+        u.wait = (int32_t)before;
+        u.t0 = t;
+        u.t1 = std::min(a.ntiles, t + tpu);
+        lu.push_back(u);
+      }
+      before += (int64_t)lu.size();
+      levels[k].push_back(std::move(lu));
+    }
+    b->total_sweeps += (int64_t)csw.size();
+    b->updates += (double)d.n_ops * (double)((int64_t)1 << n);
+
+    // Pauli passes: one level after the last sweep
+    if (d.n_terms > 0) {
+      PauliPlan pp;
+      plan_pauli(n, d.terms, d.n_terms, pp);
+      if (pp.wide_begin != (int)pp.terms.size())
+        return fail(SV_EUNSUPPORTED, "circuit %d: a term's X/Y support does not fit in one %d-qubit tile",
+                    k, std::min(13, n));
+      const int term_off = (int)terms.size();
+      terms.insert(terms.end(), pp.terms.begin(), pp.terms.end());
+      std::vector<BatchUnit> lu;
+      for (const PauliPlan::Pass &ps : pp.passes) {
+        PauliPassArgs pa;
+        std::memset(&pa, 0, sizeof pa);
+        pa.terms = (const PauliTermDev *)nullptr;
+        pa.n = n;
+        pa.m = ps.m;
+        pa.c = ps.c;
+        pa.nh = ps.nh;
+        for (int q = 0; q < SVI_MMAX; q++) pa.hb[q] = q < ps.nh ? ps.hb[q] : 0;
+        pa.t_begin = term_off + ps.t0;
+        pa.t_end = term_off + ps.t1;
+        pa.ntiles = (int64_t)1 << (n - ps.m);
+        pa.lre = (void *)(intptr_t)k;   // circuit id until patched
+        const int idx = (int)passes.size();
+        passes.push_back(pa);
+        const int64_t tpu = tiles_per_unit(pa.ntiles);
+        for (int64_t t = 0; t < pa.ntiles; t += tpu) {
+          BatchUnit u{};
+          u.kind = UK_PAULI;
+          u.circ = k;
+          u.arg = idx;
+          u.wait = (int32_t)before;
+          u.t0 = t;
+          u.t1 = std::min(pa.ntiles, t + tpu);
+          u.part = (int32_t)npart;
+          for (int j = ps.t0; j < ps.t1; j++) red[k].push_back({pp.terms[j].c, (int)(npart + j - ps.t0)});
+          npart += ps.t1 - ps.t0;
+          lu.push_back(u);
+        }
+      }
+      levels[k].push_back(std::move(lu));
+    }
+  }
+  b->param_off[n_circuits] = nparam;
+
+  // ---- queue: level by level; within a level, circuits with more levels first
+  std::vector<int> order(n_circuits);
+  for (int k = 0; k < n_circuits; k++) order[k] = k;
+  std::stable_sort(order.begin(), order.end(), [&](int a, int c2) {
+    return levels[a].size() > levels[c2].size();
+  });
+  size_t maxlev = 0;
+  for (int k = 0; k < n_circuits; k++) maxlev = std::max(maxlev, levels[k].size());
+  std::vector<BatchUnit> units;
+  for (size_t l = 0; l < maxlev; l++)
+    for (int k : order)
+      if (l < levels[k].size())
+        units.insert(units.end(), levels[k][l].begin(), levels[k][l].end());
+  if (units.size() > (size_t)INT32_MAX) return fail(SV_ENOMEM, "batch too large");
+  b->nunits = (int)units.size();
+
+  // ---- reduction rows
+  std::vector<int32_t> redrow(n_circuits + 1, 0), redslot;
+  std::vector<double> redcoef;
+  for (int k = 0; k < n_circuits; k++) {
+    for (auto &e : red[k]) { redcoef.push_back(e.first); redslot.push_back(e.second); }
+    redrow[k + 1] = (int32_t)redslot.size();
+  }
+
+  // ---- device memory (everything above is host-only planning)
+  DevInfo di;
+  s = device_info(di);
+  if (s) return s;
+  HIPCHK(hipMalloc(&b->d_state, std::max<size_t>(state_bytes, 256)));
+  auto align = [](size_t v) { return (v + 255) & ~(size_t)255; };
+  size_t off = 0;
+  auto take = [&](size_t bytes) { size_t o = off; off = align(off + std::max<size_t>(bytes, 8)); return o; };
+  const size_t o_params = take((size_t)nparam * 8);
+  const size_t o_coef = take((size_t)ncoef * 8);
+  const size_t o_statics = take(statics.size() * 8);
+  const size_t o_part = take((size_t)npart * 8);
+  const size_t o_results = take((size_t)n_circuits * 8);
+  const size_t o_redcoef = take(redcoef.size() * 8);
+  const size_t o_coefdesc = take(coefs.size() * sizeof(CoefDesc));
+  const size_t o_factors = take(factors.size() * sizeof(TabFactor));
+  const size_t o_units = take(units.size() * sizeof(BatchUnit));
+  const size_t o_sweeps = take(sweeps.size() * sizeof(SweepArgs));
+  const size_t o_passes = take(passes.size() * sizeof(PauliPassArgs));
+  const size_t o_terms = take(terms.size() * sizeof(PauliTermDev));
+  const size_t o_stages = take(stages.size() * sizeof(StageDesc));
+  const size_t o_ops = take(ops.size() * sizeof(MicroOp));
+  const size_t o_ctl = take((size_t)(n_circuits + 2) * 4);
+  const size_t o_redrow = take(redrow.size() * 4);
+  const size_t o_redslot = take(redslot.size() * 4);
+  HIPCHK(hipMalloc(&b->d_meta, off));
+  char *mb = (char *)b->d_meta;
+  b->d_params = (double *)(mb + o_params);
+  b->d_coef = (double *)(mb + o_coef);
+  b->d_statics = (double *)(mb + o_statics);
+  b->d_part = (double *)(mb + o_part);
+  b->d_results = (double *)(mb + o_results);
+  b->d_redcoef = (double *)(mb + o_redcoef);
+  b->d_coefdesc = (CoefDesc *)(mb + o_coefdesc);
+  b->d_factors = (TabFactor *)(mb + o_factors);
+  b->d_units = (BatchUnit *)(mb + o_units);
+  b->d_sweeps = (SweepArgs *)(mb + o_sweeps);
+  b->d_passes = (PauliPassArgs *)(mb + o_passes);
+  b->d_terms = (PauliTermDev *)(mb + o_terms);
+  b->d_stages = (StageDesc *)(mb + o_stages);
+  b->d_ops = (MicroOp *)(mb + o_ops);
+  b->d_ctl = (int32_t *)(mb + o_ctl);
+  b->d_redrow = (int32_t *)(mb + o_redrow);
+  b->d_redslot = (int32_t *)(mb + o_redslot);
+  b->ncoefdesc = (int)coefs.size();
+
+  // patch pointers
+  char *sb = (char *)b->d_state;
+  for (SweepArgs &a : sweeps) {
+    const int k = (int)(intptr_t)a.re2;
+    const size_t plane = (((size_t)1 << b->nq[k]) * es + 255) & ~(size_t)255;
+    a.re = sb + b->state_off[k];
+    a.im = sb + b->state_off[k] + plane;
+    a.re2 = a.im2 = nullptr;
+    a.gpart = nullptr;
+    a.stages = b->d_stages + (intptr_t)a.stages;
+    a.ops = b->d_ops + (intptr_t)a.ops;
+    a.coef = b->d_coef + (intptr_t)a.coef;
+  }
+  for (PauliPassArgs &pa : passes) {
+    const int k = (int)(intptr_t)pa.lre;
+    const size_t plane = (((size_t)1 << b->nq[k]) * es + 255) & ~(size_t)255;
+    pa.re = sb + b->state_off[k];
+    pa.im = sb + b->state_off[k] + plane;
+    pa.lre = pa.lim = nullptr;
+    pa.terms = b->d_terms;
+    pa.part = nullptr;
+  }
+  std::vector<double> params_init((size_t)std::max<int64_t>(nparam, 1), 0.0);
+  for (auto &ci : const_init) params_init[ci.first] = ci.second;
+  auto up = [&](void *dst, const void *src, size_t bytes) -> sv_status {
+    if (bytes) HIPCHK(hipMemcpy(dst, src, bytes, hipMemcpyHostToDevice));
+    return SV_OK;
+  };
+  if ((s = up(b->d_params, params_init.data(), (size_t)nparam * 8))) return s;
+  if ((s = up(b->d_statics, statics.data(), statics.size() * 8))) return s;
+  if ((s = up(b->d_redcoef, redcoef.data(), redcoef.size() * 8))) return s;
+  if ((s = up(b->d_coefdesc, coefs.data(), coefs.size() * sizeof(CoefDesc)))) return s;
+  if ((s = up(b->d_factors, factors.data(), factors.size() * sizeof(TabFactor)))) return s;
+  if ((s = up(b->d_units, units.data(), units.size() * sizeof(BatchUnit)))) return s;
+  if ((s = up(b->d_sweeps, sweeps.data(), sweeps.size() * sizeof(SweepArgs)))) return s;
+  if ((s = up(b->d_passes, passes.data(), passes.size() * sizeof(PauliPassArgs)))) return s;
+  if ((s = up(b->d_terms, terms.data(), terms.size() * sizeof(PauliTermDev)))) return s;
+  if ((s = up(b->d_stages, stages.data(), stages.size() * sizeof(StageDesc)))) return s;
+  if ((s = up(b->d_ops, ops.data(), ops.size() * sizeof(MicroOp)))) return s;
+  if ((s = up(b->d_redrow, redrow.data(), redrow.size() * 4))) return s;
+  if ((s = up(b->d_redslot, redslot.data(), redslot.size() * 4))) return s;
+  HIPCHK(hipMemset(b->d_results, 0, (size_t)n_circuits * 8));
+
+  const int occ = svk_batch_occupancy(dbl, M, R);
+  b->grid = std::max(1, std::min(b->nunits, di.cus * std::max(1, occ)));
+  *out = b.release();
+  return SV_OK;
+}
+
+static sv_status batch_enqueue(sv_batch *b, hipStream_t s) {
+  hipError_t e = svk_launch_batch_reset(b->d_ctl, b->d_ctl + 2, b->d_ctl + 1, b->nc, s);
+  if (e == hipSuccess)
+    e = svk_launch_coefs(b->d_coefdesc, b->ncoefdesc, b->d_params, b->d_statics, b->d_factors,
+                         b->d_coef, s);
+  if (e == hipSuccess) {
+    BatchKernelArgs a{};
+    a.units = b->d_units;
+    a.sweeps = b->d_sweeps;
+    a.passes = b->d_passes;
+    a.part = b->d_part;
+    a.head = b->d_ctl;
+    a.err = b->d_ctl + 1;
+    a.done = b->d_ctl + 2;
+    a.nunits = b->nunits;
+    a.spin_limit = b->spin_limit;
+    e = svk_launch_batch(b->dbl, b->M, b->R, a, b->grid, s);
+  }
+  if (e == hipSuccess)
+    e = svk_launch_batch_reduce(b->d_redrow, b->d_redslot, b->d_redcoef, b->d_part, b->d_results,
+                                b->nc, s);
+  if (e != hipSuccess) return fail(SV_EDEVICE, "batch launch: %s", hipGetErrorString(e));
+  return SV_OK;
+}
+
+extern "C" sv_status sv_batch_run(sv_batch *b, void *stream) {
+  if (!b) return fail(SV_EINVAL, "null batch");
+  return batch_enqueue(b, (hipStream_t)stream);
+}
+
+extern "C" sv_status sv_batch_graph_launch(sv_batch *b, void *stream) {
+  if (!b) return fail(SV_EINVAL, "null batch");
+  if (!b->gexec) {
+    if (!b->cap_stream) HIPCHK(hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking));
+    HIPCHK(hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal));
+    sv_status s = batch_enqueue(b, b->cap_stream);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(b->cap_stream, &g);
+    if (s) {
+      if (g) (void)hipGraphDestroy(g);
+      return s;
+    }
+    if (e != hipSuccess) return fail(SV_EDEVICE, "graph capture: %s", hipGetErrorString(e));
+    b->graph = g;
+    HIPCHK(hipGraphInstantiate(&b->gexec, b->graph, nullptr, nullptr, 0));
+  }
+  HIPCHK(hipGraphLaunch(b->gexec, (hipStream_t)stream));
+  return SV_OK;
+}
+
+extern "C" sv_status sv_batch_upload_params(sv_batch *b, const double *params, int64_t count) {
+  if (!b) return fail(SV_EINVAL, "null batch");
+  if (count != b->param_off[b->nc]) {
+    int64_t users = 0;
+    for (int k = 0; k < b->nc; k++) users += b->n_user_params[k];
+    if (count != users)
+      return fail(SV_EINVAL, "expected %lld parameters, got %lld", (long long)users, (long long)count);
+  }
+  if (count > 0 && !params) return fail(SV_EUNBOUND, "null params");
+  for (int64_t i = 0; i < count; i++)
+    if (!std::isfinite(params[i])) return fail(SV_EUNBOUND, "parameter %lld is not finite", (long long)i);
+  // concatenated user parameters, circuit by circuit, into each circuit's block
+  int64_t src = 0;
+  for (int k = 0; k < b->nc; k++) {
+    const int64_t np = b->n_user_params[k];
+    if (np) HIPCHK(hipMemcpy(b->d_params + b->param_off[k], params + src, (size_t)np * 8, hipMemcpyHostToDevice));
+    src += np;
+  }
+  return SV_OK;
+}
+
+extern "C" double *sv_batch_params_device(sv_batch *b) { return b ? b->d_params : nullptr; }
+
+extern "C" int64_t sv_batch_param_offset(const sv_batch *b, int32_t circuit) {
+  if (!b || circuit < 0 || circuit > b->nc) return -1;
+  return b->param_off[circuit];
+}
+
+extern "C" double *sv_batch_results_device(sv_batch *b) { return b ? b->d_results : nullptr; }
+
+extern "C" sv_status sv_batch_check(sv_batch *b, void *stream) {
+  if (!b) return fail(SV_EINVAL, "null batch");
+  int32_t err = 0;
+  HIPCHK(hipStreamSynchronize((hipStream_t)stream));
+  HIPCHK(hipMemcpy(&err, b->d_ctl + 1, 4, hipMemcpyDeviceToHost));
+  if (err) return fail(SV_EDEVICE, "batch: a work unit's dependency wait expired; results are invalid");
+  return SV_OK;
+}
+
+extern "C" sv_status sv_batch_set_spin_limit(sv_batch *b, int32_t polls) {
+  if (!b) return fail(SV_EINVAL, "null batch");
+  b->spin_limit = polls;
+  if (b->gexec) {   // the limit is a kernel argument: capture again on next use
+    (void)hipGraphExecDestroy(b->gexec);
+    (void)hipGraphDestroy(b->graph);
+    b->gexec = nullptr;
+    b->graph = nullptr;
+  }
+  return SV_OK;
+}
+
+extern "C" sv_status sv_batch_state(sv_batch *b, int32_t circuit, void **re, void **im) {
+  if (!b || circuit < 0 || circuit >= b->nc || !re || !im) return fail(SV_EINVAL, "bad batch state query");
+  const size_t plane = (((size_t)1 << b->nq[circuit]) * elem_size(b->dtype) + 255) & ~(size_t)255;
+  *re = (char *)b->d_state + b->state_off[circuit];
+  *im = (char *)b->d_state + b->state_off[circuit] + plane;
+  return SV_OK;
+}
+
+extern "C" sv_status sv_batch_copy_results(sv_batch *b, double *out, void *stream) {
+  if (!b || !out) return fail(SV_EINVAL, "bad batch result query");
+  HIPCHK(hipMemcpyAsync(out, b->d_results, (size_t)b->nc * 8, hipMemcpyDeviceToHost, (hipStream_t)stream));
+  HIPCHK(hipStreamSynchronize((hipStream_t)stream));
+  return SV_OK;
+}
+
+extern "C" sv_status sv_batch_copy_state(sv_batch *b, int32_t circuit, void *re, void *im,
+                                         void *stream) {
+  void *dre = nullptr, *dim = nullptr;
+  sv_status s = sv_batch_state(b, circuit, &dre, &dim);
+  if (s) return s;
+  if (!re || !im) return fail(SV_EINVAL, "null host plane");
+  const size_t bytes = ((size_t)1 << b->nq[circuit]) * elem_size(b->dtype);
+  HIPCHK(hipMemcpyAsync(re, dre, bytes, hipMemcpyDeviceToHost, (hipStream_t)stream));
+  HIPCHK(hipMemcpyAsync(im, dim, bytes, hipMemcpyDeviceToHost, (hipStream_t)stream));
+  HIPCHK(hipStreamSynchronize((hipStream_t)stream));
+  return SV_OK;
+}
+
+extern "C" sv_status sv_batch_stats(const sv_batch *b, int64_t *units, int64_t *sweeps,
+                                    double *updates) {
+  if (!b) return fail(SV_EINVAL, "null batch");
+  if (units) *units = b->nunits;
+  if (sweeps) *sweeps = b->total_sweeps;
+  if (updates) *updates = b->updates;
+  return SV_OK;
+}
+
+extern "C" sv_status sv_batch_free(sv_batch *b) {
+  if (!b) return SV_OK;
+  (void)hipDeviceSynchronize();
+  delete b;
+  return SV_OK;
+}

@@ -161,3 +161,32 @@ struct PauliPassArgs {
   int32_t accumulate;        // lambda: add to existing values
   int64_t ntiles;
 };
+
+// Ragged batch: one persistent launch drains a device queue of work units.
+// A unit is a range of tiles of one sweep (or of one Pauli pass) of one
+// circuit.  Units are queued in an order in which every unit depends only on
+// units before it, so a workgroup that holds a unit never waits on a unit that
+// has not been taken yet.
+enum { UK_SWEEP = 0, UK_PAULI = 1 };
+
+struct BatchUnit {
+  int32_t kind;        // UK_SWEEP / UK_PAULI
+  int32_t circ;        // circuit index (dependency counter)
+  int32_t arg;         // index into the sweep or Pauli-pass argument array
+  int32_t wait;        // units of this circuit that must be complete first
+  int64_t t0, t1;      // tiles [t0, t1)
+  int32_t part;        // UK_PAULI: first partial-sum slot (one per term of the pass)
+  int32_t pad;
+};
+
+struct BatchKernelArgs {
+  const BatchUnit *units;
+  const SweepArgs *sweeps;
+  const PauliPassArgs *passes;
+  double *part;        // Pauli partial sums
+  int32_t *head;       // next unit to take
+  int32_t *done;       // completed units per circuit
+  int32_t *err;        // bit 0: a dependency wait expired
+  int32_t nunits;
+  int32_t spin_limit;  // polls before a wait expires; < 0: every wait expires at once
+};

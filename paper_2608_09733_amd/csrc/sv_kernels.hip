@@ -182,8 +182,13 @@ __global__ void k_build_coefs(const CoefDesc *d, int nd, const double *params, c
     const int fmt = cd.fmt & 0xff;
     const bool dag = (cd.fmt & CF_DAGGER) != 0;
     double th[3] = {0, 0, 0};
-    for (int k = 0; k < 3; k++)
-      if (cd.pidx[k] >= 0) th[k] = params[cd.pidx[k]];
+    // pidx holds parameter indices except for the table / scale formats,
+    // where pidx[0] counts factors
+    const bool takes_params = fmt != CF_TABLE && fmt != CF_SCALE && fmt != CF_COPY &&
+                              fmt != CF_IDENT2;
+    if (takes_params)
+      for (int k = 0; k < 3; k++)
+        if (cd.pidx[k] >= 0) th[k] = params[cd.pidx[k]];
     double *out = coef + cd.dst;
     if (fmt == CF_FASTR) {
       double m[8];
@@ -824,5 +829,81 @@ hipError_t svk_launch_sampling(int dbl, const void *re, const void *im, int n, d
   int g2 = (int)(blocks < 4096 ? blocks : 4096);
   if (dbl) hipLaunchKernelGGL(k_sample<double>, dim3(g2), dim3(256), 0, s, a);
   else hipLaunchKernelGGL(k_sample<float>, dim3(g2), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------ ragged batch
+// Persistent batch kernel variants (sv_batch_variant.hip) and the two small
+// kernels around it: queue reset (a kernel rather than a memset, so a captured
+// graph replays it reliably) and the per-circuit observable reduction.
+
+#define X(T, MM, RR)                                                                \
+  hipError_t SVB_VNAME(launch, T, MM, RR)(const BatchKernelArgs &, int, hipStream_t); \
+  int SVB_VNAME(occ, T, MM, RR)();
+SVB_VARIANTS(X)
+#undef X
+
+hipError_t svk_launch_batch(int dbl, int M, int R, const BatchKernelArgs &a, int grid,
+                            hipStream_t s) {
+#define X(T, MM, RR)                                                  \
+  if ((dbl == (sizeof(T) == 8)) && M == MM && R == RR)                \
+    return SVB_VNAME(launch, T, MM, RR)(a, grid, s);
+  SVB_VARIANTS(X)
+#undef X
+  return hipErrorInvalidValue;
+}
+
+int svk_batch_occupancy(int dbl, int M, int R) {
+#define X(T, MM, RR)                                                  \
+  if ((dbl == (sizeof(T) == 8)) && M == MM && R == RR) return SVB_VNAME(occ, T, MM, RR)();
+  SVB_VARIANTS(X)
+#undef X
+  return 0;
+}
+
+int svk_has_batch(int dbl, int M, int R) {
+#define X(T, MM, RR)                                                  \
+  if ((dbl == (sizeof(T) == 8)) && M == MM && R == RR) return 1;
+  SVB_VARIANTS(X)
+#undef X
+  return 0;
+}
+
+namespace {
+
+__global__ void k_batch_reset(int32_t *head, int32_t *done, int32_t *err, int nc) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i == 0) {
+    *head = 0;
+    *err = 0;
+  }
+  if (i < nc) done[i] = 0;
+}
+
+// out[c] = sum over entries k of circuit c (rows rowptr[c]..rowptr[c+1]) of
+// coef[k] * part[slot[k]], in entry order.
+__global__ void k_batch_reduce(const int32_t *rowptr, const int32_t *slot, const double *coef,
+                               const double *part, double *out, int nc) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= nc) return;
+  double e = 0.0;
+  for (int k = rowptr[c]; k < rowptr[c + 1]; k++) e += coef[k] * part[slot[k]];
+  out[c] = e;
+}
+
+}  // namespace
+
+hipError_t svk_launch_batch_reset(int32_t *head, int32_t *done, int32_t *err, int nc,
+                                  hipStream_t s) {
+  const int n = nc > 1 ? nc : 1;
+  hipLaunchKernelGGL(k_batch_reset, dim3((n + 255) / 256), dim3(256), 0, s, head, done, err, nc);
+  return hipGetLastError();
+}
+
+hipError_t svk_launch_batch_reduce(const int32_t *rowptr, const int32_t *slot, const double *coef,
+                                   const double *part, double *out, int nc, hipStream_t s) {
+  if (nc <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_batch_reduce, dim3((nc + 255) / 256), dim3(256), 0, s, rowptr, slot, coef,
+                     part, out, nc);
   return hipGetLastError();
 }

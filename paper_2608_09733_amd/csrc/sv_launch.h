@@ -47,3 +47,12 @@ hipError_t svk_launch_sampling(int dbl, const void *re, const void *im, int n, d
 #define SVI_GSLOTS_MAX 256
 #define SVI_PTERMS_MAX 64
 #define SVI_KMAX_STAGES_HOST 16
+
+hipError_t svk_launch_batch(int dbl, int M, int R, const BatchKernelArgs &a, int grid,
+                            hipStream_t s);
+int svk_batch_occupancy(int dbl, int M, int R);
+int svk_has_batch(int dbl, int M, int R);
+hipError_t svk_launch_batch_reset(int32_t *head, int32_t *done, int32_t *err, int nc,
+                                  hipStream_t s);
+hipError_t svk_launch_batch_reduce(const int32_t *rowptr, const int32_t *slot, const double *coef,
+                                   const double *part, double *out, int nc, hipStream_t s);

@@ -22,3 +22,15 @@
 #define SVI_NVARIANTS 14
 #define SVI_VCAT(a, b, c, d, e, f) svk_##a##_##b##_##c##_##d##_##e##f
 #define SVI_VNAME(what, T, M, R, NS) SVI_VCAT(what, T, M, R, NS, _v)
+
+// The persistent ragged-batch kernel instantiations: (element type, tile bits
+// M, register group bits R), one translation unit each
+// (sv_batch_variant.hip with -DSVB_VT= -DSVB_VM= -DSVB_VR=).
+#define SVB_VARIANTS(X) \
+  X(double, 13, 3)      \
+  X(double, 13, 5)      \
+  X(float, 13, 3)       \
+  X(float, 13, 5)
+
+#define SVB_VCAT(a, b, c, d, e) svb_##a##_##b##_##c##_##d##e
+#define SVB_VNAME(what, T, M, R) SVB_VCAT(what, T, M, R, _v)

@@ -245,7 +245,7 @@ def random_circuit(n: int, depth: int, seed: int = 0, kinds: Optional[Sequence[s
         nt, npar = GATES[kind]
         if kind == "unitary":
             nt = int(rng.integers(1, min(3, n) + 1))
-        if nt > n:
+        if nt > n or nt > max_qubits:
             continue
         perm = rng.permutation(n)
         targets = tuple(int(q) for q in perm[:nt])

@@ -82,6 +82,21 @@ def lib():
         "sv_version": (C.c_char_p, []),
         "sv_timing_enable": (C.c_int, [vp, i32]),
         "sv_timing_read": (C.c_int, [vp, dp, C.POINTER(i64), dp]),
+        "sv_batch_plan": (C.c_int, [C.POINTER(SvCircuitDesc), i32, C.c_int, i32, i32, i32,
+                                    C.POINTER(vp)]),
+        "sv_batch_upload_params": (C.c_int, [vp, dp, i64]),
+        "sv_batch_params_device": (vp, [vp]),
+        "sv_batch_param_offset": (i64, [vp, i32]),
+        "sv_batch_run": (C.c_int, [vp, vp]),
+        "sv_batch_graph_launch": (C.c_int, [vp, vp]),
+        "sv_batch_results_device": (vp, [vp]),
+        "sv_batch_check": (C.c_int, [vp, vp]),
+        "sv_batch_set_spin_limit": (C.c_int, [vp, i32]),
+        "sv_batch_state": (C.c_int, [vp, i32, C.POINTER(vp), C.POINTER(vp)]),
+        "sv_batch_stats": (C.c_int, [vp, C.POINTER(i64), C.POINTER(i64), dp]),
+        "sv_batch_free": (C.c_int, [vp]),
+        "sv_batch_copy_results": (C.c_int, [vp, dp, vp]),
+        "sv_batch_copy_state": (C.c_int, [vp, i32, vp, vp, vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -306,3 +321,87 @@ def fuse_blocks(ops, width: int) -> Tuple[int, np.ndarray]:
 
 def version() -> str:
     return lib().sv_version().decode()
+
+
+class Batch:
+    """A ragged batch of independent circuits run as one persistent launch
+    (sv_batch_*).  `circuits` are objects with .n .ops .params (a Circuit of
+    paper_2608_09733_amd.inputs); `observables` one Hamiltonian per circuit
+    (or one shared by all).  Results are sum_j c_j <P_j> per circuit."""
+
+    def __init__(self, circuits, observables, dtype: str = "c128", tile_bits: int = 0,
+                 low_bits: int = 0, group_bits: int = 0):
+        L = lib()
+        self.nc = len(circuits)
+        if not isinstance(observables, (list, tuple)):
+            observables = [observables] * self.nc
+        if len(observables) != self.nc:
+            raise ValueError("one observable per circuit")
+        self.dtype = dtype
+        self._ops = [OpArray(c.ops) for c in circuits]
+        self._terms = [TermArray(h) for h in observables]
+        descs = (SvCircuitDesc * max(1, self.nc))()
+        for k, c in enumerate(circuits):
+            d = descs[k]
+            d.n_qubits = int(c.n)
+            d.n_ops = self._ops[k].n
+            d.ops = self._ops[k].ptr()
+            d.n_params = int(len(c.params))
+            d.n_terms = self._terms[k].n
+            d.terms = self._terms[k].ptr()
+        h = C.c_void_p()
+        _check(L.sv_batch_plan(descs, self.nc, SV_C128 if dtype == "c128" else SV_C64,
+                               tile_bits, low_bits, group_bits, C.byref(h)))
+        self.h = h
+        self.n_qubits = [int(c.n) for c in circuits]
+        self.n_params = [int(len(c.params)) for c in circuits]
+        self.set_params([c.params for c in circuits])
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().sv_batch_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_params(self, params_per_circuit):
+        flat = np.concatenate([np.asarray(p, dtype=np.float64).reshape(-1)
+                               for p in params_per_circuit]) if self.nc else np.zeros(0)
+        p, n = _params_ptr(flat)
+        _check(lib().sv_batch_upload_params(self.h, p.ctypes.data_as(C.POINTER(C.c_double)), n))
+
+    def run(self, stream=None, graph: bool = False):
+        f = lib().sv_batch_graph_launch if graph else lib().sv_batch_run
+        _check(f(self.h, _stream_ptr(stream)))
+
+    def check(self, stream=None):
+        _check(lib().sv_batch_check(self.h, _stream_ptr(stream)))
+
+    def set_spin_limit(self, polls: int):
+        _check(lib().sv_batch_set_spin_limit(self.h, int(polls)))
+
+    def results(self, stream=None) -> np.ndarray:
+        """Synchronise, verify the run, return the per-circuit observables."""
+        self.check(stream)
+        out = np.zeros(max(1, self.nc), dtype=np.float64)
+        _check(lib().sv_batch_copy_results(self.h, out.ctypes.data_as(C.POINTER(C.c_double)),
+                                           _stream_ptr(stream)))
+        return out[:self.nc]
+
+    def state(self, k: int, stream=None) -> np.ndarray:
+        N = 1 << self.n_qubits[k]
+        dt = np.float64 if self.dtype == "c128" else np.float32
+        r = np.zeros(N, dtype=dt)
+        i = np.zeros(N, dtype=dt)
+        _check(lib().sv_batch_copy_state(self.h, k, r.ctypes.data_as(C.c_void_p),
+                                         i.ctypes.data_as(C.c_void_p), _stream_ptr(stream)))
+        return r.astype(np.float64) + 1j * i.astype(np.float64)
+
+    def stats(self) -> Tuple[int, int, float]:
+        u, s, up = C.c_int64(), C.c_int64(), C.c_double()
+        _check(lib().sv_batch_stats(self.h, C.byref(u), C.byref(s), C.byref(up)))
+        return u.value, s.value, up.value

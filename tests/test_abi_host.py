@@ -42,7 +42,9 @@ def test_fusion_counts_match_paper(sv):
         ops = I.layered_structure(n, 4)
         nb, _ = sv.fuse_blocks(ops, 4)
         assert nb == blocks
-        assert sv.plan_stats(n, ops, 4) == (blocks, blocks)
+        # one sweep per fused block (a block may run as more than one register stage)
+        sweeps, stages = sv.plan_stats(n, ops, 4)
+        assert sweeps == blocks and stages >= blocks
 
 
 def test_fusion_blocks_preserve_order(sv):
@@ -91,3 +93,64 @@ def test_alloc_rejects_without_touching_device(sv):
     assert L.sv_alloc(4, 7, None, None, None, 0, None, C.byref(h)) == -2
     assert L.sv_alloc(4, 0, C.c_void_p(16), C.c_void_p(16), None, 0, None, C.byref(h)) == -4
     assert b"workspace" in L.sv_last_error()
+
+
+def _batch_plan_status(sv, circuits, hams, group_bits=0, low_bits=0, tile_bits=0, dtype=0):
+    import ctypes as C
+    ops = [sv.OpArray(c.ops) for c in circuits]
+    terms = [sv.TermArray(h) for h in hams]
+    descs = (sv.SvCircuitDesc * max(1, len(circuits)))()
+    for k, c in enumerate(circuits):
+        descs[k].n_qubits = c.n
+        descs[k].n_ops = ops[k].n
+        descs[k].ops = ops[k].ptr()
+        descs[k].n_params = len(c.params)
+        descs[k].n_terms = terms[k].n
+        descs[k].terms = terms[k].ptr()
+    h = C.c_void_p()
+    st = sv.lib().sv_batch_plan(descs, len(circuits), dtype, tile_bits, low_bits, group_bits,
+                                C.byref(h))
+    return st, sv.lib().sv_last_error().decode()
+
+
+def test_batch_plan_rejects_before_device_work(sv):
+    good = I.layered(6, 2, seed=0)
+    ham = I.z0z1(6)
+    # empty batch, qubit count, tiling without a kernel, dtype
+    assert _batch_plan_status(sv, [], [])[0] == -1
+    bad_n = I.Circuit(31, [], np.zeros(0))
+    assert _batch_plan_status(sv, [bad_n], [I.z0z1(31)])[0] == -1
+    assert _batch_plan_status(sv, [good], [ham], group_bits=4)[0] == -1
+    assert _batch_plan_status(sv, [good], [ham], tile_bits=12)[0] == -1
+    assert _batch_plan_status(sv, [good], [ham], low_bits=14)[0] == -1
+    assert _batch_plan_status(sv, [good], [ham], dtype=7)[0] == -2
+    # a parameter index beyond the circuit's own parameters
+    short = I.Circuit(6, good.ops, good.params[:3])
+    st, msg = _batch_plan_status(sv, [good, short], [ham, ham])
+    assert st == -3 and "circuit 1" in msg
+    # an observable mask beyond the circuit's qubits
+    st, msg = _batch_plan_status(sv, [good], [I.Hamiltonian(6, np.array([0], np.uint64),
+                                                            np.array([1 << 7], np.uint64),
+                                                            np.array([1.0]))])
+    assert st == -1 and "mask" in msg
+    # a 4-qubit gate needs 5-qubit register groups: group_bits 3 is refused
+    wide = I.random_circuit(6, 30, seed=1)
+    if max(len(o.targets) + len(o.controls) for o in wide.ops) > 3:
+        assert _batch_plan_status(sv, [wide], [ham], group_bits=3)[0] == -1
+
+
+def test_batch_host_planning_completes(sv):
+    # the whole host-side batch planner (per-circuit tile plans, Pauli passes,
+    # queue order) runs before any device call; without a GPU it must end at
+    # the device query, not earlier and not in a loop
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("host-only check")
+    circs = I.batch_circuits(64, seed=0)
+    hams = [I.z0z1(c.n) for c in circs]
+    mixed = [I.random_circuit(n, 40, seed=k, max_controls=min(2, n - 1))
+             for k, n in enumerate([1, 2, 3, 5, 8, 12, 13, 14, 16, 4, 15])]
+    mhams = [I.random_hamiltonian(c.n, 3, seed=k) for k, c in enumerate(mixed)]
+    for cs, hs, gb in ((circs, hams, 3), (circs, hams, 5), (mixed, mhams, 5)):
+        st, msg = _batch_plan_status(sv, cs, hs, group_bits=gb)
+        assert st == -6, (st, msg)

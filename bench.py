@@ -65,6 +65,87 @@ def cpu_baseline(circ, budget_s: float):
                       f"{el:.1f} s wall, plain C FP64 gate-by-gate"}
 
 
+def _median_ms(fn, reps, torch):
+    """Median over `reps` calls of fn(), each bracketed by events on the current stream."""
+    import numpy as np
+    ts = []
+    for _ in range(reps):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        fn()
+        e1.record()
+        torch.cuda.synchronize()
+        ts.append(e0.elapsed_time(e1))
+    return float(np.median(ts)), float(np.percentile(ts, 75) - np.percentile(ts, 25))
+
+
+def side_configs(sv, I, torch):
+    """The other workloads of the method at their own shapes: small-state
+    latency (12 qubits), adjoint gradient (20-qubit HEA, TFIM), and the ragged
+    batch of 512 circuits as one persistent launch vs the per-circuit loop."""
+    out = {}
+    # 12-qubit layered circuit, 20 layers, then <Z_i>: a 64 KiB state (latency-bound)
+    c1 = I.layered(12, 20, seed=0)
+    z12 = I.hamiltonian(12, [("Z", [q], 1.0) for q in range(12)])
+    s1 = sv.State(12)
+    oa1 = sv.OpArray(c1.ops)
+
+    def f1():
+        s1.reset()
+        s1.apply(None, c1.params, op_array=oa1)
+        s1.expect(z12)
+    f1()
+    ms, iqr = _median_ms(f1, 20, torch)
+    out["layered_12q_20l"] = {"ms_median": ms, "ms_iqr": iqr, "gates": len(c1.ops),
+                              "updates_per_s": len(c1.ops) * 4096 / (ms / 1e3)}
+    s1.close()
+    log(f"12q layered: {ms:.3f} ms")
+    # adjoint gradient: 20-qubit HEA (RY/RZ + CZ ring), 10 layers, 400 angles, TFIM h=0.7
+    c3 = I.hea(20, 10, seed=0)
+    h3 = I.tfim(20, 0.7)
+    s3 = sv.State(20, adjoint=True)
+    oa3 = sv.OpArray(c3.ops)
+    def f3():
+        s3.reset()
+        s3.adjoint_grad(None, c3.params, h3, op_array=oa3)
+    f3()
+    ms, iqr = _median_ms(f3, 10, torch)
+    out["adjoint_hea_20q_10l_tfim"] = {"ms_median": ms, "ms_iqr": iqr, "params": int(len(c3.params)),
+                                       "gates": len(c3.ops)}
+    s3.close()
+    log(f"20q adjoint: {ms:.3f} ms")
+    # ragged batch: 512 layered circuits, n in 8..22, L in 10..40, <Z0 Z1> each
+    circs = I.batch_circuits(512, seed=0)
+    hams = [I.z0z1(c.n) for c in circs]
+    tune = sv.batch_autotune(circs, hams, reps=2)
+    b = sv.Batch(circs, hams, low_bits=tune["low_bits"], group_bits=tune["group_bits"])
+    b.run(graph=True)
+    b.results()
+    ms, iqr = _median_ms(lambda: b.run(graph=True), 5, torch)
+    b.check()
+    units, sweeps, updates = b.stats()
+    b.close()
+    states = [sv.State(c.n) for c in circs]
+
+    def plain():
+        for stt, c, h in zip(states, circs, hams):
+            stt.reset()
+            stt.apply(c.ops, c.params)
+            stt.expect(h)
+    plain()
+    pms, _ = _median_ms(plain, 2, torch)
+    for stt in states:
+        stt.close()
+    out["batch_512_ragged"] = {"ms_median": ms, "ms_iqr": iqr, "circuits_per_s": 512 / (ms / 1e3),
+                               "updates_per_s": updates / (ms / 1e3), "updates": updates,
+                               "work_units": units, "sweeps": sweeps, "tiling": tune,
+                               "plain_loop_ms": pms, "speedup_vs_plain_loop": pms / ms}
+    log(f"batch 512: {ms:.1f} ms ({updates / (ms / 1e3):.3e} upd/s), plain loop {pms:.1f} ms, "
+        f"tiling {tune}")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -202,8 +283,15 @@ def main():
         log(f"complex64: {t32:.1f} ms, max err {err:.2e}")
         s32.close()
         del s32
-    st.close()
-    del st
+    if not args.no_extras:
+        st.close()
+        del st
+        st = None
+        torch.cuda.empty_cache()
+        extras.update(side_configs(sv, I, torch))
+    if st is not None:
+        st.close()
+        del st
     torch.cuda.empty_cache()
     if not args.no_cpu:
         result["cpu_baseline"] = cpu_baseline(circ, args.cpu_budget)

@@ -266,6 +266,17 @@ sv_status sv_batch_stats(const sv_batch *b, int64_t *units, int64_t *sweeps, dou
 /* Wait for the device, then release the batch and its device memory. */
 sv_status sv_batch_free(sv_batch *b);
 
+/* Autotuner: plans the batch with every compiled tiling (register-group
+ * width >= the widest op, contiguous low bits 2..5), times `reps` runs of each
+ * on `hip_stream` with HIP events after one warm-up run, and returns the
+ * fastest tiling (for sv_batch_plan) and its mean time in milliseconds.
+ * `params` (concatenated, as for sv_batch_upload_params) may be NULL: all
+ * angles 0.  Allocates and frees a batch per candidate; synchronous. */
+sv_status sv_batch_autotune(const sv_circuit_desc *circuits, int32_t n_circuits, sv_dtype dtype,
+                            const double *params, int32_t reps, void *hip_stream,
+                            int32_t *tile_bits, int32_t *low_bits, int32_t *group_bits,
+                            double *best_ms);
+
 /* ------------------------------------------------------- plan inspection
  * Number of full-state sweeps and register blocks sv_apply_layer would use
  * for this circuit with these settings (host-only; for tests and tuning). */

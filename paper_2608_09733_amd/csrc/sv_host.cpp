@@ -2365,3 +2365,60 @@ extern "C" sv_status sv_batch_free(sv_batch *b) {
   delete b;
   return SV_OK;
 }
+
+// Empirical choice of the batch tiling: plan every compiled candidate
+// (register-group width x contiguous low bits), time `reps` runs of each with
+// HIP events on `stream`, keep the fastest.
+extern "C" sv_status sv_batch_autotune(const sv_circuit_desc *circuits, int32_t n_circuits,
+                                       sv_dtype dtype, const double *params, int32_t reps,
+                                       void *stream, int32_t *tile_bits, int32_t *low_bits,
+                                       int32_t *group_bits, double *best_ms) {
+  if (!tile_bits || !low_bits || !group_bits) return fail(SV_EINVAL, "null output");
+  if (reps < 1) return fail(SV_EINVAL, "reps %d < 1", reps);
+  int need = 1;
+  sv_status s = batch_validate(circuits, n_circuits, need);
+  if (s) return s;
+  hipStream_t hs = (hipStream_t)stream;
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  double best = 1e300;
+  int bR = 0, bc = 0;
+  const bool dbl = dtype == SV_C128;
+  for (int R = std::max(3, need); R <= SVI_RMAX; R++) {
+    if (!svk_has_batch(dbl, 13, R)) continue;
+    for (int c : {2, 3, 4, 5}) {
+      sv_batch *b = nullptr;
+      s = sv_batch_plan(circuits, n_circuits, dtype, 13, c, R, &b);
+      if (s) break;
+      if (params) {
+        int64_t users = 0;
+        for (int k = 0; k < n_circuits; k++) users += circuits[k].n_params;
+        s = sv_batch_upload_params(b, params, users);
+      }
+      if (!s) s = sv_batch_run(b, hs);                 // warm-up
+      float ms = 0.f;
+      if (!s) {
+        (void)hipEventRecord(e0, hs);
+        for (int r = 0; r < reps && !s; r++) s = sv_batch_run(b, hs);
+        (void)hipEventRecord(e1, hs);
+        if (!s) s = sv_batch_check(b, hs);
+        if (!s && hipEventElapsedTime(&ms, e0, e1) != hipSuccess) s = fail(SV_EDEVICE, "event timing failed");
+      }
+      sv_batch_free(b);
+      if (s) break;
+      const double t = ms / reps;
+      if (t < best) { best = t; bR = R; bc = c; }
+    }
+    if (s) break;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (s) return s;
+  if (!bR) return fail(SV_EUNSUPPORTED, "no compiled batch kernel holds %d-qubit ops", need);
+  *tile_bits = 13;
+  *low_bits = bc;
+  *group_bits = bR;
+  if (best_ms) *best_ms = best;
+  return SV_OK;
+}

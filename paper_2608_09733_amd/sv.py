@@ -96,6 +96,8 @@ def lib():
         "sv_batch_stats": (C.c_int, [vp, C.POINTER(i64), C.POINTER(i64), dp]),
         "sv_batch_free": (C.c_int, [vp]),
         "sv_batch_copy_results": (C.c_int, [vp, dp, vp]),
+        "sv_batch_autotune": (C.c_int, [C.POINTER(SvCircuitDesc), i32, C.c_int, dp, i32, vp,
+                                        C.POINTER(i32), C.POINTER(i32), C.POINTER(i32), dp]),
         "sv_batch_copy_state": (C.c_int, [vp, i32, vp, vp, vp]),
     }
     for name, (res, args) in sig.items():
@@ -323,6 +325,38 @@ def version() -> str:
     return lib().sv_version().decode()
 
 
+def _circuit_descs(circuits, observables):
+    ops = [OpArray(c.ops) for c in circuits]
+    terms = [TermArray(h) for h in observables]
+    descs = (SvCircuitDesc * max(1, len(circuits)))()
+    for k, c in enumerate(circuits):
+        d = descs[k]
+        d.n_qubits = int(c.n)
+        d.n_ops = ops[k].n
+        d.ops = ops[k].ptr()
+        d.n_params = int(len(c.params))
+        d.n_terms = terms[k].n
+        d.terms = terms[k].ptr()
+    return descs, (ops, terms)
+
+
+def batch_autotune(circuits, observables, dtype: str = "c128", reps: int = 2, stream=None):
+    """Measured choice of the batch tiling: {"tile_bits", "low_bits",
+    "group_bits", "ms"} (sv_batch_autotune)."""
+    if not isinstance(observables, (list, tuple)):
+        observables = [observables] * len(circuits)
+    descs, keep = _circuit_descs(circuits, observables)
+    flat = np.concatenate([np.asarray(c.params, dtype=np.float64).reshape(-1) for c in circuits])
+    p, _ = _params_ptr(flat)
+    tb, lb, gb, ms = C.c_int32(), C.c_int32(), C.c_int32(), C.c_double()
+    _check(lib().sv_batch_autotune(descs, len(circuits), SV_C128 if dtype == "c128" else SV_C64,
+                                   p.ctypes.data_as(C.POINTER(C.c_double)), reps,
+                                   _stream_ptr(stream), C.byref(tb), C.byref(lb), C.byref(gb),
+                                   C.byref(ms)))
+    del keep
+    return {"tile_bits": tb.value, "low_bits": lb.value, "group_bits": gb.value, "ms": ms.value}
+
+
 class Batch:
     """A ragged batch of independent circuits run as one persistent launch
     (sv_batch_*).  `circuits` are objects with .n .ops .params (a Circuit of
@@ -338,17 +372,7 @@ class Batch:
         if len(observables) != self.nc:
             raise ValueError("one observable per circuit")
         self.dtype = dtype
-        self._ops = [OpArray(c.ops) for c in circuits]
-        self._terms = [TermArray(h) for h in observables]
-        descs = (SvCircuitDesc * max(1, self.nc))()
-        for k, c in enumerate(circuits):
-            d = descs[k]
-            d.n_qubits = int(c.n)
-            d.n_ops = self._ops[k].n
-            d.ops = self._ops[k].ptr()
-            d.n_params = int(len(c.params))
-            d.n_terms = self._terms[k].n
-            d.terms = self._terms[k].ptr()
+        descs, self._keep = _circuit_descs(circuits, observables)
         h = C.c_void_p()
         _check(L.sv_batch_plan(descs, self.nc, SV_C128 if dtype == "c128" else SV_C64,
                                tile_bits, low_bits, group_bits, C.byref(h)))

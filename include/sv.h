@@ -157,7 +157,11 @@ sv_status sv_adjoint_grad(sv_state *st, const sv_op *ops, int32_t n_ops, const d
                           double *energy, double *grad, int32_t *n_evals);
 
 /* As sv_adjoint_grad but asynchronous: energy then grad (1 + n_params FP64)
- * are written to DEVICE memory d_out on the handle's stream. */
+ * are written to DEVICE memory d_out on the handle's stream.  The energy is
+ * summed on the device in the library's term order (it may differ from
+ * sv_adjoint_grad's host sum in the last bits).  The first call for a circuit
+ * structure on a handle may allocate (plan, scratch) and synchronise the
+ * handle's stream; later calls enqueue only. */
 sv_status sv_adjoint_grad_device(sv_state *st, const sv_op *ops, int32_t n_ops,
                                  const double *params, int32_t n_params,
                                  const sv_pauli_term *terms, int32_t n_terms, double *d_out);

@@ -1697,21 +1697,10 @@ extern "C" sv_status sv_adjoint_grad_device(sv_state *st, const sv_op *ops, int3
   Plan *B = nullptr;
   sv_status s = adjoint_enqueue(st, ops, n_ops, params, n_params, terms, n_terms, &d_terms, &d_grad, &B);
   if (s) return s;
-  // energy in original term order: coefficients permuted to pass order
-  std::vector<int> order;
-  pauli_order(st->n, terms, n_terms, order);
-  if (n_terms) {
-    std::vector<double> cperm(n_terms);
-    for (int k = 0; k < n_terms; k++) cperm[k] = terms[order[k]].coeff;
-    // place the permuted coefficients right after the gradient
-    double *d_c = d_grad + n_params;
-    HIPCHK(hipMemcpyAsync(d_c, cperm.data(), n_terms * 8, hipMemcpyHostToDevice, st->stream));
-    HIPCHK(hipStreamSynchronize(st->stream));
-    hipError_t e = svk_launch_energy(d_terms, d_c, n_terms, d_out, st->stream);
-    if (e != hipSuccess) return fail(SV_EDEVICE, "energy: %s", hipGetErrorString(e));
-  } else {
-    HIPCHK(hipMemsetAsync(d_out, 0, 8, st->stream));
-  }
+  // energy from the device term list (pass order): no host data, no synchronisation
+  hipError_t e = svk_launch_energy_terms(d_terms, (const PauliTermDev *)st->scratch, n_terms, d_out,
+                                         st->stream);
+  if (e != hipSuccess) return fail(SV_EDEVICE, "energy: %s", hipGetErrorString(e));
   if (n_params)
     HIPCHK(hipMemcpyAsync(d_out + 1, d_grad, n_params * 8, hipMemcpyDeviceToDevice, st->stream));
   return SV_OK;

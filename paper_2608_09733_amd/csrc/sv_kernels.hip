@@ -543,6 +543,16 @@ __global__ void k_gather_grad(const double *slot_sum, const int32_t *row_ptr, co
 }
 
 // E = sum_j c_j <P_j> in term order.
+// E = sum_k c_k <P_k> with the coefficients taken from the device term list
+// (pass order), so no host data is involved.
+__global__ void k_energy_terms(const double *vals, const PauliTermDev *terms, int nt, double *out) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    double e = 0.0;
+    for (int k = 0; k < nt; k++) e += terms[k].c * vals[k];
+    out[0] = e;
+  }
+}
+
 __global__ void k_energy(const double *terms, const double *coef, int nt, double *out) {
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     double e = 0.0;
@@ -804,6 +814,12 @@ hipError_t svk_launch_gather_grad(const double *slot_sum, const int32_t *row_ptr
 hipError_t svk_launch_energy(const double *terms, const double *coef, int nt, double *out,
                              hipStream_t s) {
   hipLaunchKernelGGL(k_energy, dim3(1), dim3(64), 0, s, terms, coef, nt, out);
+  return hipGetLastError();
+}
+
+hipError_t svk_launch_energy_terms(const double *vals, const PauliTermDev *terms, int nt,
+                                   double *out, hipStream_t s) {
+  hipLaunchKernelGGL(k_energy_terms, dim3(1), dim3(64), 0, s, vals, terms, nt, out);
   return hipGetLastError();
 }
 

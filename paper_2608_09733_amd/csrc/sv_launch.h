@@ -38,6 +38,8 @@ hipError_t svk_launch_reduce_rows(const double *part, int nslots, int np, double
                                   hipStream_t s);
 hipError_t svk_launch_gather_grad(const double *slot_sum, const int32_t *row_ptr,
                                   const int32_t *slots, int np, double *grad, hipStream_t s);
+hipError_t svk_launch_energy_terms(const double *vals, const PauliTermDev *terms, int nt,
+                                   double *out, hipStream_t s);
 hipError_t svk_launch_energy(const double *terms, const double *coef, int nt, double *out,
                              hipStream_t s);
 hipError_t svk_launch_sampling(int dbl, const void *re, const void *im, int n, double *S,

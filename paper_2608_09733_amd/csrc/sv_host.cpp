@@ -1404,20 +1404,39 @@ extern "C" sv_status sv_apply_layer(sv_state *st, const sv_op *ops, int32_t n_op
 // ------------------------------------------------------- Pauli reductions
 
 struct PauliPlan {
-  std::vector<PauliTermDev> terms;    // reordered: tiled passes first, then wide terms
+  // reordered: streamed diagonal terms, then tiled passes, then wide terms
+  std::vector<PauliTermDev> terms;
   struct Pass { int m, c, nh; int hb[SVI_MMAX]; int t0, t1; };
   std::vector<Pass> passes;
+  int n_diag = 0;                     // terms[0..n_diag) run in k_zexp
   int wide_begin = 0;                 // terms[wide_begin..] run untiled (k_pauli_wide)
 };
 
-static void plan_pauli(int n, const sv_pauli_term *terms, int nt, PauliPlan &pp) {
+// Diagonal (Z-only) terms of an expectation-only call on a large state take
+// the streaming kernel; with lambda output every term takes the tile passes.
+static bool diag_stream(int n, bool lambda) { return !lambda && n >= 14; }
+
+static void plan_pauli(int n, const sv_pauli_term *terms, int nt, PauliPlan &pp,
+                       bool stream_diag = false) {
   const int M = std::min(13, n);
   const int c = std::min(3, n);
   const uint64_t low = (1ull << c) - 1;
   struct Open { uint64_t U; std::vector<int> ids; };
   std::vector<Open> open;
   std::vector<int> wide;
+  if (stream_diag)
+    for (int j = 0; j < nt; j++)
+      if (terms[j].x_mask == 0) {
+        PauliTermDev d{};
+        d.x = 0;
+        d.z = terms[j].z_mask;
+        d.c = terms[j].coeff;
+        d.term = j;
+        pp.terms.push_back(d);
+        pp.n_diag++;
+      }
   for (int j = 0; j < nt; j++) {
+    if (stream_diag && terms[j].x_mask == 0) continue;
     uint64_t xh = terms[j].x_mask & ~low;
     if (popc(xh) > M - c) { wide.push_back(j); continue; }   // cannot fit in any tile
     bool placed = false;
@@ -1459,6 +1478,17 @@ static void plan_pauli(int n, const sv_pauli_term *terms, int nt, PauliPlan &pp)
   }
 }
 
+// Partial-sum rows of every Pauli kernel have this stride (the largest grid).
+static int64_t pauli_grid_part(const DevInfo &di, bool dbl) {
+  return (int64_t)di.cus * std::max(svk_pauli_occupancy(dbl), svk_zexp_occupancy(dbl));
+}
+
+// Scratch bytes of run_pauli: terms | partials | reduced values | spare.
+static size_t pauli_scratch_bytes(size_t nterm, int64_t grid_part) {
+  size_t b = 256 + nterm * sizeof(PauliTermDev) + nterm * (size_t)grid_part * 8 + 2 * (nterm + 1) * 8 + 1024;
+  return (b + 255) & ~(size_t)255;
+}
+
 // Runs the Pauli passes; term values land in device array `d_terms` (original order).
 static sv_status run_pauli(sv_state *st, const sv_pauli_term *terms, int nt, void *re, void *im,
                            void *lre, void *lim, double **d_terms_out) {
@@ -1467,22 +1497,24 @@ static sv_status run_pauli(sv_state *st, const sv_pauli_term *terms, int nt, voi
     if (z) return z;
   }
   PauliPlan pp;
-  plan_pauli(st->n, terms, nt, pp);
+  plan_pauli(st->n, terms, nt, pp, diag_stream(st->n, lre != nullptr));
   DevInfo di;
   sv_status s = device_info(di);
   if (s) return s;
   const bool dbl = st->dtype == SV_C128;
   int occ = svk_pauli_occupancy(dbl);
   int64_t grid_max = (int64_t)di.cus * occ;
+  const int64_t grid_z = (int64_t)di.cus * svk_zexp_occupancy(dbl);
+  const int64_t grid_part = pauli_grid_part(di, dbl);
   // scratch: terms | partials | reduced (by pass order) | reduced (original order)
   size_t nterm = pp.terms.size();
-  size_t need = 256 + nterm * sizeof(PauliTermDev) + nterm * grid_max * 8 + 2 * (nterm + 1) * 8 + 1024;
+  size_t need = pauli_scratch_bytes(nterm, grid_part);
   s = ensure_scratch(st, need);
   if (s) return s;
   char *b = (char *)st->scratch;
   PauliTermDev *d_terms = (PauliTermDev *)b;
   double *d_part = (double *)(b + ((nterm * sizeof(PauliTermDev) + 255) & ~(size_t)255));
-  double *d_red = d_part + nterm * grid_max;
+  double *d_red = d_part + nterm * grid_part;
   double *d_vals = d_red + nterm + 1;
   if (nterm)
     HIPCHK(hipMemcpyAsync(d_terms, pp.terms.data(), nterm * sizeof(PauliTermDev), hipMemcpyHostToDevice, st->stream));
@@ -1490,6 +1522,15 @@ static sv_status run_pauli(sv_state *st, const sv_pauli_term *terms, int nt, voi
     size_t bytes = ((size_t)1 << st->n) * elem_size(st->dtype);
     HIPCHK(hipMemsetAsync(lre, 0, bytes, st->stream));
     HIPCHK(hipMemsetAsync(lim, 0, bytes, st->stream));
+  }
+  // streamed diagonal terms, SVI_ZTERMS_HOST per read of the state
+  for (int g0 = 0; g0 < pp.n_diag; g0 += SVI_ZTERMS_HOST) {
+    const int cnt = std::min(SVI_ZTERMS_HOST, pp.n_diag - g0);
+    double *part = d_part + (size_t)g0 * grid_part;
+    hipError_t e = svk_launch_zexp(dbl, re, im, st->n, d_terms + g0, cnt, part, (int)grid_z, st->stream);
+    if (e != hipSuccess) return fail(SV_EDEVICE, "diagonal Pauli kernel: %s", hipGetErrorString(e));
+    e = svk_launch_reduce_rows(part, cnt, (int)grid_z, d_red + g0, st->stream);
+    if (e != hipSuccess) return fail(SV_EDEVICE, "reduce kernel: %s", hipGetErrorString(e));
   }
   for (size_t p = 0; p < pp.passes.size(); p++) {
     const PauliPlan::Pass &ps = pp.passes[p];
@@ -1503,7 +1544,7 @@ static sv_status run_pauli(sv_state *st, const sv_pauli_term *terms, int nt, voi
     a.ntiles = (int64_t)1 << (st->n - ps.m);
     if (ps.m > 13 || ps.m > st->n) return fail(SV_EINVAL, "internal: Pauli tile of %d bits", ps.m);
     int64_t g = std::min<int64_t>(grid_max, a.ntiles);
-    a.part = d_part + (size_t)ps.t0 * g;
+    a.part = d_part + (size_t)ps.t0 * grid_part;
     hipError_t e = svk_launch_pauli(dbl, 13, a, (int)g, st->stream);
     if (e != hipSuccess) return fail(SV_EDEVICE, "pauli kernel: %s", hipGetErrorString(e));
     e = svk_launch_reduce_rows(a.part, ps.t1 - ps.t0, (int)g, d_red + ps.t0, st->stream);
@@ -1515,7 +1556,7 @@ static sv_status run_pauli(sv_state *st, const sv_pauli_term *terms, int nt, voi
     const int gw = (int)std::min<int64_t>(grid_max, (N + 255) / 256);
     for (size_t k = (size_t)pp.wide_begin; k < nterm; k++) {
       const PauliTermDev &d = pp.terms[k];
-      double *part = d_part + k * (size_t)grid_max;
+      double *part = d_part + k * (size_t)grid_part;
       const bool acc = !pp.passes.empty() || k > (size_t)pp.wide_begin;
       hipError_t e = svk_launch_pauli_wide(dbl, re, im, lre, lim, d.x, d.z, d.c, N, acc ? 1 : 0,
                                            part, gw, st->stream);
@@ -1530,9 +1571,10 @@ static sv_status run_pauli(sv_state *st, const sv_pauli_term *terms, int nt, voi
   return SV_OK;
 }
 
-static void pauli_order(int n, const sv_pauli_term *terms, int nt, std::vector<int> &order) {
+static void pauli_order(int n, const sv_pauli_term *terms, int nt, std::vector<int> &order,
+                        bool lambda) {
   PauliPlan pp;
-  plan_pauli(n, terms, nt, pp);
+  plan_pauli(n, terms, nt, pp, diag_stream(n, lambda));
   order.clear();
   for (auto &t : pp.terms) order.push_back(t.term);
 }
@@ -1564,7 +1606,7 @@ extern "C" sv_status sv_expect_pauli(sv_state *st, const sv_pauli_term *terms, i
   HIPCHK(hipMemcpyAsync(red.data(), d_red, n_terms * 8, hipMemcpyDeviceToHost, st->stream));
   HIPCHK(hipStreamSynchronize(st->stream));
   std::vector<int> order;
-  pauli_order(st->n, terms, n_terms, order);
+  pauli_order(st->n, terms, n_terms, order, false);
   std::vector<double> vals(n_terms);
   for (int k = 0; k < n_terms; k++) vals[order[k]] = red[k];
   if (out_terms)
@@ -1633,9 +1675,7 @@ static sv_status adjoint_enqueue(sv_state *st, const sv_op *ops, int n_ops, cons
   int64_t maxtiles = (int64_t)1 << (st->n - std::min(B->M, st->n));
   if (grid > maxtiles) grid = maxtiles;
   // scratch after the Pauli area: partials [slots][grid] | slot sums | grad
-  size_t pauli_bytes = 256 + (size_t)n_terms * sizeof(PauliTermDev) + (size_t)n_terms * di.cus *
-                       svk_pauli_occupancy(st->dtype == SV_C128) * 8 + 2 * ((size_t)n_terms + 1) * 8 + 1024;
-  pauli_bytes = (pauli_bytes + 255) & ~(size_t)255;
+  const size_t pauli_bytes = pauli_scratch_bytes((size_t)n_terms, pauli_grid_part(di, st->dtype == SV_C128));
   size_t need = pauli_bytes + (size_t)B->n_gslots * grid * 8 + (size_t)B->n_gslots * 8 +
                 ((size_t)n_params + 1) * 8 + 1024;
   if (need > st->scratch_bytes) {
@@ -1678,7 +1718,7 @@ extern "C" sv_status sv_adjoint_grad(sv_state *st, const sv_op *ops, int32_t n_o
     HIPCHK(hipMemcpyAsync(grad, d_grad, n_params * 8, hipMemcpyDeviceToHost, st->stream));
   HIPCHK(hipStreamSynchronize(st->stream));
   std::vector<int> order;
-  pauli_order(st->n, terms, n_terms, order);
+  pauli_order(st->n, terms, n_terms, order, true);
   std::vector<double> vals(std::max(n_terms, 1));
   for (int k = 0; k < n_terms; k++) vals[order[k]] = red[k];
   double e = 0.0;

@@ -479,6 +479,84 @@ __global__ void __launch_bounds__(256) k_pauli(PauliPassArgs a) {
   for (int t = tid; t < nterm; t += NT) a.part[(int64_t)t * gridDim.x + blockIdx.x] = tacc[t];
 }
 
+// Diagonal (Z-only) terms, expectation only: one streaming read of the state
+// for up to SVI_ZTERMS terms.  Each thread holds K = J * VN probabilities per
+// iteration at fixed "register" bit positions (the VN elements of a 16-byte
+// vector and J vector slots NT * VN apart); a Walsh-Hadamard transform over
+// them gives, for every z pattern on those bits, the signed sum
+// sum_x (-1)^{popcount(z & x)} p_x, so each term costs one indexed read plus
+// a sign from the thread's and the chunk's bits.
+#define SVI_ZTERMS 32
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_zexp(const T *re, const T *im, int64_t nchunks,
+                                              const PauliTermDev *terms, int nt, double *part) {
+  constexpr int NT = 256;
+  constexpr int VN = V4T<T>::N;
+  constexpr int LV = VN == 2 ? 1 : 2;            // log2 VN
+  constexpr int J = 4;
+  constexpr int K = J * VN;
+  constexpr int CH = NT * VN * J;                // amplitudes per chunk
+  using V4 = typename V4T<T>::type;
+  __shared__ double wsum[NT / 64][SVI_ZTERMS];
+  const int tid = threadIdx.x;
+  const SVI_CONST PauliTermDev *tm = cptr(terms);
+  // this thread's sign bits (one per term) from its own index bits
+  uint32_t tpar = 0;
+  for (int t = 0; t < nt; t++)
+    tpar |= (uint32_t)(__builtin_popcountll(tm[t].z & ((uint64_t)tid * VN)) & 1) << t;
+  double acc[SVI_ZTERMS];
+#pragma unroll
+  for (int t = 0; t < SVI_ZTERMS; t++) acc[t] = 0.0;
+  for (int64_t ch = blockIdx.x; ch < nchunks; ch += gridDim.x) {
+    const uint64_t cb = (uint64_t)ch * CH;
+    double p[K];
+#pragma unroll
+    for (int j = 0; j < J; j++) {
+      const uint64_t g = cb + (uint64_t)j * (NT * VN) + (uint64_t)tid * VN;
+      const V4 vr = *(const V4 *)(re + g);
+      const V4 vi = *(const V4 *)(im + g);
+      const T *r = (const T *)&vr, *i = (const T *)&vi;
+#pragma unroll
+      for (int v = 0; v < VN; v++) p[j * VN + v] = (double)r[v] * (double)r[v] + (double)i[v] * (double)i[v];
+    }
+#pragma unroll
+    for (int h = 1; h < K; h <<= 1)
+#pragma unroll
+      for (int x = 0; x < K; x++)
+        if (!(x & h)) {
+          const double a = p[x], b = p[x + h];
+          p[x] = a + b;
+          p[x + h] = a - b;
+        }
+#pragma unroll
+    for (int t = 0; t < SVI_ZTERMS; t++) {
+      if (t < nt) {
+        const uint64_t z = tm[t].z;
+        const int zr = (int)(z & (VN - 1)) | (int)(((z >> (LV + 8)) & (J - 1)) << LV);
+        double w = 0.0;
+#pragma unroll
+        for (int x = 0; x < K; x++) w = zr == x ? p[x] : w;
+        const bool neg = ((tpar >> t) & 1) ^ (uint32_t)(__builtin_popcountll(cb & z) & 1);
+        acc[t] += neg ? -w : w;
+      }
+    }
+  }
+#pragma unroll
+  for (int t = 0; t < SVI_ZTERMS; t++) {
+    if (t < nt) {
+      const double v = wave_sum(acc[t]);
+      if ((tid & 63) == 0) wsum[tid >> 6][t] = v;
+    }
+  }
+  __syncthreads();
+  if (tid < nt) {
+    double v = 0.0;
+    for (int w = 0; w < NT / 64; w++) v += wsum[w][tid];
+    part[(int64_t)tid * gridDim.x + blockIdx.x] = v;
+  }
+}
+
 // One Pauli term with an arbitrary x-mask, untiled: every work item reads
 // psi_b and psi_{b^x} from HBM.  Used for terms whose X/Y support does not fit
 // in a tile.  Expectation partial sums per workgroup in part[blockIdx];
@@ -815,6 +893,28 @@ hipError_t svk_launch_energy(const double *terms, const double *coef, int nt, do
                              hipStream_t s) {
   hipLaunchKernelGGL(k_energy, dim3(1), dim3(64), 0, s, terms, coef, nt, out);
   return hipGetLastError();
+}
+
+hipError_t svk_launch_zexp(int dbl, const void *re, const void *im, int n, const PauliTermDev *terms,
+                           int nt, double *part, int grid, hipStream_t s) {
+  if (nt < 1 || nt > SVI_ZTERMS) return hipErrorInvalidValue;
+  const int64_t ch = dbl ? 2048 : 4096;
+  const int64_t N = (int64_t)1 << n;
+  if (N < ch) return hipErrorInvalidValue;
+  if (dbl)
+    hipLaunchKernelGGL(k_zexp<double>, dim3(grid), dim3(256), 0, s, (const double *)re,
+                       (const double *)im, N / ch, terms, nt, part);
+  else
+    hipLaunchKernelGGL(k_zexp<float>, dim3(grid), dim3(256), 0, s, (const float *)re,
+                       (const float *)im, N / ch, terms, nt, part);
+  return hipGetLastError();
+}
+
+int svk_zexp_occupancy(int dbl) {
+  int nb = 0;
+  hipError_t e = dbl ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_zexp<double>, 256, 0)
+                     : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_zexp<float>, 256, 0);
+  return (e == hipSuccess && nb > 0) ? nb : 1;
 }
 
 hipError_t svk_launch_energy_terms(const double *vals, const PauliTermDev *terms, int nt,

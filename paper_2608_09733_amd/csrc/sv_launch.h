@@ -38,6 +38,10 @@ hipError_t svk_launch_reduce_rows(const double *part, int nslots, int np, double
                                   hipStream_t s);
 hipError_t svk_launch_gather_grad(const double *slot_sum, const int32_t *row_ptr,
                                   const int32_t *slots, int np, double *grad, hipStream_t s);
+hipError_t svk_launch_zexp(int dbl, const void *re, const void *im, int n, const PauliTermDev *terms,
+                           int nt, double *part, int grid, hipStream_t s);
+int svk_zexp_occupancy(int dbl);
+#define SVI_ZTERMS_HOST 32
 hipError_t svk_launch_energy_terms(const double *vals, const PauliTermDev *terms, int nt,
                                    double *out, hipStream_t s);
 hipError_t svk_launch_energy(const double *terms, const double *coef, int nt, double *out,

@@ -307,3 +307,28 @@ def test_expectation_z_terms_and_lambda_large(sv):
         tr, er, _ = O.expect(n, ref, h)
         assert np.max(np.abs(t - tr)) <= TOL and abs(e - er) <= TOL
     st.close()
+
+
+@pytest.mark.parametrize("n,dtype", [(14, "c128"), (19, "c128"), (18, "c64")])
+def test_expectation_diagonal_stream(sv, n, dtype):
+    # more Z-only terms than one streamed read holds (two groups), strings on
+    # the lowest, middle and highest qubits, the identity term, and X/Y terms
+    # in the same call
+    circ = I.random_circuit(n, 50, seed=300 + n)
+    rng = np.random.default_rng(n)
+    spec = [("Z", [q], 0.5) for q in range(n)]
+    spec += [("ZZ", [q, (q + 7) % n], -0.25) for q in range(n)]
+    spec += [("ZZZ", [0, n // 2, n - 1], 1.5), ("I", [0], 2.0), ("XZ", [1, n - 1], 0.7)]
+    spec += [("".join(rng.choice(list("IZ"), n)), list(range(n)), float(rng.normal()))
+             for _ in range(6)]
+    ham = I.hamiltonian(n, spec)
+    assert sum(1 for x in ham.x if int(x) == 0) > 32
+    _say("expect diag", n, dtype, len(ham))
+    st = sv.State(n, dtype)
+    st.apply(circ.ops, circ.params, fuse=-1)
+    t, e = st.expect(ham)
+    st.close()
+    ref = O.run_circuit(circ)
+    tr, er, _ = O.expect(n, ref, ham)
+    tol = TOL if dtype == "c128" else 4 * TOL32
+    assert np.max(np.abs(t - tr)) <= tol and abs(e - er) <= tol * np.sum(np.abs(ham.c))

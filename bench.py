@@ -65,6 +65,32 @@ def cpu_baseline(circ, budget_s: float):
                       f"{el:.1f} s wall, plain C FP64 gate-by-gate"}
 
 
+def measured_traffic():
+    """Bytes per launch of the tile sweep from the committed counter summary
+    (FETCH_SIZE / WRITE_SIZE scaled by a plain copy), or None when the kernel
+    sources have changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "k_sweep_kron_30q_layered_fp64.md")
+    try:
+        txt = open(path).read()
+    except OSError:
+        return None
+    vals = {}
+    for line in txt.splitlines():
+        line = line.strip()
+        for key in ("traffic_bytes_per_launch:", "kernel_source_sha256:", "kernel_sources:"):
+            if line.startswith(key):
+                vals[key[:-1]] = line[len(key):].strip()
+    if len(vals) != 3:
+        return None
+    h = hashlib.sha256()
+    for f in vals["kernel_sources"].split():
+        h.update(open(os.path.join(ROOT, "paper_2608_09733_amd", "csrc", f), "rb").read())
+    if h.hexdigest() != vals["kernel_source_sha256"]:
+        return None
+    return float(vals["traffic_bytes_per_launch"])
+
+
 def _median_ms(fn, reps, torch):
     """Median over `reps` calls of fn(), each bracketed by events on the current stream."""
     import numpy as np
@@ -169,6 +195,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only run a plain 2 GiB device-to-device copy (counter calibration)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -182,6 +210,15 @@ def main():
     from paper_2608_09733_amd import sv
 
     torch.cuda.set_device(0)
+    if args.copy_probe:
+        # a plain copy of known size: 2 GiB read + 2 GiB written per dispatch
+        a = torch.ones(1 << 28, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        log(f"copy probe: 3 copies of {a.numel() * 8} bytes")
+        return
     n, L = args.n, args.layers
     circ = I.layered(n, L, seed=0)
     gates = len(circ.ops)
@@ -245,7 +282,7 @@ def main():
                    "sweeps": sweeps, "register_blocks": blocks,
                    "state_bytes": 16 * (1 << n)},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(),
                      "kernel": "svk::k_sweep_kron<double,13,3> (tile sweep)",
                      "bytes_per_launch": bytes_per_launch, "avg_launch_ms": avg_launch_ms,
                      "launches": launches},

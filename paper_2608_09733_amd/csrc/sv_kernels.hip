@@ -497,29 +497,57 @@ __global__ void __launch_bounds__(256) k_zexp(const T *re, const T *im, int64_t 
   constexpr int J = 4;
   constexpr int K = J * VN;
   constexpr int CH = NT * VN * J;                // amplitudes per chunk
+  constexpr int LCH = LV + 8 + 2;                // log2 CH
   using V4 = typename V4T<T>::type;
   __shared__ double wsum[NT / 64][SVI_ZTERMS];
+  __shared__ double wl[K][NT];                   // this thread's transform, column tid
   const int tid = threadIdx.x;
   const SVI_CONST PauliTermDev *tm = cptr(terms);
-  // this thread's sign bits (one per term) from its own index bits
+  // per term, hoisted out of the chunk loop: the z bits on the chunk index,
+  // the transform slot of its z bits on the register positions, and the sign
+  // from this thread's index bits (applied once at the end)
+  uint32_t zc[SVI_ZTERMS];
+  int zr[SVI_ZTERMS];
   uint32_t tpar = 0;
-  for (int t = 0; t < nt; t++)
-    tpar |= (uint32_t)(__builtin_popcountll(tm[t].z & ((uint64_t)tid * VN)) & 1) << t;
+#pragma unroll
+  for (int t = 0; t < SVI_ZTERMS; t++) {
+    const uint64_t z = t < nt ? tm[t].z : 0;
+    zc[t] = (uint32_t)(z >> LCH);
+    zr[t] = (int)(z & (VN - 1)) | (int)(((z >> (LV + 8)) & (J - 1)) << LV);
+    tpar |= (uint32_t)(__builtin_popcountll(z & ((uint64_t)tid * VN)) & 1) << t;
+  }
   double acc[SVI_ZTERMS];
 #pragma unroll
   for (int t = 0; t < SVI_ZTERMS; t++) acc[t] = 0.0;
-  for (int64_t ch = blockIdx.x; ch < nchunks; ch += gridDim.x) {
+  // software pipeline: the next chunk's loads are in flight while the
+  // current chunk's transform and term sums run
+  V4 nr[J], ni[J];
+  auto fetch = [&](int64_t ch) {
     const uint64_t cb = (uint64_t)ch * CH;
-    double p[K];
 #pragma unroll
     for (int j = 0; j < J; j++) {
       const uint64_t g = cb + (uint64_t)j * (NT * VN) + (uint64_t)tid * VN;
-      const V4 vr = *(const V4 *)(re + g);
-      const V4 vi = *(const V4 *)(im + g);
-      const T *r = (const T *)&vr, *i = (const T *)&vi;
-#pragma unroll
-      for (int v = 0; v < VN; v++) p[j * VN + v] = (double)r[v] * (double)r[v] + (double)i[v] * (double)i[v];
+      nr[j] = *(const V4 *)(re + g);
+      ni[j] = *(const V4 *)(im + g);
     }
+  };
+  if (blockIdx.x < nchunks) fetch(blockIdx.x);
+  for (int64_t ch = blockIdx.x; ch < nchunks; ch += gridDim.x) {
+    double p[K];
+#pragma unroll
+    for (int j = 0; j < J; j++) {
+      auto sq = [](T a, T b) { return (double)a * (double)a + (double)b * (double)b; };
+      if constexpr (VN == 2) {
+        p[j * 2] = sq(nr[j].x, ni[j].x);
+        p[j * 2 + 1] = sq(nr[j].y, ni[j].y);
+      } else {
+        p[j * 4] = sq(nr[j].x, ni[j].x);
+        p[j * 4 + 1] = sq(nr[j].y, ni[j].y);
+        p[j * 4 + 2] = sq(nr[j].z, ni[j].z);
+        p[j * 4 + 3] = sq(nr[j].w, ni[j].w);
+      }
+    }
+    if (ch + gridDim.x < nchunks) fetch(ch + gridDim.x);
 #pragma unroll
     for (int h = 1; h < K; h <<= 1)
 #pragma unroll
@@ -529,23 +557,23 @@ __global__ void __launch_bounds__(256) k_zexp(const T *re, const T *im, int64_t 
           p[x] = a + b;
           p[x + h] = a - b;
         }
+    // the transform goes through this thread's own LDS column, so each term
+    // picks its slot with one indexed read instead of a select chain
+#pragma unroll
+    for (int x = 0; x < K; x++) wl[x][tid] = p[x];
+    const uint32_t chl = (uint32_t)ch;
+    // all SVI_ZTERMS slots run unconditionally (slots >= nt read slot 0 and
+    // are never written out), so the reads batch without branches
 #pragma unroll
     for (int t = 0; t < SVI_ZTERMS; t++) {
-      if (t < nt) {
-        const uint64_t z = tm[t].z;
-        const int zr = (int)(z & (VN - 1)) | (int)(((z >> (LV + 8)) & (J - 1)) << LV);
-        double w = 0.0;
-#pragma unroll
-        for (int x = 0; x < K; x++) w = zr == x ? p[x] : w;
-        const bool neg = ((tpar >> t) & 1) ^ (uint32_t)(__builtin_popcountll(cb & z) & 1);
-        acc[t] += neg ? -w : w;
-      }
+      const double sg = (__builtin_popcount(chl & zc[t]) & 1) ? -1.0 : 1.0;
+      acc[t] = fma(sg, wl[zr[t]][tid], acc[t]);
     }
   }
 #pragma unroll
   for (int t = 0; t < SVI_ZTERMS; t++) {
     if (t < nt) {
-      const double v = wave_sum(acc[t]);
+      const double v = wave_sum((tpar >> t) & 1 ? -acc[t] : acc[t]);
       if ((tid & 63) == 0) wsum[tid >> 6][t] = v;
     }
   }

@@ -86,6 +86,14 @@ __device__ __forceinline__ uint64_t tile_base(int64_t tile, int c, const int32_t
   return insert_zeros64(x, hb, nh);
 }
 
+// Tile-local index whose bits land on output index i under the output bit
+// permutation pm (output bit k <- bit pm[k]).
+__device__ __forceinline__ int perm_bits(int i, const int32_t *pm, int m) {
+  int j = 0;
+  for (int b = 0; b < m; b++) j |= ((i >> b) & 1) << pm[b];
+  return j;
+}
+
 // ------------------------------------------------------------ micro-ops
 // All group arrays are indexed with compile-time indices only.
 
@@ -604,26 +612,29 @@ __global__ void __launch_bounds__(1 << (M - R)) k_sweep(SweepArgs a) {
       }
     }
 
-    // ---- store tile
+    // ---- store tile (through the output bit permutation of a remapping sweep)
+    const bool operm = (a.flags & SW_OPERM) != 0;
 #pragma unroll
     for (int s = 0; s < NS; s++) {
       T *pr = s == 0 ? pre0 : pre1;
       T *pi = s == 0 ? pim0 : pim1;
       if (vec) {
+        const int so1 = operm ? swz<T>(perm_bits(1, a.operm, m)) : 1;
+        const int so2 = operm ? swz<T>(perm_bits(2, a.operm, m)) : 2;
 #pragma unroll
         for (int k = 0; k < NIT; k++) {
           const int i = (tid + k * NT) * VN;
           if (i < ntile_el) {
             const uint64_t g = base + roff[k];
-            const int si = tsw ^ swz<T>(k * NT * VN);
+            const int si = operm ? swz<T>(perm_bits(i, a.operm, m)) : tsw ^ swz<T>(k * NT * VN);
             V4 vr, vi;
             if constexpr (VN == 2) {
-              const C2 p0 = lds[s][si], p1 = lds[s][si ^ 1];
+              const C2 p0 = lds[s][si], p1 = lds[s][si ^ so1];
               vr = V4{p0.x, p1.x};
               vi = V4{p0.y, p1.y};
             } else {
-              const C2 p0 = lds[s][si], p1 = lds[s][si ^ 1];
-              const C2 p2 = lds[s][si ^ 2], p3 = lds[s][si ^ 3];
+              const C2 p0 = lds[s][si], p1 = lds[s][si ^ so1];
+              const C2 p2 = lds[s][si ^ so2], p3 = lds[s][si ^ so1 ^ so2];
               vr = V4{p0.x, p1.x, p2.x, p3.x};
               vi = V4{p0.y, p1.y, p2.y, p3.y};
             }
@@ -634,7 +645,7 @@ __global__ void __launch_bounds__(1 << (M - R)) k_sweep(SweepArgs a) {
       } else {
         for (int i = tid; i < ntile_el; i += NT) {
           const uint64_t g = base + spread_row(i >> c, hb_s, nh) + (uint64_t)(i & ((1 << c) - 1));
-          const C2 p = lds[s][swz<T>(i)];
+          const C2 p = lds[s][swz<T>(operm ? perm_bits(i, a.operm, m) : i)];
           pr[g] = p.x;
           pi[g] = p.y;
         }
@@ -697,6 +708,16 @@ __global__ void __launch_bounds__(1 << (M - R)) k_sweep_kron(SweepArgs a) {
   const int tsw = swz<T>(tid * VN);
   T *const pre = (T *)a.re, *const pim = (T *)a.im;
   char *const lb = (char *)lds;
+  // LDS slots the stores read: the tile's own order, or the output bit
+  // permutation of a remapping sweep (both linear, so one base per vector
+  // plus a per-element offset)
+  const bool operm = (a.flags & SW_OPERM) != 0;
+  int ss[NIT];
+#pragma unroll
+  for (int k = 0; k < NIT; k++)
+    ss[k] = operm ? swz<T>(perm_bits((tid + k * NT) * VN, a.operm, m)) : tsw ^ swz<T>(k * NT * VN);
+  const int so1 = operm ? swz<T>(perm_bits(1, a.operm, m)) : 1;
+  const int so2 = operm ? swz<T>(perm_bits(2, a.operm, m)) : 2;
 
   // Software pipeline: the next tile's HBM loads are issued into registers
   // before the current tile's stages run, so their latency hides behind the
@@ -776,14 +797,14 @@ __global__ void __launch_bounds__(1 << (M - R)) k_sweep_kron(SweepArgs a) {
         const int i = (tid + k * NT) * VN;
         if (i < ntile_el) {
           const uint64_t g = base + roff[k];
-          const int si = tsw ^ swz<T>(k * NT * VN);
+          const int si = ss[k];
           V4 vr, vi;
           if constexpr (VN == 2) {
-            const C2 p0 = lds[si], p1 = lds[si ^ 1];
+            const C2 p0 = lds[si], p1 = lds[si ^ so1];
             vr = V4{p0.x, p1.x};
             vi = V4{p0.y, p1.y};
           } else {
-            const C2 p0 = lds[si], p1 = lds[si ^ 1], p2 = lds[si ^ 2], p3 = lds[si ^ 3];
+            const C2 p0 = lds[si], p1 = lds[si ^ so1], p2 = lds[si ^ so2], p3 = lds[si ^ so1 ^ so2];
             vr = V4{p0.x, p1.x, p2.x, p3.x};
             vi = V4{p0.y, p1.y, p2.y, p3.y};
           }
@@ -794,7 +815,7 @@ __global__ void __launch_bounds__(1 << (M - R)) k_sweep_kron(SweepArgs a) {
     } else {
       for (int i = tid; i < ntile_el; i += NT) {
         const uint64_t g = base + spread_row(i >> c, hb_s, nh) + (uint64_t)(i & ((1 << c) - 1));
-        const C2 p = lds[swz<T>(i)];
+        const C2 p = lds[swz<T>(operm ? perm_bits(i, a.operm, m) : i)];
         pre[g] = p.x;
         pim[g] = p.y;
       }

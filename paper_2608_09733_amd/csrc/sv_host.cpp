@@ -262,7 +262,10 @@ static int closure_kron(const std::vector<GateRec> &recs, const std::vector<int>
 
 struct SweepP {
   int m = 0, c = 0, nh = 0;
-  int hb[SVI_MMAX] = {0};
+  int hb[SVI_MMAX] = {0};     // physical bit positions of tile bits c..m-1
+  int lq[SVI_MMAX] = {0};     // logical qubit held by each tile-local bit (input side)
+  bool operm = false;         // the sweep permutes tile bits on output
+  int perm[SVI_MMAX] = {0};   // output tile bit k takes input tile bit perm[k]
   std::vector<StageP> stages;
 };
 
@@ -311,19 +314,37 @@ static uint64_t first_blocked_qubits(const std::vector<GateRec> &recs, const std
   return 0;
 }
 
+// Tile-local bit of logical qubit q (-1 if q is not in the tile).
 static int tile_pos(const SweepP &sw, int q) {
-  if (q < sw.c) return q;
-  for (int k = 0; k < sw.nh; k++)
-    if (sw.hb[k] == q) return sw.c + k;
+  for (int p = 0; p < sw.m; p++)
+    if (sw.lq[p] == q) return p;
   return -1;
 }
 
-static void set_tile(SweepP &sw, int n, uint64_t T, int c) {
+// Tile over logical qubit set T with physical layout occ (physical position ->
+// logical qubit; identity when null): the c lowest physical positions, whose
+// occupants must lie in T, plus the physical positions of T's other qubits.
+static void set_tile(SweepP &sw, int n, uint64_t T, int c, const int *occ = nullptr) {
+  if (popc(T) > SVI_MMAX) abort();   // planner invariant: a tile holds at most SVI_MMAX qubits
   sw.c = c;
   sw.nh = 0;
-  for (int q = c; q < n; q++)
-    if (T & (1ull << q)) sw.hb[sw.nh++] = q;
+  for (int p = 0; p < c; p++) sw.lq[p] = occ ? occ[p] : p;
+  for (int p = c; p < n; p++) {
+    const int q = occ ? occ[p] : p;
+    if (T & (1ull << q)) {
+      sw.hb[sw.nh] = p;
+      sw.lq[c + sw.nh] = q;
+      sw.nh++;
+    }
+  }
   sw.m = c + sw.nh;
+}
+
+// Logical qubits held by the tile, as a mask.
+static uint64_t tile_mask(const SweepP &sw) {
+  uint64_t T = 0;
+  for (int p = 0; p < sw.m; p++) T |= 1ull << sw.lq[p];
+  return T;
 }
 
 // Split one sweep's records into register stages of <= R qubits.
@@ -333,9 +354,7 @@ static void plan_stages(const std::vector<GateRec> &recs, const std::vector<int>
   std::vector<char> veto(recs.size(), 0);
   for (int r : take)
     if (recs[r].mo == MO_DENSE) veto[r] = 1;
-  uint64_t Ttile = 0;
-  for (int q = 0; q < sw.c; q++) Ttile |= 1ull << q;
-  for (int k = 0; k < sw.nh; k++) Ttile |= 1ull << sw.hb[k];
+  const uint64_t Ttile = tile_mask(sw);
   size_t left = take.size();
   const int mm = std::max(sw.m, R);
   while (left) {
@@ -407,27 +426,80 @@ static void plan_stages(const std::vector<GateRec> &recs, const std::vector<int>
   }
 }
 
-// AUTO planner: DAG-aware tile clustering.
+// Output layout of a remapping sweep: the tile's positions get the occupants
+// in `want` (physical position -> logical qubit, tile positions only); records
+// the tile-local output permutation in sw and applies it to occ.
+static void set_output_layout(SweepP &sw, std::vector<int> &occ, const std::vector<int> &want) {
+  bool change = false;
+  for (int k = 0; k < sw.m; k++) {
+    const int phys = k < sw.c ? k : sw.hb[k - sw.c];
+    const int q = want[phys];
+    sw.perm[k] = tile_pos(sw, q);
+    if (sw.perm[k] != k) change = true;
+  }
+  sw.operm = change;
+  for (int k = 0; k < sw.m; k++) {
+    const int phys = k < sw.c ? k : sw.hb[k - sw.c];
+    occ[phys] = want[phys];
+  }
+}
+
+// Replays a plan's qubit layout: every tile's logical map matches the layout
+// it reads, every output permutation is a bijection of the tile bits, and the
+// plan ends in the identity layout.
+static bool layout_consistent(const std::vector<SweepP> &sweeps, int n) {
+  std::vector<int> occ(n);
+  for (int p = 0; p < n; p++) occ[p] = p;
+  for (const SweepP &sw : sweeps) {
+    if (sw.m > SVI_MMAX || sw.m != sw.c + sw.nh) return false;
+    std::vector<int> nxt = occ;
+    uint32_t used = 0;
+    for (int k = 0; k < sw.m; k++) {
+      const int phys = k < sw.c ? k : sw.hb[k - sw.c];
+      if (phys < 0 || phys >= n || sw.lq[k] != occ[phys]) return false;
+      const int src = sw.operm ? sw.perm[k] : k;
+      if (src < 0 || src >= sw.m || (used >> src) & 1) return false;
+      used |= 1u << src;
+      nxt[phys] = sw.lq[src];
+    }
+    occ = nxt;
+  }
+  for (int p = 0; p < n; p++)
+    if (occ[p] != p) return false;
+  return true;
+}
+
+// AUTO planner: DAG-aware tile clustering.  With `remap`, the c low physical
+// positions (contiguous rows in HBM) are not tied to qubits 0..c-1: at the end
+// of each sweep the tile's qubits are permuted so that the low positions hold
+// the qubits the earliest pending gates need, and the last sweep (or one extra
+// sweep) restores the identity layout.
 static void plan_auto(const std::vector<GateRec> &recs, int n, const Tiling &tl,
-                      std::vector<SweepP> &out, double cost_cap, bool kron = false) {
+                      std::vector<SweepP> &out, double cost_cap, bool kron = false,
+                      bool remap = false) {
   const int M = std::min(tl.M, n);
   const int c = std::min(tl.c, n);
   std::vector<int> cand(recs.size());
   for (size_t i = 0; i < recs.size(); i++) cand[i] = (int)i;
   std::vector<char> done(recs.size(), 0);
   size_t left = recs.size();
-  uint64_t low = c >= 64 ? ~0ull : ((1ull << c) - 1);
+  std::vector<int> occ(n);
+  for (int p = 0; p < n; p++) occ[p] = p;
+  // restoring the layout needs the low positions and the homes of their
+  // occupants in one tile
+  remap = remap && n > M && 2 * c <= M;
   size_t start = 0;
   while (left) {
     while (start < cand.size() && done[cand[start]]) start++;
     std::vector<int> sub(cand.begin() + start, cand.end());
-    uint64_t T = low;
+    uint64_t T = 0;
+    for (int p = 0; p < c; p++) T |= 1ull << occ[p];
     if (n <= M) {
       T = n >= 64 ? ~0ull : ((1ull << n) - 1);
     } else {
       for (int step = c; step < M; step++) {
         int best = -1, bestv = closure(recs, sub, done, T, nullptr, nullptr, cost_cap);
-        for (int q = c; q < n; q++) {
+        for (int q = 0; q < n; q++) {
           if (T & (1ull << q)) continue;
           int v = closure(recs, sub, done, T | (1ull << q), nullptr, nullptr, cost_cap);
           if (v > bestv) { bestv = v; best = q; }
@@ -441,7 +513,7 @@ static void plan_auto(const std::vector<GateRec> &recs, int n, const Tiling &tl,
         T |= 1ull << best;
       }
       // fill the tile to M qubits (larger tiles cost nothing extra)
-      for (int q = c; q < n && popc(T) < M; q++) T |= 1ull << q;
+      for (int q = 0; q < n && popc(T) < M; q++) T |= 1ull << q;
     }
     std::vector<int> take;
     closure(recs, sub, done, T, &take, nullptr, cost_cap);
@@ -450,10 +522,109 @@ static void plan_auto(const std::vector<GateRec> &recs, int n, const Tiling &tl,
       take.push_back(sub[0]);
     }
     SweepP sw;
-    set_tile(sw, n, T, c);
+    set_tile(sw, n, T, c, occ.data());
     plan_stages(recs, take, sw, tl.R, n, kron);
     for (int r : take) { done[r] = 1; left--; }
+    if (remap) {
+      std::vector<int> want = occ;
+      if (!left) {
+        for (int k = 0; k < sw.m; k++) {
+          const int phys = k < sw.c ? k : sw.hb[k - sw.c];
+          want[phys] = phys;
+        }
+        // a qubit whose home position is outside this tile cannot go home here
+        bool ok = true;
+        for (int k = 0; k < sw.m; k++) {
+          const int phys = k < sw.c ? k : sw.hb[k - sw.c];
+          if (tile_pos(sw, phys) < 0) ok = false;
+        }
+        if (!ok) want = occ;
+      } else {
+        // Layout invariant: a high position p holds qubit p or one of the
+        // qubits 0..c-1, so at most c high positions are ever displaced and the
+        // identity layout comes back within one tile.
+        // Wanted low occupants: tile qubits of the earliest pending records.
+        std::vector<int> pick;
+        uint64_t seen = 0;
+        for (size_t i = start; i < cand.size() && (int)pick.size() < c; i++) {
+          const int r = cand[i];
+          if (done[r]) continue;
+          uint64_t q = recs[r].qmask & T & ~seen;
+          while (q && (int)pick.size() < c) {
+            const int b = __builtin_ctzll(q);
+            q &= q - 1;
+            pick.push_back(b);
+            seen |= 1ull << b;
+          }
+        }
+        uint64_t lowset = 0;
+        for (int p = 0; p < c; p++) lowset |= 1ull << occ[p];
+        std::vector<int> incoming;
+        for (int q : pick)
+          if (!(lowset & (1ull << q))) incoming.push_back(q);
+        // low positions whose occupant is not wanted, evictable ones only: an
+        // outgoing qubit >= c must go home, so its home position must be in the tile
+        auto has_pos = [&](int phys) {
+          if (phys < sw.c) return true;
+          for (int k = 0; k < sw.nh; k++)
+            if (sw.hb[k] == phys) return true;
+          return false;
+        };
+        std::vector<int> freed;
+        for (int p = 0; p < c; p++) {
+          const int x = occ[p];
+          if (seen & (1ull << x)) continue;
+          if (x >= c && !has_pos(x)) continue;
+          freed.push_back(p);
+        }
+        const size_t moves = std::min(freed.size(), incoming.size());
+        std::vector<int> avail, place;
+        for (size_t i = 0; i < moves; i++) {
+          const int q = incoming[i];
+          for (int k = 0; k < sw.m; k++) {
+            const int phys = k < sw.c ? k : sw.hb[k - sw.c];
+            if (occ[phys] == q) avail.push_back(phys);
+          }
+          want[freed[i]] = q;
+        }
+        for (size_t i = 0; i < moves; i++) {
+          const int x = occ[freed[i]];
+          if (x < c) {
+            place.push_back(x);
+            continue;
+          }
+          want[x] = x;   // back home
+          auto it = std::find(avail.begin(), avail.end(), x);
+          if (it != avail.end()) avail.erase(it);
+          else place.push_back(occ[x]);   // the low qubit parked there moves on
+        }
+        for (size_t i = 0; i < avail.size(); i++) want[avail[i]] = place[i];
+      }
+      set_output_layout(sw, occ, want);
+    }
     out.push_back(std::move(sw));
+  }
+  if (remap) {
+    // restore the identity layout with one sweep that holds every displaced position
+    uint64_t D = 0;
+    for (int p = 0; p < n; p++)
+      if (occ[p] != p) D |= 1ull << p;
+    if (D) {
+      uint64_t T = 0;
+      for (int p = 0; p < c; p++) T |= 1ull << occ[p];
+      for (int p = 0; p < n; p++)
+        if (D & (1ull << p)) T |= 1ull << occ[p];
+      for (int q = 0; q < n && popc(T) < M; q++) T |= 1ull << q;
+      SweepP sw;
+      set_tile(sw, n, T, c, occ.data());
+      std::vector<int> want = occ;
+      for (int k = 0; k < sw.m; k++) {
+        const int phys = k < sw.c ? k : sw.hb[k - sw.c];
+        want[phys] = phys;
+      }
+      set_output_layout(sw, occ, want);
+      out.push_back(std::move(sw));
+    }
   }
 }
 
@@ -589,6 +760,10 @@ static void emit_sweep(Plan &P, std::vector<GateRec> &recs, const SweepP &sw, in
   a.nh = sw.nh;
   for (int k = 0; k < SVI_MMAX; k++) a.hb[k] = k < sw.nh ? sw.hb[k] : 0;
   a.flags = flags;
+  if (sw.operm) {
+    a.flags |= SW_OPERM;
+    for (int k = 0; k < SVI_MMAX; k++) a.operm[k] = k < sw.m ? sw.perm[k] : 0;
+  }
   a.ntiles = (int64_t)1 << (n - sw.m);
   a.stage_begin = (int)P.stages.size();
   a.gslot_begin = gslot_base;
@@ -1121,8 +1296,26 @@ static void collect_user_mats(Plan &P, const sv_op *ops, int n_ops) {
 }
 
 // mode: 0 = one sweep per gate, 2..5 = paper fusion width, -1 = AUTO
+// AUTO plan with and without qubit remapping; the one with fewer sweeps (then
+// fewer register stages) wins.
+static void plan_auto_best(const std::vector<GateRec> &recs, int n, const Tiling &tl,
+                           std::vector<SweepP> &out, bool allow_remap) {
+  plan_auto(recs, n, tl, out, 1e300, true, false);
+  if (!allow_remap) return;
+  std::vector<SweepP> alt;
+  plan_auto(recs, n, tl, alt, 1e300, true, true);
+  auto stages = [](const std::vector<SweepP> &v) {
+    size_t s = 0;
+    for (auto &w : v) s += w.stages.size();
+    return s;
+  };
+  if (!layout_consistent(alt, n)) return;
+  if (alt.size() < out.size() || (alt.size() == out.size() && stages(alt) < stages(out)))
+    out.swap(alt);
+}
+
 static sv_status build_forward_plan(int mode, int n, bool dbl, const Tiling &tl, const sv_op *ops,
-                                    int n_ops, int n_params, Plan &P) {
+                                    int n_ops, int n_params, Plan &P, bool remap = true) {
   P.n = n;
   P.dbl = dbl;
   P.M = tl.M;
@@ -1156,7 +1349,7 @@ static sv_status build_forward_plan(int mode, int n, bool dbl, const Tiling &tl,
     }
   } else {
     std::vector<SweepP> sweeps;
-    if (mode < 0) plan_auto(recs, n, tl, sweeps, 1e300, true);
+    if (mode < 0) plan_auto_best(recs, n, tl, sweeps, remap);
     else plan_fused(recs, n, tl, mode, sweeps, true);
     for (const SweepP &sw : sweeps) {
       int used = 0;
@@ -1864,10 +2057,11 @@ extern "C" sv_status sv_plan_stats(int32_t n, const sv_op *ops, int32_t n_ops, i
     if (n_blocks) *n_blocks = (int)live.size();
     return SV_OK;
   } else if (fuse_width < 0) {
-    plan_auto(live, n, tl, sweeps, 1e300, true);
+    plan_auto_best(live, n, tl, sweeps, true);
   } else {
     plan_fused(live, n, tl, fuse_width, sweeps, true);
   }
+  if (!layout_consistent(sweeps, n)) return fail(SV_EINVAL, "internal: inconsistent qubit layout in plan");
   for (auto &sw : sweeps) blocks += (int)sw.stages.size();
   if (n_sweeps) *n_sweeps = (int)sweeps.size();
   if (n_blocks) *n_blocks = blocks;
@@ -2006,7 +2200,7 @@ extern "C" sv_status sv_batch_plan(const sv_circuit_desc *circuits, int32_t n_ci
     const size_t plane = (((size_t)1 << n) * es + 255) & ~(size_t)255;
     state_bytes += 2 * plane;
     Plan P;
-    s = build_forward_plan(-1, n, dbl, tl, d.ops, d.n_ops, d.n_params, P);
+    s = build_forward_plan(-1, n, dbl, tl, d.ops, d.n_ops, d.n_params, P, false);
     if (s) return s;
     if (P.M != M || P.R != R) return fail(SV_EINVAL, "internal: plan tiling mismatch");
     for (const Step &st : P.steps)

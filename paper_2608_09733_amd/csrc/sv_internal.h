@@ -103,9 +103,11 @@ struct SweepArgs {
   int32_t flags;             // SW_INIT_ZERO ...
   int32_t gslot_begin, n_gslots;  // adjoint: gradient slots used by this sweep
   int64_t ntiles;
+  int32_t operm[SVI_MMAX];   // SW_OPERM: output tile bit k takes LDS tile bit operm[k]
 };
 
 #define SW_INIT_ZERO 1       // synthesise |0..0> instead of loading state 0
+#define SW_OPERM 2           // permute tile bits on the way out (qubit remapping)
 
 // Coefficient descriptors (built on the device from the parameter vector).
 enum {

@@ -154,3 +154,24 @@ def test_batch_host_planning_completes(sv):
     for cs, hs, gb in ((circs, hams, 3), (circs, hams, 5), (mixed, mhams, 5)):
         st, msg = _batch_plan_status(sv, cs, hs, group_bits=gb)
         assert st == -6, (st, msg)
+
+
+def test_remapping_plans_are_consistent(sv):
+    # every AUTO plan (with or without qubit remapping) replays to the identity
+    # layout; sv_plan_stats checks that and fails otherwise
+    ops = I.layered_structure(30, 20)
+    for M in (11, 12, 13):
+        for c in range(1, 9):
+            for R in (3, 4, 5):
+                s, b = sv.plan_stats(30, ops, -1, M, c, R)
+                assert 0 < s <= b
+    for seed in range(30):
+        n = 14 + seed % 9
+        circ = I.random_circuit(n, 150, seed=seed, max_qubits=3)
+        for M, c in ((13, 5), (12, 4), (13, 6), (11, 5), (13, 3)):
+            sv.plan_stats(n, circ.ops, -1, M, c, 3)
+
+
+def test_remapping_reduces_sweeps_on_layered_ansatz(sv):
+    ops = I.layered_structure(30, 20)
+    assert sv.plan_stats(30, ops, -1, 13, 4, 3)[0] <= 24

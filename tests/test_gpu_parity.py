@@ -332,3 +332,18 @@ def test_expectation_diagonal_stream(sv, n, dtype):
     tr, er, _ = O.expect(n, ref, ham)
     tol = TOL if dtype == "c128" else 4 * TOL32
     assert np.max(np.abs(t - tr)) <= tol and abs(e - er) <= tol * np.sum(np.abs(ham.c))
+
+
+@pytest.mark.parametrize("tiling", [(13, 3, 4), (12, 3, 3), (13, 3, 5), (12, 4, 4)])
+def test_remapped_layout_plans(sv, tiling):
+    # tilings whose AUTO plans permute qubits among tile positions between
+    # sweeps and restore the layout at the end
+    n = 20
+    circ = I.layered(n, 8, seed=11)
+    _say("remap", tiling)
+    psi = _forward(sv, circ, -1, tiling=tiling)
+    ref = O.run_circuit(circ)
+    assert np.max(np.abs(psi - ref)) <= TOL
+    circ2 = I.random_circuit(18, 120, seed=12, max_qubits=3)
+    psi2 = _forward(sv, circ2, -1, tiling=tiling)
+    assert np.max(np.abs(psi2 - O.run_circuit(circ2))) <= TOL

@@ -106,7 +106,7 @@ def _median_ms(fn, reps, torch):
     return float(np.median(ts)), float(np.percentile(ts, 75) - np.percentile(ts, 25))
 
 
-def side_configs(sv, I, torch):
+def side_configs(sv, I, torch, serving=True):
     """The other workloads of the method at their own shapes: small-state
     latency (12 qubits), adjoint gradient (20-qubit HEA, TFIM), and the ragged
     batch of 512 circuits as one persistent launch vs the per-circuit loop."""
@@ -150,7 +150,7 @@ def side_configs(sv, I, torch):
     b.results()
     ms, iqr = _median_ms(lambda: b.run(graph=True), 5, torch)
     b.check()
-    units, sweeps, updates = b.stats()
+    units, sweeps, updates, nbytes = b.stats()
     b.close()
     states = [sv.State(c.n) for c in circs]
 
@@ -166,9 +166,12 @@ def side_configs(sv, I, torch):
     out["batch_512_ragged"] = {"ms_median": ms, "ms_iqr": iqr, "circuits_per_s": 512 / (ms / 1e3),
                                "updates_per_s": updates / (ms / 1e3), "updates": updates,
                                "work_units": units, "sweeps": sweeps, "tiling": tune,
+                               "algorithmic_bytes": nbytes, "hbm_gbs": nbytes / (ms / 1e3) / 1e9,
                                "plain_loop_ms": pms, "speedup_vs_plain_loop": pms / ms}
     log(f"batch 512: {ms:.1f} ms ({updates / (ms / 1e3):.3e} upd/s), plain loop {pms:.1f} ms, "
         f"tiling {tune}")
+    if not serving:
+        return out
     # serving: Poisson arrivals at 200 req/s, n log-uniform in [10, 28], TFIM,
     # (E, grad) per request; 4 lanes vs serial FIFO, bounded trace length
     from paper_2608_09733_amd import serving as S
@@ -195,6 +198,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--side-only", action="store_true",
+                    help="only the side workloads (12-qubit latency, adjoint, batch), no serving")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 2 GiB device-to-device copy (counter calibration)")
     args = ap.parse_args()
@@ -218,6 +223,11 @@ def main():
             b.copy_(a)
         torch.cuda.synchronize()
         log(f"copy probe: 3 copies of {a.numel() * 8} bytes")
+        return
+    if args.side_only:
+        from paper_2608_09733_amd import inputs as I
+        from paper_2608_09733_amd import sv
+        print(json.dumps(side_configs(sv, I, torch, serving=False)), flush=True)
         return
     n, L = args.n, args.layers
     circ = I.layered(n, L, seed=0)

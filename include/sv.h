@@ -263,9 +263,12 @@ sv_status sv_batch_state(sv_batch *b, int32_t circuit, void **re, void **im);
 sv_status sv_batch_copy_results(sv_batch *b, double *out, void *hip_stream);
 sv_status sv_batch_copy_state(sv_batch *b, int32_t circuit, void *re, void *im, void *hip_stream);
 
-/* Statistics: work units in the queue, total sweeps, and the sum over
- * circuits of n_ops * 2^n (gate-amplitude updates). */
-sv_status sv_batch_stats(const sv_batch *b, int64_t *units, int64_t *sweeps, double *updates);
+/* Statistics: work units in the queue, total sweeps, the sum over circuits
+ * of n_ops * 2^n (gate-amplitude updates), and the algorithmic HBM bytes of
+ * one run (each sweep reads and writes both planes, the first only writes;
+ * each Pauli pass reads both planes).  Any output may be NULL. */
+sv_status sv_batch_stats(const sv_batch *b, int64_t *units, int64_t *sweeps, double *updates,
+                         double *bytes);
 
 /* Wait for the device, then release the batch and its device memory. */
 sv_status sv_batch_free(sv_batch *b);

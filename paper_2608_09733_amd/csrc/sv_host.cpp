@@ -2086,6 +2086,7 @@ struct sv_batch {
   int nunits = 0;
   int64_t total_sweeps = 0;
   double updates = 0.0;
+  double bytes = 0.0;                // algorithmic HBM bytes of one run
   std::vector<int> nq;
   std::vector<int64_t> param_off;    // per circuit; [nc] = total
   std::vector<int64_t> n_user_params;
@@ -2279,6 +2280,8 @@ extern "C" sv_status sv_batch_plan(const sv_circuit_desc *circuits, int32_t n_ci
     }
     b->total_sweeps += (int64_t)csw.size();
     b->updates += (double)d.n_ops * (double)((int64_t)1 << n);
+    // each sweep reads and writes both planes (the first one only writes)
+    b->bytes += (double)(4 * (int64_t)csw.size() - 2) * (double)es * (double)((int64_t)1 << n);
 
     // Pauli passes: one level after the last sweep
     if (d.n_terms > 0) {
@@ -2321,6 +2324,7 @@ extern "C" sv_status sv_batch_plan(const sv_circuit_desc *circuits, int32_t n_ci
         }
       }
       levels[k].push_back(std::move(lu));
+      b->bytes += 2.0 * (double)pp.passes.size() * (double)es * (double)((int64_t)1 << n);
     }
   }
   b->param_off[n_circuits] = nparam;
@@ -2574,11 +2578,12 @@ extern "C" sv_status sv_batch_copy_state(sv_batch *b, int32_t circuit, void *re,
 }
 
 extern "C" sv_status sv_batch_stats(const sv_batch *b, int64_t *units, int64_t *sweeps,
-                                    double *updates) {
+                                    double *updates, double *bytes) {
   if (!b) return fail(SV_EINVAL, "null batch");
   if (units) *units = b->nunits;
   if (sweeps) *sweeps = b->total_sweeps;
   if (updates) *updates = b->updates;
+  if (bytes) *bytes = b->bytes;
   return SV_OK;
 }
 

@@ -93,7 +93,7 @@ def lib():
         "sv_batch_check": (C.c_int, [vp, vp]),
         "sv_batch_set_spin_limit": (C.c_int, [vp, i32]),
         "sv_batch_state": (C.c_int, [vp, i32, C.POINTER(vp), C.POINTER(vp)]),
-        "sv_batch_stats": (C.c_int, [vp, C.POINTER(i64), C.POINTER(i64), dp]),
+        "sv_batch_stats": (C.c_int, [vp, C.POINTER(i64), C.POINTER(i64), dp, dp]),
         "sv_batch_free": (C.c_int, [vp]),
         "sv_batch_copy_results": (C.c_int, [vp, dp, vp]),
         "sv_batch_autotune": (C.c_int, [C.POINTER(SvCircuitDesc), i32, C.c_int, dp, i32, vp,
@@ -425,7 +425,8 @@ class Batch:
                                          i.ctypes.data_as(C.c_void_p), _stream_ptr(stream)))
         return r.astype(np.float64) + 1j * i.astype(np.float64)
 
-    def stats(self) -> Tuple[int, int, float]:
-        u, s, up = C.c_int64(), C.c_int64(), C.c_double()
-        _check(lib().sv_batch_stats(self.h, C.byref(u), C.byref(s), C.byref(up)))
-        return u.value, s.value, up.value
+    def stats(self) -> Tuple[int, int, float, float]:
+        """(work units, sweeps, gate-amplitude updates, algorithmic HBM bytes) of one run."""
+        u, s, up, by = C.c_int64(), C.c_int64(), C.c_double(), C.c_double()
+        _check(lib().sv_batch_stats(self.h, C.byref(u), C.byref(s), C.byref(up), C.byref(by)))
+        return u.value, s.value, up.value, by.value

@@ -297,6 +297,10 @@ sv_status sv_plan_stats(int32_t n_qubits, const sv_op *ops, int32_t n_ops, int32
  * combination without a compiled kernel is SV_EINVAL. */
 sv_status sv_set_tiling(sv_state *st, int32_t tile_bits, int32_t low_bits, int32_t group_bits);
 
+/* The same for the backward sweeps of sv_adjoint_grad (two states per tile). */
+sv_status sv_set_adjoint_tiling(sv_state *st, int32_t tile_bits, int32_t low_bits,
+                                int32_t group_bits);
+
 /* Greedy in-order fusion (paper Section 9.2 ablation planner): block id per
  * op into block_of (host array of n_ops), returns the block count in *n_blocks. */
 sv_status sv_fuse_blocks(const sv_op *ops, int32_t n_ops, int32_t width, int32_t *block_of,

@@ -347,24 +347,39 @@ __device__ __forceinline__ void mo_fastr(T *re, T *im, CP cf) {
 #undef SVI_FR
 }
 
-// Static Kronecker stage: s * D_after * (R~_{R-1} (x) ... (x) R~_0) * D_before.
+// Static Kronecker stage: s * D_after * (R~_{R-1} (x) ... (x) R~_0) * D_before,
+// in three parts so that gradient terms can be taken between them.
 template <typename T, int R, typename CP>
-__device__ __forceinline__ void kron_stage(T *re, T *im, CP cf, uint32_t rmask, int dflags) {
-  constexpr int G = 1 << R;
-  CP tb = cf + 4 * R;
-  CP ta = tb + 2 * G;
-  if (dflags & 1) mo_diagt<T, R>(re, im, tb);
+__device__ __forceinline__ void kron_pre(T *re, T *im, CP cf, int dflags) {
+  if (dflags & 1) mo_diagt<T, R>(re, im, cf + 4 * R);
+}
+
+template <typename T, int R, typename CP>
+__device__ __forceinline__ void kron_rot(T *re, T *im, CP cf, uint32_t rmask) {
   if (rmask & 1u) mo_fastr<T, R, 0>(re, im, cf + 0);
   if (rmask & 2u) mo_fastr<T, R, 1>(re, im, cf + 4);
   if constexpr (R > 2) { if (rmask & 4u) mo_fastr<T, R, 2>(re, im, cf + 8); }
   if constexpr (R > 3) { if (rmask & 8u) mo_fastr<T, R, 3>(re, im, cf + 12); }
   if constexpr (R > 4) { if (rmask & 16u) mo_fastr<T, R, 4>(re, im, cf + 16); }
+}
+
+template <typename T, int R, typename CP>
+__device__ __forceinline__ void kron_post(T *re, T *im, CP cf, int dflags) {
+  constexpr int G = 1 << R;
+  CP ta = cf + 4 * R + 2 * G;
   if (dflags & 2) mo_diagt<T, R>(re, im, ta);
   if (dflags & 4) {
     const T sc = (T)ta[2 * G];
 #pragma unroll
     for (int j = 0; j < G; j++) { re[j] *= sc; im[j] *= sc; }
   }
+}
+
+template <typename T, int R, typename CP>
+__device__ __forceinline__ void kron_stage(T *re, T *im, CP cf, uint32_t rmask, int dflags) {
+  kron_pre<T, R>(re, im, cf, dflags);
+  kron_rot<T, R>(re, im, cf, rmask);
+  kron_post<T, R>(re, im, cf, dflags);
 }
 
 #define SVI_T5(F, t, ...)                                   \
@@ -469,6 +484,7 @@ __device__ __forceinline__ double wave_sum(double v) {
 // accumulates gradient partials).
 
 #define SVI_GSLOTS 256
+#define SVI_GSLOTS_LEAN 32   // gradient slots per sweep of the two-state Kronecker kernel
 
 template <typename T, int M, int R, int NS>
 __global__ void __launch_bounds__(1 << (M - R)) k_sweep(SweepArgs a) {
@@ -578,8 +594,35 @@ __global__ void __launch_bounds__(1 << (M - R)) k_sweep(SweepArgs a) {
         }
       }
       if (sd.kind == ST_KRON) {
-        kron_stage<T, R>(re[0], im[0], cptr(a.coef) + sd.kcoef, sd.rmask, sd.dflags);
-        if constexpr (NS == 2) kron_stage<T, R>(re[1], im[1], cptr(a.coef) + sd.kcoef, sd.rmask, sd.dflags);
+        const SVI_CONST double *kc = cptr(a.coef) + sd.kcoef;
+        if constexpr (NS == 2) {
+          // gradient terms Im <lam| G |psi> at the stage point where each
+          // record's generator commutes with the rest of the stage; terms taken
+          // after the fast-Givens rotations see both states divided by the
+          // stage scale s, so they are multiplied by s^2
+          auto grads = [&](int b, int e, double mult) {
+            for (int o = b; o < e; o++) {
+              const MicroOp op = a.ops[o];
+              double v = active ? mult * grad_op<T, R>(op, re[0], im[0], re[1], im[1]) : 0.0;
+              v = wave_sum(v);
+              if ((tid & 63) == 0) wsum[tid >> 6][op.coef] = v;
+            }
+          };
+          grads(sd.op_begin, sd.g1, 1.0);
+          kron_pre<T, R>(re[0], im[0], kc, sd.dflags);
+          kron_pre<T, R>(re[1], im[1], kc, sd.dflags);
+          grads(sd.g1, sd.g2, 1.0);
+          kron_rot<T, R>(re[0], im[0], kc, sd.rmask);
+          kron_rot<T, R>(re[1], im[1], kc, sd.rmask);
+          if (sd.g2 < sd.op_end) {
+            const double sc = kc[4 * R + 4 * G];
+            grads(sd.g2, sd.op_end, sc * sc);
+          }
+          kron_post<T, R>(re[0], im[0], kc, sd.dflags);
+          kron_post<T, R>(re[1], im[1], kc, sd.dflags);
+        } else {
+          kron_stage<T, R>(re[0], im[0], kc, sd.rmask, sd.dflags);
+        }
       } else
       for (int o = sd.op_begin; o < sd.op_end; o++) {
         const MicroOp op = a.ops[o];
@@ -823,6 +866,190 @@ __global__ void __launch_bounds__(1 << (M - R)) k_sweep_kron(SweepArgs a) {
     lds_barrier();
     r0 += gridDim.x;
     tile = next;
+  }
+}
+
+// ------------------------------------------- two-state Kronecker sweep
+// Adjoint backward sweeps whose every stage is a Kronecker stage: psi and
+// lambda tiles side by side in LDS, the stage applied to both, and the
+// gradient terms Im <lam| G |psi> taken at the three stage points (stage
+// input, after D_before, after the rotations) and reduced per workgroup.
+template <typename T, int M, int R>
+__global__ void __launch_bounds__(1 << (M - R)) k_sweep_kron2(SweepArgs a) {
+  constexpr int NT = 1 << (M - R);
+  constexpr int G = 1 << R;
+  constexpr int VN = V4T<T>::N;
+  constexpr int NIT = (1 << M) / (VN * NT);
+  constexpr int NWAVE = NT / 64;
+  using C2 = typename C2T<T>::type;
+  using V4 = typename V4T<T>::type;
+  __shared__ C2 lds[2][1 << M];
+  __shared__ double wsum[NWAVE][SVI_GSLOTS_LEAN];
+  __shared__ int32_t hb_s[SVI_MMAX];
+
+  const int tid = threadIdx.x;
+  const int m = a.m, c = a.c, nh = a.nh;
+  const int ntile_el = 1 << m;
+  const bool vec = c >= (VN == 2 ? 1 : 2);
+  const SVI_CONST StageDesc *stages = cptr(a.stages + a.stage_begin);
+  const int nst = a.stage_end - a.stage_begin;
+  const SVI_CONST double *coef = cptr(a.coef);
+
+  if (tid < SVI_MMAX) hb_s[tid] = a.hb[tid < nh ? tid : 0];
+  __syncthreads();
+
+  uint64_t roff[NIT];
+#pragma unroll
+  for (int k = 0; k < NIT; k++) {
+    const int i = (tid + k * NT) * (vec ? VN : 1);
+    roff[k] = spread_row(i >> c, hb_s, nh) + (uint64_t)(i & ((1 << c) - 1));
+  }
+  const int tsw = swz<T>(tid * VN);
+  // per-thread gradient accumulators, one per slot of this sweep: the terms
+  // of all tiles are summed in registers and reduced across the wave once, at
+  // the end, instead of once per tile
+  double gr[SVI_GSLOTS_LEAN];
+#pragma unroll
+  for (int k = 0; k < SVI_GSLOTS_LEAN; k++) gr[k] = 0.0;
+  T *const pr[2] = {(T *)a.re, (T *)a.re2};
+  T *const pi[2] = {(T *)a.im, (T *)a.im2};
+
+  int64_t r0 = 0;
+  for (int64_t tile = tile_of(0, blockIdx.x, gridDim.x); tile < a.ntiles;) {
+    const uint64_t base = tile_base(tile, c, hb_s, nh);
+    // ---- both tiles into LDS
+#pragma unroll
+    for (int s = 0; s < 2; s++) {
+      if (vec) {
+#pragma unroll
+        for (int k = 0; k < NIT; k++) {
+          const int i = (tid + k * NT) * VN;
+          if (i < ntile_el) {
+            const uint64_t g = base + roff[k];
+            const V4 vr = *(const V4 *)(pr[s] + g);
+            const V4 vi = *(const V4 *)(pi[s] + g);
+            const int si = tsw ^ swz<T>(k * NT * VN);
+            if constexpr (VN == 2) {
+              lds[s][si] = C2{vr.x, vi.x};
+              lds[s][si ^ 1] = C2{vr.y, vi.y};
+            } else {
+              lds[s][si] = C2{vr.x, vi.x};
+              lds[s][si ^ 1] = C2{vr.y, vi.y};
+              lds[s][si ^ 2] = C2{vr.z, vi.z};
+              lds[s][si ^ 3] = C2{vr.w, vi.w};
+            }
+          }
+        }
+      } else {
+        for (int i = tid; i < ntile_el; i += NT) {
+          const uint64_t g = base + spread_row(i >> c, hb_s, nh) + (uint64_t)(i & ((1 << c) - 1));
+          lds[s][swz<T>(i)] = C2{pr[s][g], pi[s][g]};
+        }
+      }
+    }
+    lds_barrier();
+    // ---- stages
+    for (int st = 0; st < nst; st++) {
+      const SVI_CONST StageDesc &sd = stages[st];
+      const int gbs = swz<T>(insert_zeros32c(tid, sd.sbits, R)) * (int)sizeof(C2);
+      const bool active = tid < (1 << (m > R ? m - R : 0));
+      T re[2][G], im[2][G];
+#pragma unroll
+      for (int s = 0; s < 2; s++) {
+        const char *lb = (const char *)lds[s];
+#pragma unroll
+        for (int j = 0; j < G; j++) {
+          const C2 v = *(const C2 *)(lb + (gbs ^ sd.ld_off[j]));
+          re[s][j] = v.x;
+          im[s][j] = v.y;
+        }
+      }
+      const SVI_CONST double *kc = coef + sd.kcoef;
+      auto grads = [&](int b, int e, double mult) {
+        for (int o = b; o < e; o++) {
+          const MicroOp op = a.ops[o];
+          const double v = active ? mult * grad_op<T, R>(op, re[0], im[0], re[1], im[1]) : 0.0;
+          switch (op.coef) {   // uniform: the slot is a register index
+#define SVI_GS(K) case K: gr[K] += v; break;
+            SVI_GS(0) SVI_GS(1) SVI_GS(2) SVI_GS(3) SVI_GS(4) SVI_GS(5) SVI_GS(6) SVI_GS(7)
+            SVI_GS(8) SVI_GS(9) SVI_GS(10) SVI_GS(11) SVI_GS(12) SVI_GS(13) SVI_GS(14)
+            SVI_GS(15) SVI_GS(16) SVI_GS(17) SVI_GS(18) SVI_GS(19) SVI_GS(20) SVI_GS(21)
+            SVI_GS(22) SVI_GS(23) SVI_GS(24) SVI_GS(25) SVI_GS(26) SVI_GS(27) SVI_GS(28)
+            SVI_GS(29) SVI_GS(30) SVI_GS(31)
+#undef SVI_GS
+            default: break;
+          }
+        }
+      };
+      grads(sd.op_begin, sd.g1, 1.0);
+      kron_pre<T, R>(re[0], im[0], kc, sd.dflags);
+      kron_pre<T, R>(re[1], im[1], kc, sd.dflags);
+      grads(sd.g1, sd.g2, 1.0);
+      kron_rot<T, R>(re[0], im[0], kc, sd.rmask);
+      kron_rot<T, R>(re[1], im[1], kc, sd.rmask);
+      if (sd.g2 < sd.op_end) {
+        const double sc = kc[4 * R + 4 * G];
+        grads(sd.g2, sd.op_end, sc * sc);
+      }
+      kron_post<T, R>(re[0], im[0], kc, sd.dflags);
+      kron_post<T, R>(re[1], im[1], kc, sd.dflags);
+#pragma unroll
+      for (int s = 0; s < 2; s++) {
+        char *lb = (char *)lds[s];
+#pragma unroll
+        for (int j = 0; j < G; j++) *(C2 *)(lb + (gbs ^ sd.st_off[j])) = C2{re[s][j], im[s][j]};
+      }
+      __syncthreads();
+    }
+    // ---- LDS to HBM
+#pragma unroll
+    for (int s = 0; s < 2; s++) {
+      if (vec) {
+#pragma unroll
+        for (int k = 0; k < NIT; k++) {
+          const int i = (tid + k * NT) * VN;
+          if (i < ntile_el) {
+            const uint64_t g = base + roff[k];
+            const int si = tsw ^ swz<T>(k * NT * VN);
+            V4 vr, vi;
+            if constexpr (VN == 2) {
+              const C2 p0 = lds[s][si], p1 = lds[s][si ^ 1];
+              vr = V4{p0.x, p1.x};
+              vi = V4{p0.y, p1.y};
+            } else {
+              const C2 p0 = lds[s][si], p1 = lds[s][si ^ 1], p2 = lds[s][si ^ 2], p3 = lds[s][si ^ 3];
+              vr = V4{p0.x, p1.x, p2.x, p3.x};
+              vi = V4{p0.y, p1.y, p2.y, p3.y};
+            }
+            *(V4 *)(pr[s] + g) = vr;
+            *(V4 *)(pi[s] + g) = vi;
+          }
+        }
+      } else {
+        for (int i = tid; i < ntile_el; i += NT) {
+          const uint64_t g = base + spread_row(i >> c, hb_s, nh) + (uint64_t)(i & ((1 << c) - 1));
+          const C2 p = lds[s][swz<T>(i)];
+          pr[s][g] = p.x;
+          pi[s][g] = p.y;
+        }
+      }
+    }
+    __syncthreads();
+    r0 += gridDim.x;
+    tile = tile_of(r0, blockIdx.x, gridDim.x);
+  }
+#pragma unroll
+  for (int k = 0; k < SVI_GSLOTS_LEAN; k++) {
+    if (k < a.n_gslots) {
+      const double v = wave_sum(gr[k]);
+      if ((tid & 63) == 0) wsum[tid >> 6][k] = v;
+    }
+  }
+  __syncthreads();
+  for (int sl = tid; sl < a.n_gslots; sl += NT) {
+    double v = 0.0;
+    for (int w = 0; w < NWAVE; w++) v += wsum[w][sl];
+    a.gpart[(int64_t)(a.gslot_begin + sl) * gridDim.x + blockIdx.x] = v;
   }
 }
 

@@ -213,9 +213,15 @@ struct StageP {
 
 // Records a Kronecker stage can hold: uncontrolled RY rotations, diagonal
 // gates (any controls) and permutations (any controls).
+// A gradient record (adjoint backward program) fits too when its generator
+// commutes with everything the stage applies between the stage point where its
+// gradient is evaluated and the gate itself: a diagonal generator for diagonal
+// gates (evaluated on the stage input, or after the rotations for diagonal gates
+// that follow a rotation), Y on the rotated qubit for an RY (evaluated after the
+// leading diagonal table; the other rotations act on other qubits).
 static bool kron_eligible(const GateRec &g) {
-  if (g.grad) return false;
   if (g.mo == MO_R) return g.nc == 0 && g.nt == 1 && g.kind == SV_RY;
+  if (g.grad) return g.mo == MO_P && g.gx == 0;
   return g.mo == MO_P || g.mo == MO_NEG || g.mo == MO_X || g.mo == MO_SWAP;
 }
 
@@ -776,9 +782,13 @@ static void emit_sweep(Plan &P, std::vector<GateRec> &recs, const SweepP &sw, in
         if (st.gq[i] == p) return i;
       return -1;
     };
-    std::vector<MicroOp> mops;
+    std::vector<MicroOp> mops;                 // ST_OPS: gradient op, then gate op
+    std::vector<MicroOp> gate_mop, grad_mop;   // per record of the stage (grad type -1: none)
     for (int r : st.recs) {
       GateRec &g = recs[r];
+      MicroOp none{};
+      none.type = -1;
+      grad_mop.push_back(none);
       uint32_t cm = 0, cv = 0;
       for (int i = 0; i < g.nc; i++) {
         int l = local_of(g.c[i]);
@@ -803,6 +813,7 @@ static void emit_sweep(Plan &P, std::vector<GateRec> &recs, const SweepP &sw, in
         P.slot_param.push_back(g.gparam);
         gs++;
         mops.push_back(go);
+        grad_mop.back() = go;
       }
       MicroOp op{};
       op.type = g.mo;
@@ -844,6 +855,7 @@ static void emit_sweep(Plan &P, std::vector<GateRec> &recs, const SweepP &sw, in
         default: break;
       }
       mops.push_back(op);
+      gate_mop.push_back(op);
     }
     StageDesc sd;
     std::memset(&sd, 0, sizeof sd);
@@ -854,11 +866,12 @@ static void emit_sweep(Plan &P, std::vector<GateRec> &recs, const SweepP &sw, in
     std::vector<MicroOp> leadp, trailp, body;
     if (st.kron) {
       // mops holds every record's micro-op in stage order; split by role
-      auto mop_of = [&](int r) {
+      auto idx_of = [&](int r) {
         for (size_t k = 0; k < st.recs.size(); k++)
-          if (st.recs[k] == r) return mops[k];
-        return MicroOp{};
+          if (st.recs[k] == r) return (int)k;
+        return -1;
       };
+      auto mop_of = [&](int r) { return gate_mop[idx_of(r)]; };
       for (int r : st.lead) leadp.push_back(mop_of(r));
       for (int r : st.trail) trailp.push_back(mop_of(r));
       sd.kind = ST_KRON;
@@ -888,9 +901,11 @@ static void emit_sweep(Plan &P, std::vector<GateRec> &recs, const SweepP &sw, in
           P.factors.push_back(f);
         }
       };
+      bool dag = false;
+      for (int r : st.recs) dag = dag || recs[r].dagger;
       auto table = [&](const std::vector<int> &rs, int dst, bool scales) {
         CoefDesc cd{};
-        cd.fmt = CF_TABLE;
+        cd.fmt = CF_TABLE | (dag ? CF_DAGGER : 0);
         cd.src = (int)P.factors.size();
         cd.len = R;
         cd.dst = dst;
@@ -914,10 +929,28 @@ static void emit_sweep(Plan &P, std::vector<GateRec> &recs, const SweepP &sw, in
       if (!st.dafter.empty()) {
         sd.dflags |= 2;
         table(st.dafter, sd.kcoef + 4 * R + 2 * G, true);
-      } else if (!st.rops.empty()) {
-        sd.dflags |= 4;
+      }
+      // gradient ops at the three stage points (diagonal gates before any
+      // rotation: stage input; rotations: after D_before; diagonal gates
+      // after a rotation: after the rotations)
+      sd.op_begin = (int)P.ops.size();
+      for (int r : st.dbefore)
+        if (grad_mop[idx_of(r)].type == MO_GRAD) P.ops.push_back(grad_mop[idx_of(r)]);
+      sd.g1 = (int)P.ops.size();
+      for (int r : st.rops)
+        if (grad_mop[idx_of(r)].type == MO_GRAD) P.ops.push_back(grad_mop[idx_of(r)]);
+      sd.g2 = (int)P.ops.size();
+      for (int r : st.dafter)
+        if (grad_mop[idx_of(r)].type == MO_GRAD) P.ops.push_back(grad_mop[idx_of(r)]);
+      sd.op_end = (int)P.ops.size();
+      // the scalar slot holds the product of the fast-Givens scales: applied
+      // to the state when there is no D_after to carry it, and used to rescale
+      // gradients taken between the rotations and D_after
+      const bool scalar = st.dafter.empty() && !st.rops.empty();
+      if (scalar || sd.g2 < sd.op_end) {
+        if (scalar) sd.dflags |= 4;
         CoefDesc cd{};
-        cd.fmt = CF_SCALE;
+        cd.fmt = CF_SCALE | (dag ? CF_DAGGER : 0);
         cd.src = (int)P.factors.size();
         push_scales();
         cd.pidx[0] = (int)P.factors.size() - cd.src;
@@ -935,6 +968,10 @@ static void emit_sweep(Plan &P, std::vector<GateRec> &recs, const SweepP &sw, in
       trailp.assign(mops.begin() + trail, mops.end());
       body.assign(mops.begin() + lead, mops.begin() + trail);
       sd.kind = ST_OPS;
+      sd.op_begin = (int)P.ops.size();
+      for (const MicroOp &m : body) P.ops.push_back(m);
+      sd.op_end = (int)P.ops.size();
+      sd.g1 = sd.g2 = sd.op_end;
     }
     for (int j = 0; j < (1 << R); j++) {
       int jl = j;
@@ -944,15 +981,13 @@ static void emit_sweep(Plan &P, std::vector<GateRec> &recs, const SweepP &sw, in
       for (size_t k = 0; k < trailp.size(); k++) js = perm_apply(trailp[k], js);
       sd.st_off[j] = svi_swz(spread_local(js, st.gq, R), SWB) * EB;
     }
-    sd.op_begin = (int)P.ops.size();
-    for (const MicroOp &m : body) P.ops.push_back(m);
-    sd.op_end = (int)P.ops.size();
     P.stages.push_back(sd);
     P.n_blocks++;
   }
   a.stage_end = (int)P.stages.size();
   a.n_gslots = gs;
-  s.all_kron = gs == 0;
+  // the two-state Kronecker kernel keeps at most SVI_GSLOTS_MAX gradient slots in registers
+  s.all_kron = gs <= SVI_GSLOTS_MAX;
   for (int k = a.stage_begin; k < a.stage_end; k++)
     if (P.stages[k].kind != ST_KRON) s.all_kron = false;
   gslots_used = gs;
@@ -1049,6 +1084,7 @@ struct sv_state {
   hipStream_t stream = nullptr;
   Tiling tiling;
   int dev = 0;
+  Tiling adj_tiling;                 // backward sweeps of the adjoint
   std::unordered_map<std::string, std::unique_ptr<Plan>> plans;
   // growable scratch (partials)
   void *scratch = nullptr;
@@ -1120,7 +1156,8 @@ static Tiling default_tiling(int n, sv_dtype dt, int NS) {
     // forward: 13-qubit tiles, 256-byte rows, 8-amplitude register groups
     // (1024-thread workgroups, 4 waves per SIMD); measured best on the
     // 30-qubit layered workload among the compiled tilings
-    if (NS == 2) { t.M = 12; t.R = 4; t.c = 3; }
+    // adjoint backward: two 12-qubit tiles (psi, lambda), 8-amplitude groups
+    if (NS == 2) { t.M = 12; t.R = 3; t.c = 4; }
     else { t.M = 13; t.R = 3; t.c = 5; }
   } else {
     if (NS == 2) { t.M = 13; t.R = 4; t.c = 3; }
@@ -1154,6 +1191,7 @@ extern "C" sv_status sv_alloc(int32_t n, sv_dtype dtype, void *re, void *im, voi
   st->ws_bytes = ws_bytes;
   st->stream = (hipStream_t)stream;
   st->tiling = default_tiling(n, dtype, 1);
+  st->adj_tiling = default_tiling(n, dtype, 2);
   (void)hipGetDevice(&st->dev);
   st->pending_zero = true;
   *out = st;
@@ -1193,6 +1231,20 @@ extern "C" sv_status sv_set_tiling(sv_state *st, int32_t tile_bits, int32_t low_
   if (t.c < 1 || t.c > t.M - t.R + 1) return fail(SV_EINVAL, "low_bits %d out of range", t.c);
   st->tiling = t;
   st->plans.clear();
+  return SV_OK;
+}
+
+extern "C" sv_status sv_set_adjoint_tiling(sv_state *st, int32_t tile_bits, int32_t low_bits,
+                                          int32_t group_bits) {
+  if (!st) return fail(SV_EINVAL, "null handle");
+  Tiling t = st->adj_tiling;
+  if (tile_bits) t.M = tile_bits;
+  if (group_bits) t.R = group_bits;
+  if (low_bits) t.c = low_bits;
+  if (!svk_has_sweep(st->dtype == SV_C128, t.M, t.R, 2))
+    return fail(SV_EINVAL, "no adjoint sweep kernel for tile_bits %d, group_bits %d", t.M, t.R);
+  if (t.c < 1 || t.c > t.M) return fail(SV_EINVAL, "low_bits %d outside 1..%d", t.c, t.M);
+  st->adj_tiling = t;
   return SV_OK;
 }
 
@@ -1422,7 +1474,7 @@ static sv_status build_adjoint_plan(int n, bool dbl, const Tiling &tl, const sv_
     recs.push_back(g);
   }
   std::vector<SweepP> sweeps;
-  plan_auto(recs, n, tl, sweeps, 1e300);
+  plan_auto(recs, n, tl, sweeps, 1e300, true);
   // cap gradient slots per sweep by splitting sweeps whose stages exceed the limit
   int gbase = 0;
   for (const SweepP &sw0 : sweeps) {
@@ -1441,6 +1493,9 @@ static sv_status build_adjoint_plan(int n, bool dbl, const Tiling &tl, const sv_
     for (const StageP &st : sw0.stages) {
       int g = 0;
       for (int r : st.recs) g += recs[r].grad ? 1 : 0;
+      if (g > SVI_GSLOTS_HARD)
+        return fail(SV_EUNSUPPORTED, "adjoint: %d parameterised gates in one register stage (max %d)",
+                    g, SVI_GSLOTS_HARD);
       if (cnt + g > SVI_GSLOTS_MAX) flush();
       cur.stages.push_back(st);
       cnt += g;
@@ -1522,7 +1577,7 @@ static sv_status run_steps(sv_state *st, Plan &P, void *re, void *im, void *re2,
   }
   const bool dbl = st->dtype == SV_C128;
   int occ = svk_sweep_occupancy(dbl, P.M, P.R, P.NS);
-  int occk = P.NS == 1 ? svk_sweep_kron_occupancy(dbl, P.M, P.R) : 0;
+  int occk = svk_sweep_kron_occupancy(dbl, P.M, P.R, P.NS);
   for (Step &stp : P.steps) {
     if (stp.kind == 0) {
       SweepArgs a = stp.sa;
@@ -1532,7 +1587,9 @@ static sv_status run_steps(sv_state *st, Plan &P, void *re, void *im, void *re2,
       a.ops = P.d_ops;
       a.coef = P.d_coef;
       a.gpart = gpart;
-      const bool lean = stp.all_kron && P.NS == 1 && occk > 0;
+      // the two-state lean kernel takes gradient terms over whole register
+      // groups, so it needs tiles at least one group wide
+      const bool lean = stp.all_kron && occk > 0 && (P.NS == 1 || stp.sa.m >= P.R);
       int64_t g = (int64_t)di.cus * (lean ? occk : occ);
       if (grid_override > 0) g = grid_override;
       if (g > a.ntiles) g = a.ntiles;
@@ -1542,7 +1599,7 @@ static sv_status run_steps(sv_state *st, Plan &P, void *re, void *im, void *re2,
         e1 = next_event(st);
         if (e0) (void)hipEventRecord(e0, st->stream);
       }
-      hipError_t e = lean ? svk_launch_sweep_kron(dbl, P.M, P.R, a, (int)g, st->stream)
+      hipError_t e = lean ? svk_launch_sweep_kron(dbl, P.M, P.R, P.NS, a, (int)g, st->stream)
                           : svk_launch_sweep(dbl, P.M, P.R, P.NS, a, (int)g, st->stream);
       if (e != hipSuccess) return fail(SV_EDEVICE, "sweep kernel: %s", hipGetErrorString(e));
       if (a.flags & SW_INIT_ZERO) st->pending_zero = false;
@@ -1826,14 +1883,27 @@ static sv_status adjoint_enqueue(sv_state *st, const sv_op *ops, int n_ops, cons
     return fail(SV_ENOMEM, "workspace too small for the adjoint (%zu < %zu)", st->ws_bytes,
                 sv_workspace_bytes(st->n, st->dtype, SV_WS_ADJOINT));
   Tiling tf = st->tiling;
-  Tiling tb = default_tiling(st->n, st->dtype, 2);
+  Tiling tb = st->adj_tiling;
   int width = 1;
   for (int i = 0; i < n_ops; i++) width = std::max(width, ops[i].n_targets + ops[i].n_controls);
   s = widen_groups(st->dtype == SV_C128, width, tf);
   if (s) return s;
-  if (width > tb.R)
-    return fail(SV_EUNSUPPORTED, "adjoint: ops on %d qubits exceed the %d-qubit backward groups",
-                width, tb.R);
+  if (width > tb.R) {
+    // wider ops need wider backward register groups (same tile if compiled)
+    bool found = false;
+    for (int R = width; R <= SVI_RMAX && !found; R++)
+      for (int M : {tb.M, 12, 11, 13})
+        if (svk_has_sweep(st->dtype == SV_C128, M, R, 2)) {
+          tb.M = M;
+          tb.R = R;
+          tb.c = std::min(tb.c, M - R);
+          found = true;
+          break;
+        }
+    if (!found)
+      return fail(SV_EUNSUPPORTED, "adjoint: ops on %d qubits exceed the widest backward groups",
+                  width);
+  }
   Plan *F = nullptr, *B = nullptr;
   if (n_ops > 0) {
     s = get_plan(st, SV_FUSE_AUTO, tf, ops, n_ops, n_params, false, &F);
@@ -1863,7 +1933,8 @@ static sv_status adjoint_enqueue(sv_state *st, const sv_op *ops, int n_ops, cons
   DevInfo di;
   s = device_info(di);
   if (s) return s;
-  int occ = svk_sweep_occupancy(st->dtype == SV_C128, B->M, B->R, 2);
+  int occ = std::max(svk_sweep_occupancy(st->dtype == SV_C128, B->M, B->R, 2),
+                     svk_sweep_kron_occupancy(st->dtype == SV_C128, B->M, B->R, 2));
   int64_t grid = (int64_t)di.cus * occ;
   int64_t maxtiles = (int64_t)1 << (st->n - std::min(B->M, st->n));
   if (grid > maxtiles) grid = maxtiles;

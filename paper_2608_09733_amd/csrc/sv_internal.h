@@ -66,7 +66,8 @@ struct StageDesc {
   uint32_t rmask;              // ST_KRON: group bits carrying a real 2x2
   int32_t dflags;              // ST_KRON: 1 = D_before, 2 = D_after
   int32_t kcoef;               // ST_KRON: coefficient offset (doubles)
-  int32_t pad;
+  int32_t g1, g2;              // ST_KRON: MO_GRAD ops [op_begin, g1) run on the stage input,
+                               // [g1, g2) after D_before, [g2, op_end) after the rotations
   int32_t ld_off[SVI_GMAX];    // swizzled tile-local BYTE offset loaded into slot j
   int32_t st_off[SVI_GMAX];    // swizzled tile-local BYTE offset slot j is stored to
 };

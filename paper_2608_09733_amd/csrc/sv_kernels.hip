@@ -197,6 +197,7 @@ __global__ void k_build_coefs(const CoefDesc *d, int nd, const double *params, c
       if (dag) { const double t = r[1]; r[1] = r[2]; r[2] = t; }
       fast_givens(r, out);
     } else if (fmt == CF_SCALE) {
+      // product of the fast-Givens scales of the (daggered, if flagged) real gates
       double sc = 1.0;
       for (int f = cd.src; f < cd.src + cd.pidx[0]; f++) {
         const TabFactor tf = fac[f];
@@ -204,6 +205,7 @@ __global__ void k_build_coefs(const CoefDesc *d, int nd, const double *params, c
         double tt[3] = {tf.pidx >= 0 ? params[tf.pidx] : 0.0, 0.0, 0.0};
         gate_local(tf.kind, tt, m);
         double r[4] = {m[0], m[2], m[4], m[6]};
+        if (dag) { const double t = r[1]; r[1] = r[2]; r[2] = t; }
         fast_givens(r, rec);
         sc *= rec[2];
       }
@@ -221,6 +223,7 @@ __global__ void k_build_coefs(const CoefDesc *d, int nd, const double *params, c
         double gsc = 1.0;
         if (tf.neg == 2) {
           double r[4] = {m[0], m[2], m[4], m[6]}, rec[4];
+          if (dag) { const double t = r[1]; r[1] = r[2]; r[2] = t; }
           fast_givens(r, rec);
           gsc = rec[2];
         }
@@ -801,19 +804,19 @@ __global__ void __launch_bounds__(256) k_sample(SampleArgs a) {
 SVI_VARIANTS(X)
 #undef X
 
-hipError_t svk_launch_sweep_kron(int dbl, int M, int R, const SweepArgs &a, int grid,
+hipError_t svk_launch_sweep_kron(int dbl, int M, int R, int NS, const SweepArgs &a, int grid,
                                  hipStream_t s) {
 #define X(T, MM, RR, NN)                                                        \
-  if (NN == 1 && (dbl == (sizeof(T) == 8)) && M == MM && R == RR)               \
+  if (NN == NS && (dbl == (sizeof(T) == 8)) && M == MM && R == RR)              \
     return SVI_VNAME(launchk, T, MM, RR, NN)(a, grid, s);
   SVI_VARIANTS(X)
 #undef X
   return hipErrorInvalidValue;
 }
 
-int svk_sweep_kron_occupancy(int dbl, int M, int R) {
+int svk_sweep_kron_occupancy(int dbl, int M, int R, int NS) {
 #define X(T, MM, RR, NN)                                                        \
-  if (NN == 1 && (dbl == (sizeof(T) == 8)) && M == MM && R == RR)               \
+  if (NN == NS && (dbl == (sizeof(T) == 8)) && M == MM && R == RR)              \
     return SVI_VNAME(occk, T, MM, RR, NN)();
   SVI_VARIANTS(X)
 #undef X

@@ -20,9 +20,9 @@ struct GateArgsHost {
 hipError_t svk_launch_sweep(int dbl, int M, int R, int NS, const SweepArgs &a, int grid,
                             hipStream_t s);
 int svk_sweep_occupancy(int dbl, int M, int R, int NS);
-hipError_t svk_launch_sweep_kron(int dbl, int M, int R, const SweepArgs &a, int grid,
+hipError_t svk_launch_sweep_kron(int dbl, int M, int R, int NS, const SweepArgs &a, int grid,
                                  hipStream_t s);
-int svk_sweep_kron_occupancy(int dbl, int M, int R);
+int svk_sweep_kron_occupancy(int dbl, int M, int R, int NS);
 int svk_has_sweep(int dbl, int M, int R, int NS);
 hipError_t svk_launch_gate(int dbl, const GateArgsHost &a, hipStream_t s);
 hipError_t svk_launch_init_zero(int dbl, void *re, void *im, int64_t n, hipStream_t s);
@@ -50,7 +50,8 @@ hipError_t svk_launch_sampling(int dbl, const void *re, const void *im, int n, d
                                double *P, uint64_t seed, int64_t shots, const int32_t *qubits,
                                int nq, uint64_t *out, hipStream_t s);
 
-#define SVI_GSLOTS_MAX 256
+#define SVI_GSLOTS_MAX 32    // gradient slots per backward sweep (two-state kernel registers)
+#define SVI_GSLOTS_HARD 256  // gradient slots of the general two-state kernel (LDS)
 #define SVI_PTERMS_MAX 64
 #define SVI_KMAX_STAGES_HOST 16
 

@@ -27,11 +27,20 @@ int SVI_VNAME(occ, SVI_VT, SVI_VM, SVI_VR, SVI_VNS)() {
 }
 
 #if SVI_VNS != 1
-hipError_t SVI_VNAME(launchk, SVI_VT, SVI_VM, SVI_VR, SVI_VNS)(const SweepArgs &, int,
-                                                               hipStream_t) {
-  return hipErrorInvalidValue;
+hipError_t SVI_VNAME(launchk, SVI_VT, SVI_VM, SVI_VR, SVI_VNS)(const SweepArgs &a, int grid,
+                                                               hipStream_t s) {
+  hipLaunchKernelGGL((svk::k_sweep_kron2<SVI_VT, SVI_VM, SVI_VR>), dim3(grid),
+                     dim3(1 << (SVI_VM - SVI_VR)), 0, s, a);
+  return hipGetLastError();
 }
-int SVI_VNAME(occk, SVI_VT, SVI_VM, SVI_VR, SVI_VNS)() { return 0; }
+
+int SVI_VNAME(occk, SVI_VT, SVI_VM, SVI_VR, SVI_VNS)() {
+  int nb = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
+          &nb, svk::k_sweep_kron2<SVI_VT, SVI_VM, SVI_VR>, 1 << (SVI_VM - SVI_VR), 0) != hipSuccess)
+    return 1;
+  return nb > 0 ? nb : 1;
+}
 #else
 hipError_t SVI_VNAME(launchk, SVI_VT, SVI_VM, SVI_VR, SVI_VNS)(const SweepArgs &a, int grid,
                                                                hipStream_t s) {

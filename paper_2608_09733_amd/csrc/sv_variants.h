@@ -15,11 +15,13 @@
   X(double, 11, 5, 1)        \
   X(double, 12, 4, 2)        \
   X(double, 11, 4, 2)        \
+  X(double, 12, 3, 2)        \
+  X(double, 11, 3, 2)        \
   X(float, 14, 5, 1)         \
   X(float, 13, 5, 1)         \
   X(float, 13, 4, 2)
 
-#define SVI_NVARIANTS 14
+#define SVI_NVARIANTS 16
 #define SVI_VCAT(a, b, c, d, e, f) svk_##a##_##b##_##c##_##d##_##e##f
 #define SVI_VNAME(what, T, M, R, NS) SVI_VCAT(what, T, M, R, NS, _v)
 

@@ -78,6 +78,7 @@ def lib():
         "sv_plan_stats": (C.c_int, [i32, opp, i32, i32, i32, i32, i32, C.POINTER(i32),
                                     C.POINTER(i32)]),
         "sv_set_tiling": (C.c_int, [vp, i32, i32, i32]),
+        "sv_set_adjoint_tiling": (C.c_int, [vp, i32, i32, i32]),
         "sv_fuse_blocks": (C.c_int, [opp, i32, i32, C.POINTER(i32), C.POINTER(i32)]),
         "sv_version": (C.c_char_p, []),
         "sv_timing_enable": (C.c_int, [vp, i32]),
@@ -216,6 +217,9 @@ class State:
 
     def set_tiling(self, tile_bits: int = 0, low_bits: int = 0, group_bits: int = 0):
         _check(lib().sv_set_tiling(self.h, tile_bits, low_bits, group_bits))
+
+    def set_adjoint_tiling(self, tile_bits: int = 0, low_bits: int = 0, group_bits: int = 0):
+        _check(lib().sv_set_adjoint_tiling(self.h, tile_bits, low_bits, group_bits))
 
     def reset(self):
         _check(lib().sv_reset(self.h))

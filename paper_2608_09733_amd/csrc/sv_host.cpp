@@ -1156,8 +1156,8 @@ static Tiling default_tiling(int n, sv_dtype dt, int NS) {
     // forward: 13-qubit tiles, 256-byte rows, 8-amplitude register groups
     // (1024-thread workgroups, 4 waves per SIMD); measured best on the
     // 30-qubit layered workload among the compiled tilings
-    // adjoint backward: two 12-qubit tiles (psi, lambda), 8-amplitude groups
-    if (NS == 2) { t.M = 12; t.R = 3; t.c = 4; }
+    // adjoint backward: two 11-qubit tiles (psi, lambda), 8-amplitude groups
+    if (NS == 2) { t.M = 11; t.R = 3; t.c = 3; }
     else { t.M = 13; t.R = 3; t.c = 5; }
   } else {
     if (NS == 2) { t.M = 13; t.R = 4; t.c = 3; }

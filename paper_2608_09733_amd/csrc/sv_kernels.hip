@@ -320,10 +320,13 @@ __global__ void k_build_coefs(const CoefDesc *d, int nd, const double *params, c
 // P|b> = i^{nY} (-1)^{popcount(b & z)} |b ^ x>).
 
 #define SVI_PTERMS 64
+// 1024 threads: 16 waves per CU hold the one 128 KiB tile a CU fits, so the
+// tile's loads and the per-term sums have enough waves in flight
+#define SVI_PAULI_NT 1024
 
 template <typename T, int M>
-__global__ void __launch_bounds__(256) k_pauli(PauliPassArgs a) {
-  constexpr int NT = 256;
+__global__ void __launch_bounds__(SVI_PAULI_NT) k_pauli(PauliPassArgs a) {
+  constexpr int NT = SVI_PAULI_NT;
   constexpr int EPT = (1 << M) / NT;   // elements per thread: i = tid + k * NT
   constexpr int NWAVE = NT / 64;
   using C2 = typename C2T<T>::type;
@@ -881,8 +884,8 @@ hipError_t svk_launch_coefs(const CoefDesc *d, int nd, const double *params, con
 }
 
 hipError_t svk_launch_pauli(int dbl, int M, const PauliPassArgs &a, int grid, hipStream_t s) {
-  if (dbl && M == 13) hipLaunchKernelGGL((k_pauli<double, 13>), dim3(grid), dim3(256), 0, s, a);
-  else if (!dbl && M == 13) hipLaunchKernelGGL((k_pauli<float, 13>), dim3(grid), dim3(256), 0, s, a);
+  if (dbl && M == 13) hipLaunchKernelGGL((k_pauli<double, 13>), dim3(grid), dim3(SVI_PAULI_NT), 0, s, a);
+  else if (!dbl && M == 13) hipLaunchKernelGGL((k_pauli<float, 13>), dim3(grid), dim3(SVI_PAULI_NT), 0, s, a);
   else return hipErrorInvalidValue;
   return hipGetLastError();
 }
@@ -901,8 +904,8 @@ hipError_t svk_launch_pauli_wide(int dbl, const void *re, const void *im, void *
 
 int svk_pauli_occupancy(int dbl) {
   int nb = 0;
-  hipError_t e = dbl ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_pauli<double, 13>, 256, 0)
-                     : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_pauli<float, 13>, 256, 0);
+  hipError_t e = dbl ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_pauli<double, 13>, SVI_PAULI_NT, 0)
+                     : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_pauli<float, 13>, SVI_PAULI_NT, 0);
   return (e == hipSuccess && nb > 0) ? nb : 1;
 }
 

@@ -34,8 +34,9 @@ struct BatchLds {
   int32_t unit;
 };
 
-// Tiles [t0, t1) of one sweep of one circuit (one state).
-template <typename T, int M, int R>
+// Tiles [t0, t1) of one sweep of one circuit (one state).  KO: every stage
+// of the batch is a Kronecker stage (no micro-op interpreter in the kernel).
+template <typename T, int M, int R, bool KO>
 __device__ void sweep_tiles(const SVI_CONST SweepArgs &a, int64_t t0, int64_t t1,
                             BatchLds<T, M, R> &L) {
   constexpr int NT = 1 << (M - R);
@@ -118,7 +119,7 @@ __device__ void sweep_tiles(const SVI_CONST SweepArgs &a, int64_t t0, int64_t t1
         re[j] = v.x;
         im[j] = v.y;
       }
-      if (sd.kind == ST_KRON) {
+      if (KO || sd.kind == ST_KRON) {
         kron_stage<T, R>(re, im, cptr(coef) + sd.kcoef, sd.rmask, sd.dflags);
       } else {
         for (int o = sd.op_begin; o < sd.op_end; o++) {
@@ -245,7 +246,7 @@ __device__ void pauli_tiles(const SVI_CONST PauliPassArgs &p, int64_t t0, int64_
   for (int t = tid; t < nterm; t += NT) out[t] = L.tacc[t];
 }
 
-template <typename T, int M, int R>
+template <typename T, int M, int R, bool KO>
 __global__ void __launch_bounds__(1 << (M - R)) k_batch(BatchKernelArgs b) {
   static_assert(M - R >= 6, "workgroups of whole waves");
   __shared__ BatchLds<T, M, R> L;
@@ -287,7 +288,7 @@ __global__ void __launch_bounds__(1 << (M - R)) k_batch(BatchKernelArgs b) {
     // acquire: the producers' state writes are visible to this wave's loads
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     if (un.kind == UK_SWEEP)
-      sweep_tiles<T, M, R>(cptr(b.sweeps)[un.arg], un.t0, un.t1, L);
+      sweep_tiles<T, M, R, KO>(cptr(b.sweeps)[un.arg], un.t0, un.t1, L);
     else
       pauli_tiles<T, M, R>(cptr(b.passes)[un.arg], un.t0, un.t1, b.part + un.part, L);
     // release: this wave's writes are visible device-wide before the count
@@ -301,16 +302,23 @@ __global__ void __launch_bounds__(1 << (M - R)) k_batch(BatchKernelArgs b) {
 }  // namespace svk
 
 hipError_t SVB_VNAME(launch, SVB_VT, SVB_VM, SVB_VR)(const BatchKernelArgs &a, int grid,
-                                                    hipStream_t s) {
-  hipLaunchKernelGGL((svk::k_batch<SVB_VT, SVB_VM, SVB_VR>), dim3(grid),
-                     dim3(1 << (SVB_VM - SVB_VR)), 0, s, a);
+                                                    int kron_only, hipStream_t s) {
+  if (kron_only)
+    hipLaunchKernelGGL((svk::k_batch<SVB_VT, SVB_VM, SVB_VR, true>), dim3(grid),
+                       dim3(1 << (SVB_VM - SVB_VR)), 0, s, a);
+  else
+    hipLaunchKernelGGL((svk::k_batch<SVB_VT, SVB_VM, SVB_VR, false>), dim3(grid),
+                       dim3(1 << (SVB_VM - SVB_VR)), 0, s, a);
   return hipGetLastError();
 }
 
-int SVB_VNAME(occ, SVB_VT, SVB_VM, SVB_VR)() {
+int SVB_VNAME(occ, SVB_VT, SVB_VM, SVB_VR)(int kron_only) {
   int nb = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, svk::k_batch<SVB_VT, SVB_VM, SVB_VR>,
-                                                   1 << (SVB_VM - SVB_VR), 0) != hipSuccess)
-    return 1;
+  const hipError_t e =
+      kron_only ? hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                      &nb, svk::k_batch<SVB_VT, SVB_VM, SVB_VR, true>, 1 << (SVB_VM - SVB_VR), 0)
+                : hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                      &nb, svk::k_batch<SVB_VT, SVB_VM, SVB_VR, false>, 1 << (SVB_VM - SVB_VR), 0);
+  if (e != hipSuccess) return 1;
   return nb > 0 ? nb : 1;
 }

@@ -2151,6 +2151,7 @@ struct sv_batch {
   sv_dtype dtype = SV_C128;
   bool dbl = true;
   int M = 13, R = 3, c = 5;
+  bool kron_only = true;             // every stage of every sweep is a Kronecker stage
   int grid = 1;
   int32_t spin_limit = 1 << 20;   // ~1-2 s of polls
   int ncoefdesc = 0;
@@ -2275,8 +2276,10 @@ extern "C" sv_status sv_batch_plan(const sv_circuit_desc *circuits, int32_t n_ci
     s = build_forward_plan(-1, n, dbl, tl, d.ops, d.n_ops, d.n_params, P, false);
     if (s) return s;
     if (P.M != M || P.R != R) return fail(SV_EINVAL, "internal: plan tiling mismatch");
-    for (const Step &st : P.steps)
+    for (const Step &st : P.steps) {
       if (st.kind != 0) return fail(SV_EUNSUPPORTED, "circuit %d: plan needs a single-gate kernel", k);
+      if (!st.all_kron) b->kron_only = false;
+    }
     const int64_t stage_off = (int64_t)stages.size(), op_off = (int64_t)ops.size();
     const int64_t factor_off = (int64_t)factors.size(), static_off = (int64_t)statics.size();
     const int64_t coef_off = ncoef;
@@ -2513,7 +2516,7 @@ extern "C" sv_status sv_batch_plan(const sv_circuit_desc *circuits, int32_t n_ci
   if ((s = up(b->d_redslot, redslot.data(), redslot.size() * 4))) return s;
   HIPCHK(hipMemset(b->d_results, 0, (size_t)n_circuits * 8));
 
-  const int occ = svk_batch_occupancy(dbl, M, R);
+  const int occ = svk_batch_occupancy(dbl, M, R, b->kron_only ? 1 : 0);
   b->grid = std::max(1, std::min(b->nunits, di.cus * std::max(1, occ)));
   *out = b.release();
   return SV_OK;
@@ -2535,7 +2538,7 @@ static sv_status batch_enqueue(sv_batch *b, hipStream_t s) {
     a.done = b->d_ctl + 2;
     a.nunits = b->nunits;
     a.spin_limit = b->spin_limit;
-    e = svk_launch_batch(b->dbl, b->M, b->R, a, b->grid, s);
+    e = svk_launch_batch(b->dbl, b->M, b->R, b->kron_only ? 1 : 0, a, b->grid, s);
   }
   if (e == hipSuccess)
     e = svk_launch_batch_reduce(b->d_redrow, b->d_redslot, b->d_redcoef, b->d_part, b->d_results,

@@ -987,25 +987,25 @@ hipError_t svk_launch_sampling(int dbl, const void *re, const void *im, int n, d
 // kernels around it: queue reset (a kernel rather than a memset, so a captured
 // graph replays it reliably) and the per-circuit observable reduction.
 
-#define X(T, MM, RR)                                                                \
-  hipError_t SVB_VNAME(launch, T, MM, RR)(const BatchKernelArgs &, int, hipStream_t); \
-  int SVB_VNAME(occ, T, MM, RR)();
+#define X(T, MM, RR)                                                                     \
+  hipError_t SVB_VNAME(launch, T, MM, RR)(const BatchKernelArgs &, int, int, hipStream_t); \
+  int SVB_VNAME(occ, T, MM, RR)(int);
 SVB_VARIANTS(X)
 #undef X
 
-hipError_t svk_launch_batch(int dbl, int M, int R, const BatchKernelArgs &a, int grid,
-                            hipStream_t s) {
+hipError_t svk_launch_batch(int dbl, int M, int R, int kron_only, const BatchKernelArgs &a,
+                            int grid, hipStream_t s) {
 #define X(T, MM, RR)                                                  \
   if ((dbl == (sizeof(T) == 8)) && M == MM && R == RR)                \
-    return SVB_VNAME(launch, T, MM, RR)(a, grid, s);
+    return SVB_VNAME(launch, T, MM, RR)(a, grid, kron_only, s);
   SVB_VARIANTS(X)
 #undef X
   return hipErrorInvalidValue;
 }
 
-int svk_batch_occupancy(int dbl, int M, int R) {
+int svk_batch_occupancy(int dbl, int M, int R, int kron_only) {
 #define X(T, MM, RR)                                                  \
-  if ((dbl == (sizeof(T) == 8)) && M == MM && R == RR) return SVB_VNAME(occ, T, MM, RR)();
+  if ((dbl == (sizeof(T) == 8)) && M == MM && R == RR) return SVB_VNAME(occ, T, MM, RR)(kron_only);
   SVB_VARIANTS(X)
 #undef X
   return 0;

@@ -55,9 +55,9 @@ hipError_t svk_launch_sampling(int dbl, const void *re, const void *im, int n, d
 #define SVI_PTERMS_MAX 64
 #define SVI_KMAX_STAGES_HOST 16
 
-hipError_t svk_launch_batch(int dbl, int M, int R, const BatchKernelArgs &a, int grid,
-                            hipStream_t s);
-int svk_batch_occupancy(int dbl, int M, int R);
+hipError_t svk_launch_batch(int dbl, int M, int R, int kron_only, const BatchKernelArgs &a,
+                            int grid, hipStream_t s);
+int svk_batch_occupancy(int dbl, int M, int R, int kron_only);
 int svk_has_batch(int dbl, int M, int R);
 hipError_t svk_launch_batch_reset(int32_t *head, int32_t *done, int32_t *err, int nc,
                                   hipStream_t s);

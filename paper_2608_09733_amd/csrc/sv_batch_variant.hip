@@ -111,7 +111,7 @@ __device__ void sweep_tiles(const SVI_CONST SweepArgs &a, int64_t t0, int64_t t1
 
     for (int st = st_begin; st < st_end; st++) {
       const SVI_CONST StageDesc &sd = stages[st];
-      const int gbs = swz<T>(insert_zeros32c(tid, sd.sbits, R)) * (int)sizeof(C2);
+      const int gbs = swz<T>(stage_base<R>(tid, sd)) * (int)sizeof(C2);
       T re[G], im[G];
 #pragma unroll
       for (int j = 0; j < G; j++) {
@@ -127,6 +127,7 @@ __device__ void sweep_tiles(const SVI_CONST SweepArgs &a, int64_t t0, int64_t t1
           apply_op<T, R>(op, re, im, coef);
         }
       }
+      if (sd.dflags & SD_XCHG) __syncthreads();
 #pragma unroll
       for (int j = 0; j < G; j++) *(C2 *)(lb + (gbs ^ sd.st_off[j])) = C2{re[j], im[j]};
       __syncthreads();

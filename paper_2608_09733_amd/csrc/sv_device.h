@@ -7,6 +7,8 @@
 // (Section 5.3), but indices are computed by bit insertion instead of an index
 // table, and many gates are applied per HBM round trip (see sv_internal.h).
 #include <hip/hip_runtime.h>
+
+#include <type_traits>
 #include <stdint.h>
 
 #include "sv_internal.h"
@@ -64,6 +66,23 @@ __device__ __forceinline__ int insert_zeros32c(int x, const SVI_CONST int32_t *p
   return x;
 }
 
+// Tile-local base index of thread tid in a stage: zeros at the group bits,
+// the thread index deposited into the other bits in ascending order, then the
+// stage's lane swaps (SD_LSWAP) applied.
+template <int R>
+__device__ __forceinline__ int stage_base(int tid, const SVI_CONST StageDesc &sd) {
+  int b = insert_zeros32c(tid, sd.sbits, R);
+  if (sd.dflags & SD_LSWAP) {
+#pragma unroll
+    for (int k = 0; k < 2; k++) {
+      const int x = sd.lsa[k], y = sd.lsb[k];
+      const int t = ((b >> x) ^ (b >> y)) & 1;
+      b ^= (t << x) | (t << y);
+    }
+  }
+  return b;
+}
+
 __device__ __forceinline__ int insert_zeros32(int x, const int32_t *pos, int np) {
   for (int k = 0; k < np; k++) {
     const int p = pos[k];
@@ -78,6 +97,12 @@ __device__ __forceinline__ uint64_t spread_row(int r, const int32_t *hb, int nh)
   uint64_t o = 0;
   for (int k = 0; k < nh; k++) o |= (uint64_t)((r >> k) & 1) << hb[k];
   return o;
+}
+
+// Offset of tile element i from its tile's base: the low c bits stay, bit
+// c + k goes to qubit hb[k].
+__device__ __forceinline__ uint64_t tile_off(int i, int c, const int32_t *hb, int nh) {
+  return spread_row(i >> c, hb, nh) + (uint64_t)(i & ((1 << c) - 1));
 }
 
 // Base index of tile `tile`: zeros inserted at the tile's qubits (0..c-1 and hb).
@@ -581,7 +606,7 @@ __global__ void __launch_bounds__(1 << (M - R)) k_sweep(SweepArgs a) {
       // beyond the tile's groups work on LDS slots above 2^mm, which are
       // never written back.
       const bool active = tid < ngroups;
-      const int gbs = swz<T>(insert_zeros32c(tid, sd.sbits, R)) * (int)sizeof(C2);
+      const int gbs = swz<T>(stage_base<R>(tid, sd)) * (int)sizeof(C2);
       T re[NS][G], im[NS][G];
 #pragma unroll
       for (int s = 0; s < NS; s++) {
@@ -637,6 +662,7 @@ __global__ void __launch_bounds__(1 << (M - R)) k_sweep(SweepArgs a) {
         apply_op<T, R>(op, re[0], im[0], a.coef);
         if constexpr (NS == 2) apply_op<T, R>(op, re[1], im[1], a.coef);
       }
+      if (sd.dflags & SD_XCHG) lds_barrier();
 #pragma unroll
       for (int s = 0; s < NS; s++) {
         char *lb = (char *)lds[s];
@@ -723,17 +749,13 @@ template <typename T, int M, int R>
 __global__ void __launch_bounds__(1 << (M - R)) k_sweep_kron(SweepArgs a) {
   constexpr int NT = 1 << (M - R);
   constexpr int G = 1 << R;
-  constexpr int VN = V4T<T>::N;
-  constexpr int NIT = (1 << M) / (VN * NT);
   using C2 = typename C2T<T>::type;
-  using V4 = typename V4T<T>::type;
   __shared__ C2 lds[1 << M];
   __shared__ int32_t hb_s[SVI_MMAX];
 
   const int tid = threadIdx.x;
   const int m = a.m, c = a.c, nh = a.nh;
   const int ntile_el = 1 << m;
-  const bool vec = c >= (VN == 2 ? 1 : 2);
   const bool init0 = (a.flags & SW_INIT_ZERO) != 0;
   const SVI_CONST StageDesc *stages = cptr(a.stages + a.stage_begin);
   const int nst = a.stage_end - a.stage_begin;
@@ -742,130 +764,166 @@ __global__ void __launch_bounds__(1 << (M - R)) k_sweep_kron(SweepArgs a) {
   if (tid < SVI_MMAX) hb_s[tid] = a.hb[tid < nh ? tid : 0];
   __syncthreads();
 
-  uint64_t roff[NIT];
+  // Lane tid moves tile elements i = tid + k * NT (k < G) between HBM and
+  // LDS, one amplitude per access: consecutive lanes take consecutive
+  // addresses along the tile's contiguous qubits, and every loaded value is
+  // already the register that the (re, im) LDS write takes.  (Loading pairs
+  // of amplitudes of one plane would need a register shuffle into (re, im)
+  // pairs, which the compiler places, with a wait for the load, right after
+  // the load.)
+  //
+  // Element i sits at tile_base + tile_off(i); tile_off is a bit deposit, so
+  // it splits over the disjoint bit fields of tid and k * NT into a per-lane
+  // part and wave-uniform parts.  Past the end of a small tile (i >= 2^m) the
+  // deposit drops the missing tile bits, so the address stays inside the tile:
+  // loads there are issued (and discarded) rather than branched around, and
+  // stores are skipped.
+  const uint64_t loff = tile_off(tid, c, hb_s, nh);
+  uint64_t kb[R];
 #pragma unroll
-  for (int k = 0; k < NIT; k++) {
-    const int i = (tid + k * NT) * (vec ? VN : 1);
-    roff[k] = spread_row(i >> c, hb_s, nh) + (uint64_t)(i & ((1 << c) - 1));
+  for (int r = 0; r < R; r++) kb[r] = tile_off(NT << r, c, a.hb, nh);
+  uint64_t loff_p;
+  auto goff = [&](int k) {
+    uint64_t o = loff_p;
+#pragma unroll
+    for (int r = 0; r < R; r++)
+      if ((k >> r) & 1) o += kb[r];
+    return o;
+  };
+  // LDS slots: element i is written to swz(i) and, for the store, read from
+  // swz(P(i)) with P the identity or the output bit permutation of a
+  // remapping sweep; swz and P are linear over XOR, so each is a per-lane
+  // slot XOR wave-uniform parts.
+  const bool operm = (a.flags & SW_OPERM) != 0;
+  const int tsl = swz<T>(tid);
+  const int ssl = swz<T>(operm ? perm_bits(tid, a.operm, m) : tid);
+  int wsb[R], ssb[R];
+#pragma unroll
+  for (int r = 0; r < R; r++) {
+    wsb[r] = swz<T>(NT << r);
+    ssb[r] = swz<T>(operm ? perm_bits(NT << r, a.operm, m) : NT << r);
   }
-  const int tsw = swz<T>(tid * VN);
+  auto slot = [&](int base, const int *sb, int k) {
+    int o = base;
+#pragma unroll
+    for (int r = 0; r < R; r++)
+      if ((k >> r) & 1) o ^= sb[r];
+    return o;
+  };
   T *const pre = (T *)a.re, *const pim = (T *)a.im;
   char *const lb = (char *)lds;
-  // LDS slots the stores read: the tile's own order, or the output bit
-  // permutation of a remapping sweep (both linear, so one base per vector
-  // plus a per-element offset)
-  const bool operm = (a.flags & SW_OPERM) != 0;
-  int ss[NIT];
-#pragma unroll
-  for (int k = 0; k < NIT; k++)
-    ss[k] = operm ? swz<T>(perm_bits((tid + k * NT) * VN, a.operm, m)) : tsw ^ swz<T>(k * NT * VN);
-  const int so1 = operm ? swz<T>(perm_bits(1, a.operm, m)) : 1;
-  const int so2 = operm ? swz<T>(perm_bits(2, a.operm, m)) : 2;
+  // The per-lane bases are re-declared opaque before each phase, so the
+  // compiler recomputes the (cheap) per-element addresses next to their use
+  // instead of hoisting all of them out of the tile loop and spilling them:
+  // a scratch reload would wait on every outstanding HBM access.
+  loff_p = loff;
+  int tsl_p = tsl, ssl_p = ssl;
+  auto opaque = [](auto &v) { asm volatile("" : "+v"(v)); };
 
   // Software pipeline: the next tile's HBM loads are issued into registers
   // before the current tile's stages run, so their latency hides behind the
-  // LDS / VALU work.
-  V4 nr[NIT], ni[NIT];
-  auto fetch = [&](int64_t tile) {
-    const uint64_t base = tile_base(tile, c, hb_s, nh);
+  // LDS / VALU work, and the current tile's stores drain behind the next
+  // tile's stages.  Inside the loop the next tile enters LDS after this
+  // tile's stores, on one straight path: every HBM access sits in fixed-count
+  // unrolled code, so the wait for the loads leaves the stores (issued after
+  // them) in flight.  The loop is instantiated separately for a sweep that
+  // synthesises |0..0> (no loads), so neither copy merges a path with loads
+  // in flight into one without.  A full tile (m == M, every n >= M) takes a
+  // copy with no per-element guards, so no HBM access or LDS write sits
+  // under a lane branch whose skipped path would make the waits conservative.
+  auto run = [&](auto synth, auto full) {
+    constexpr bool I0 = decltype(synth)::value;
+    constexpr bool FULL = decltype(full)::value;
+    T nr[G], ni[G];
+    auto fetch = [&](int64_t t) {
+      const uint64_t b0 = tile_base(t, c, hb_s, nh);
 #pragma unroll
-    for (int k = 0; k < NIT; k++) {
-      const int i = (tid + k * NT) * VN;
-      if (i < ntile_el) {
-        const uint64_t g = base + roff[k];
-        nr[k] = *(const V4 *)(pre + g);
-        ni[k] = *(const V4 *)(pim + g);
+      for (int k = 0; k < G; k++) {
+        const uint64_t g = b0 + goff(k);
+        nr[k] = pre[g];
+        ni[k] = pim[g];
       }
-    }
-  };
-  const bool pipe = vec && !init0;
-  int64_t r0 = 0;
-  int64_t tile = tile_of(0, blockIdx.x, gridDim.x);
-  if (pipe && tile < a.ntiles) fetch(tile);
-
-  while (tile < a.ntiles) {
-    const uint64_t base = tile_base(tile, c, hb_s, nh);
-    const int64_t next = tile_of(r0 + gridDim.x, blockIdx.x, gridDim.x);
-    // ---- tile into LDS
-    if (pipe) {
+    };
+    auto tile_in = [&](int64_t t) {
+      opaque(tsl_p);
 #pragma unroll
-      for (int k = 0; k < NIT; k++) {
-        const int i = (tid + k * NT) * VN;
-        if (i < ntile_el) {
-          const int si = tsw ^ swz<T>(k * NT * VN);
-          if constexpr (VN == 2) {
-            lds[si] = C2{nr[k].x, ni[k].x};
-            lds[si ^ 1] = C2{nr[k].y, ni[k].y};
+      for (int k = 0; k < G; k++) {
+        if (FULL || tid + k * NT < ntile_el) {
+          if constexpr (I0) {
+            const T v = (t == 0 && tid + k * NT == 0) ? (T)1 : (T)0;
+            lds[slot(tsl_p, wsb, k)] = C2{v, 0};
           } else {
-            lds[si] = C2{nr[k].x, ni[k].x};
-            lds[si ^ 1] = C2{nr[k].y, ni[k].y};
-            lds[si ^ 2] = C2{nr[k].z, ni[k].z};
-            lds[si ^ 3] = C2{nr[k].w, ni[k].w};
+            lds[slot(tsl_p, wsb, k)] = C2{nr[k], ni[k]};
           }
         }
       }
-    } else if (init0) {
-      for (int i = tid; i < ntile_el; i += NT) {
-        const T v = (base == 0 && i == 0) ? (T)1 : (T)0;
-        lds[swz<T>(i)] = C2{v, 0};
-      }
-    } else {
-      for (int i = tid; i < ntile_el; i += NT) {
-        const uint64_t g = base + spread_row(i >> c, hb_s, nh) + (uint64_t)(i & ((1 << c) - 1));
-        lds[swz<T>(i)] = C2{pre[g], pim[g]};
-      }
-    }
-    lds_barrier();
-    if (pipe && next < a.ntiles) fetch(next);
-    // ---- stages
-    for (int st = 0; st < nst; st++) {
-      const SVI_CONST StageDesc &sd = stages[st];
-      const int gbs = swz<T>(insert_zeros32c(tid, sd.sbits, R)) * (int)sizeof(C2);
-      T re[G], im[G];
-#pragma unroll
-      for (int j = 0; j < G; j++) {
-        const C2 v = *(const C2 *)(lb + (gbs ^ sd.ld_off[j]));
-        re[j] = v.x;
-        im[j] = v.y;
-      }
-      kron_stage<T, R>(re, im, coef + sd.kcoef, sd.rmask, sd.dflags);
-#pragma unroll
-      for (int j = 0; j < G; j++) *(C2 *)(lb + (gbs ^ sd.st_off[j])) = C2{re[j], im[j]};
+    };
+    int64_t r0 = 0;
+    int64_t tile = tile_of(0, blockIdx.x, gridDim.x);
+    if (tile < a.ntiles) {
+      if constexpr (!I0) fetch(tile);
+      tile_in(tile);
       lds_barrier();
     }
-    // ---- LDS to HBM
-    if (vec) {
-#pragma unroll
-      for (int k = 0; k < NIT; k++) {
-        const int i = (tid + k * NT) * VN;
-        if (i < ntile_el) {
-          const uint64_t g = base + roff[k];
-          const int si = ss[k];
-          V4 vr, vi;
-          if constexpr (VN == 2) {
-            const C2 p0 = lds[si], p1 = lds[si ^ so1];
-            vr = V4{p0.x, p1.x};
-            vi = V4{p0.y, p1.y};
-          } else {
-            const C2 p0 = lds[si], p1 = lds[si ^ so1], p2 = lds[si ^ so2], p3 = lds[si ^ so1 ^ so2];
-            vr = V4{p0.x, p1.x, p2.x, p3.x};
-            vi = V4{p0.y, p1.y, p2.y, p3.y};
-          }
-          *(V4 *)(pre + g) = vr;
-          *(V4 *)(pim + g) = vi;
+
+    while (tile < a.ntiles) {
+      const uint64_t base = tile_base(tile, c, hb_s, nh);
+      const int64_t next = tile_of(r0 + gridDim.x, blockIdx.x, gridDim.x);
+      const bool more = next < a.ntiles;
+      if constexpr (!I0) {
+        if (more) {
+          opaque(loff_p);
+          fetch(next);
         }
       }
-    } else {
-      for (int i = tid; i < ntile_el; i += NT) {
-        const uint64_t g = base + spread_row(i >> c, hb_s, nh) + (uint64_t)(i & ((1 << c) - 1));
-        const C2 p = lds[swz<T>(operm ? perm_bits(i, a.operm, m) : i)];
-        pre[g] = p.x;
-        pim[g] = p.y;
+      // ---- stages
+      for (int st = 0; st < nst; st++) {
+        const SVI_CONST StageDesc &sd = stages[st];
+        const int gbs = swz<T>(stage_base<R>(tid, sd)) * (int)sizeof(C2);
+        T re[G], im[G];
+#pragma unroll
+        for (int j = 0; j < G; j++) {
+          const C2 v = *(const C2 *)(lb + (gbs ^ sd.ld_off[j]));
+          re[j] = v.x;
+          im[j] = v.y;
+        }
+        kron_stage<T, R>(re, im, coef + sd.kcoef, sd.rmask, sd.dflags);
+        if (sd.dflags & SD_XCHG) lds_barrier();
+#pragma unroll
+        for (int j = 0; j < G; j++) *(C2 *)(lb + (gbs ^ sd.st_off[j])) = C2{re[j], im[j]};
+        lds_barrier();
       }
+      // ---- LDS to HBM
+      opaque(ssl_p);
+      opaque(loff_p);
+#pragma unroll
+      for (int k = 0; k < G; k++) {
+        if (FULL || tid + k * NT < ntile_el) {
+          const C2 p = lds[slot(ssl_p, ssb, k)];
+          const uint64_t g = base + goff(k);
+          pre[g] = p.x;
+          pim[g] = p.y;
+        }
+      }
+      lds_barrier();
+      // ---- next tile into LDS
+      if (!more) break;
+      tile_in(next);
+      lds_barrier();
+      r0 += gridDim.x;
+      tile = next;
     }
-    lds_barrier();
-    r0 += gridDim.x;
-    tile = next;
+  };
+  if (m == M) {
+    if (init0)
+      run(std::true_type{}, std::true_type{});
+    else
+      run(std::false_type{}, std::true_type{});
+  } else {
+    if (init0)
+      run(std::true_type{}, std::false_type{});
+    else
+      run(std::false_type{}, std::false_type{});
   }
 }
 
@@ -951,7 +1009,7 @@ __global__ void __launch_bounds__(1 << (M - R)) k_sweep_kron2(SweepArgs a) {
     // ---- stages
     for (int st = 0; st < nst; st++) {
       const SVI_CONST StageDesc &sd = stages[st];
-      const int gbs = swz<T>(insert_zeros32c(tid, sd.sbits, R)) * (int)sizeof(C2);
+      const int gbs = swz<T>(stage_base<R>(tid, sd)) * (int)sizeof(C2);
       const bool active = tid < (1 << (m > R ? m - R : 0));
       T re[2][G], im[2][G];
 #pragma unroll
@@ -993,6 +1051,7 @@ __global__ void __launch_bounds__(1 << (M - R)) k_sweep_kron2(SweepArgs a) {
       }
       kron_post<T, R>(re[0], im[0], kc, sd.dflags);
       kron_post<T, R>(re[1], im[1], kc, sd.dflags);
+      if (sd.dflags & SD_XCHG) lds_barrier();
 #pragma unroll
       for (int s = 0; s < 2; s++) {
         char *lb = (char *)lds[s];

@@ -212,7 +212,10 @@ struct StageP {
 };
 
 // Records a Kronecker stage can hold: uncontrolled RY rotations, diagonal
-// gates (any controls) and permutations (any controls).
+// gates (any controls) and permutations (any controls).  A leading or trailing
+// X whose controls are group qubits may target any tile qubit: the bit flip
+// then depends on the register slot only, so it is a fixed XOR on the slot's
+// LDS offset, whichever thread holds the slot.
 // A gradient record (adjoint backward program) fits too when its generator
 // commutes with everything the stage applies between the stage point where its
 // gradient is evaluated and the gate itself: a diagonal generator for diagonal
@@ -225,9 +228,13 @@ static bool kron_eligible(const GateRec &g) {
   return g.mo == MO_P || g.mo == MO_NEG || g.mo == MO_X || g.mo == MO_SWAP;
 }
 
-// Closure of records that fit  P_trail * D_after * (x) R * D_before * P_lead  inside S.
+// Closure of records that fit  P_trail * D_after * (x) R * D_before * P_lead  inside S
+// (an X of P_lead / P_trail: controls in S, target anywhere in the tile Tt).
+// Returns a score: rotations weigh more than diagonal gates and permutations,
+// which can ride along in many stages, while every rotation costs a stage slot.
+static constexpr int kRotWeight = 4;
 static int closure_kron(const std::vector<GateRec> &recs, const std::vector<int> &cand,
-                        const std::vector<char> &done, uint64_t S, StageP *st) {
+                        const std::vector<char> &done, uint64_t S, uint64_t Tt, StageP *st) {
   uint64_t blocked = 0, rq = 0, dA = 0, pq = 0;
   bool leading = true;
   int cnt = 0;
@@ -235,7 +242,9 @@ static int closure_kron(const std::vector<GateRec> &recs, const std::vector<int>
     if (done[r]) continue;
     const GateRec &g = recs[r];
     const uint64_t q = g.qmask;
-    bool ok = (q & ~S) == 0 && (q & blocked) == 0 && kron_eligible(g);
+    const uint64_t tq = g.mo == MO_X ? 1ull << g.t[0] : 0;
+    const bool fits = (q & ~S) == 0 || (tq && (q & ~tq & ~S) == 0 && (tq & Tt) != 0);
+    bool ok = fits && (q & blocked) == 0 && kron_eligible(g);
     int role = -1;   // 0 lead, 1 dbefore, 2 r, 3 dafter, 4 trail
     if (ok) {
       if (g.mo == MO_X || g.mo == MO_SWAP) {
@@ -252,7 +261,7 @@ static int closure_kron(const std::vector<GateRec> &recs, const std::vector<int>
     }
     if (ok) {
       if (role != 0) leading = false;
-      cnt++;
+      cnt += role == 2 ? kRotWeight : 1;
       if (st) {
         st->recs.push_back(r);
         std::vector<int> *dst[5] = {&st->lead, &st->dbefore, &st->rops, &st->dafter, &st->trail};
@@ -372,17 +381,17 @@ static void plan_stages(const std::vector<GateRec> &recs, const std::vector<int>
     if (allow_kron && kron_eligible(recs[first])) {
       uint64_t S = recs[first].qmask;
       while (popc(S) < R) {
-        int best = -1, bestv = closure_kron(recs, take, done, S, nullptr);
+        int best = -1, bestv = closure_kron(recs, take, done, S, Ttile, nullptr);
         for (int q = 0; q < n; q++) {
           if (!(Ttile & (1ull << q)) || (S & (1ull << q))) continue;
-          int v = closure_kron(recs, take, done, S | (1ull << q), nullptr);
+          int v = closure_kron(recs, take, done, S | (1ull << q), Ttile, nullptr);
           if (v > bestv) { bestv = v; best = q; }
         }
         if (best < 0) break;
         S |= 1ull << best;
       }
       st.kron = true;
-      closure_kron(recs, take, done, S, &st);
+      closure_kron(recs, take, done, S, Ttile, &st);
       for (int r : st.recs) { done[r] = 1; left--; }
       for (int q = 0; q < n; q++)
         if (S & (1ull << q)) grp.push_back(q);
@@ -973,13 +982,66 @@ static void emit_sweep(Plan &P, std::vector<GateRec> &recs, const SweepP &sw, in
       sd.op_end = (int)P.ops.size();
       sd.g1 = sd.g2 = sd.op_end;
     }
+    // slot j's tile-local offsets: its group bits placed, then the leading
+    // permutations undone (load) or the trailing ones applied (store), on tile
+    // positions, since a Kronecker stage's X may target a non-group tile bit
+    auto perm_tile = [&](int r, int x) {
+      const GateRec &g = recs[r];
+      for (int i = 0; i < g.nc; i++) {
+        const int b = (x >> tile_pos(sw, g.c[i])) & 1;
+        if (b != (int)((g.cs >> i) & 1u)) return x;
+      }
+      if (g.mo == MO_X) return x ^ (1 << tile_pos(sw, g.t[0]));
+      const int a = tile_pos(sw, g.t[0]), b = tile_pos(sw, g.t[1]);
+      return ((x >> a) & 1) != ((x >> b) & 1) ? x ^ (1 << a) ^ (1 << b) : x;
+    };
+    const int gmask = spread_local((1 << R) - 1, st.gq, R);
+    int xbits = 0;   // tile bits outside the group that the slot offsets reach
     for (int j = 0; j < (1 << R); j++) {
+      if (st.kron) {
+        int xl = spread_local(j, st.gq, R);
+        for (size_t k = st.lead.size(); k-- > 0;) xl = perm_tile(st.lead[k], xl);
+        sd.ld_off[j] = svi_swz(xl, SWB) * EB;
+        int xs = spread_local(j, st.gq, R);
+        for (size_t k = 0; k < st.trail.size(); k++) xs = perm_tile(st.trail[k], xs);
+        sd.st_off[j] = svi_swz(xs, SWB) * EB;
+        xbits |= (xl | xs) & ~gmask;
+        continue;
+      }
       int jl = j;
       for (size_t k = leadp.size(); k-- > 0;) jl = perm_apply(leadp[k], jl);
       sd.ld_off[j] = svi_swz(spread_local(jl, st.gq, R), SWB) * EB;
       int js = j;
       for (size_t k = 0; k < trailp.size(); k++) js = perm_apply(trailp[k], js);
       sd.st_off[j] = svi_swz(spread_local(js, st.gq, R), SWB) * EB;
+    }
+    if (xbits) {
+      // Threads exchange slots across the bits in xbits.  The thread index
+      // fills the non-group tile bits in ascending order, its low 6 bits
+      // (the lane) first; swap each exchanged bit that a wave bit would hold
+      // with a lane bit outside xbits, so every exchange stays in one wave.
+      int ng[SVI_MMAX + SVI_RMAX], nng = 0;
+      for (int p = 0; p < P.M; p++)
+        if (!((gmask >> p) & 1)) ng[nng++] = p;
+      const int lanes = std::min(6, nng);
+      int nsw = 0;
+      bool ok = true;
+      int spare = lanes - 1;
+      for (int i = lanes; i < nng; i++) {
+        if (!((xbits >> ng[i]) & 1)) continue;
+        while (spare >= 0 && ((xbits >> ng[spare]) & 1)) spare--;
+        if (spare < 0 || nsw == 2) { ok = false; break; }
+        sd.lsa[nsw] = ng[i];
+        sd.lsb[nsw] = ng[spare];
+        spare--;
+        nsw++;
+      }
+      if (ok) {
+        sd.dflags |= SD_LSWAP;
+        for (int k = nsw; k < 2; k++) sd.lsa[k] = sd.lsb[k] = 0;
+      } else {
+        sd.dflags |= SD_XCHG;
+      }
     }
     P.stages.push_back(sd);
     P.n_blocks++;

@@ -59,15 +59,28 @@ struct MicroOp {
 //              form 1: x' = k x - y, y' = x + k y      (|s| >  |c|, k = c/s, scale s)
 enum { ST_OPS = 0, ST_KRON = 1 };
 
+// dflags bits for stages whose slot offsets reach tile bits outside the group
+// (an X controlled by group qubits whose target is another tile qubit): a
+// thread then stores to slots that other threads load.
+//   SD_LSWAP: the planner made those tile bits lane bits of the thread index
+//             (each thread's base swaps tile bits lsa[k] and lsb[k]), so every
+//             exchange stays inside one wave, whose loads complete before its
+//             stores (they feed them); no barrier.
+//   SD_XCHG:  otherwise every load of the stage completes (workgroup barrier)
+//             before any store.
+#define SD_XCHG 8
+#define SD_LSWAP 16
+
 struct StageDesc {
   int32_t sbits[SVI_RMAX];     // tile-local bit positions of the group bits, ascending
   int32_t op_begin, op_end;    // micro-ops [op_begin, op_end)
   int32_t kind;                // ST_OPS / ST_KRON
   uint32_t rmask;              // ST_KRON: group bits carrying a real 2x2
-  int32_t dflags;              // ST_KRON: 1 = D_before, 2 = D_after
+  int32_t dflags;              // ST_KRON: 1 = D_before, 2 = D_after; SD_XCHG (any kind)
   int32_t kcoef;               // ST_KRON: coefficient offset (doubles)
   int32_t g1, g2;              // ST_KRON: MO_GRAD ops [op_begin, g1) run on the stage input,
                                // [g1, g2) after D_before, [g2, op_end) after the rotations
+  int32_t lsa[2], lsb[2];      // SD_LSWAP: tile bit pairs swapped in each thread's base
   int32_t ld_off[SVI_GMAX];    // swizzled tile-local BYTE offset loaded into slot j
   int32_t st_off[SVI_GMAX];    // swizzled tile-local BYTE offset slot j is stored to
 };

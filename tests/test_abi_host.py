@@ -175,3 +175,18 @@ def test_remapping_plans_are_consistent(sv):
 def test_remapping_reduces_sweeps_on_layered_ansatz(sv):
     ops = I.layered_structure(30, 20)
     assert sv.plan_stats(30, ops, -1, 13, 4, 3)[0] <= 24
+
+
+def test_kronecker_stages_take_ladder_cnots_with_outside_targets(sv):
+    # A CNOT ladder links every register group to the next qubit.  A CNOT whose
+    # control is a group qubit is a fixed per-slot offset even when its target
+    # lies outside the group, so a 3-qubit stage can take the ladder step that
+    # leaves it and still hold three rotations.  Without that, a stage on
+    # {q, q+1, q+2} holds two rotations (the third waits for CNOT(q+2, q+3)).
+    n, L = 30, 20
+    ops = I.layered_structure(n, L)
+    sweeps, stages = sv.plan_stats(n, ops, -1, 13, 5, 3)
+    assert sweeps == 30
+    assert n * L / stages >= 2.3, stages
+    sweeps4, stages4 = sv.plan_stats(n, ops, -1, 13, 5, 4)
+    assert n * L / stages4 >= 3.0, stages4

@@ -858,24 +858,26 @@ __global__ void __launch_bounds__(1 << (M - R)) k_sweep_kron(SweepArgs a) {
         }
       }
     };
+    // Prefetch distance one tile: the loads of tile t+1 are issued right after
+    // tile t enters LDS (in the same straight-line block that consumed the
+    // previous prefetch registers, so no wait precedes them) and run behind
+    // tile t's stages; tile t's stores drain behind tile t+1's stages.
     int64_t r0 = 0;
     int64_t tile = tile_of(0, blockIdx.x, gridDim.x);
-    if (tile < a.ntiles) {
-      if constexpr (!I0) fetch(tile);
-      tile_in(tile);
-      lds_barrier();
+    if (tile >= a.ntiles) return;
+    int64_t next = tile_of(r0 + gridDim.x, blockIdx.x, gridDim.x);
+    if constexpr (!I0) fetch(tile);
+    tile_in(tile);
+    lds_barrier();
+    if constexpr (!I0) {
+      if (next < a.ntiles) {
+        opaque(loff_p);
+        fetch(next);
+      }
     }
 
-    while (tile < a.ntiles) {
+    while (true) {
       const uint64_t base = tile_base(tile, c, hb_s, nh);
-      const int64_t next = tile_of(r0 + gridDim.x, blockIdx.x, gridDim.x);
-      const bool more = next < a.ntiles;
-      if constexpr (!I0) {
-        if (more) {
-          opaque(loff_p);
-          fetch(next);
-        }
-      }
       // ---- stages
       for (int st = 0; st < nst; st++) {
         const SVI_CONST StageDesc &sd = stages[st];
@@ -906,12 +908,19 @@ __global__ void __launch_bounds__(1 << (M - R)) k_sweep_kron(SweepArgs a) {
         }
       }
       lds_barrier();
-      // ---- next tile into LDS
-      if (!more) break;
+      if (next >= a.ntiles) break;
+      // ---- next tile into LDS, then the prefetch of the one after
       tile_in(next);
       lds_barrier();
       r0 += gridDim.x;
       tile = next;
+      next = tile_of(r0 + gridDim.x, blockIdx.x, gridDim.x);
+      if constexpr (!I0) {
+        if (next < a.ntiles) {
+          opaque(loff_p);
+          fetch(next);
+        }
+      }
     }
   };
   if (m == M) {

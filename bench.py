@@ -238,6 +238,8 @@ def main():
     log(f"workload n={n} L={L} gates={gates} plan fuse={args.fuse}: {sweeps} sweeps, {blocks} blocks")
 
     st = sv.State(n, "c128")
+    dt = sv.default_tiling(n)
+    tiling = (args.tile or dt[0], args.low or dt[1], args.group or dt[2])
     if args.tile or args.low or args.group:
         st.set_tiling(args.tile, args.low, args.group)
 
@@ -293,7 +295,7 @@ def main():
                    "state_bytes": 16 * (1 << n)},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(),
-                     "kernel": "svk::k_sweep_kron<double,13,3> (tile sweep)",
+                     "kernel": f"svk::k_sweep_kron<double,{tiling[0]},{tiling[2]}> (tile sweep)",
                      "bytes_per_launch": bytes_per_launch, "avg_launch_ms": avg_launch_ms,
                      "launches": launches},
     }

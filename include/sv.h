@@ -291,6 +291,14 @@ sv_status sv_plan_stats(int32_t n_qubits, const sv_op *ops, int32_t n_ops, int32
                         int32_t tile_bits, int32_t low_bits, int32_t group_bits,
                         int32_t *n_sweeps, int32_t *n_blocks);
 
+/* Default tiling of sv_apply_layer (backward = 0) or of the backward sweeps
+ * of sv_adjoint_grad (backward = 1) for an n_qubits state of this dtype, as
+ * used by a handle without sv_set_tiling / sv_set_adjoint_tiling (host-only).
+ * Writes the three values (see sv_set_tiling); SV_EINVAL on a bad dtype or
+ * null output. */
+sv_status sv_default_tiling(int32_t n_qubits, sv_dtype dtype, int32_t backward,
+                            int32_t *tile_bits, int32_t *low_bits, int32_t *group_bits);
+
 /* Tiling used by SV_FUSE_AUTO for a handle (0 = keep the default): tile_bits =
  * qubits per LDS tile, low_bits = contiguous low qubits in every tile (rows of
  * 2^low_bits elements in HBM), group_bits = qubits per register block.  A

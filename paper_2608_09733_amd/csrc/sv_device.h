@@ -351,11 +351,10 @@ __device__ __forceinline__ double mo_grad(const T *pr, const T *pi, const T *lr,
 }
 
 // Fast-Givens rotation on group bit TB (record {form, k, scale, 0}, form 0 or
-// 1; the scale is applied separately).  Gentleman's scaled rotation: each
-// output is one FMA with a +-1 coefficient on one input.
+// 1, always 0 for FP64; the scale is applied separately).  Gentleman's scaled
+// rotation: each output is one FMA with a +-1 coefficient on one input.
 template <typename T, int R, int TB, typename CP>
 __device__ __forceinline__ void mo_fastr(T *re, T *im, CP cf) {
-  const int form = (int)cf[0];
   const T k = (T)cf[1];
 #define SVI_FR(XR, XI, YR, YI)                                   \
   _Pragma("unroll") for (int j = 0; j < (1 << R); j++) {         \
@@ -364,10 +363,17 @@ __device__ __forceinline__ void mo_fastr(T *re, T *im, CP cf) {
     const T xr = re[j], xi = im[j], yr = re[l], yi = im[l];      \
     re[j] = XR; im[j] = XI; re[l] = YR; im[l] = YI;              \
   }
-  if (form == 0) {
+  if constexpr (sizeof(T) == 8) {
+    // FP64 coefficients are always form 0 (CF_FORM0): straight-line FMAs,
+    // with no branch whose two arms the compiler would merge with copies
     SVI_FR(xr - k * yr, xi - k * yi, k * xr + yr, k * xi + yi)
   } else {
-    SVI_FR(k * xr - yr, k * xi - yi, xr + k * yr, xi + k * yi)
+    const int form = (int)cf[0];
+    if (form == 0) {
+      SVI_FR(xr - k * yr, xi - k * yi, k * xr + yr, k * xi + yi)
+    } else {
+      SVI_FR(k * xr - yr, k * xi - yi, xr + k * yr, xi + k * yi)
+    }
   }
 #undef SVI_FR
 }
@@ -386,6 +392,16 @@ __device__ __forceinline__ void kron_rot(T *re, T *im, CP cf, uint32_t rmask) {
   if constexpr (R > 2) { if (rmask & 4u) mo_fastr<T, R, 2>(re, im, cf + 8); }
   if constexpr (R > 3) { if (rmask & 8u) mo_fastr<T, R, 3>(re, im, cf + 12); }
   if constexpr (R > 4) { if (rmask & 16u) mo_fastr<T, R, 4>(re, im, cf + 16); }
+}
+
+// Every group bit rotated (rmask full), no conditionals.
+template <typename T, int R, typename CP>
+__device__ __forceinline__ void kron_rot_all(T *re, T *im, CP cf) {
+  mo_fastr<T, R, 0>(re, im, cf + 0);
+  mo_fastr<T, R, 1>(re, im, cf + 4);
+  if constexpr (R > 2) mo_fastr<T, R, 2>(re, im, cf + 8);
+  if constexpr (R > 3) mo_fastr<T, R, 3>(re, im, cf + 12);
+  if constexpr (R > 4) mo_fastr<T, R, 4>(re, im, cf + 16);
 }
 
 template <typename T, int R, typename CP>
@@ -882,17 +898,32 @@ __global__ void __launch_bounds__(1 << (M - R)) k_sweep_kron(SweepArgs a) {
       for (int st = 0; st < nst; st++) {
         const SVI_CONST StageDesc &sd = stages[st];
         const int gbs = swz<T>(stage_base<R>(tid, sd)) * (int)sizeof(C2);
-        T re[G], im[G];
+        // The common stage (every group bit rotated, then D_after) runs as its
+        // own straight-line body from loads to stores; the general body
+        // branches on the stage's parts.  Separate bodies leave nothing to
+        // merge, so neither pays register copies for the other's branches.
+        auto body = [&](auto full_stage) {
+          T re[G], im[G];
 #pragma unroll
-        for (int j = 0; j < G; j++) {
-          const C2 v = *(const C2 *)(lb + (gbs ^ sd.ld_off[j]));
-          re[j] = v.x;
-          im[j] = v.y;
-        }
-        kron_stage<T, R>(re, im, coef + sd.kcoef, sd.rmask, sd.dflags);
-        if (sd.dflags & SD_XCHG) lds_barrier();
+          for (int j = 0; j < G; j++) {
+            const C2 v = *(const C2 *)(lb + (gbs ^ sd.ld_off[j]));
+            re[j] = v.x;
+            im[j] = v.y;
+          }
+          if constexpr (decltype(full_stage)::value) {
+            kron_rot_all<T, R>(re, im, coef + sd.kcoef);
+            mo_diagt<T, R>(re, im, coef + sd.kcoef + 4 * R + 2 * G);
+          } else {
+            kron_stage<T, R>(re, im, coef + sd.kcoef, sd.rmask, sd.dflags);
+          }
+          if (sd.dflags & SD_XCHG) lds_barrier();
 #pragma unroll
-        for (int j = 0; j < G; j++) *(C2 *)(lb + (gbs ^ sd.st_off[j])) = C2{re[j], im[j]};
+          for (int j = 0; j < G; j++) *(C2 *)(lb + (gbs ^ sd.st_off[j])) = C2{re[j], im[j]};
+        };
+        if (sd.rmask == (1u << R) - 1 && (sd.dflags & 7) == 2)
+          body(std::true_type{});
+        else
+          body(std::false_type{});
         lds_barrier();
       }
       // ---- LDS to HBM

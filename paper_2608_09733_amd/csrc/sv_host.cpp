@@ -894,7 +894,7 @@ static void emit_sweep(Plan &P, std::vector<GateRec> &recs, const SweepP &sw, in
         rmask |= 1u << t;
         CoefDesc cd{};
         cd.kind = g.coef_kind;
-        cd.fmt = CF_FASTR | (g.dagger ? CF_DAGGER : 0);
+        cd.fmt = CF_FASTR | (g.dagger ? CF_DAGGER : 0) | (P.dbl ? CF_FORM0 : 0);
         for (int k = 0; k < 3; k++) cd.pidx[k] = g.pidx[k];
         cd.dst = sd.kcoef + 4 * t;
         P.coefs.push_back(cd);
@@ -914,7 +914,7 @@ static void emit_sweep(Plan &P, std::vector<GateRec> &recs, const SweepP &sw, in
       for (int r : st.recs) dag = dag || recs[r].dagger;
       auto table = [&](const std::vector<int> &rs, int dst, bool scales) {
         CoefDesc cd{};
-        cd.fmt = CF_TABLE | (dag ? CF_DAGGER : 0);
+        cd.fmt = CF_TABLE | (dag ? CF_DAGGER : 0) | (P.dbl ? CF_FORM0 : 0);
         cd.src = (int)P.factors.size();
         cd.len = R;
         cd.dst = dst;
@@ -959,7 +959,7 @@ static void emit_sweep(Plan &P, std::vector<GateRec> &recs, const SweepP &sw, in
       if (scalar || sd.g2 < sd.op_end) {
         if (scalar) sd.dflags |= 4;
         CoefDesc cd{};
-        cd.fmt = CF_SCALE | (dag ? CF_DAGGER : 0);
+        cd.fmt = CF_SCALE | (dag ? CF_DAGGER : 0) | (P.dbl ? CF_FORM0 : 0);
         cd.src = (int)P.factors.size();
         push_scales();
         cd.pidx[0] = (int)P.factors.size() - cd.src;
@@ -1215,18 +1215,29 @@ static sv_status ensure_scratch(sv_state *st, size_t bytes) {
 static Tiling default_tiling(int n, sv_dtype dt, int NS) {
   Tiling t;
   if (dt == SV_C128) {
-    // forward: 13-qubit tiles, 256-byte rows, 8-amplitude register groups
-    // (1024-thread workgroups, 4 waves per SIMD); measured best on the
+    // forward: 13-qubit tiles, 256-byte rows; 16-amplitude register groups
+    // (512-thread workgroups) when the state spans several tiles, 8-amplitude
+    // groups (1024 threads) when one tile holds it; measured best on the
     // 30-qubit layered workload among the compiled tilings
     // adjoint backward: two 11-qubit tiles (psi, lambda), 8-amplitude groups
     if (NS == 2) { t.M = 11; t.R = 3; t.c = 3; }
-    else { t.M = 13; t.R = 3; t.c = 5; }
+    else { t.M = 13; t.R = n > 13 ? 4 : 3; t.c = 5; }
   } else {
     if (NS == 2) { t.M = 13; t.R = 4; t.c = 3; }
     else { t.M = 14; t.R = 5; t.c = 3; }
   }
-  (void)n;
   return t;
+}
+
+extern "C" sv_status sv_default_tiling(int32_t n, sv_dtype dtype, int32_t backward,
+                                      int32_t *tile_bits, int32_t *low_bits, int32_t *group_bits) {
+  if (dtype != SV_C128 && dtype != SV_C64) return fail(SV_EINVAL, "dtype %d", (int)dtype);
+  if (!tile_bits || !low_bits || !group_bits) return fail(SV_EINVAL, "null output");
+  const Tiling t = default_tiling(n, dtype, backward ? 2 : 1);
+  *tile_bits = t.M;
+  *low_bits = t.c;
+  *group_bits = t.R;
+  return SV_OK;
 }
 
 extern "C" sv_status sv_alloc(int32_t n, sv_dtype dtype, void *re, void *im, void *ws,

@@ -55,8 +55,10 @@ struct MicroOp {
 //            into D_after) and P folded into st_off.  Coefficients at kcoef:
 //            [R_0 .. R_{R-1}: 4 doubles each][D_before: 2^(R+1)][D_after: 2^(R+1)][s].
 //            Fast-Givens record of R_t: {form, k, scale, 0} with
-//              form 0: x' = x - k y, y' = k x + y      (|c| >= |s|, k = s/c, scale c)
-//              form 1: x' = k x - y, y' = x + k y      (|s| >  |c|, k = c/s, scale s)
+//              form 0: x' = x - k y, y' = k x + y      (k = s/c, scale c)
+//              form 1: x' = k x - y, y' = x + k y      (k = c/s, scale s)
+//            FP64 plans always take form 0 (CF_FORM0); FP32 plans take form 1
+//            when |s| > |c|, so that |k| <= 1.
 enum { ST_OPS = 0, ST_KRON = 1 };
 
 // dflags bits for stages whose slot offsets reach tile bits outside the group
@@ -133,7 +135,7 @@ enum {
   CF_COPY = 6,     // copy `len` doubles from the static (user-matrix) area
   CF_TABLE = 7,    // diagonal table of 2^len complex entries from factors [src, src+pidx[0])
   CF_IDENT2 = 8,   // 2x2 real identity (4 doubles)
-  CF_FASTR = 9,    // fast-Givens record {form, k, scale, 0} of a real 1q gate
+  CF_FASTR = 9,    // fast-Givens record {form, k, scale, 0} of a real 1q gate (see CF_FORM0)
   CF_SCALE = 10,   // real scalar: product of the fast-Givens scales of factors [src, +pidx[0])
 };
 
@@ -148,6 +150,11 @@ struct TabFactor {
   int32_t neg;
 };
 #define CF_DAGGER 0x100
+// CF_FASTR / CF_SCALE / CF_TABLE scale factors: a rotation always takes form 0
+// (k = s / c, scale c; the FP64 kernels apply it without a form branch).
+// Without the flag the form with |k| <= 1 is chosen (FP32, whose range a
+// product of large k could leave).
+#define CF_FORM0 0x200
 
 struct CoefDesc {
   int32_t kind;        // sv_gate_kind

@@ -158,13 +158,16 @@ __device__ void gate_local(int kind, const double *th, double *m /* interleaved,
 
 // Fast-Givens factorisation of a real orthogonal 2x2 r = [[r0, r1], [r2, r3]]
 // (Gentleman 1973): out = {form, k, scale, 0}, r = scale * (form matrix).
-__device__ void fast_givens(const double *r, double *out) {
+// form0: a rotation always takes form 0 (k = s / c; c is never exactly zero
+// for a rotation angle that is a double, so k is finite, and the error of
+// (x - k y) c stays within a few ulps of |x c| + |y s|).
+__device__ void fast_givens(const double *r, double *out, bool form0 = false) {
   // rotation [[c,-s],[s,c]] vs reflection [[a,b],[b,-a]]
   const bool rot = fabs(r[0] - r[3]) + fabs(r[1] + r[2]) <= fabs(r[0] + r[3]) + fabs(r[1] - r[2]);
   if (rot) {
     // [[c, -s], [s, c]]
     const double c = r[0], s = r[2];
-    if (fabs(c) >= fabs(s)) { out[0] = 0; out[1] = s / c; out[2] = c; }
+    if (form0 || fabs(c) >= fabs(s)) { out[0] = 0; out[1] = s / c; out[2] = c; }
     else { out[0] = 1; out[1] = c / s; out[2] = s; }
   } else {
     // [[a, b], [b, -a]]
@@ -181,6 +184,7 @@ __global__ void k_build_coefs(const CoefDesc *d, int nd, const double *params, c
     const CoefDesc cd = d[i];
     const int fmt = cd.fmt & 0xff;
     const bool dag = (cd.fmt & CF_DAGGER) != 0;
+    const bool f0 = (cd.fmt & CF_FORM0) != 0;
     double th[3] = {0, 0, 0};
     // pidx holds parameter indices except for the table / scale formats,
     // where pidx[0] counts factors
@@ -195,7 +199,7 @@ __global__ void k_build_coefs(const CoefDesc *d, int nd, const double *params, c
       gate_local(cd.kind, th, m);
       double r[4] = {m[0], m[2], m[4], m[6]};   // real 2x2
       if (dag) { const double t = r[1]; r[1] = r[2]; r[2] = t; }
-      fast_givens(r, out);
+      fast_givens(r, out, f0);
     } else if (fmt == CF_SCALE) {
       // product of the fast-Givens scales of the (daggered, if flagged) real gates
       double sc = 1.0;
@@ -206,7 +210,7 @@ __global__ void k_build_coefs(const CoefDesc *d, int nd, const double *params, c
         gate_local(tf.kind, tt, m);
         double r[4] = {m[0], m[2], m[4], m[6]};
         if (dag) { const double t = r[1]; r[1] = r[2]; r[2] = t; }
-        fast_givens(r, rec);
+        fast_givens(r, rec, f0);
         sc *= rec[2];
       }
       out[0] = sc;
@@ -224,7 +228,7 @@ __global__ void k_build_coefs(const CoefDesc *d, int nd, const double *params, c
         if (tf.neg == 2) {
           double r[4] = {m[0], m[2], m[4], m[6]}, rec[4];
           if (dag) { const double t = r[1]; r[1] = r[2]; r[2] = t; }
-          fast_givens(r, rec);
+          fast_givens(r, rec, f0);
           gsc = rec[2];
         }
         for (int j = 0; j < G; j++) {

@@ -75,6 +75,8 @@ def lib():
         "sv_copy_to_host": (C.c_int, [vp, vp, vp, u64, u64]),
         "sv_copy_from_host": (C.c_int, [vp, vp, vp, u64, u64]),
         "sv_last_error": (C.c_char_p, []),
+        "sv_default_tiling": (C.c_int, [i32, C.c_int, i32, C.POINTER(i32), C.POINTER(i32),
+                                        C.POINTER(i32)]),
         "sv_plan_stats": (C.c_int, [i32, opp, i32, i32, i32, i32, i32, C.POINTER(i32),
                                     C.POINTER(i32)]),
         "sv_set_tiling": (C.c_int, [vp, i32, i32, i32]),
@@ -304,6 +306,15 @@ class State:
         im = np.ascontiguousarray(im, dtype=self.np_dtype)
         _check(lib().sv_copy_from_host(self.h, C.c_void_p(re.ctypes.data), C.c_void_p(im.ctypes.data),
                                        offset, int(re.size)))
+
+
+def default_tiling(n: int, dtype: str = "c128", backward: bool = False) -> Tuple[int, int, int]:
+    """(tile_bits, low_bits, group_bits) a handle uses unless set_tiling overrides them."""
+    t, c, r = C.c_int32(0), C.c_int32(0), C.c_int32(0)
+    code = SV_C128 if dtype == "c128" else SV_C64
+    _check(lib().sv_default_tiling(n, code, 1 if backward else 0, C.byref(t), C.byref(c),
+                                   C.byref(r)))
+    return int(t.value), int(c.value), int(r.value)
 
 
 def plan_stats(n: int, ops, fuse: int = SV_FUSE_AUTO, tile_bits: int = 0, low_bits: int = 0,

@@ -190,3 +190,14 @@ def test_kronecker_stages_take_ladder_cnots_with_outside_targets(sv):
     assert n * L / stages >= 2.3, stages
     sweeps4, stages4 = sv.plan_stats(n, ops, -1, 13, 5, 4)
     assert n * L / stages4 >= 3.0, stages4
+
+
+def test_default_tiling_query(sv):
+    import ctypes as C
+    # multi-tile FP64 states take 16-amplitude register groups, single-tile ones 8
+    assert sv.default_tiling(30) == (13, 5, 4)
+    assert sv.default_tiling(12) == (13, 5, 3)
+    assert sv.default_tiling(26, backward=True) == (11, 3, 3)
+    t = C.c_int32(0)
+    assert sv.lib().sv_default_tiling(20, 7, 0, C.byref(t), C.byref(t), C.byref(t)) == -1
+    assert sv.lib().sv_default_tiling(20, 0, 0, None, C.byref(t), C.byref(t)) == -1

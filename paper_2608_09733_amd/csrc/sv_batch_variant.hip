@@ -12,6 +12,8 @@
 // circuits (n <= tile bits) are one unit each: the whole circuit runs in LDS.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "sv_device.h"
 #include "sv_variants.h"
 
@@ -112,24 +114,35 @@ __device__ void sweep_tiles(const SVI_CONST SweepArgs &a, int64_t t0, int64_t t1
     for (int st = st_begin; st < st_end; st++) {
       const SVI_CONST StageDesc &sd = stages[st];
       const int gbs = swz<T>(stage_base<R>(tid, sd)) * (int)sizeof(C2);
-      T re[G], im[G];
+      // a full Kronecker stage (every group bit rotated, then D_after) runs as
+      // its own straight-line body, loads to stores; the general body branches
+      auto body = [&](auto full_stage) {
+        T re[G], im[G];
 #pragma unroll
-      for (int j = 0; j < G; j++) {
-        const C2 v = *(const C2 *)(lb + (gbs ^ sd.ld_off[j]));
-        re[j] = v.x;
-        im[j] = v.y;
-      }
-      if (KO || sd.kind == ST_KRON) {
-        kron_stage<T, R>(re, im, cptr(coef) + sd.kcoef, sd.rmask, sd.dflags);
-      } else {
-        for (int o = sd.op_begin; o < sd.op_end; o++) {
-          const MicroOp op = ops[o];
-          apply_op<T, R>(op, re, im, coef);
+        for (int j = 0; j < G; j++) {
+          const C2 v = *(const C2 *)(lb + (gbs ^ sd.ld_off[j]));
+          re[j] = v.x;
+          im[j] = v.y;
         }
-      }
-      if (sd.dflags & SD_XCHG) __syncthreads();
+        if constexpr (decltype(full_stage)::value) {
+          kron_rot_all<T, R>(re, im, cptr(coef) + sd.kcoef);
+          mo_diagt<T, R>(re, im, cptr(coef) + sd.kcoef + 4 * R + 2 * G);
+        } else if (KO || sd.kind == ST_KRON) {
+          kron_stage<T, R>(re, im, cptr(coef) + sd.kcoef, sd.rmask, sd.dflags);
+        } else {
+          for (int o = sd.op_begin; o < sd.op_end; o++) {
+            const MicroOp op = ops[o];
+            apply_op<T, R>(op, re, im, coef);
+          }
+        }
+        if (sd.dflags & SD_XCHG) __syncthreads();
 #pragma unroll
-      for (int j = 0; j < G; j++) *(C2 *)(lb + (gbs ^ sd.st_off[j])) = C2{re[j], im[j]};
+        for (int j = 0; j < G; j++) *(C2 *)(lb + (gbs ^ sd.st_off[j])) = C2{re[j], im[j]};
+      };
+      if (sd.kind == ST_KRON && sd.rmask == (1u << R) - 1 && (sd.dflags & 7) == 2)
+        body(std::true_type{});
+      else
+        body(std::false_type{});
       __syncthreads();
     }
 

@@ -766,8 +766,16 @@ __global__ void __launch_bounds__(1 << (M - R)) k_sweep_kron(SweepArgs a) {
   constexpr int NT = 1 << (M - R);
   constexpr int G = 1 << R;
   using C2 = typename C2T<T>::type;
+  // Per-stage thread bases (tile-local slot offset of the thread's register
+  // group) depend on the thread and the stage, not on the tile: the first
+  // GTAB stages take theirs from a table built once per launch in the LDS
+  // the tile leaves free (sized so the workgroups per CU stay as they are).
+  constexpr int TILE_BYTES = (1 << M) * (int)sizeof(C2);
+  constexpr int GTAB_BYTES = TILE_BYTES >= 131072 ? 30720 : TILE_BYTES >= 65536 ? 14336 : 6144;
+  constexpr int GTAB = GTAB_BYTES / (4 * NT) > 0 ? GTAB_BYTES / (4 * NT) : 1;
   __shared__ C2 lds[1 << M];
   __shared__ int32_t hb_s[SVI_MMAX];
+  __shared__ int32_t gtab[GTAB * NT];
 
   const int tid = threadIdx.x;
   const int m = a.m, c = a.c, nh = a.nh;
@@ -778,6 +786,9 @@ __global__ void __launch_bounds__(1 << (M - R)) k_sweep_kron(SweepArgs a) {
   const SVI_CONST double *coef = cptr(a.coef);
 
   if (tid < SVI_MMAX) hb_s[tid] = a.hb[tid < nh ? tid : 0];
+  const int ntab = nst < GTAB ? nst : GTAB;
+  for (int st = 0; st < ntab; st++)   // each thread reads back only its own entries
+    gtab[st * NT + tid] = swz<T>(stage_base<R>(tid, stages[st])) * (int)sizeof(C2);
   __syncthreads();
 
   // Lane tid moves tile elements i = tid + k * NT (k < G) between HBM and
@@ -897,7 +908,8 @@ __global__ void __launch_bounds__(1 << (M - R)) k_sweep_kron(SweepArgs a) {
       // ---- stages
       for (int st = 0; st < nst; st++) {
         const SVI_CONST StageDesc &sd = stages[st];
-        const int gbs = swz<T>(stage_base<R>(tid, sd)) * (int)sizeof(C2);
+        const int gbs =
+            st < ntab ? gtab[st * NT + tid] : swz<T>(stage_base<R>(tid, sd)) * (int)sizeof(C2);
         // The common stage (every group bit rotated, then D_after) runs as its
         // own straight-line body from loads to stores; the general body
         // branches on the stage's parts.  Separate bodies leave nothing to

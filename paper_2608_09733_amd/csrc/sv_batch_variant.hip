@@ -113,7 +113,7 @@ __device__ void sweep_tiles(const SVI_CONST SweepArgs &a, int64_t t0, int64_t t1
 
     for (int st = st_begin; st < st_end; st++) {
       const SVI_CONST StageDesc &sd = stages[st];
-      const int gbs = swz<T>(stage_base<R>(tid, sd)) * (int)sizeof(C2);
+      const int gbs = swz<T>(stage_base<M, R>(tid, sd)) * (int)sizeof(C2);
       // a full Kronecker stage (every group bit rotated, then D_after) runs as
       // its own straight-line body, loads to stores; the general body branches
       auto body = [&](auto full_stage) {

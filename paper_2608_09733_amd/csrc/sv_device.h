@@ -66,20 +66,13 @@ __device__ __forceinline__ int insert_zeros32c(int x, const SVI_CONST int32_t *p
   return x;
 }
 
-// Tile-local base index of thread tid in a stage: zeros at the group bits,
-// the thread index deposited into the other bits in ascending order, then the
-// stage's lane swaps (SD_LSWAP) applied.
-template <int R>
+// Tile-local base index of thread tid in a stage: thread-index bit k placed
+// on tile bit tpos[k] (the group bits stay zero).
+template <int M, int R>
 __device__ __forceinline__ int stage_base(int tid, const SVI_CONST StageDesc &sd) {
-  int b = insert_zeros32c(tid, sd.sbits, R);
-  if (sd.dflags & SD_LSWAP) {
+  int b = 0;
 #pragma unroll
-    for (int k = 0; k < 2; k++) {
-      const int x = sd.lsa[k], y = sd.lsb[k];
-      const int t = ((b >> x) ^ (b >> y)) & 1;
-      b ^= (t << x) | (t << y);
-    }
-  }
+  for (int k = 0; k < M - R; k++) b |= ((tid >> k) & 1) << sd.tpos[k];
   return b;
 }
 
@@ -622,7 +615,7 @@ __global__ void __launch_bounds__(1 << (M - R)) k_sweep(SweepArgs a) {
       // beyond the tile's groups work on LDS slots above 2^mm, which are
       // never written back.
       const bool active = tid < ngroups;
-      const int gbs = swz<T>(stage_base<R>(tid, sd)) * (int)sizeof(C2);
+      const int gbs = swz<T>(stage_base<M, R>(tid, sd)) * (int)sizeof(C2);
       T re[NS][G], im[NS][G];
 #pragma unroll
       for (int s = 0; s < NS; s++) {
@@ -788,7 +781,7 @@ __global__ void __launch_bounds__(1 << (M - R)) k_sweep_kron(SweepArgs a) {
   if (tid < SVI_MMAX) hb_s[tid] = a.hb[tid < nh ? tid : 0];
   const int ntab = nst < GTAB ? nst : GTAB;
   for (int st = 0; st < ntab; st++)   // each thread reads back only its own entries
-    gtab[st * NT + tid] = swz<T>(stage_base<R>(tid, stages[st])) * (int)sizeof(C2);
+    gtab[st * NT + tid] = swz<T>(stage_base<M, R>(tid, stages[st])) * (int)sizeof(C2);
   __syncthreads();
 
   // Lane tid moves tile elements i = tid + k * NT (k < G) between HBM and
@@ -909,7 +902,7 @@ __global__ void __launch_bounds__(1 << (M - R)) k_sweep_kron(SweepArgs a) {
       for (int st = 0; st < nst; st++) {
         const SVI_CONST StageDesc &sd = stages[st];
         const int gbs =
-            st < ntab ? gtab[st * NT + tid] : swz<T>(stage_base<R>(tid, sd)) * (int)sizeof(C2);
+            st < ntab ? gtab[st * NT + tid] : swz<T>(stage_base<M, R>(tid, sd)) * (int)sizeof(C2);
         // The common stage (every group bit rotated, then D_after) runs as its
         // own straight-line body from loads to stores; the general body
         // branches on the stage's parts.  Separate bodies leave nothing to
@@ -936,7 +929,15 @@ __global__ void __launch_bounds__(1 << (M - R)) k_sweep_kron(SweepArgs a) {
           body(std::true_type{});
         else
           body(std::false_type{});
-        lds_barrier();
+        if (sd.dflags & SD_WLOCAL) {
+          // the next stage reads only slots this wave wrote: keep the wave's
+          // LDS accesses in order, no workgroup barrier
+          __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront", "local");
+          __builtin_amdgcn_wave_barrier();
+          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront", "local");
+        } else {
+          lds_barrier();
+        }
       }
       // ---- LDS to HBM
       opaque(ssl_p);
@@ -1061,7 +1062,7 @@ __global__ void __launch_bounds__(1 << (M - R)) k_sweep_kron2(SweepArgs a) {
     // ---- stages
     for (int st = 0; st < nst; st++) {
       const SVI_CONST StageDesc &sd = stages[st];
-      const int gbs = swz<T>(stage_base<R>(tid, sd)) * (int)sizeof(C2);
+      const int gbs = swz<T>(stage_base<M, R>(tid, sd)) * (int)sizeof(C2);
       const bool active = tid < (1 << (m > R ? m - R : 0));
       T re[2][G], im[2][G];
 #pragma unroll

@@ -760,6 +760,60 @@ static int perm_apply(const MicroOp &op, int j) {
   return j;
 }
 
+// Thread maps of one sweep's stages (StageDesc::tpos): the lane bits take
+// the stage's exchanged tile bits, the wave bits stay where the previous
+// stage had them whenever that stage's group and exchanged bits allow it
+// (then the transition is wave-local: SD_WLOCAL on the previous stage), and
+// otherwise move to the non-group tile bits that the following stages leave
+// free longest.
+static void assign_thread_maps(Plan &P, int first, const std::vector<int> &gm,
+                               const std::vector<int> &xb, int R) {
+  const int M = P.M, ntb = M - R, nw = std::max(0, ntb - 6);
+  const int ns = (int)gm.size();
+  std::vector<int> wprev;
+  for (int s = 0; s < ns; s++) {
+    StageDesc &sd = P.stages[first + s];
+    const int ng = ((1 << M) - 1) & ~gm[s];
+    int xs = xb[s] & ng;
+    if (__builtin_popcount((unsigned)xs) > 6) {   // cannot all be lane bits
+      sd.dflags |= SD_XCHG;
+      xs = 0;
+    }
+    const int avail = ng & ~xs;
+    std::vector<int> w;
+    bool keep = s > 0 && (int)wprev.size() == nw;
+    for (int p : wprev)
+      if (!((avail >> p) & 1)) keep = false;
+    if (keep) {
+      w = wprev;
+      P.stages[first + s - 1].dflags |= SD_WLOCAL;
+    } else {
+      // free run of each candidate bit over the following stages
+      std::vector<std::pair<int, int>> cand;
+      for (int p = 0; p < M; p++) {
+        if (!((avail >> p) & 1)) continue;
+        int run = 0;
+        for (int t = s + 1; t < ns && !(((gm[t] | xb[t]) >> p) & 1); t++) run++;
+        cand.push_back({run, p});
+      }
+      std::sort(cand.begin(), cand.end(), [](const std::pair<int, int> &x, const std::pair<int, int> &y) {
+        return x.first != y.first ? x.first > y.first : x.second > y.second;
+      });
+      for (int i = 0; i < nw; i++) w.push_back(cand[i].second);
+      std::sort(w.begin(), w.end());
+    }
+    int wmask = 0;
+    for (int p : w) wmask |= 1 << p;
+    int k = 0;
+    for (int p = 0; p < M; p++)
+      if (((ng >> p) & 1) && !((wmask >> p) & 1)) sd.tpos[k++] = (int8_t)p;
+    if (k != ntb - nw) abort();   // planner invariant: 6 lane bits (or all bits, for small groups)
+    for (int p : w) sd.tpos[k++] = (int8_t)p;
+    for (; k < 16; k++) sd.tpos[k] = 0;
+    wprev = w;
+  }
+}
+
 // Emit the device descriptors of one tile sweep.
 static void emit_sweep(Plan &P, std::vector<GateRec> &recs, const SweepP &sw, int n, int R,
                        int flags, int gslot_base, int &gslots_used) {
@@ -783,6 +837,7 @@ static void emit_sweep(Plan &P, std::vector<GateRec> &recs, const SweepP &sw, in
   a.stage_begin = (int)P.stages.size();
   a.gslot_begin = gslot_base;
   int gs = 0;
+  std::vector<int> st_gmask, st_xbits;   // per stage: group bits, exchanged bits
   for (const StageP &st : sw.stages) {
     // group bits: qubit of tile position st.gq[i]
     auto local_of = [&](int q) {
@@ -1015,38 +1070,13 @@ static void emit_sweep(Plan &P, std::vector<GateRec> &recs, const SweepP &sw, in
       for (size_t k = 0; k < trailp.size(); k++) js = perm_apply(trailp[k], js);
       sd.st_off[j] = svi_swz(spread_local(js, st.gq, R), SWB) * EB;
     }
-    if (xbits) {
-      // Threads exchange slots across the bits in xbits.  The thread index
-      // fills the non-group tile bits in ascending order, its low 6 bits
-      // (the lane) first; swap each exchanged bit that a wave bit would hold
-      // with a lane bit outside xbits, so every exchange stays in one wave.
-      int ng[SVI_MMAX + SVI_RMAX], nng = 0;
-      for (int p = 0; p < P.M; p++)
-        if (!((gmask >> p) & 1)) ng[nng++] = p;
-      const int lanes = std::min(6, nng);
-      int nsw = 0;
-      bool ok = true;
-      int spare = lanes - 1;
-      for (int i = lanes; i < nng; i++) {
-        if (!((xbits >> ng[i]) & 1)) continue;
-        while (spare >= 0 && ((xbits >> ng[spare]) & 1)) spare--;
-        if (spare < 0 || nsw == 2) { ok = false; break; }
-        sd.lsa[nsw] = ng[i];
-        sd.lsb[nsw] = ng[spare];
-        spare--;
-        nsw++;
-      }
-      if (ok) {
-        sd.dflags |= SD_LSWAP;
-        for (int k = nsw; k < 2; k++) sd.lsa[k] = sd.lsb[k] = 0;
-      } else {
-        sd.dflags |= SD_XCHG;
-      }
-    }
+    st_gmask.push_back(gmask);
+    st_xbits.push_back(xbits);
     P.stages.push_back(sd);
     P.n_blocks++;
   }
   a.stage_end = (int)P.stages.size();
+  assign_thread_maps(P, a.stage_begin, st_gmask, st_xbits, R);
   a.n_gslots = gs;
   // the two-state Kronecker kernel keeps at most SVI_GSLOTS_MAX gradient slots in registers
   s.all_kron = gs <= SVI_GSLOTS_MAX;

@@ -61,28 +61,31 @@ struct MicroOp {
 //            when |s| > |c|, so that |k| <= 1.
 enum { ST_OPS = 0, ST_KRON = 1 };
 
-// dflags bits for stages whose slot offsets reach tile bits outside the group
-// (an X controlled by group qubits whose target is another tile qubit): a
-// thread then stores to slots that other threads load.
-//   SD_LSWAP: the planner made those tile bits lane bits of the thread index
-//             (each thread's base swaps tile bits lsa[k] and lsb[k]), so every
-//             exchange stays inside one wave, whose loads complete before its
-//             stores (they feed them); no barrier.
-//   SD_XCHG:  otherwise every load of the stage completes (workgroup barrier)
-//             before any store.
+// Thread mapping of a stage: thread-index bit k sits on tile bit tpos[k]
+// (k < tile bits - group bits); the lane bits (k < 6) hold every tile bit that
+// the stage's slot offsets reach outside the group (an X controlled by group
+// qubits whose target is another tile qubit: a thread then stores to slots
+// that other threads load), so those exchanges stay inside one wave, whose
+// loads complete before its stores (they feed them).
+// dflags bits:
+//   SD_XCHG:   the exchanged bits did not fit the lane bits: every load of the
+//              stage completes (workgroup barrier) before any store.
+//   SD_WLOCAL: the next stage of the sweep keeps this stage's wave bits
+//              (tpos[6..]), so each wave reads there exactly the slots it
+//              wrote here: no workgroup barrier is needed in between.
 #define SD_XCHG 8
-#define SD_LSWAP 16
+#define SD_WLOCAL 16
 
 struct StageDesc {
   int32_t sbits[SVI_RMAX];     // tile-local bit positions of the group bits, ascending
   int32_t op_begin, op_end;    // micro-ops [op_begin, op_end)
   int32_t kind;                // ST_OPS / ST_KRON
   uint32_t rmask;              // ST_KRON: group bits carrying a real 2x2
-  int32_t dflags;              // ST_KRON: 1 = D_before, 2 = D_after; SD_XCHG (any kind)
+  int32_t dflags;              // ST_KRON: 1 = D_before, 2 = D_after; SD_* (any kind)
   int32_t kcoef;               // ST_KRON: coefficient offset (doubles)
   int32_t g1, g2;              // ST_KRON: MO_GRAD ops [op_begin, g1) run on the stage input,
                                // [g1, g2) after D_before, [g2, op_end) after the rotations
-  int32_t lsa[2], lsb[2];      // SD_LSWAP: tile bit pairs swapped in each thread's base
+  int8_t tpos[16];             // tile bit of thread-index bit k (see above)
   int32_t ld_off[SVI_GMAX];    // swizzled tile-local BYTE offset loaded into slot j
   int32_t st_off[SVI_GMAX];    // swizzled tile-local BYTE offset slot j is stored to
 };

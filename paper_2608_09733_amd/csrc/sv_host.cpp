@@ -765,29 +765,43 @@ static int perm_apply(const MicroOp &op, int j) {
 // stage had them whenever that stage's group and exchanged bits allow it
 // (then the transition is wave-local: SD_WLOCAL on the previous stage), and
 // otherwise move to the non-group tile bits that the following stages leave
-// free longest.
+// free longest.  Tile bits at or above mm exist only past a small state's
+// tile (m < M): they take the highest thread bits, so that the threads below
+// 2^(mm - R) are exactly the ones holding the state (the gradient kernels
+// count only those).
 static void assign_thread_maps(Plan &P, int first, const std::vector<int> &gm,
-                               const std::vector<int> &xb, int R) {
+                               const std::vector<int> &xb, int R, int mm) {
   const int M = P.M, ntb = M - R, nw = std::max(0, ntb - 6);
   const int ns = (int)gm.size();
+  const int real = (1 << mm) - 1;
   std::vector<int> wprev;
   for (int s = 0; s < ns; s++) {
     StageDesc &sd = P.stages[first + s];
     const int ng = ((1 << M) - 1) & ~gm[s];
-    int xs = xb[s] & ng;
+    const int ngr = ng & real, ngp = ng & ~real;
+    std::vector<int> phant;
+    for (int p = 0; p < M; p++)
+      if ((ngp >> p) & 1) phant.push_back(p);
+    int xs = xb[s] & ngr;
     if (__builtin_popcount((unsigned)xs) > 6) {   // cannot all be lane bits
       sd.dflags |= SD_XCHG;
       xs = 0;
     }
-    const int avail = ng & ~xs;
-    std::vector<int> w;
-    bool keep = s > 0 && (int)wprev.size() == nw;
+    std::vector<int> wr;   // wave bits on real tile bits
+    const int nwr = nw - std::min(nw, (int)phant.size());
+    const int avail = ngr & ~xs;
+    bool keep = s > 0;
+    int nprev_real = 0;
     for (int p : wprev)
-      if (!((avail >> p) & 1)) keep = false;
+      if ((real >> p) & 1) {
+        nprev_real++;
+        if (!((avail >> p) & 1)) keep = false;
+      }
+    if (nprev_real != nwr) keep = false;
     if (keep) {
-      w = wprev;
-      P.stages[first + s - 1].dflags |= SD_WLOCAL;
-    } else {
+      for (int p : wprev)
+        if ((real >> p) & 1) wr.push_back(p);
+    } else if (nwr > 0) {
       // free run of each candidate bit over the following stages
       std::vector<std::pair<int, int>> cand;
       for (int p = 0; p < M; p++) {
@@ -799,15 +813,41 @@ static void assign_thread_maps(Plan &P, int first, const std::vector<int> &gm,
       std::sort(cand.begin(), cand.end(), [](const std::pair<int, int> &x, const std::pair<int, int> &y) {
         return x.first != y.first ? x.first > y.first : x.second > y.second;
       });
-      for (int i = 0; i < nw; i++) w.push_back(cand[i].second);
-      std::sort(w.begin(), w.end());
+      for (int i = 0; i < nwr; i++) wr.push_back(cand[i].second);
+      std::sort(wr.begin(), wr.end());
     }
+    // wave bits: the real ones, then the highest phantom ones
+    std::vector<int> w = wr;
+    const int nwp = nw - nwr;
+    for (int i = (int)phant.size() - nwp; i < (int)phant.size(); i++) w.push_back(phant[i]);
+    if (keep || (s > 0 && w == wprev)) P.stages[first + s - 1].dflags |= SD_WLOCAL;
     int wmask = 0;
     for (int p : w) wmask |= 1 << p;
+    // lane bits: the real ones first, then the remaining phantom ones
+    std::vector<int> lanes, lanep;
+    for (int p = 0; p < M; p++) {
+      if (!((ng >> p) & 1) || ((wmask >> p) & 1)) continue;
+      if ((real >> p) & 1) lanes.push_back(p);
+      else lanep.push_back(p);
+    }
+    if ((int)(lanes.size() + lanep.size()) != ntb - nw) abort();   // planner invariant
+    // An LDS access of one complex element serves 2^B consecutive lanes per
+    // pass (B = 3 for 16-byte FP64 elements, 4 for 8-byte FP32 ones), and the
+    // swizzle folds tile bit p onto element bit p mod B: the B lowest lane bits
+    // go on tile bits of distinct p mod B where the real lane bits allow it.
+    const int B = P.dbl ? 3 : 4;
+    if ((int)lanes.size() >= B) {
+      for (int i = 0; i < B; i++) {
+        int used = 0;
+        for (int j = 0; j < i; j++) used |= 1 << (lanes[j] % B);
+        if (!((used >> (lanes[i] % B)) & 1)) continue;
+        for (size_t j = i + 1; j < lanes.size(); j++)
+          if (!((used >> (lanes[j] % B)) & 1)) { std::swap(lanes[i], lanes[j]); break; }
+      }
+    }
     int k = 0;
-    for (int p = 0; p < M; p++)
-      if (((ng >> p) & 1) && !((wmask >> p) & 1)) sd.tpos[k++] = (int8_t)p;
-    if (k != ntb - nw) abort();   // planner invariant: 6 lane bits (or all bits, for small groups)
+    for (int p : lanes) sd.tpos[k++] = (int8_t)p;
+    for (int p : lanep) sd.tpos[k++] = (int8_t)p;
     for (int p : w) sd.tpos[k++] = (int8_t)p;
     for (; k < 16; k++) sd.tpos[k] = 0;
     wprev = w;
@@ -1076,7 +1116,7 @@ static void emit_sweep(Plan &P, std::vector<GateRec> &recs, const SweepP &sw, in
     P.n_blocks++;
   }
   a.stage_end = (int)P.stages.size();
-  assign_thread_maps(P, a.stage_begin, st_gmask, st_xbits, R);
+  assign_thread_maps(P, a.stage_begin, st_gmask, st_xbits, R, std::max(sw.m, R));
   a.n_gslots = gs;
   // the two-state Kronecker kernel keeps at most SVI_GSLOTS_MAX gradient slots in registers
   s.all_kron = gs <= SVI_GSLOTS_MAX;
@@ -1245,17 +1285,17 @@ static sv_status ensure_scratch(sv_state *st, size_t bytes) {
 static Tiling default_tiling(int n, sv_dtype dt, int NS) {
   Tiling t;
   if (dt == SV_C128) {
-    // forward: 13-qubit tiles, 256-byte rows; 16-amplitude register groups
-    // (512-thread workgroups) when the state spans several tiles, 8-amplitude
-    // groups (1024 threads) when one tile holds it; measured best on the
-    // 30-qubit layered workload among the compiled tilings
+    // forward: 13-qubit tiles, 256-byte rows, 8-amplitude register groups
+    // (1024-thread workgroups); measured best on the 30-qubit layered
+    // workload among the compiled tilings with 5 low qubits
     // adjoint backward: two 11-qubit tiles (psi, lambda), 8-amplitude groups
     if (NS == 2) { t.M = 11; t.R = 3; t.c = 3; }
-    else { t.M = 13; t.R = n > 13 ? 4 : 3; t.c = 5; }
+    else { t.M = 13; t.R = 3; t.c = 5; }
   } else {
     if (NS == 2) { t.M = 13; t.R = 4; t.c = 3; }
     else { t.M = 14; t.R = 5; t.c = 3; }
   }
+  (void)n;
   return t;
 }
 

@@ -194,9 +194,9 @@ def test_kronecker_stages_take_ladder_cnots_with_outside_targets(sv):
 
 def test_default_tiling_query(sv):
     import ctypes as C
-    # multi-tile FP64 states take 16-amplitude register groups, single-tile ones 8
-    assert sv.default_tiling(30) == (13, 5, 4)
+    assert sv.default_tiling(30) == (13, 5, 3)
     assert sv.default_tiling(12) == (13, 5, 3)
+    assert sv.default_tiling(30, "c64") == (14, 3, 5)
     assert sv.default_tiling(26, backward=True) == (11, 3, 3)
     t = C.c_int32(0)
     assert sv.lib().sv_default_tiling(20, 7, 0, C.byref(t), C.byref(t), C.byref(t)) == -1

@@ -994,9 +994,18 @@ __global__ void __launch_bounds__(1 << (M - R)) k_sweep_kron2(SweepArgs a) {
   constexpr int NWAVE = NT / 64;
   using C2 = typename C2T<T>::type;
   using V4 = typename V4T<T>::type;
+  // per-stage thread bases from a table built once per launch (as in
+  // k_sweep_kron), in the LDS left by the tiles and the per-wave sums within
+  // the workgroup's share of the CU (one workgroup per CU for 128 KiB of
+  // tiles, two for 64 KiB)
+  constexpr int TILE_BYTES = 2 * (1 << M) * (int)sizeof(C2);
+  constexpr int WG_LDS = TILE_BYTES >= 131072 ? 163840 : TILE_BYTES >= 65536 ? 81920 : 40960;
+  constexpr int GTAB_BYTES = WG_LDS - TILE_BYTES - NWAVE * SVI_GSLOTS_LEAN * 8 - 4 * SVI_MMAX - 256;
+  constexpr int GTAB = GTAB_BYTES / (4 * NT) > 0 ? GTAB_BYTES / (4 * NT) : 1;
   __shared__ C2 lds[2][1 << M];
   __shared__ double wsum[NWAVE][SVI_GSLOTS_LEAN];
   __shared__ int32_t hb_s[SVI_MMAX];
+  __shared__ int32_t gtab[GTAB * NT];
 
   const int tid = threadIdx.x;
   const int m = a.m, c = a.c, nh = a.nh;
@@ -1007,6 +1016,9 @@ __global__ void __launch_bounds__(1 << (M - R)) k_sweep_kron2(SweepArgs a) {
   const SVI_CONST double *coef = cptr(a.coef);
 
   if (tid < SVI_MMAX) hb_s[tid] = a.hb[tid < nh ? tid : 0];
+  const int ntab = nst < GTAB ? nst : GTAB;
+  for (int st = 0; st < ntab; st++)   // each thread reads back only its own entries
+    gtab[st * NT + tid] = swz<T>(stage_base<M, R>(tid, stages[st])) * (int)sizeof(C2);
   __syncthreads();
 
   uint64_t roff[NIT];
@@ -1062,7 +1074,8 @@ __global__ void __launch_bounds__(1 << (M - R)) k_sweep_kron2(SweepArgs a) {
     // ---- stages
     for (int st = 0; st < nst; st++) {
       const SVI_CONST StageDesc &sd = stages[st];
-      const int gbs = swz<T>(stage_base<M, R>(tid, sd)) * (int)sizeof(C2);
+      const int gbs =
+          st < ntab ? gtab[st * NT + tid] : swz<T>(stage_base<M, R>(tid, sd)) * (int)sizeof(C2);
       const bool active = tid < (1 << (m > R ? m - R : 0));
       T re[2][G], im[2][G];
 #pragma unroll
@@ -1111,7 +1124,14 @@ __global__ void __launch_bounds__(1 << (M - R)) k_sweep_kron2(SweepArgs a) {
 #pragma unroll
         for (int j = 0; j < G; j++) *(C2 *)(lb + (gbs ^ sd.st_off[j])) = C2{re[s][j], im[s][j]};
       }
-      __syncthreads();
+      if (sd.dflags & SD_WLOCAL) {
+        // the next stage reads only slots this wave wrote
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront", "local");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront", "local");
+      } else {
+        lds_barrier();
+      }
     }
     // ---- LDS to HBM
 #pragma unroll

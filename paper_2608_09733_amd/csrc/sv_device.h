@@ -70,9 +70,16 @@ __device__ __forceinline__ int insert_zeros32c(int x, const SVI_CONST int32_t *p
 // on tile bit tpos[k] (the group bits stay zero).
 template <int M, int R>
 __device__ __forceinline__ int stage_base(int tid, const SVI_CONST StageDesc &sd) {
+  // tpos read as aligned 32-bit words (scalar loads; byte loads of the
+  // descriptor would become vector loads, whose waits also wait for the
+  // tile prefetch in flight), bytes extracted with scalar shifts
+  const SVI_CONST int32_t *w = (const SVI_CONST int32_t *)sd.tpos;
   int b = 0;
 #pragma unroll
-  for (int k = 0; k < M - R; k++) b |= ((tid >> k) & 1) << sd.tpos[k];
+  for (int k = 0; k < M - R; k++) {
+    const int pos = (w[k >> 2] >> (8 * (k & 3))) & 0xff;
+    b |= ((tid >> k) & 1) << pos;
+  }
   return b;
 }
 
@@ -765,10 +772,10 @@ __global__ void __launch_bounds__(1 << (M - R)) k_sweep_kron(SweepArgs a) {
   // the tile leaves free (sized so the workgroups per CU stay as they are).
   constexpr int TILE_BYTES = (1 << M) * (int)sizeof(C2);
   constexpr int GTAB_BYTES = TILE_BYTES >= 131072 ? 30720 : TILE_BYTES >= 65536 ? 14336 : 6144;
-  constexpr int GTAB = GTAB_BYTES / (4 * NT) > 0 ? GTAB_BYTES / (4 * NT) : 1;
+  constexpr int GTAB = GTAB_BYTES / (2 * NT) > 0 ? GTAB_BYTES / (2 * NT) : 1;
   __shared__ C2 lds[1 << M];
   __shared__ int32_t hb_s[SVI_MMAX];
-  __shared__ int32_t gtab[GTAB * NT];
+  __shared__ uint16_t gtab[GTAB * NT];   // swizzled element index (tiles hold <= 2^14)
 
   const int tid = threadIdx.x;
   const int m = a.m, c = a.c, nh = a.nh;
@@ -781,7 +788,7 @@ __global__ void __launch_bounds__(1 << (M - R)) k_sweep_kron(SweepArgs a) {
   if (tid < SVI_MMAX) hb_s[tid] = a.hb[tid < nh ? tid : 0];
   const int ntab = nst < GTAB ? nst : GTAB;
   for (int st = 0; st < ntab; st++)   // each thread reads back only its own entries
-    gtab[st * NT + tid] = swz<T>(stage_base<M, R>(tid, stages[st])) * (int)sizeof(C2);
+    gtab[st * NT + tid] = (uint16_t)swz<T>(stage_base<M, R>(tid, stages[st]));
   __syncthreads();
 
   // Lane tid moves tile elements i = tid + k * NT (k < G) between HBM and
@@ -902,7 +909,7 @@ __global__ void __launch_bounds__(1 << (M - R)) k_sweep_kron(SweepArgs a) {
       for (int st = 0; st < nst; st++) {
         const SVI_CONST StageDesc &sd = stages[st];
         const int gbs =
-            st < ntab ? gtab[st * NT + tid] : swz<T>(stage_base<M, R>(tid, sd)) * (int)sizeof(C2);
+            (st < ntab ? (int)gtab[st * NT + tid] : swz<T>(stage_base<M, R>(tid, sd))) * (int)sizeof(C2);
         // The common stage (every group bit rotated, then D_after) runs as its
         // own straight-line body from loads to stores; the general body
         // branches on the stage's parts.  Separate bodies leave nothing to

@@ -131,7 +131,7 @@ __device__ void sweep_tiles(const SVI_CONST SweepArgs &a, int64_t t0, int64_t t1
           kron_stage<T, R>(re, im, cptr(coef) + sd.kcoef, sd.rmask, sd.dflags);
         } else {
           for (int o = sd.op_begin; o < sd.op_end; o++) {
-            const MicroOp op = ops[o];
+            const MicroOp op = op_at(ops, o);
             apply_op<T, R>(op, re, im, coef);
           }
         }

@@ -66,6 +66,25 @@ __device__ __forceinline__ int insert_zeros32c(int x, const SVI_CONST int32_t *p
   return x;
 }
 
+// Micro-op o, read through the constant address space (uniform index:
+// scalar loads, not vector loads whose waits would also wait for other
+// memory traffic in flight).
+__device__ __forceinline__ MicroOp op_at(const MicroOp *ops, int o) {
+  const SVI_CONST MicroOp &s = cptr(ops)[o];
+  MicroOp m;
+  m.type = s.type;
+  m.t0 = s.t0;
+  m.t1 = s.t1;
+  m.mask = s.mask;
+  m.cm = s.cm;
+  m.cv = s.cv;
+  m.coef = s.coef;
+  m.gz = s.gz;
+  m.galpha = s.galpha;
+  m.gbeta = s.gbeta;
+  return m;
+}
+
 // Tile-local base index of thread tid in a stage: thread-index bit k placed
 // on tile bit tpos[k] (the group bits stay zero).
 template <int M, int R>
@@ -643,7 +662,7 @@ __global__ void __launch_bounds__(1 << (M - R)) k_sweep(SweepArgs a) {
           // stage scale s, so they are multiplied by s^2
           auto grads = [&](int b, int e, double mult) {
             for (int o = b; o < e; o++) {
-              const MicroOp op = a.ops[o];
+              const MicroOp op = op_at(a.ops, o);
               double v = active ? mult * grad_op<T, R>(op, re[0], im[0], re[1], im[1]) : 0.0;
               v = wave_sum(v);
               if ((tid & 63) == 0) wsum[tid >> 6][op.coef] = v;
@@ -666,7 +685,7 @@ __global__ void __launch_bounds__(1 << (M - R)) k_sweep(SweepArgs a) {
         }
       } else
       for (int o = sd.op_begin; o < sd.op_end; o++) {
-        const MicroOp op = a.ops[o];
+        const MicroOp op = op_at(a.ops, o);
         if constexpr (NS == 2) {
           if (op.type == MO_GRAD) {
             double v = active ? grad_op<T, R>(op, re[0], im[0], re[1], im[1]) : 0.0;
@@ -1098,7 +1117,7 @@ __global__ void __launch_bounds__(1 << (M - R)) k_sweep_kron2(SweepArgs a) {
       const SVI_CONST double *kc = coef + sd.kcoef;
       auto grads = [&](int b, int e, double mult) {
         for (int o = b; o < e; o++) {
-          const MicroOp op = a.ops[o];
+          const MicroOp op = op_at(a.ops, o);
           const double v = active ? mult * grad_op<T, R>(op, re[0], im[0], re[1], im[1]) : 0.0;
           switch (op.coef) {   // uniform: the slot is a register index
 #define SVI_GS(K) case K: gr[K] += v; break;

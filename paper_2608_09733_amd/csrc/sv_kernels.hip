@@ -328,6 +328,19 @@ __global__ void k_build_coefs(const CoefDesc *d, int nd, const double *params, c
 // tile's loads and the per-term sums have enough waves in flight
 #define SVI_PAULI_NT 1024
 
+// Term t, read through the constant address space (uniform index: scalar
+// loads instead of vector loads and their waits inside the tile loop).
+__device__ __forceinline__ PauliTermDev term_at(const PauliTermDev *terms, int t) {
+  const SVI_CONST PauliTermDev &s = cptr(terms)[t];
+  PauliTermDev p;
+  p.x = s.x;
+  p.z = s.z;
+  p.c = s.c;
+  p.term = s.term;
+  p.pad = 0;
+  return p;
+}
+
 template <typename T, int M>
 __global__ void __launch_bounds__(SVI_PAULI_NT) k_pauli(PauliPassArgs a) {
   constexpr int NT = SVI_PAULI_NT;
@@ -387,7 +400,7 @@ __global__ void __launch_bounds__(SVI_PAULI_NT) k_pauli(PauliPassArgs a) {
     // Z-only terms: sign(i) = parity(base & z) ^ parity(tid & z) ^ parity((k*NT) & z)
     for (int t = 0; t < nterm; t++) {
       if (xl_s[t] != 0) continue;
-      const PauliTermDev pt = a.terms[a.t_begin + t];
+      const PauliTermDev pt = term_at(a.terms, a.t_begin + t);
       const uint32_t zl = zl_s[t];
       const bool sneg = (__builtin_popcountll(base & pt.z) ^ __builtin_popcount((uint32_t)tid & zl)) & 1;
       const uint32_t zk = zl / NT;
@@ -421,7 +434,7 @@ __global__ void __launch_bounds__(SVI_PAULI_NT) k_pauli(PauliPassArgs a) {
     for (int t = 0; t < nterm; t++) {
       const uint32_t xl = xl_s[t];
       if (xl == 0) continue;
-      const PauliTermDev pt = a.terms[a.t_begin + t];
+      const PauliTermDev pt = term_at(a.terms, a.t_begin + t);
       const uint32_t zl = zl_s[t];
       const int ny = __builtin_popcountll(pt.x & pt.z) & 3;
       const bool bneg = __builtin_popcountll(base & pt.z) & 1;   // non-tile bits' sign

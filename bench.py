@@ -141,6 +141,28 @@ def side_configs(sv, I, torch, serving=True):
                                        "gates": len(c3.ops)}
     s3.close()
     log(f"20q adjoint: {ms:.3f} ms")
+    # the same ansatz at 26 qubits (1 GiB per state: psi, lambda and the psi
+    # copy live in HBM), against a forward pass + <H> on the same state
+    c4 = I.hea(26, 10, seed=0)
+    h4 = I.tfim(26, 0.7)
+    s4 = sv.State(26, adjoint=True)
+    oa4 = sv.OpArray(c4.ops)
+    def f4():
+        s4.reset()
+        s4.adjoint_grad(None, c4.params, h4, op_array=oa4)
+    def g4():
+        s4.reset()
+        s4.apply(None, c4.params, op_array=oa4)
+        s4.expect(h4)
+    f4()
+    g4()
+    ms, iqr = _median_ms(f4, 5, torch)
+    fms, _ = _median_ms(g4, 5, torch)
+    out["adjoint_hea_26q_10l_tfim"] = {"ms_median": ms, "ms_iqr": iqr, "params": int(len(c4.params)),
+                                       "gates": len(c4.ops), "forward_expect_ms": fms,
+                                       "ratio_to_forward": ms / fms}
+    s4.close()
+    log(f"26q adjoint: {ms:.2f} ms (forward + <H>: {fms:.2f} ms)")
     # ragged batch: 512 layered circuits, n in 8..22, L in 10..40, <Z0 Z1> each
     circs = I.batch_circuits(512, seed=0)
     hams = [I.z0z1(c.n) for c in circs]

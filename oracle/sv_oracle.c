@@ -399,7 +399,12 @@ done:
  *   1. p_b = fma(x_b, x_b, y_b * y_b) in binary64.
  *   2. Chunks of C = 2^min(n,10) consecutive indices; S_k = pairwise tree sum
  *      of chunk k (adjacent pairs, level by level).
- *   3. P_0 = 0, P_{k+1} = P_k + S_k sequentially; T = P_K.
+ *   3. Blocks of G = 2^10 consecutive chunks (a single block when K <= G).
+ *      Inside block j: L_k = S of the block's chunks before k, added left to
+ *      right from 0.0; Q_j = the same sum over the whole block.  Block
+ *      offsets E_0 = 0, E_{j+1} = E_j + Q_j, left to right.  P_k = E_j + L_k
+ *      for k in block j, and T = P_K = E_J.  With one block this is the plain
+ *      left-to-right prefix P_{k+1} = P_k + S_k.
  *   4. u_s = (splitmix64(seed, s) >> 11) * 2^-53.
  *   5. t = u_s * T; k* = first k with P_{k+1} > t, else the last k with S_k > 0.
  *   6. r = t - P_{k*}; a += p_b left to right inside chunk k*; pick the first
@@ -438,8 +443,17 @@ int orc_sample_prefix(int n, const double *psi_, double *S, double *P) {
     S[k] = tree_sum(buf, C);
   }
   free(buf);
-  P[0] = 0.0;
-  for (uint64_t k = 0; k < K; k++) P[k + 1] = P[k] + S[k];
+  const uint64_t G = K < 1024 ? K : 1024, J = K / G;
+  double E = 0.0;  /* E_j, the sum of the block totals before block j */
+  for (uint64_t j = 0; j < J; j++) {
+    double Lk = 0.0;
+    for (uint64_t k = j * G; k < (j + 1) * G; k++) {
+      P[k] = E + Lk;
+      Lk = Lk + S[k];
+    }
+    E = E + Lk;
+  }
+  P[K] = E;
   return 0;
 }
 

@@ -343,6 +343,42 @@ def test_sampling_prefix_total_is_norm():
     assert np.all(np.diff(P) >= 0)
 
 
+def test_sampling_blocked_prefix_exact_dyadic():
+    # n = 22: K = 4096 chunks in 4 blocks of 1024.  One amplitude per chunk,
+    # a power of two, so every probability and every partial sum is an exact
+    # binary fraction and the prefix must equal the exact cumulative sum
+    # whatever the order: this pins the block and chunk indexing.
+    n = 22
+    K = 1 << (n - 10)
+    rng = np.random.default_rng(9)
+    e = rng.integers(11, 14, size=K)            # amplitude 2^-e, p = 2^-2e
+    psi = np.zeros(1 << n, dtype=complex)
+    pos = np.arange(K) * 1024 + rng.integers(0, 1024, size=K)
+    psi[pos] = 2.0 ** -e.astype(float)
+    S, P = O.sample_prefix(n, psi)
+    units = [1 << (2 * (13 - int(x))) for x in e]   # p in units of 2^-26
+    exact = np.concatenate([[0], np.cumsum(units)]).astype(np.float64) * 2.0 ** -26
+    assert np.array_equal(S, np.array(units, dtype=np.float64) * 2.0 ** -26)
+    assert np.array_equal(P, exact)
+
+
+def test_sampling_blocked_prefix_rounding_order():
+    # n = 21: two blocks of 1024 chunks.  S_0 = 1 and every other chunk sum is
+    # 2^-53 (x = y = 2^-27).  Inside block 0 each 1 + 2^-53 rounds back to 1
+    # (ties to even), so P_1024 = 1; block 1 sums its 1024 chunks exactly to
+    # 2^-43 before the block offset is added, so T = 1 + 2^-43 and
+    # P_1026 = 1 + 2^-52.  A single left-to-right prefix would give T = 1.
+    n = 21
+    psi = np.zeros(1 << n, dtype=complex)
+    psi[0] = 1.0
+    psi[1024::1024] = 2.0 ** -27 * (1 + 1j)
+    S, P = O.sample_prefix(n, psi)
+    assert S[0] == 1.0 and np.all(S[1:] == 2.0 ** -53)
+    assert np.all(P[1:1025] == 1.0)
+    assert P[1026] == 1.0 + 2.0 ** -52
+    assert P[2048] == 1.0 + 2.0 ** -43
+
+
 # --------------------------------------------------------------- fusion
 
 def test_fusion_counts_match_paper_table():

@@ -363,6 +363,33 @@ def main():
         log(f"complex64: {t32:.1f} ms, max err {err:.2e}")
         s32.close()
         del s32
+        # terminal sampling from the resident FP64 state: 2^20 shots of all
+        # qubits per call (chunk sums, blocked prefix, draws, 8 MiB to the host)
+        shots = 1 << 20
+        allq = list(range(n))
+        st.sample(1, shots, allq)
+        ts = []
+        for k in range(5):
+            t0 = time.time()
+            st.sample(k + 2, shots, allq)
+            ts.append((time.time() - t0) * 1e3)
+        extras["sampling_2p20_shots"] = {"ms_median": float(np.median(ts)), "shots": shots,
+                                         "shots_per_s": shots / (np.median(ts) / 1e3),
+                                         "state_read_bytes": 16.0 * (1 << n)}
+        log(f"sampling: {np.median(ts):.2f} ms per {shots} shots")
+        # explicit exit: 2^28 amplitudes (4 GiB) into pinned host buffers
+        cnt = 1 << min(n, 28)
+        pre = torch.empty(cnt, dtype=torch.float64, pin_memory=True)
+        pim = torch.empty(cnt, dtype=torch.float64, pin_memory=True)
+        outp = (pre.numpy(), pim.numpy())
+        st.planes(0, cnt, out=outp)
+        t0 = time.time()
+        st.planes(0, cnt, out=outp)
+        tx = (time.time() - t0) * 1e3
+        extras["exit_to_pinned_host"] = {"amplitudes": cnt, "bytes": 16.0 * cnt, "ms": tx,
+                                         "gb_s": 16.0 * cnt / (tx / 1e3) / 1e9}
+        log(f"exit: {16.0 * cnt / 2**30:.0f} GiB in {tx:.1f} ms")
+        del pre, pim, outp
     if not args.no_extras:
         st.close()
         del st

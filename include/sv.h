@@ -169,7 +169,9 @@ sv_status sv_adjoint_grad_device(sv_state *st, const sv_op *ops, int32_t n_ops,
 /* Terminal Z-basis sampling (paper Section 5.3 measurement path) by a fixed
  * order of floating-point operations, so equal states give equal bits:
  * p_b = fma(x,x,y*y) in FP64; chunk sums over 2^min(n,10) indices by pairwise
- * tree; sequential prefix over chunks; u_s = (splitmix64(seed, s) >> 11) 2^-53;
+ * tree; prefix over chunks in blocks of 2^10 chunks (local prefixes left to
+ * right, block totals prefixed left to right, P_k = block offset + local
+ * prefix); u_s = (splitmix64(seed, s) >> 11) 2^-53;
  * inverse-CDF search with a strict '>' (see DESIGN notes for the fallbacks).
  * out[s] packs bit qubits[i] of the drawn index into bit i.  Waits. */
 sv_status sv_sample(sv_state *st, uint64_t seed, int64_t shots, const int32_t *qubits,

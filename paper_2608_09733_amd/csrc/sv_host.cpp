@@ -2170,11 +2170,15 @@ extern "C" sv_status sv_sample(sv_state *st, uint64_t seed, int64_t shots, const
   ws_layout(st, &S, &P, &a, &b, &c, &d);
   sv_status s = materialize_zero(st);
   if (s) return s;
-  s = ensure_scratch(st, (size_t)shots * 8 + 1024);
+  // scratch: block totals and offsets of the blocked prefix, then the samples
+  const int64_t K = sample_K(st->n), J = K / (K < 1024 ? K : 1024);
+  const size_t qe_bytes = (((size_t)(2 * J + 1) * 8) + 255) & ~(size_t)255;
+  s = ensure_scratch(st, qe_bytes + (size_t)shots * 8 + 1024);
   if (s) return s;
-  uint64_t *d_out = (uint64_t *)st->scratch;
-  hipError_t e = svk_launch_sampling(st->dtype == SV_C128, st->re, st->im, st->n, S, P, seed, shots,
-                                     qubits, n_measured, d_out, st->stream);
+  double *QE = (double *)st->scratch;
+  uint64_t *d_out = (uint64_t *)((char *)st->scratch + qe_bytes);
+  hipError_t e = svk_launch_sampling(st->dtype == SV_C128, st->re, st->im, st->n, S, P, QE, seed,
+                                     shots, qubits, n_measured, d_out, st->stream);
   if (e != hipSuccess) return fail(SV_EDEVICE, "sampling: %s", hipGetErrorString(e));
   HIPCHK(hipMemcpyAsync(out, d_out, (size_t)shots * 8, hipMemcpyDeviceToHost, st->stream));
   HIPCHK(hipStreamSynchronize(st->stream));

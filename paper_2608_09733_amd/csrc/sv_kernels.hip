@@ -692,7 +692,7 @@ __global__ void k_energy(const double *terms, const double *coef, int nt, double
 
 // ------------------------------------------------------------ sampling
 // Fixed-order specification (see sv.h): p_b = fma(x, x, y*y); chunk sums by
-// pairwise tree; sequential prefix; counter-based SplitMix64 uniforms.
+// pairwise tree; blocked prefix; counter-based SplitMix64 uniforms.
 
 #pragma clang fp contract(off)
 
@@ -723,27 +723,64 @@ __global__ void __launch_bounds__(256) k_chunk_sums(const T *re, const T *im, in
   }
 }
 
-__global__ void __launch_bounds__(256) k_prefix(const double *S, int64_t K, double *P) {
-  __shared__ double buf[4096];
-  __shared__ double carry;
-  if (threadIdx.x == 0) { P[0] = 0.0; carry = 0.0; }
-  __syncthreads();
-  for (int64_t b0 = 0; b0 < K; b0 += 4096) {
-    const int len = (int)((K - b0) < 4096 ? (K - b0) : 4096);
-    for (int i = threadIdx.x; i < len; i += blockDim.x) buf[i] = S[b0 + i];
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      double acc = carry;
-      for (int i = 0; i < len; i++) {
-        acc = acc + buf[i];
-        buf[i] = acc;
+// Prefix over the K chunk sums in blocks of G = min(K, 1024) chunks: the
+// local exclusive prefix L_k of each block runs left to right, the block
+// totals Q_j are prefixed left to right into the offsets E_j, and
+// P_k = E_j + L_k, P_K = E_J.  Each chain is one lane's sequence of dependent
+// additions, read from LDS in batches so the reads overlap the adds.
+__device__ __forceinline__ double chain_lds(const double *v, double *w, int len, double acc) {
+  for (int i0 = 0; i0 < len; i0 += 8) {
+    double x[8];
+#pragma unroll
+    for (int j = 0; j < 8; j++) x[j] = (i0 + j < len) ? v[i0 + j] : 0.0;
+#pragma unroll
+    for (int j = 0; j < 8; j++)
+      if (i0 + j < len) {
+        w[i0 + j] = acc;
+        acc = acc + x[j];
       }
-      carry = acc;
-    }
-    __syncthreads();
-    for (int i = threadIdx.x; i < len; i += blockDim.x) P[b0 + i + 1] = buf[i];
-    __syncthreads();
   }
+  return acc;
+}
+
+// One wave per block of G chunk sums: P[jG + i] <- L, Q[j] <- block total.
+__global__ void __launch_bounds__(64) k_prefix_local(const double *S, int G, double *P, double *Q) {
+  __shared__ double v[1024], w[1024];
+  const int64_t base = (int64_t)blockIdx.x * G;
+  for (int i = threadIdx.x; i < G; i += 64) v[i] = S[base + i];
+  __syncthreads();
+  if (threadIdx.x == 0) Q[blockIdx.x] = chain_lds(v, w, G, 0.0);
+  __syncthreads();
+  for (int i = threadIdx.x; i < G; i += 64) P[base + i] = w[i];
+}
+
+// One wave: E[j] = sum of Q[0..j) left to right (J + 1 entries), P[K] = E[J].
+__global__ void __launch_bounds__(64) k_prefix_blocks(const double *Q, int64_t J, double *E,
+                                                      double *P, int64_t K) {
+  __shared__ double v[1024], w[1024];
+  __shared__ double carry;
+  if (threadIdx.x == 0) carry = 0.0;
+  for (int64_t b0 = 0; b0 < J; b0 += 1024) {
+    const int len = (int)((J - b0) < 1024 ? (J - b0) : 1024);
+    __syncthreads();
+    for (int i = threadIdx.x; i < len; i += 64) v[i] = Q[b0 + i];
+    __syncthreads();
+    if (threadIdx.x == 0) carry = chain_lds(v, w, len, carry);
+    __syncthreads();
+    for (int i = threadIdx.x; i < len; i += 64) E[b0 + i] = w[i];
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    E[J] = carry;
+    P[K] = carry;
+  }
+}
+
+// P_k = E_j + L_k for the G chunks of block j.
+__global__ void __launch_bounds__(256) k_prefix_add(const double *E, int G, double *P) {
+  const double e = E[blockIdx.x];
+  const int64_t base = (int64_t)blockIdx.x * G;
+  for (int i = threadIdx.x; i < G; i += 256) P[base + i] = e + P[base + i];
 }
 
 __device__ __forceinline__ uint64_t splitmix64(uint64_t seed, uint64_t s) {
@@ -790,14 +827,31 @@ __global__ void __launch_bounds__(256) k_sample(SampleArgs a) {
     const double r = t - a.P[ks];
     double acc = 0.0;
     int64_t pick = -1, lastpos = -1;
-    for (int64_t i = 0; i < C; i++) {
-      const uint64_t b = (uint64_t)(ks * C + i);
-      const double p = prob_at(re, im, b);
-      acc = acc + p;
-      if (p > 0.0) lastpos = (int64_t)b;
-      if (acc > r) { pick = (int64_t)b; break; }
+    const int64_t b0 = ks * C;
+    if (C >= 16) {
+      // same left-to-right accumulation, with the chunk's amplitudes read 16
+      // at a time (independent loads) instead of one per dependent step
+      for (int64_t i0 = 0; i0 < C && pick < 0; i0 += 16) {
+        double p[16];
+#pragma unroll
+        for (int j = 0; j < 16; j++) p[j] = prob_at(re, im, (uint64_t)(b0 + i0 + j));
+#pragma unroll
+        for (int j = 0; j < 16; j++)
+          if (pick < 0) {
+            acc = acc + p[j];
+            if (p[j] > 0.0) lastpos = b0 + i0 + j;
+            if (acc > r) pick = b0 + i0 + j;
+          }
+      }
+    } else {
+      for (int64_t i = 0; i < C; i++) {
+        const double p = prob_at(re, im, (uint64_t)(b0 + i));
+        acc = acc + p;
+        if (p > 0.0) lastpos = b0 + i;
+        if (acc > r) { pick = b0 + i; break; }
+      }
     }
-    if (pick < 0) pick = lastpos >= 0 ? lastpos : ks * C;
+    if (pick < 0) pick = lastpos >= 0 ? lastpos : b0;
     uint64_t o = 0;
     for (int i = 0; i < a.nq; i++) o |= (((uint64_t)pick >> a.qubits[i]) & 1ull) << i;
     a.out[s] = o;
@@ -975,8 +1029,8 @@ hipError_t svk_launch_energy_terms(const double *vals, const PauliTermDev *terms
 }
 
 hipError_t svk_launch_sampling(int dbl, const void *re, const void *im, int n, double *S, double *P,
-                               uint64_t seed, int64_t shots, const int32_t *qubits, int nq,
-                               uint64_t *out, hipStream_t s) {
+                               double *QE, uint64_t seed, int64_t shots, const int32_t *qubits,
+                               int nq, uint64_t *out, hipStream_t s) {
   const int cbits = n < 10 ? n : 10;
   const int64_t K = (1ll << n) >> cbits;
   int grid = (int)(K < 4096 ? K : 4096);
@@ -984,7 +1038,12 @@ hipError_t svk_launch_sampling(int dbl, const void *re, const void *im, int n, d
   else hipLaunchKernelGGL(k_chunk_sums<float>, dim3(grid), dim3(256), 0, s, (const float *)re, (const float *)im, cbits, K, S);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_prefix, dim3(1), dim3(256), 0, s, S, K, P);
+  const int G = (int)(K < 1024 ? K : 1024);
+  const int64_t J = K / G;
+  double *Q = QE, *E = QE + J;
+  hipLaunchKernelGGL(k_prefix_local, dim3((unsigned)J), dim3(64), 0, s, S, G, P, Q);
+  hipLaunchKernelGGL(k_prefix_blocks, dim3(1), dim3(64), 0, s, Q, J, E, P, K);
+  hipLaunchKernelGGL(k_prefix_add, dim3((unsigned)J), dim3(256), 0, s, E, G, P);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   if (shots <= 0) return hipSuccess;

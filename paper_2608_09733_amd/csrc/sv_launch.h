@@ -46,9 +46,10 @@ hipError_t svk_launch_energy_terms(const double *vals, const PauliTermDev *terms
                                    double *out, hipStream_t s);
 hipError_t svk_launch_energy(const double *terms, const double *coef, int nt, double *out,
                              hipStream_t s);
+// QE: 2 * (K / min(K, 1024)) + 1 doubles of device scratch (block totals and offsets).
 hipError_t svk_launch_sampling(int dbl, const void *re, const void *im, int n, double *S,
-                               double *P, uint64_t seed, int64_t shots, const int32_t *qubits,
-                               int nq, uint64_t *out, hipStream_t s);
+                               double *P, double *QE, uint64_t seed, int64_t shots,
+                               const int32_t *qubits, int nq, uint64_t *out, hipStream_t s);
 
 #define SVI_GSLOTS_MAX 32    // gradient slots per backward sweep (two-state kernel registers)
 #define SVI_GSLOTS_HARD 256  // gradient slots of the general two-state kernel (LDS)

@@ -287,12 +287,23 @@ class State:
                                out.ctypes.data_as(C.POINTER(C.c_uint64))))
         return out[:shots]
 
-    def planes(self, offset: int = 0, count: Optional[int] = None) -> Tuple[np.ndarray, np.ndarray]:
+    def planes(self, offset: int = 0, count: Optional[int] = None,
+               out: Optional[Tuple[np.ndarray, np.ndarray]] = None) -> Tuple[np.ndarray, np.ndarray]:
+        """Copy amplitudes [offset, offset + count) of both planes to the host;
+        `out` = (re, im) reuses caller buffers (e.g. numpy views of pinned
+        tensors), each contiguous, of the state's element type and >= count long."""
         N = 1 << self.n
         if count is None:
             count = N - offset
-        re = np.empty(count, dtype=self.np_dtype)
-        im = np.empty(count, dtype=self.np_dtype)
+        if out is None:
+            re = np.empty(count, dtype=self.np_dtype)
+            im = np.empty(count, dtype=self.np_dtype)
+        else:
+            re, im = out
+            for a in (re, im):
+                if a.dtype != self.np_dtype or a.size < count or not a.flags["C_CONTIGUOUS"]:
+                    raise ValueError("out buffers must be contiguous, of the state's element "
+                                     "type and at least count long")
         _check(lib().sv_copy_to_host(self.h, C.c_void_p(re.ctypes.data), C.c_void_p(im.ctypes.data),
                                      offset, count))
         return re, im

@@ -192,7 +192,7 @@ def test_adjoint_config3_vs_oracle(sv):
     st.close()
 
 
-@pytest.mark.parametrize("n", [3, 9, 12, 16])
+@pytest.mark.parametrize("n", [3, 9, 12, 16, 22])
 def test_sampling_bit_exact(sv, n):
     circ = I.layered(n, 3, seed=n)
     _say("sample", n)
@@ -207,6 +207,54 @@ def test_sampling_bit_exact(sv, n):
     # contract B: the oracle's state gives the same draws on this seed
     b = O.sample(n, O.run_circuit(circ), 12345, 10000, qubits)
     assert np.array_equal(got, b)
+    st.close()
+
+
+def _dyadic_state(n, seed):
+    # one power-of-two amplitude per chunk of 1024: exact partial sums
+    K = 1 << (n - 10)
+    rng = np.random.default_rng(seed)
+    psi = np.zeros(1 << n, dtype=complex)
+    pos = np.arange(K) * 1024 + rng.integers(0, 1024, size=K)
+    psi[pos] = 2.0 ** -rng.integers(11, 14, size=K).astype(float)
+    return psi
+
+
+def _rounding_state(n):
+    # chunk sum 1 first, 2^-53 for every other chunk: the blocked prefix
+    # total is 1 + 2^-43 only when the blocks are summed as specified
+    psi = np.zeros(1 << n, dtype=complex)
+    psi[0] = 1.0
+    psi[1024::1024] = 2.0 ** -27 * (1 + 1j)
+    return psi
+
+
+@pytest.mark.parametrize("case", ["dyadic22", "rounding21", "layered23"])
+def test_sampling_blocked_prefix_states(sv, case):
+    # several prefix blocks (K > 1024 chunks): GPU draws equal the
+    # specification's on the same state, bit for bit
+    _say("sample blocked", case)
+    if case == "dyadic22":
+        n, psi = 22, _dyadic_state(22, 9)
+    elif case == "rounding21":
+        n, psi = 21, _rounding_state(21)
+    else:
+        n = 23
+        psi = None
+    st = sv.State(n)
+    if psi is None:
+        circ = I.layered(n, 2, seed=3)
+        st.apply(circ.ops, circ.params, fuse=-1)
+        psi = st.to_numpy()
+    else:
+        st.set_planes(psi.real.copy(), psi.imag.copy())
+    qubits = list(range(n))
+    got = st.sample(seed=777, shots=20000, qubits=qubits)
+    want = O.sample(n, psi, 777, 20000, qubits)
+    assert np.array_equal(got, want)
+    if case == "rounding21":
+        # the heavy amplitude takes every draw below 1 / (1 + 2^-43)
+        assert np.count_nonzero(got == 0) >= 19990
     st.close()
 
 

@@ -106,6 +106,46 @@ def _median_ms(fn, reps, torch):
     return float(np.median(ts)), float(np.percentile(ts, 75) - np.percentile(ts, 25))
 
 
+def sampling_and_exit(st, n, torch):
+    """Terminal sampling and the explicit exit on a resident n-qubit FP64 state:
+    2^20 shots of all qubits per call (chunk sums, blocked prefix, draws, 8 MiB
+    of samples to the host), and 2^min(n,28) amplitudes copied into pinned host
+    buffers."""
+    import numpy as np
+    out = {}
+    shots = 1 << 20
+    allq = list(range(n))
+    st.sample(1, shots, allq)
+    ts = []
+    for k in range(5):
+        t0 = time.time()
+        st.sample(k + 2, shots, allq)
+        ts.append((time.time() - t0) * 1e3)
+    out["sampling_2p20_shots"] = {"ms_median": float(np.median(ts)), "shots": shots,
+                                  "shots_per_s": shots / (np.median(ts) / 1e3),
+                                  "state_read_bytes": 16.0 * (1 << n)}
+    log(f"sampling: {np.median(ts):.2f} ms per {shots} shots")
+    ts = []
+    for k in range(5):
+        t0 = time.time()
+        st.sample(k + 2, 1000, allq)
+        ts.append((time.time() - t0) * 1e3)
+    out["sampling_1000_shots"] = {"ms_median": float(np.median(ts)), "shots": 1000}
+    log(f"sampling: {np.median(ts):.2f} ms per 1000 shots")
+    cnt = 1 << min(n, 28)
+    pre = torch.empty(cnt, dtype=torch.float64, pin_memory=True)
+    pim = torch.empty(cnt, dtype=torch.float64, pin_memory=True)
+    bufs = (pre.numpy(), pim.numpy())
+    st.planes(0, cnt, out=bufs)
+    t0 = time.time()
+    st.planes(0, cnt, out=bufs)
+    tx = (time.time() - t0) * 1e3
+    out["exit_to_pinned_host"] = {"amplitudes": cnt, "bytes": 16.0 * cnt, "ms": tx,
+                                  "gb_s": 16.0 * cnt / (tx / 1e3) / 1e9}
+    log(f"exit: {16.0 * cnt / 2**30:.0f} GiB in {tx:.1f} ms")
+    return out
+
+
 def side_configs(sv, I, torch, serving=True):
     """The other workloads of the method at their own shapes: small-state
     latency (12 qubits), adjoint gradient (20-qubit HEA, TFIM), and the ragged
@@ -222,6 +262,8 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--side-only", action="store_true",
                     help="only the side workloads (12-qubit latency, adjoint, batch), no serving")
+    ap.add_argument("--sample-only", action="store_true",
+                    help="only sampling and the exit copy on the resident --n qubit state")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 2 GiB device-to-device copy (counter calibration)")
     args = ap.parse_args()
@@ -250,6 +292,13 @@ def main():
         from paper_2608_09733_amd import inputs as I
         from paper_2608_09733_amd import sv
         print(json.dumps(side_configs(sv, I, torch, serving=False)), flush=True)
+        return
+    if args.sample_only:
+        circ = I.layered(args.n, args.layers, seed=0)
+        st = sv.State(args.n, "c128")
+        st.apply(None, circ.params, op_array=sv.OpArray(circ.ops))
+        print(json.dumps(sampling_and_exit(st, args.n, torch)), flush=True)
+        st.close()
         return
     n, L = args.n, args.layers
     circ = I.layered(n, L, seed=0)
@@ -363,33 +412,7 @@ def main():
         log(f"complex64: {t32:.1f} ms, max err {err:.2e}")
         s32.close()
         del s32
-        # terminal sampling from the resident FP64 state: 2^20 shots of all
-        # qubits per call (chunk sums, blocked prefix, draws, 8 MiB to the host)
-        shots = 1 << 20
-        allq = list(range(n))
-        st.sample(1, shots, allq)
-        ts = []
-        for k in range(5):
-            t0 = time.time()
-            st.sample(k + 2, shots, allq)
-            ts.append((time.time() - t0) * 1e3)
-        extras["sampling_2p20_shots"] = {"ms_median": float(np.median(ts)), "shots": shots,
-                                         "shots_per_s": shots / (np.median(ts) / 1e3),
-                                         "state_read_bytes": 16.0 * (1 << n)}
-        log(f"sampling: {np.median(ts):.2f} ms per {shots} shots")
-        # explicit exit: 2^28 amplitudes (4 GiB) into pinned host buffers
-        cnt = 1 << min(n, 28)
-        pre = torch.empty(cnt, dtype=torch.float64, pin_memory=True)
-        pim = torch.empty(cnt, dtype=torch.float64, pin_memory=True)
-        outp = (pre.numpy(), pim.numpy())
-        st.planes(0, cnt, out=outp)
-        t0 = time.time()
-        st.planes(0, cnt, out=outp)
-        tx = (time.time() - t0) * 1e3
-        extras["exit_to_pinned_host"] = {"amplitudes": cnt, "bytes": 16.0 * cnt, "ms": tx,
-                                         "gb_s": 16.0 * cnt / (tx / 1e3) / 1e9}
-        log(f"exit: {16.0 * cnt / 2**30:.0f} GiB in {tx:.1f} ms")
-        del pre, pim, outp
+        extras.update(sampling_and_exit(st, n, torch))
     if not args.no_extras:
         st.close()
         del st

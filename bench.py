@@ -65,6 +65,50 @@ def cpu_baseline(circ, budget_s: float):
                       f"{el:.1f} s wall, plain C FP64 gate-by-gate"}
 
 
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def oracle_single_thread_child():
+    """Runs in a child process started with OMP_NUM_THREADS=1 (never touches
+    the GPU): the oracle on the 12-qubit layered circuit (state + <Z_i>) and on
+    the 20-qubit HEA/TFIM energy + adjoint gradient; prints one JSON line."""
+    import numpy as np
+    from oracle import oracle as O
+    from paper_2608_09733_amd import inputs as I
+    out = {"threads": O.threads()}
+    c1 = I.layered(12, 20, seed=0)
+    z12 = I.hamiltonian(12, [("Z", [q], 1.0) for q in range(12)])
+    ts = []
+    for _ in range(5):
+        t0 = time.time()
+        psi = O.run_circuit(c1)
+        O.expect(12, psi, z12)
+        ts.append(time.time() - t0)
+    out["layered_12q_20l_ms"] = float(np.median(ts) * 1e3)
+    c3 = I.hea(20, 10, seed=0)
+    t0 = time.time()
+    O.adjoint_grad(c3, I.tfim(20, 0.7))
+    out["adjoint_hea_20q_10l_tfim_ms"] = (time.time() - t0) * 1e3
+    print(json.dumps(out), flush=True)
+
+
+def oracle_single_thread():
+    import subprocess
+    env = dict(os.environ, OMP_NUM_THREADS="1")
+    r = subprocess.run([sys.executable, os.path.abspath(__file__), "--oracle-single-child"],
+                       env=env, capture_output=True, text=True, timeout=300)
+    if r.returncode != 0:
+        raise RuntimeError("single-thread oracle run failed: " + r.stderr[-2000:])
+    return json.loads(r.stdout.strip().splitlines()[-1])
+
+
 def measured_traffic():
     """Bytes per launch of the tile sweep from the committed counter summary
     (FETCH_SIZE / WRITE_SIZE scaled by a plain copy), or None when the kernel
@@ -266,7 +310,11 @@ def main():
                     help="only sampling and the exit copy on the resident --n qubit state")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 2 GiB device-to-device copy (counter calibration)")
+    ap.add_argument("--oracle-single-child", action="store_true", help=argparse.SUPPRESS)
     args = ap.parse_args()
+    if args.oracle_single_child:
+        oracle_single_thread_child()
+        return
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build runs on one GPU only (the state-vector path is measured on "
@@ -425,6 +473,9 @@ def main():
     torch.cuda.empty_cache()
     if not args.no_cpu:
         result["cpu_baseline"] = cpu_baseline(circ, args.cpu_budget)
+        result["cpu_baseline"]["cpu_model"] = cpu_model()
+        result["cpu_baseline"]["single_thread_oracle"] = oracle_single_thread()
+        log(f"single-thread oracle: {result['cpu_baseline']['single_thread_oracle']}")
         log(f"cpu_baseline {result['cpu_baseline']['value']:.3e} updates/s on "
             f"{result['cpu_baseline']['cores']} threads")
     result["extras"] = extras

@@ -317,8 +317,8 @@ def main():
         return
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py: this build runs on one GPU only (the state-vector path is measured on "
-              "one MI355X); --gpus must be 1", file=sys.stderr)
+        print("bench.py: the state-vector path runs and is measured on one GPU only "
+              "(one MI355X holds the whole 30-qubit state); --gpus must be 1", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

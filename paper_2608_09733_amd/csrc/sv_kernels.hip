@@ -858,6 +858,88 @@ __global__ void __launch_bounds__(256) k_sample(SampleArgs a) {
   }
 }
 
+// FP64 draws with chunks of >= 8 amplitudes, done cooperatively: the 64
+// shots of a wave walk their chunks together, 8 amplitudes per shot per step.
+// Eight lanes fetch one shot's 8 re and 8 im values as 16-byte pieces (a
+// 64-byte run per plane, so a load instruction covers 8 shots' runs instead
+// of 64 scattered words), the pieces pass through LDS, and each lane then
+// runs the same left-to-right accumulation as k_sample for its own shot.
+__global__ void __launch_bounds__(256) k_sample_coop(SampleArgs a) {
+  __shared__ double2 stage[4][64 * 9];  // per wave: 64 shots x 8 pieces, +1 pad
+  const double *re = (const double *)a.re, *im = (const double *)a.im;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  double2 *buf = stage[w];
+  const int64_t C = 1ll << a.cbits;
+  const double Tot = a.P[a.K];
+  const int part = lane & 7;  // 0..3: pieces of re, 4..7: pieces of im
+  const double *plane = part < 4 ? re : im;
+  const int q2 = 2 * (part & 3);
+  for (int64_t s0 = ((int64_t)blockIdx.x * 4 + w) * 64; s0 < a.shots;
+       s0 += (int64_t)gridDim.x * 256) {
+    const int64_t s = s0 + lane;
+    const bool live = s < a.shots;
+    int64_t ks = 0;
+    double r = 0.0;
+    if (live) {
+      const double u = (double)(splitmix64(a.seed, (uint64_t)s) >> 11) * 0x1.0p-53;
+      const double t = u * Tot;
+      int64_t lo = 0, hi = a.K;
+      while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (a.P[mid + 1] > t) hi = mid; else lo = mid + 1;
+      }
+      ks = lo;
+      if (ks >= a.K) {
+        ks = -1;
+        for (int64_t k = a.K - 1; k >= 0; k--)
+          if (a.S[k] > 0.0) { ks = k; break; }
+        if (ks < 0) ks = 0;
+      }
+      r = t - a.P[ks];
+    }
+    const int64_t b0 = ks * C;
+    double acc = 0.0;
+    int64_t pick = live ? -1 : 0, lastpos = -1;
+    long long src[8];
+#pragma unroll
+    for (int i = 0; i < 8; i++) src[i] = __shfl((long long)b0, 8 * i + (lane >> 3));
+    for (int64_t i0 = 0; i0 < C; i0 += 8) {
+      const unsigned long long todo = __ballot(pick < 0);
+      if (todo == 0) break;
+#pragma unroll
+      for (int i = 0; i < 8; i++) {
+        const int T = 8 * i + (lane >> 3);
+        if ((todo >> T) & 1ull) buf[T * 9 + part] = *(const double2 *)(plane + src[i] + i0 + q2);
+      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront", "local");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront", "local");
+      if (pick < 0) {
+#pragma unroll
+        for (int j = 0; j < 8; j++) {
+          const double2 vr = buf[lane * 9 + (j >> 1)], vi = buf[lane * 9 + 4 + (j >> 1)];
+          const double x = (j & 1) ? vr.y : vr.x, y = (j & 1) ? vi.y : vi.x;
+          const double p = __fma_rn(x, x, y * y);
+          if (pick < 0) {
+            acc = acc + p;
+            if (p > 0.0) lastpos = b0 + i0 + j;
+            if (acc > r) pick = b0 + i0 + j;
+          }
+        }
+      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront", "local");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront", "local");
+    }
+    if (live) {
+      if (pick < 0) pick = lastpos >= 0 ? lastpos : b0;
+      uint64_t o = 0;
+      for (int i = 0; i < a.nq; i++) o |= (((uint64_t)pick >> a.qubits[i]) & 1ull) << i;
+      a.out[s] = o;
+    }
+  }
+}
+
 #pragma clang fp contract(on)
 
 }  // namespace
@@ -1053,7 +1135,11 @@ hipError_t svk_launch_sampling(int dbl, const void *re, const void *im, int n, d
   a.seed = seed; a.shots = shots; a.out = out;
   int64_t blocks = (shots + 255) / 256;
   int g2 = (int)(blocks < 4096 ? blocks : 4096);
-  if (dbl) hipLaunchKernelGGL(k_sample<double>, dim3(g2), dim3(256), 0, s, a);
+  // both kernels draw the same indices; the cooperative one pays off once
+  // there are enough waves to keep the memory system busy
+  if (dbl && cbits >= 3 && shots >= 4096)
+    hipLaunchKernelGGL(k_sample_coop, dim3(g2), dim3(256), 0, s, a);
+  else if (dbl) hipLaunchKernelGGL(k_sample<double>, dim3(g2), dim3(256), 0, s, a);
   else hipLaunchKernelGGL(k_sample<float>, dim3(g2), dim3(256), 0, s, a);
   return hipGetLastError();
 }

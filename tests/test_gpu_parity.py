@@ -207,6 +207,9 @@ def test_sampling_bit_exact(sv, n):
     # contract B: the oracle's state gives the same draws on this seed
     b = O.sample(n, O.run_circuit(circ), 12345, 10000, qubits)
     assert np.array_equal(got, b)
+    # fewer shots take the per-lane draw kernel instead of the cooperative one
+    few = st.sample(seed=99, shots=1000, qubits=qubits)
+    assert np.array_equal(few, O.sample(n, psi_gpu, 99, 1000, qubits))
     st.close()
 
 

@@ -261,3 +261,120 @@ def fuse_greedy(k: int, ops: Sequence) -> Tuple[int, np.ndarray]:
 
 def threads() -> int:
     return int(lib().orc_threads())
+
+
+# ------------------------------------------------------------ shot readout
+# Terminal readout with a finite number of shots (Section 4.4: terminal
+# readout returns bit-string counts; the shot estimator rotates Pauli terms
+# into their measurement bases, groups qubit-wise commuting terms and splits a
+# shot budget over the groups, reporting per-term values, the energy and its
+# variance).  The paper fixes neither the grouping rule, nor the split, nor the
+# variance; the readings implemented here:
+#   * terms are taken in order; an identity term is exact (value 1, no shots);
+#     any other term joins the first group whose measurement basis agrees
+#     with it on every qubit both act on, else it opens a new group;
+#   * group g of G draws floor(S/G) shots, one more when g < S mod G, with
+#     seed + g, from its rotated state by the sampling specification, reading
+#     the group's qubits in increasing order;
+#   * rotation into the Z basis: H on an X qubit; S^dagger, then H, on a Y qubit;
+#   * a term's value is (N - 2*odd) / N, odd = the number of the group's N
+#     shots whose bits on the term's qubits have odd parity;
+#   * per group, y = sum_j c_j s_j over its terms (s_j = +-1 per shot) has the
+#     empirical variance Var(y) = sum_j sum_k c_j c_k (v_jk - v_j v_k), v_jk the
+#     value of the parity over the symmetric difference of the two terms'
+#     qubits; the reported variance of the energy is sum_g Var(y_g) / N_g;
+#   * energy = sum_j c_j v_j, in term order.
+
+
+class _Gate:
+    """Minimal gate record for the oracle's own basis rotations."""
+
+    def __init__(self, kind, q):
+        self.kind = kind
+        self.targets = (q,)
+        self.controls = ()
+        self.control_states = 0
+        self.params = ()
+        self.matrix = None
+
+
+def _letters(x: int, z: int, n: int):
+    out = {}
+    for q in range(n):
+        bx, bz = (x >> q) & 1, (z >> q) & 1
+        if bx or bz:
+            out[q] = "Y" if (bx and bz) else ("X" if bx else "Z")
+    return out
+
+
+def qwc_groups(ham):
+    """Greedy qubit-wise-commuting groups: list of (term indices, {qubit: letter})."""
+    groups = []
+    for j in range(len(ham)):
+        let = _letters(int(ham.x[j]), int(ham.z[j]), ham.n)
+        if not let:
+            continue
+        for ids, basis in groups:
+            if all(basis.get(q, b) == b for q, b in let.items()):
+                ids.append(j)
+                basis.update(let)
+                break
+        else:
+            groups.append(([j], dict(let)))
+    return groups
+
+
+def shot_counts(n: int, psi: np.ndarray, seed: int, shots: int, qubits: Sequence[int]) -> np.ndarray:
+    """Bit-string counts of `shots` terminal samples of `qubits` (bit i = qubits[i])."""
+    s = sample(n, psi, seed, shots, qubits)
+    return np.bincount(s.astype(np.int64), minlength=1 << len(qubits)).astype(np.uint64)
+
+
+def _odd_parity(samples: np.ndarray, mask: int) -> int:
+    v = samples & np.uint64(mask)
+    par = np.zeros(v.shape, dtype=np.uint64)
+    for b in range(64):
+        par ^= (v >> np.uint64(b)) & np.uint64(1)
+    return int(par.sum())
+
+
+def shot_estimate(n: int, psi: np.ndarray, seed: int, shots: int, ham):
+    """(per-term values, energy, variance of the energy, number of groups)."""
+    groups = qwc_groups(ham)
+    G = len(groups)
+    if G and shots < G:
+        raise ValueError("fewer shots than measurement groups")
+    values = np.ones(len(ham))
+    variance = 0.0
+    for g, (ids, basis) in enumerate(groups):
+        N = shots // G + (1 if g < shots % G else 0)
+        rot = []
+        for q in sorted(basis):
+            if basis[q] == "X":
+                rot.append(_Gate("h", q))
+            elif basis[q] == "Y":
+                rot.append(_Gate("sdg", q))
+                rot.append(_Gate("h", q))
+        phi = run(n, rot, [], psi) if rot else np.asarray(psi, dtype=np.complex128)
+        support = sorted(basis)
+        pos = {q: i for i, q in enumerate(support)}
+        smp = sample(n, phi, (seed + g) % (1 << 64), N, support)
+        masks = []
+        for j in ids:
+            m = 0
+            for q in _letters(int(ham.x[j]), int(ham.z[j]), n):
+                m |= 1 << pos[q]
+            masks.append(m)
+        v = [(N - 2 * _odd_parity(smp, m)) / N for m in masks]
+        for j, vj in zip(ids, v):
+            values[j] = vj
+        var = 0.0
+        for a, j in enumerate(ids):
+            for b, k in enumerate(ids):
+                vjk = (N - 2 * _odd_parity(smp, masks[a] ^ masks[b])) / N
+                var += ham.c[j] * ham.c[k] * (vjk - v[a] * v[b])
+        variance += var / N
+    energy = 0.0
+    for j in range(len(ham)):
+        energy += ham.c[j] * values[j]
+    return values, energy, variance, G

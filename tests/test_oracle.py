@@ -379,6 +379,67 @@ def test_sampling_blocked_prefix_rounding_order():
     assert P[2048] == 1.0 + 2.0 ** -43
 
 
+# ---------------------------------------------------------- shot readout
+
+def test_qwc_grouping():
+    assert [ids for ids, _ in O.qwc_groups(I.tfim(6))] == [[0, 1, 2, 3, 4], [5, 6, 7, 8, 9, 10]]
+    # X0 opens g0; Z0 clashes on qubit 0 and opens g1; X0X1 joins g0; Y1
+    # clashes with g0 on qubit 1 and joins g1; the identity term is in none
+    h = I.hamiltonian(3, [("X", [0], 1.0), ("Z", [0], 1.0), ("XX", [0, 1], 1.0),
+                          ("Y", [1], 1.0), ("I", [2], 2.0)])
+    groups = O.qwc_groups(h)
+    assert [ids for ids, _ in groups] == [[0, 2], [1, 3]]
+    assert groups[0][1] == {0: "X", 1: "X"} and groups[1][1] == {0: "Z", 1: "Y"}
+
+
+def test_shot_estimate_eigenstates_exact():
+    # RX(-pi/2)|0> is the +1 eigenstate of Y; H|0> of X; X|0> the -1 one of Z
+    n = 3
+    ops = [I.Op("rx", (0,), params=(0,)), I.Op("h", (1,)), I.Op("x", (2,))]
+    psi = O.run(n, ops, [-math.pi / 2])
+    h = I.hamiltonian(n, [("Y", [0], 0.5), ("X", [1], 2.0), ("Z", [2], 1.0),
+                          ("YXZ", [0, 1, 2], -1.5), ("I", [0], 3.0)])
+    vals, e, var, G = O.shot_estimate(n, psi, 5, 999, h)
+    assert G == 1
+    assert list(vals) == [1.0, 1.0, -1.0, -1.0, 1.0]
+    assert e == 0.5 + 2.0 - 1.0 + 1.5 + 3.0 and var == 0.0
+
+
+def test_shot_estimate_single_term_variance_closed_form():
+    # one Z term on |+>: per-shot +-1, so Var(y) = 1 - v^2 and the reported
+    # variance of the mean is (1 - v^2) / N
+    psi = O.run(1, [I.Op("h", (0,))], [])
+    h = I.hamiltonian(1, [("Z", [0], 1.0)])
+    N = 4001
+    vals, e, var, _ = O.shot_estimate(1, psi, 17, N, h)
+    assert abs(var - (1 - vals[0] ** 2) / N) < 1e-15
+    assert abs(vals[0]) < 6 / math.sqrt(N) and e == vals[0]
+
+
+def test_shot_counts_basis_state():
+    n = 6
+    psi = np.zeros(1 << n, dtype=complex)
+    psi[0b101100] = 1j
+    counts = O.shot_counts(n, psi, 3, 500, [2, 5, 0])
+    want = np.zeros(8, dtype=np.uint64)
+    want[0b011] = 500          # bits of qubits 2, 5, 0 are 1, 1, 0
+    assert np.array_equal(counts, want)
+
+
+def test_shot_estimate_unbiased():
+    n = 6
+    psi = O.run_circuit(I.random_circuit(n, 40, seed=8))
+    h = I.hamiltonian(n, [("Y", [0], 1.0), ("XY", [1, 2], -0.7), ("ZZ", [3, 4], 0.4),
+                          ("X", [5], 1.1), ("YZ", [0, 3], 0.3)])
+    shots = 60000
+    vals, e, var, G = O.shot_estimate(n, psi, 21, shots, h)
+    exact, ee, _ = O.expect(n, psi, h)
+    per = shots // G
+    for j in range(len(h)):
+        assert abs(vals[j] - exact[j]) < 5 * math.sqrt(max(1 - exact[j] ** 2, 1e-4) / per)
+    assert abs(e - ee) < 5 * math.sqrt(var) + 1e-12
+
+
 # --------------------------------------------------------------- fusion
 
 def test_fusion_counts_match_paper_table():

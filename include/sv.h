@@ -177,6 +177,35 @@ sv_status sv_adjoint_grad_device(sv_state *st, const sv_op *ops, int32_t n_ops,
 sv_status sv_sample(sv_state *st, uint64_t seed, int64_t shots, const int32_t *qubits,
                     int32_t n_measured, uint64_t *out);
 
+/* Terminal readout counts (paper Section 4.4: terminal readout returns
+ * bit-string counts): draws `shots` samples of the n_measured qubits exactly
+ * as sv_sample does and writes the HOST array counts[2^n_measured], counts[b]
+ * = number of draws whose packed bits (bit i = qubit qubits[i]) equal b.
+ * n_measured <= SV_COUNTS_MAX_QUBITS.  Waits. */
+#define SV_COUNTS_MAX_QUBITS 24
+sv_status sv_sample_counts(sv_state *st, uint64_t seed, int64_t shots, const int32_t *qubits,
+                           int32_t n_measured, uint64_t *counts);
+
+/* Shot-based estimate of sum_j c_j <P_j> (paper Section 4.4 shot estimator:
+ * Pauli terms rotated into their measurement bases, qubit-wise commuting
+ * terms grouped, a shot budget split over the groups).  Fixed readings:
+ * terms in order join the first group whose basis agrees on every shared
+ * qubit (identity terms join none and are exact, value 1); group g of G gets
+ * floor(shots/G) draws, one more if g < shots mod G, sampled with seed + g
+ * from a copy of the state rotated by H (X qubits) or S^dagger then H (Y
+ * qubits), reading the group's qubits in increasing order.  values[j] =
+ * (N - 2*odd_j)/N with odd_j the draws of odd parity on term j's qubits;
+ * *energy = sum_j c_j values[j] in term order; *variance = sum over groups of
+ * sum_{j,k} c_j c_k (v_jk - v_j v_k) / N (v_jk: parity over the symmetric
+ * difference of the two terms' qubits), the variance of the energy estimate.
+ * The state is not modified; the first call allocates a second pair of
+ * planes for the rotated copy.  shots >= number of groups; a group holds at
+ * most SV_SHOT_GROUP_MAX_TERMS terms (SV_EUNSUPPORTED beyond).  Waits. */
+#define SV_SHOT_GROUP_MAX_TERMS 1024
+sv_status sv_shot_estimate(sv_state *st, uint64_t seed, int64_t shots, const sv_pauli_term *terms,
+                           int32_t n_terms, double *values, double *energy, double *variance,
+                           int32_t *n_groups);
+
 /* Copy amplitudes [offset, offset+count) of both planes to HOST buffers of
  * the state's element type (the paper's explicit to_numpy exit).  Waits. */
 sv_status sv_copy_to_host(const sv_state *st, void *re, void *im, uint64_t offset,

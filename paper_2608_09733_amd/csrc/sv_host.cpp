@@ -1228,8 +1228,12 @@ struct sv_state {
   std::vector<hipEvent_t> ev_pool;
   size_t ev_used = 0;
   std::vector<double> ev_bytes;      // algorithmic bytes of each timed launch
+  // second pair of planes for the shot estimator's rotated copies (on demand)
+  void *copy = nullptr;
+  size_t copy_bytes = 0;
   ~sv_state() {
     if (scratch) (void)hipFree(scratch);
+    if (copy) (void)hipFree(copy);
     for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
   }
 };
@@ -2155,6 +2159,37 @@ extern "C" sv_status sv_adjoint_grad_device(sv_state *st, const sv_op *ops, int3
 
 // ---------------------------------------------------------------- sampling
 
+// Scratch of one sampling call: block totals and offsets of the blocked
+// prefix, the samples, then `extra_bytes` for the caller.
+struct SampleScratch {
+  double *QE = nullptr;
+  uint64_t *samples = nullptr;
+  void *extra = nullptr;
+};
+
+static sv_status sample_scratch(sv_state *st, int64_t shots, size_t extra_bytes, SampleScratch &sc) {
+  const int64_t K = sample_K(st->n), J = K / (K < 1024 ? K : 1024);
+  const size_t qe_bytes = (((size_t)(2 * J + 1) * 8) + 255) & ~(size_t)255;
+  const size_t smp_bytes = ((size_t)shots * 8 + 255) & ~(size_t)255;
+  sv_status s = ensure_scratch(st, qe_bytes + smp_bytes + extra_bytes + 1024);
+  if (s) return s;
+  sc.QE = (double *)st->scratch;
+  sc.samples = (uint64_t *)((char *)st->scratch + qe_bytes);
+  sc.extra = (char *)st->scratch + qe_bytes + smp_bytes;
+  return SV_OK;
+}
+
+static sv_status sample_on_device(sv_state *st, const void *re, const void *im, uint64_t seed,
+                                  int64_t shots, const int32_t *qubits, int nq, const SampleScratch &sc) {
+  double *S, *P;
+  void *a, *b, *c, *d;
+  ws_layout(st, &S, &P, &a, &b, &c, &d);
+  hipError_t e = svk_launch_sampling(st->dtype == SV_C128, re, im, st->n, S, P, sc.QE, seed, shots,
+                                     qubits, nq, sc.samples, st->stream);
+  if (e != hipSuccess) return fail(SV_EDEVICE, "sampling: %s", hipGetErrorString(e));
+  return SV_OK;
+}
+
 extern "C" sv_status sv_sample(sv_state *st, uint64_t seed, int64_t shots, const int32_t *qubits,
                                int32_t n_measured, uint64_t *out) {
   if (!st) return fail(SV_EINVAL, "null handle");
@@ -2165,23 +2200,207 @@ extern "C" sv_status sv_sample(sv_state *st, uint64_t seed, int64_t shots, const
     if (qubits[i] < 0 || qubits[i] >= st->n) return fail(SV_EINVAL, "measured qubit %d out of range", qubits[i]);
   if (shots > 0 && !out) return fail(SV_EINVAL, "null output");
   if (shots == 0) return SV_OK;
-  double *S, *P;
-  void *a, *b, *c, *d;
-  ws_layout(st, &S, &P, &a, &b, &c, &d);
   sv_status s = materialize_zero(st);
   if (s) return s;
-  // scratch: block totals and offsets of the blocked prefix, then the samples
-  const int64_t K = sample_K(st->n), J = K / (K < 1024 ? K : 1024);
-  const size_t qe_bytes = (((size_t)(2 * J + 1) * 8) + 255) & ~(size_t)255;
-  s = ensure_scratch(st, qe_bytes + (size_t)shots * 8 + 1024);
+  SampleScratch sc;
+  s = sample_scratch(st, shots, 0, sc);
   if (s) return s;
-  double *QE = (double *)st->scratch;
-  uint64_t *d_out = (uint64_t *)((char *)st->scratch + qe_bytes);
-  hipError_t e = svk_launch_sampling(st->dtype == SV_C128, st->re, st->im, st->n, S, P, QE, seed,
-                                     shots, qubits, n_measured, d_out, st->stream);
-  if (e != hipSuccess) return fail(SV_EDEVICE, "sampling: %s", hipGetErrorString(e));
-  HIPCHK(hipMemcpyAsync(out, d_out, (size_t)shots * 8, hipMemcpyDeviceToHost, st->stream));
+  s = sample_on_device(st, st->re, st->im, seed, shots, qubits, n_measured, sc);
+  if (s) return s;
+  HIPCHK(hipMemcpyAsync(out, sc.samples, (size_t)shots * 8, hipMemcpyDeviceToHost, st->stream));
   HIPCHK(hipStreamSynchronize(st->stream));
+  return SV_OK;
+}
+
+extern "C" sv_status sv_sample_counts(sv_state *st, uint64_t seed, int64_t shots,
+                                      const int32_t *qubits, int32_t n_measured, uint64_t *counts) {
+  if (!st) return fail(SV_EINVAL, "null handle");
+  if (shots < 0) return fail(SV_EINVAL, "negative shots");
+  if (n_measured < 0 || n_measured > SV_COUNTS_MAX_QUBITS)
+    return fail(SV_EINVAL, "n_measured %d outside 0..%d", n_measured, SV_COUNTS_MAX_QUBITS);
+  if (n_measured > 0 && !qubits) return fail(SV_EINVAL, "null qubits");
+  for (int i = 0; i < n_measured; i++)
+    if (qubits[i] < 0 || qubits[i] >= st->n) return fail(SV_EINVAL, "measured qubit %d out of range", qubits[i]);
+  if (!counts) return fail(SV_EINVAL, "null counts");
+  const size_t nb = (size_t)1 << n_measured;
+  if (shots == 0) {
+    std::memset(counts, 0, nb * 8);
+    return SV_OK;
+  }
+  sv_status s = materialize_zero(st);
+  if (s) return s;
+  SampleScratch sc;
+  s = sample_scratch(st, shots, nb * 8, sc);
+  if (s) return s;
+  s = sample_on_device(st, st->re, st->im, seed, shots, qubits, n_measured, sc);
+  if (s) return s;
+  uint64_t *d_counts = (uint64_t *)sc.extra;
+  hipError_t e = svk_launch_histogram(sc.samples, shots, n_measured, d_counts, st->stream);
+  if (e != hipSuccess) return fail(SV_EDEVICE, "histogram: %s", hipGetErrorString(e));
+  HIPCHK(hipMemcpyAsync(counts, d_counts, nb * 8, hipMemcpyDeviceToHost, st->stream));
+  HIPCHK(hipStreamSynchronize(st->stream));
+  return SV_OK;
+}
+
+// Greedy qubit-wise-commuting groups in term order; identity terms join none.
+struct ShotGroup {
+  std::vector<int> terms;
+  uint64_t xs = 0, zs = 0;  // measurement basis: X on xs & ~zs, Y on xs & zs, Z on zs & ~xs
+  uint64_t support() const { return xs | zs; }
+};
+
+static std::vector<ShotGroup> qwc_group(const sv_pauli_term *terms, int nt) {
+  std::vector<ShotGroup> groups;
+  for (int j = 0; j < nt; j++) {
+    const uint64_t x = terms[j].x_mask, z = terms[j].z_mask, u = x | z;
+    if (!u) continue;
+    bool placed = false;
+    for (ShotGroup &g : groups) {
+      const uint64_t both = g.support() & u;
+      if (((g.xs ^ x) & both) || ((g.zs ^ z) & both)) continue;  // a letter differs on a shared qubit
+      g.terms.push_back(j);
+      g.xs |= x;
+      g.zs |= z;
+      placed = true;
+      break;
+    }
+    if (!placed) {
+      ShotGroup g;
+      g.terms.push_back(j);
+      g.xs = x;
+      g.zs = z;
+      groups.push_back(g);
+    }
+  }
+  return groups;
+}
+
+static uint64_t pack_bits(uint64_t mask, uint64_t support) {
+  uint64_t out = 0;
+  int pos = 0;
+  for (int q = 0; q < 64; q++)
+    if (support >> q & 1) {
+      if (mask >> q & 1) out |= 1ull << pos;
+      pos++;
+    }
+  return out;
+}
+
+extern "C" sv_status sv_shot_estimate(sv_state *st, uint64_t seed, int64_t shots,
+                                      const sv_pauli_term *terms, int32_t n_terms, double *values,
+                                      double *energy, double *variance, int32_t *n_groups) {
+  if (!st) return fail(SV_EINVAL, "null handle");
+  sv_status s = validate_terms(st->n, terms, n_terms);
+  if (s) return s;
+  if (shots < 0) return fail(SV_EINVAL, "negative shots");
+  if ((n_terms > 0 && !values) || !energy || !variance) return fail(SV_EINVAL, "null output");
+  std::vector<ShotGroup> groups = qwc_group(terms, n_terms);
+  const int G = (int)groups.size();
+  if (G > 0 && shots < G) return fail(SV_EINVAL, "%lld shots for %d measurement groups", (long long)shots, G);
+  for (const ShotGroup &g : groups)
+    if (g.terms.size() > (size_t)SV_SHOT_GROUP_MAX_TERMS)
+      return fail(SV_EUNSUPPORTED, "a measurement group of %zu terms (at most %d)", g.terms.size(),
+                  SV_SHOT_GROUP_MAX_TERMS);
+  for (int j = 0; j < n_terms; j++) values[j] = 1.0;
+  double var_total = 0.0;
+  if (G > 0) {
+    s = materialize_zero(st);
+    if (s) return s;
+    const size_t plane = ((size_t)1 << st->n) * elem_size(st->dtype);
+    if (st->copy_bytes < 2 * plane) {
+      HIPCHK(hipStreamSynchronize(st->stream));
+      if (st->copy) (void)hipFree(st->copy);
+      st->copy = nullptr;
+      st->copy_bytes = 0;
+      if (hipMalloc(&st->copy, 2 * plane) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(SV_ENOMEM, "no device memory for the rotated copy (%zu bytes)", 2 * plane);
+      }
+      st->copy_bytes = 2 * plane;
+    }
+    void *cre = st->copy, *cim = (char *)st->copy + plane;
+    size_t max_masks = 0;
+    for (const ShotGroup &g : groups) max_masks = std::max(max_masks, g.terms.size() * (g.terms.size() + 1) / 2);
+    const int64_t max_n = shots / G + 1;
+    SampleScratch sc;
+    s = sample_scratch(st, max_n, 16 * max_masks + 256, sc);
+    if (s) return s;
+    uint64_t *d_masks = (uint64_t *)sc.extra;
+    uint64_t *d_odd = d_masks + max_masks;
+    const bool dbl = st->dtype == SV_C128;
+    for (int gi = 0; gi < G; gi++) {
+      const ShotGroup &g = groups[gi];
+      const int64_t N = shots / G + (gi < shots % G ? 1 : 0);
+      HIPCHK(hipMemcpyAsync(cre, st->re, plane, hipMemcpyDeviceToDevice, st->stream));
+      HIPCHK(hipMemcpyAsync(cim, st->im, plane, hipMemcpyDeviceToDevice, st->stream));
+      // rotate the copy into the Z basis: H on X qubits, S^dagger then H on Y qubits
+      std::vector<sv_op> rot;
+      for (int q = 0; q < st->n; q++) {
+        if (!(g.xs >> q & 1)) continue;
+        sv_op o{};
+        o.n_targets = 1;
+        o.targets[0] = q;
+        if (g.zs >> q & 1) {
+          o.kind = SV_SDG;
+          rot.push_back(o);
+        }
+        o.kind = SV_H;
+        rot.push_back(o);
+      }
+      if (!rot.empty()) {
+        Tiling tl = st->tiling;
+        s = widen_groups(dbl, 1, tl);
+        if (s) return s;
+        Plan *P = nullptr;
+        s = get_plan(st, SV_FUSE_AUTO, tl, rot.data(), (int)rot.size(), 0, false, &P);
+        if (s) return s;
+        s = upload_call_data(st, *P, rot.data(), (int)rot.size(), nullptr, 0);
+        if (s) return s;
+        s = run_steps(st, *P, cre, cim, nullptr, nullptr, nullptr, 0);
+        if (s) return s;
+      }
+      int32_t q_list[64];
+      int nq = 0;
+      for (int q = 0; q < st->n; q++)
+        if (g.support() >> q & 1) q_list[nq++] = q;
+      s = sample_on_device(st, cre, cim, seed + (uint64_t)gi, N, q_list, nq, sc);
+      if (s) return s;
+      // masks: each term, then each pair j < k (symmetric difference)
+      const int T = (int)g.terms.size();
+      std::vector<uint64_t> masks;
+      for (int a = 0; a < T; a++)
+        masks.push_back(pack_bits(terms[g.terms[a]].x_mask | terms[g.terms[a]].z_mask, g.support()));
+      for (int a = 0; a < T; a++)
+        for (int b = a + 1; b < T; b++) masks.push_back(masks[a] ^ masks[b]);
+      const int nm = (int)masks.size();
+      HIPCHK(hipMemcpyAsync(d_masks, masks.data(), (size_t)nm * 8, hipMemcpyHostToDevice, st->stream));
+      hipError_t e = svk_launch_parity_counts(sc.samples, N, d_masks, nm, d_odd, st->stream);
+      if (e != hipSuccess) return fail(SV_EDEVICE, "parity counts: %s", hipGetErrorString(e));
+      std::vector<uint64_t> odd(nm);
+      HIPCHK(hipMemcpyAsync(odd.data(), d_odd, (size_t)nm * 8, hipMemcpyDeviceToHost, st->stream));
+      HIPCHK(hipStreamSynchronize(st->stream));
+      auto val = [&](uint64_t o) { return (double)(N - 2 * (int64_t)o) / (double)N; };
+      std::vector<double> v(T);
+      for (int a = 0; a < T; a++) {
+        v[a] = val(odd[a]);
+        values[g.terms[a]] = v[a];
+      }
+      // pair index of (a, b), a < b, after the T single-term masks
+      auto pair = [&](int a, int b) { return T + a * (2 * T - a - 1) / 2 + (b - a - 1); };
+      double var = 0.0;
+      for (int a = 0; a < T; a++)
+        for (int b = 0; b < T; b++) {
+          const double vab = a == b ? 1.0 : val(odd[a < b ? pair(a, b) : pair(b, a)]);
+          var += terms[g.terms[a]].coeff * terms[g.terms[b]].coeff * (vab - v[a] * v[b]);
+        }
+      var_total += var / (double)N;
+    }
+  }
+  double e = 0.0;
+  for (int j = 0; j < n_terms; j++) e += terms[j].coeff * values[j];
+  *energy = e;
+  *variance = var_total;
+  if (n_groups) *n_groups = G;
   return SV_OK;
 }
 

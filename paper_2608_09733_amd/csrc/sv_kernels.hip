@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <algorithm>
+
 #include "sv_device.h"
 
 namespace {
@@ -940,6 +942,40 @@ __global__ void __launch_bounds__(256) k_sample_coop(SampleArgs a) {
   }
 }
 
+// ------------------------------------------------------------ shot readout
+// Integer counting over device samples: exact and independent of the order
+// in which threads add their counts.
+
+__global__ void __launch_bounds__(256) k_zero_u64(unsigned long long *p, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = 0ull;
+}
+
+// counts[b] += number of samples equal to b (b < 2^nq)
+__global__ void __launch_bounds__(256) k_histogram(const uint64_t *samples, int64_t shots,
+                                                   unsigned long long *counts) {
+  for (int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; s < shots;
+       s += (int64_t)gridDim.x * blockDim.x)
+    atomicAdd(&counts[samples[s]], 1ull);
+}
+
+// odd[m] += number of samples in this block's slice whose bits under
+// masks[m] have odd parity (one thread per mask, slices along blockIdx.y)
+__global__ void __launch_bounds__(256) k_parity_counts(const uint64_t *samples, int64_t shots,
+                                                       const uint64_t *masks, int nm,
+                                                       unsigned long long *odd) {
+  const int m = blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t per = (shots + gridDim.y - 1) / gridDim.y;
+  const int64_t s0 = (int64_t)blockIdx.y * per;
+  const int64_t s1 = s0 + per < shots ? s0 + per : shots;
+  if (m >= nm || s0 >= s1) return;
+  const uint64_t mask = masks[m];
+  unsigned long long c = 0;
+  for (int64_t s = s0; s < s1; s++) c += (unsigned long long)(__popcll(samples[s] & mask) & 1);
+  atomicAdd(&odd[m], c);
+}
+
 #pragma clang fp contract(on)
 
 }  // namespace
@@ -1141,6 +1177,33 @@ hipError_t svk_launch_sampling(int dbl, const void *re, const void *im, int n, d
     hipLaunchKernelGGL(k_sample_coop, dim3(g2), dim3(256), 0, s, a);
   else if (dbl) hipLaunchKernelGGL(k_sample<double>, dim3(g2), dim3(256), 0, s, a);
   else hipLaunchKernelGGL(k_sample<float>, dim3(g2), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t svk_launch_histogram(const uint64_t *samples, int64_t shots, int nq,
+                                uint64_t *counts, hipStream_t s) {
+  const int64_t nb = 1ll << nq;
+  unsigned long long *c = (unsigned long long *)counts;
+  hipLaunchKernelGGL(k_zero_u64, dim3((unsigned)std::min<int64_t>((nb + 255) / 256, 4096)), dim3(256), 0,
+                     s, c, nb);
+  if (shots > 0)
+    hipLaunchKernelGGL(k_histogram, dim3((unsigned)std::min<int64_t>((shots + 255) / 256, 4096)),
+                       dim3(256), 0, s, samples, shots, c);
+  return hipGetLastError();
+}
+
+hipError_t svk_launch_parity_counts(const uint64_t *samples, int64_t shots, const uint64_t *masks,
+                                    int nm, uint64_t *odd, hipStream_t s) {
+  unsigned long long *o = (unsigned long long *)odd;
+  hipLaunchKernelGGL(k_zero_u64, dim3((unsigned)std::min<int64_t>((nm + 255) / 256, 4096)), dim3(256), 0,
+                     s, o, (int64_t)nm);
+  if (shots > 0 && nm > 0) {
+    const unsigned gx = (unsigned)((nm + 255) / 256);
+    // enough slices along y for a few hundred blocks, each at least 1024 shots long
+    int64_t gy = std::max<int64_t>(1, std::min<int64_t>((shots + 1023) / 1024, 1024 / (int64_t)gx));
+    hipLaunchKernelGGL(k_parity_counts, dim3(gx, (unsigned)gy), dim3(256), 0, s, samples, shots,
+                       masks, nm, o);
+  }
   return hipGetLastError();
 }
 

@@ -51,6 +51,13 @@ hipError_t svk_launch_sampling(int dbl, const void *re, const void *im, int n, d
                                double *P, double *QE, uint64_t seed, int64_t shots,
                                const int32_t *qubits, int nq, uint64_t *out, hipStream_t s);
 
+// counts[0 .. 2^nq) <- histogram of samples (zeroed first)
+hipError_t svk_launch_histogram(const uint64_t *samples, int64_t shots, int nq, uint64_t *counts,
+                                hipStream_t s);
+// odd[m] <- number of samples with odd parity under masks[m] (zeroed first)
+hipError_t svk_launch_parity_counts(const uint64_t *samples, int64_t shots, const uint64_t *masks,
+                                    int nm, uint64_t *odd, hipStream_t s);
+
 #define SVI_GSLOTS_MAX 32    // gradient slots per backward sweep (two-state kernel registers)
 #define SVI_GSLOTS_HARD 256  // gradient slots of the general two-state kernel (LDS)
 #define SVI_PTERMS_MAX 64

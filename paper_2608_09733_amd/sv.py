@@ -72,6 +72,8 @@ def lib():
         "sv_adjoint_grad": (C.c_int, [vp, opp, i32, dp, i32, tp, i32, dp, dp, C.POINTER(i32)]),
         "sv_adjoint_grad_device": (C.c_int, [vp, opp, i32, dp, i32, tp, i32, vp]),
         "sv_sample": (C.c_int, [vp, u64, i64, C.POINTER(i32), i32, u64p]),
+        "sv_sample_counts": (C.c_int, [vp, u64, i64, C.POINTER(i32), i32, u64p]),
+        "sv_shot_estimate": (C.c_int, [vp, u64, i64, tp, i32, dp, dp, dp, C.POINTER(i32)]),
         "sv_copy_to_host": (C.c_int, [vp, vp, vp, u64, u64]),
         "sv_copy_from_host": (C.c_int, [vp, vp, vp, u64, u64]),
         "sv_last_error": (C.c_char_p, []),
@@ -286,6 +288,29 @@ class State:
                                q.ctypes.data_as(C.POINTER(C.c_int32)), nq,
                                out.ctypes.data_as(C.POINTER(C.c_uint64))))
         return out[:shots]
+
+    def sample_counts(self, seed: int, shots: int, qubits: Sequence[int]) -> np.ndarray:
+        q = np.ascontiguousarray(np.asarray(list(qubits), dtype=np.int32))
+        nq = int(q.size)
+        if nq == 0:
+            q = np.zeros(1, dtype=np.int32)
+        out = np.zeros(1 << nq, dtype=np.uint64)
+        _check(lib().sv_sample_counts(self.h, C.c_uint64(seed), int(shots),
+                                      q.ctypes.data_as(C.POINTER(C.c_int32)), nq,
+                                      out.ctypes.data_as(C.POINTER(C.c_uint64))))
+        return out
+
+    def shot_estimate(self, seed: int, shots: int, ham) -> Tuple[np.ndarray, float, float, int]:
+        """(per-term values, energy, variance of the energy, number of groups)."""
+        ta = TermArray(ham)
+        vals = np.zeros(max(1, ta.n))
+        e = C.c_double(0.0)
+        v = C.c_double(0.0)
+        g = C.c_int32(0)
+        _check(lib().sv_shot_estimate(self.h, C.c_uint64(seed), int(shots), ta.ptr(), ta.n,
+                                      vals.ctypes.data_as(C.POINTER(C.c_double)), C.byref(e),
+                                      C.byref(v), C.byref(g)))
+        return vals[:ta.n], float(e.value), float(v.value), int(g.value)
 
     def planes(self, offset: int = 0, count: Optional[int] = None,
                out: Optional[Tuple[np.ndarray, np.ndarray]] = None) -> Tuple[np.ndarray, np.ndarray]:

@@ -1,0 +1,99 @@
+"""GPU shot readout (terminal counts, grouped shot estimator) against the
+oracle applied to the GPU's own state, through the C ABI.
+
+Counts and per-term values are integer-derived, so they must match exactly;
+the energy and variance are sums of the same values in the same order, held
+to 1e-12.  The state must be unchanged by an estimate (the rotations act on a
+copy)."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2608_09733_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def sv():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2608_09733_amd import sv as _sv
+    _sv.lib()
+    return _sv
+
+
+def _say(*a):
+    print("[case]", *a, flush=True)
+
+
+def _mixed_ham(n):
+    return I.hamiltonian(n, [("Y", [0], 1.0), ("XY", [1, 2], -0.7), ("ZZ", [3, n - 1], 0.4),
+                             ("X", [n - 2], 1.1), ("YZ", [0, 3], 0.3), ("I", [1], 2.5),
+                             ("Z", [n // 2], -0.9), ("XX", [1, n - 2], 0.6)])
+
+
+@pytest.mark.parametrize("n", [6, 16])
+def test_counts_match_oracle(sv, n):
+    _say("shot counts", n)
+    circ = I.random_circuit(n, 40, seed=n)
+    st = sv.State(n)
+    st.apply(circ.ops, circ.params, fuse=-1)
+    qubits = [n - 1, 0, 3, 2]
+    got = st.sample_counts(31, 20000, qubits)
+    psi = st.to_numpy()
+    assert np.array_equal(got, O.shot_counts(n, psi, 31, 20000, qubits))
+    assert int(got.sum()) == 20000
+    st.close()
+
+
+@pytest.mark.parametrize("n,ham", [(8, "mixed"), (16, "mixed"), (20, "tfim")])
+def test_shot_estimate_matches_oracle(sv, n, ham):
+    _say("shot estimate", n, ham)
+    circ = I.layered(n, 3, seed=n) if ham == "tfim" else I.random_circuit(n, 40, seed=100 + n)
+    h = I.tfim(n) if ham == "tfim" else _mixed_ham(n)
+    st = sv.State(n)
+    st.apply(circ.ops, circ.params, fuse=-1)
+    psi = st.to_numpy()
+    vals, e, var, G = st.shot_estimate(9, 30001, h)
+    ov, oe, ovar, oG = O.shot_estimate(n, psi, 9, 30001, h)
+    assert G == oG
+    assert np.array_equal(vals, ov)
+    assert abs(e - oe) <= 1e-12 * max(1.0, abs(oe))
+    assert abs(var - ovar) <= 1e-12 * max(1e-12, abs(ovar))
+    # the rotations ran on a copy
+    assert np.array_equal(st.to_numpy(), psi)
+    # and the estimate is within 6 standard deviations of the exact energy
+    _, exact, _ = O.expect(n, psi, h)
+    assert abs(e - exact) <= 6 * math.sqrt(var) + 1e-12
+    st.close()
+
+
+def test_shot_estimate_eigenstates(sv):
+    _say("shot estimate eigenstates")
+    n = 3
+    ops = [I.Op("rx", (0,), params=(0,)), I.Op("h", (1,)), I.Op("x", (2,))]
+    h = I.hamiltonian(n, [("Y", [0], 0.5), ("X", [1], 2.0), ("Z", [2], 1.0),
+                          ("YXZ", [0, 1, 2], -1.5), ("I", [0], 3.0)])
+    st = sv.State(n)
+    st.apply(ops, np.array([-math.pi / 2]), fuse=-1)
+    vals, e, var, G = st.shot_estimate(5, 999, h)
+    assert G == 1 and list(vals) == [1.0, 1.0, -1.0, -1.0, 1.0]
+    assert e == 6.0 and var == 0.0
+    st.close()
+
+
+def test_shot_errors(sv):
+    _say("shot errors")
+    st = sv.State(4)
+    st.reset()
+    with pytest.raises(sv.SvError):
+        st.shot_estimate(1, 1, I.hamiltonian(4, [("X", [0], 1.0), ("Z", [0], 1.0)]))
+    with pytest.raises(sv.SvError):
+        st.sample_counts(1, 10, [0, 7])
+    # identity-only observables need no shots
+    vals, e, var, G = st.shot_estimate(1, 0, I.hamiltonian(4, [("I", [0], 1.5)]))
+    assert G == 0 and e == 1.5 and var == 0.0
+    st.close()

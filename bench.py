@@ -176,6 +176,19 @@ def sampling_and_exit(st, n, torch):
         ts.append((time.time() - t0) * 1e3)
     out["sampling_1000_shots"] = {"ms_median": float(np.median(ts)), "shots": 1000}
     log(f"sampling: {np.median(ts):.2f} ms per 1000 shots")
+    # grouped shot estimator: TFIM (ZZ group and X group), 2^20 shots in all
+    from paper_2608_09733_amd import inputs as I
+    ham = I.tfim(n, 0.7)
+    st.shot_estimate(1, 1 << 20, ham)
+    ts = []
+    for k in range(3):
+        t0 = time.time()
+        vals, e, var, G = st.shot_estimate(k + 2, 1 << 20, ham)
+        ts.append((time.time() - t0) * 1e3)
+    out["shot_estimate_tfim_2p20_shots"] = {"ms_median": float(np.median(ts)), "shots": 1 << 20,
+                                            "groups": G, "terms": len(ham), "energy": e,
+                                            "std_error": math.sqrt(var)}
+    log(f"shot estimator: {np.median(ts):.1f} ms, {G} groups, E = {e:.4f} +- {math.sqrt(var):.4f}")
     cnt = 1 << min(n, 28)
     pre = torch.empty(cnt, dtype=torch.float64, pin_memory=True)
     pim = torch.empty(cnt, dtype=torch.float64, pin_memory=True)

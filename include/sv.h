@@ -193,7 +193,7 @@ sv_status sv_sample_counts(sv_state *st, uint64_t seed, int64_t shots, const int
  * qubit (identity terms join none and are exact, value 1); group g of G gets
  * floor(shots/G) draws, one more if g < shots mod G, sampled with seed + g
  * from a copy of the state rotated by H (X qubits) or S^dagger then H (Y
- * qubits), reading the group's qubits in increasing order.  values[j] =
+ * qubits; applied as Z or S, then RY(pi/2)), reading the group's qubits in increasing order.  values[j] =
  * (N - 2*odd_j)/N with odd_j the draws of odd parity on term j's qubits;
  * *energy = sum_j c_j values[j] in term order; *variance = sum over groups of
  * sum_{j,k} c_j c_k (v_jk - v_j v_k) / N (v_jk: parity over the symmetric

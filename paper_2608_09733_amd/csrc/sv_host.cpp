@@ -2333,28 +2333,36 @@ extern "C" sv_status sv_shot_estimate(sv_state *st, uint64_t seed, int64_t shots
       const int64_t N = shots / G + (gi < shots % G ? 1 : 0);
       HIPCHK(hipMemcpyAsync(cre, st->re, plane, hipMemcpyDeviceToDevice, st->stream));
       HIPCHK(hipMemcpyAsync(cim, st->im, plane, hipMemcpyDeviceToDevice, st->stream));
-      // rotate the copy into the Z basis: H on X qubits, S^dagger then H on Y qubits
+      // rotate the copy into the Z basis: H on X qubits, H S^dagger on Y
+      // qubits, written as H = RY(pi/2) Z and H S^dagger = RY(pi/2) S so the
+      // plan takes Kronecker stages (diagonal tables and rotations)
       std::vector<sv_op> rot;
       for (int q = 0; q < st->n; q++) {
         if (!(g.xs >> q & 1)) continue;
         sv_op o{};
         o.n_targets = 1;
         o.targets[0] = q;
-        if (g.zs >> q & 1) {
-          o.kind = SV_SDG;
-          rot.push_back(o);
-        }
-        o.kind = SV_H;
+        o.kind = (g.zs >> q & 1) ? SV_S : SV_Z;
         rot.push_back(o);
       }
+      for (int q = 0; q < st->n; q++) {
+        if (!(g.xs >> q & 1)) continue;
+        sv_op o{};
+        o.n_targets = 1;
+        o.targets[0] = q;
+        o.kind = SV_RY;
+        o.param_index[0] = 0;
+        rot.push_back(o);
+      }
+      const double half_pi = 1.5707963267948966;
       if (!rot.empty()) {
         Tiling tl = st->tiling;
         s = widen_groups(dbl, 1, tl);
         if (s) return s;
         Plan *P = nullptr;
-        s = get_plan(st, SV_FUSE_AUTO, tl, rot.data(), (int)rot.size(), 0, false, &P);
+        s = get_plan(st, SV_FUSE_AUTO, tl, rot.data(), (int)rot.size(), 1, false, &P);
         if (s) return s;
-        s = upload_call_data(st, *P, rot.data(), (int)rot.size(), nullptr, 0);
+        s = upload_call_data(st, *P, rot.data(), (int)rot.size(), &half_pi, 1);
         if (s) return s;
         s = run_steps(st, *P, cre, cim, nullptr, nullptr, nullptr, 0);
         if (s) return s;

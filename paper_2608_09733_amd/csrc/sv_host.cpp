@@ -1524,7 +1524,25 @@ static sv_status build_forward_plan(int mode, int n, bool dbl, const Tiling &tl,
   collect_user_mats(P, ops, n_ops);
   std::vector<GateRec> recs;
   int um = 0;
+  int half_pi = -1;  // parameter slot of the constant pi/2, once needed
   for (int i = 0; i < n_ops; i++) {
+    if (mode == SV_FUSE_AUTO && ops[i].kind == SV_H && ops[i].n_controls == 0) {
+      // H = RY(pi/2) Z: a diagonal and a rotation, both Kronecker-stage parts
+      if (half_pi < 0) {
+        P.constants.push_back(1.57079632679489661923);
+        half_pi = n_params + (int)P.constants.size() - 1;
+      }
+      sv_op z{};
+      z.kind = SV_Z;
+      z.n_targets = 1;
+      z.targets[0] = ops[i].targets[0];
+      recs.push_back(lower_one(z, -1));
+      sv_op ry = z;
+      ry.kind = SV_RY;
+      ry.param_index[0] = half_pi;
+      recs.push_back(lower_one(ry, -1));
+      continue;
+    }
     GateRec g = lower_one(ops[i], ops[i].kind == SV_UNITARY ? um : -1);
     if (ops[i].kind == SV_UNITARY) um++;
     if (g.mo == MO_NOP) continue;

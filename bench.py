@@ -474,6 +474,22 @@ def main():
         s32.close()
         del s32
         extras.update(sampling_and_exit(st, n, torch))
+        # the paper's other circuit families at the same size (Section 9.1)
+        for name, c in (("qft", I.qft(n)), ("ghz", I.ghz(n))):
+            oac = sv.OpArray(c.ops)
+            st.reset()
+            st.apply(None, c.params, op_array=oac)
+            torch.cuda.synchronize()
+            e0.record()
+            for _ in range(3):
+                st.reset()
+                st.apply(None, c.params, op_array=oac)
+            e1.record()
+            torch.cuda.synchronize()
+            tc = e0.elapsed_time(e1) / 3
+            extras[f"{name}_{n}q"] = {"gates": len(c.ops), "ms": tc,
+                                      "updates_per_s": len(c.ops) * float(1 << n) / (tc / 1e3)}
+            log(f"{name} {n}q: {len(c.ops)} gates, {tc:.1f} ms")
     if not args.no_extras:
         st.close()
         del st

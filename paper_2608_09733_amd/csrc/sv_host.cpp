@@ -1513,8 +1513,13 @@ static void plan_auto_best(const std::vector<GateRec> &recs, int n, const Tiling
     out.swap(alt);
 }
 
+// split1q: write uncontrolled H, RX, Y, U2, U3 as Kronecker-stage parts.  The
+// batch planner keeps them whole: a batch launches its Kronecker-only kernel
+// only when every circuit qualifies, and a circuit must round the same alone
+// and in any mix.
 static sv_status build_forward_plan(int mode, int n, bool dbl, const Tiling &tl, const sv_op *ops,
-                                    int n_ops, int n_params, Plan &P, bool remap = true) {
+                                    int n_ops, int n_params, Plan &P, bool remap = true,
+                                    bool split1q = true) {
   P.n = n;
   P.dbl = dbl;
   P.M = tl.M;
@@ -1525,23 +1530,48 @@ static sv_status build_forward_plan(int mode, int n, bool dbl, const Tiling &tl,
   std::vector<GateRec> recs;
   int um = 0;
   int half_pi = -1;  // parameter slot of the constant pi/2, once needed
+  auto const_half_pi = [&]() {
+    if (half_pi < 0) {
+      P.constants.push_back(1.57079632679489661923);
+      half_pi = n_params + (int)P.constants.size() - 1;
+    }
+    return half_pi;
+  };
+  // one-qubit record of `kind` on qubit q, parameter slot p
+  auto push1 = [&](int kind, int q, int p) {
+    sv_op o{};
+    o.kind = kind;
+    o.n_targets = 1;
+    o.targets[0] = q;
+    o.param_index[0] = p;
+    recs.push_back(lower_one(o, -1));
+  };
   for (int i = 0; i < n_ops; i++) {
-    if (mode == SV_FUSE_AUTO && ops[i].kind == SV_H && ops[i].n_controls == 0) {
-      // H = RY(pi/2) Z: a diagonal and a rotation, both Kronecker-stage parts
-      if (half_pi < 0) {
-        P.constants.push_back(1.57079632679489661923);
-        half_pi = n_params + (int)P.constants.size() - 1;
+    const sv_op &op = ops[i];
+    if (split1q && mode == SV_FUSE_AUTO && op.n_controls == 0) {
+      // Uncontrolled one-qubit gates written as diagonals, RY rotations and
+      // permutations, all Kronecker-stage parts (listed in the order applied):
+      //   H = RY(pi/2) Z,  RX(t) = S^dag RY(t) S,  Y = S X S^dag,
+      //   U3(t, f, l) = P(f) RY(t) P(l),  U2(f, l) = U3(pi/2, f, l)
+      const int q = op.targets[0];
+      bool split = true;
+      switch (op.kind) {
+        case SV_H: push1(SV_Z, q, 0); push1(SV_RY, q, const_half_pi()); break;
+        case SV_RX: push1(SV_S, q, 0); push1(SV_RY, q, op.param_index[0]); push1(SV_SDG, q, 0); break;
+        case SV_Y: push1(SV_SDG, q, 0); push1(SV_X, q, 0); push1(SV_S, q, 0); break;
+        case SV_U3:
+          push1(SV_P, q, op.param_index[2]);
+          push1(SV_RY, q, op.param_index[0]);
+          push1(SV_P, q, op.param_index[1]);
+          break;
+        case SV_U2:
+          push1(SV_P, q, op.param_index[1]);
+          push1(SV_RY, q, const_half_pi());
+          push1(SV_P, q, op.param_index[0]);
+          break;
+        default: split = false;
       }
-      sv_op z{};
-      z.kind = SV_Z;
-      z.n_targets = 1;
-      z.targets[0] = ops[i].targets[0];
-      recs.push_back(lower_one(z, -1));
-      sv_op ry = z;
-      ry.kind = SV_RY;
-      ry.param_index[0] = half_pi;
-      recs.push_back(lower_one(ry, -1));
-      continue;
+      if (split) continue;
     }
     GateRec g = lower_one(ops[i], ops[i].kind == SV_UNITARY ? um : -1);
     if (ops[i].kind == SV_UNITARY) um++;
@@ -2665,7 +2695,7 @@ extern "C" sv_status sv_batch_plan(const sv_circuit_desc *circuits, int32_t n_ci
     const size_t plane = (((size_t)1 << n) * es + 255) & ~(size_t)255;
     state_bytes += 2 * plane;
     Plan P;
-    s = build_forward_plan(-1, n, dbl, tl, d.ops, d.n_ops, d.n_params, P, false);
+    s = build_forward_plan(-1, n, dbl, tl, d.ops, d.n_ops, d.n_params, P, false, false);
     if (s) return s;
     if (P.M != M || P.R != R) return fail(SV_EINVAL, "internal: plan tiling mismatch");
     for (const Step &st : P.steps) {

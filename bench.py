@@ -475,7 +475,8 @@ def main():
         del s32
         extras.update(sampling_and_exit(st, n, torch))
         # the paper's other circuit families at the same size (Section 9.1)
-        for name, c in (("qft", I.qft(n)), ("ghz", I.ghz(n))):
+        for name, c in (("qft", I.qft(n)), ("ghz", I.ghz(n)),
+                        ("random300", I.random_circuit(n, 300, seed=0))):
             oac = sv.OpArray(c.ops)
             st.reset()
             st.apply(None, c.params, op_array=oac)

@@ -97,3 +97,24 @@ def test_shot_errors(sv):
     vals, e, var, G = st.shot_estimate(1, 0, I.hamiltonian(4, [("I", [0], 1.5)]))
     assert G == 0 and e == 1.5 and var == 0.0
     st.close()
+
+
+def test_counts_no_qubits_and_complex64_estimate(sv):
+    _say("shot counts nq=0, complex64 estimate")
+    n = 12
+    circ = I.layered(n, 4, seed=3)
+    st = sv.State(n)
+    st.apply(circ.ops, circ.params, fuse=-1)
+    c0 = st.sample_counts(4, 777, [])
+    assert c0.shape == (1,) and int(c0[0]) == 777
+    st.close()
+    # complex64 state: the estimate lands within 6 standard deviations of the
+    # exact FP64 energy of the same circuit
+    s32 = sv.State(n, "c64")
+    s32.apply(circ.ops, circ.params, fuse=-1)
+    h = I.tfim(n)
+    vals, e, var, G = s32.shot_estimate(8, 40000, h)
+    _, exact, _ = O.expect(n, O.run_circuit(circ), h)
+    assert G == 2 and var > 0
+    assert abs(e - exact) <= 6 * math.sqrt(var)
+    s32.close()

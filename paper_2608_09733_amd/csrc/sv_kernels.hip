@@ -746,6 +746,33 @@ __device__ __forceinline__ double chain_lds(const double *v, double *w, int len,
 }
 
 // One wave per block of G chunk sums: P[jG + i] <- L, Q[j] <- block total.
+// Chunk sums for 1024-amplitude chunks, one wave per chunk and no LDS: lane l
+// reads amplitudes 128 j + 2 l, +1 of each of the chunk's eight 128-wide
+// slabs (coalesced), adds each pair (tree level 1), combines adjacent blocks
+// across lanes with shuffle-downs by 1..32 (levels 2-7: lane 0 then holds
+// each slab's sum), and lane 0 adds the eight slab sums pairwise (levels
+// 8-10): the same pairwise tree as k_chunk_sums.
+template <typename T>
+__global__ void __launch_bounds__(256) k_chunk_sums_wave(const T *re, const T *im, int64_t K,
+                                                         double *S) {
+  const int lane = threadIdx.x & 63;
+  const int64_t nw = (int64_t)gridDim.x * 4;
+  for (int64_t k = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); k < K; k += nw) {
+    const uint64_t base = (uint64_t)k * 1024 + 2 * lane;
+    double v[8];
+#pragma unroll
+    for (int j = 0; j < 8; j++) {
+      const uint64_t b = base + 128 * j;
+      v[j] = prob_at(re, im, b) + prob_at(re, im, b + 1);
+    }
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1)
+#pragma unroll
+      for (int j = 0; j < 8; j++) v[j] = v[j] + __shfl_down(v[j], d);
+    if (lane == 0) S[k] = ((v[0] + v[1]) + (v[2] + v[3])) + ((v[4] + v[5]) + (v[6] + v[7]));
+  }
+}
+
 __global__ void __launch_bounds__(64) k_prefix_local(const double *S, int G, double *P, double *Q) {
   __shared__ double v[1024], w[1024];
   const int64_t base = (int64_t)blockIdx.x * G;
@@ -1152,8 +1179,15 @@ hipError_t svk_launch_sampling(int dbl, const void *re, const void *im, int n, d
   const int cbits = n < 10 ? n : 10;
   const int64_t K = (1ll << n) >> cbits;
   int grid = (int)(K < 4096 ? K : 4096);
-  if (dbl) hipLaunchKernelGGL(k_chunk_sums<double>, dim3(grid), dim3(256), 0, s, (const double *)re, (const double *)im, cbits, K, S);
-  else hipLaunchKernelGGL(k_chunk_sums<float>, dim3(grid), dim3(256), 0, s, (const float *)re, (const float *)im, cbits, K, S);
+  if (cbits == 10) {
+    const int gw = (int)std::min<int64_t>((K + 3) / 4, 8192);
+    if (dbl) hipLaunchKernelGGL(k_chunk_sums_wave<double>, dim3(gw), dim3(256), 0, s, (const double *)re, (const double *)im, K, S);
+    else hipLaunchKernelGGL(k_chunk_sums_wave<float>, dim3(gw), dim3(256), 0, s, (const float *)re, (const float *)im, K, S);
+  } else if (dbl) {
+    hipLaunchKernelGGL(k_chunk_sums<double>, dim3(grid), dim3(256), 0, s, (const double *)re, (const double *)im, cbits, K, S);
+  } else {
+    hipLaunchKernelGGL(k_chunk_sums<float>, dim3(grid), dim3(256), 0, s, (const float *)re, (const float *)im, cbits, K, S);
+  }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const int G = (int)(K < 1024 ? K : 1024);

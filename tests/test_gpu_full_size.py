@@ -11,7 +11,9 @@ at any size:
 * the circuit followed by its inverse returns |0...0>;
 * two unrelated plans (LDS tile clusters with Kronecker stages, and the
   paper's in-order blocks of up to 5 qubits as dense block sweeps) give the
-  same amplitudes and <Z_i>.
+  same amplitudes and <Z_i>;
+* terminal draws of a basis state all return it, and a grouped shot estimate
+  lands within 6 standard deviations of the exact <H>.
 """
 import math
 
@@ -89,6 +91,27 @@ def test_full_size_basis_state_tracking(sv):
     vals, _ = st.expect(_zs(N))
     want = np.array([-1.0 if (b >> q) & 1 else 1.0 for q in range(N)] + [1.0])
     assert np.max(np.abs(vals - want)) <= TOL
+    # every terminal draw is that basis state (the leaked amplitudes of
+    # RY(pi) are ~1e-16, probabilities ~1e-32)
+    draws = st.sample(3, 4096, list(range(N)))
+    assert np.all(draws == b)
+    qs = [29, 0, 17, 4]
+    counts = st.sample_counts(3, 4096, qs)
+    packed = sum(((b >> q) & 1) << i for i, q in enumerate(qs))
+    assert int(counts[packed]) == 4096 and int(counts.sum()) == 4096
+    st.close()
+
+
+def test_full_size_shot_estimate(sv):
+    _say("full size: grouped shot estimate of TFIM", N, L)
+    circ = I.layered(N, L, seed=0)
+    h = I.tfim(N, 0.7)
+    st = sv.State(N)
+    st.apply(None, circ.params, op_array=sv.OpArray(circ.ops))
+    _, exact = st.expect(h)
+    vals, e, var, G = st.shot_estimate(5, 1 << 18, h)
+    assert G == 2 and var > 0
+    assert abs(e - exact) <= 6 * math.sqrt(var)
     st.close()
 
 

@@ -158,3 +158,31 @@ def test_full_size_two_plans_agree(sv):
         assert np.max(np.abs(ra - rb)) <= TOL and np.max(np.abs(ia - ib)) <= TOL, off
     a.close()
     b.close()
+
+
+def test_adjoint_26q_matches_parameter_shift(sv):
+    # the adjoint extra's workload (26-qubit HEA, 10 layers, TFIM): sampled
+    # gradient components against the parameter-shift rule
+    # dE/dtheta_j = (E(theta_j + pi/2) - E(theta_j - pi/2)) / 2, each energy a
+    # forward pass and <H> on the same handle
+    n = 26
+    _say("full size: 26-qubit adjoint vs parameter shift")
+    circ = I.hea(n, 10, seed=0)
+    h = I.tfim(n, 0.7)
+    oa = sv.OpArray(circ.ops)
+    st = sv.State(n, adjoint=True)
+    st.reset()
+    e, g = st.adjoint_grad(None, circ.params, h, op_array=oa)
+    for j in (0, 1, 2 * n + 7, len(circ.params) // 2 + 3, len(circ.params) - 1):
+        es = []
+        for sgn in (1.0, -1.0):
+            p = circ.params.copy()
+            p[j] += sgn * math.pi / 2
+            st.reset()
+            st.apply(None, p, op_array=oa)
+            es.append(st.expect(h)[1])
+        assert abs((es[0] - es[1]) / 2 - g[j]) <= 1e-10, (j, g[j], es)
+    st.reset()
+    st.apply(None, circ.params, op_array=oa)
+    assert abs(st.expect(h)[1] - e) <= 1e-10
+    st.close()

@@ -378,3 +378,60 @@ def shot_estimate(n: int, psi: np.ndarray, seed: int, shots: int, ham):
     for j in range(len(ham)):
         energy += ham.c[j] * values[j]
     return values, energy, variance, G
+
+
+# ------------------------------------------------------- density matrices
+# rho of n qubits as a dense 2^n x 2^n matrix (Section 4.1 density-matrix
+# state): gates act as U rho U^dagger, channels as sum_k K rho K^dagger, and
+# <P> = Re Tr(rho P).  Written out densely for small n: the full U is built
+# column by column with the state-vector oracle, one-qubit Kraus operators and
+# Pauli strings by Kronecker products (qubit 0 is the least significant bit).
+
+_PAULI = {"I": np.eye(2, dtype=complex), "X": np.array([[0, 1], [1, 0]], dtype=complex),
+          "Y": np.array([[0, -1j], [1j, 0]]), "Z": np.diag([1.0 + 0j, -1.0])}
+
+
+def dm_unitary(n: int, ops: Sequence, params) -> np.ndarray:
+    N = 1 << n
+    U = np.zeros((N, N), dtype=complex)
+    for b in range(N):
+        e = np.zeros(N, dtype=complex)
+        e[b] = 1.0
+        U[:, b] = run(n, ops, params, e)
+    return U
+
+
+def dm_run(n: int, ops: Sequence, params, rho0: Optional[np.ndarray] = None) -> np.ndarray:
+    N = 1 << n
+    if rho0 is None:
+        rho0 = np.zeros((N, N), dtype=complex)
+        rho0[0, 0] = 1.0
+    U = dm_unitary(n, ops, params)
+    return U @ rho0 @ U.conj().T
+
+
+def _embed1(n: int, q: int, m: np.ndarray) -> np.ndarray:
+    return np.kron(np.kron(np.eye(1 << (n - q - 1)), m), np.eye(1 << q))
+
+
+def dm_kraus(n: int, rho: np.ndarray, qubit: int, kraus: Sequence[np.ndarray]) -> np.ndarray:
+    out = np.zeros_like(rho)
+    for K in kraus:
+        Kf = _embed1(n, qubit, np.asarray(K, dtype=complex))
+        out += Kf @ rho @ Kf.conj().T
+    return out
+
+
+def dm_expect(n: int, rho: np.ndarray, ham) -> Tuple[np.ndarray, float]:
+    vals = np.zeros(len(ham))
+    for j in range(len(ham)):
+        x, z = int(ham.x[j]), int(ham.z[j])
+        P = np.eye(1, dtype=complex)
+        for q in range(n - 1, -1, -1):
+            bx, bz = (x >> q) & 1, (z >> q) & 1
+            P = np.kron(P, _PAULI["Y" if bx and bz else "X" if bx else "Z" if bz else "I"])
+        vals[j] = np.trace(rho @ P).real
+    e = 0.0
+    for j in range(len(ham)):
+        e += ham.c[j] * vals[j]
+    return vals, e

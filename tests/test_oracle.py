@@ -440,6 +440,46 @@ def test_shot_estimate_unbiased():
     assert abs(e - ee) < 5 * math.sqrt(var) + 1e-12
 
 
+# ----------------------------------------------------------- density matrix
+
+def _depolarizing(p):
+    s = math.sqrt(p / 3)
+    return [math.sqrt(1 - p) * np.eye(2), s * np.array([[0, 1], [1, 0]]),
+            s * np.array([[0, -1j], [1j, 0]]), s * np.diag([1.0, -1.0])]
+
+
+def test_dm_pure_evolution_is_outer_product():
+    n = 4
+    circ = I.random_circuit(n, 25, seed=4, allow_unitary=True)
+    rho = O.dm_run(n, circ.ops, circ.params)
+    psi = O.run_circuit(circ)
+    assert np.max(np.abs(rho - np.outer(psi, psi.conj()))) < 1e-13
+    h = I.random_hamiltonian(n, 8, seed=2)
+    vals, e = O.dm_expect(n, rho, h)
+    ev, ee, _ = O.expect(n, psi, h)
+    assert np.max(np.abs(vals - ev)) < 1e-13 and abs(e - ee) < 1e-12
+
+
+def test_dm_depolarizing_closed_form():
+    # (1-p) rho + p/3 (X rho X + Y rho Y + Z rho Z) on |0><0| gives <Z> = 1 - 4p/3
+    rho = O.dm_run(1, [], [])
+    p = 0.3
+    r = O.dm_kraus(1, rho, 0, _depolarizing(p))
+    vals, _ = O.dm_expect(1, r, I.hamiltonian(1, [("Z", [0], 1.0), ("X", [0], 1.0), ("I", [0], 1.0)]))
+    assert abs(vals[0] - (1 - 4 * p / 3)) < 1e-15 and abs(vals[1]) < 1e-15 and abs(vals[2] - 1) < 1e-15
+
+
+def test_dm_amplitude_damping_closed_form():
+    # |1><1| under amplitude damping gamma: <Z> = -1 + 2 gamma, <X> stays 0
+    n, q, g = 3, 1, 0.35
+    rho = O.dm_run(n, [I.Op("x", (q,))], [])
+    K = [np.array([[1, 0], [0, math.sqrt(1 - g)]]), np.array([[0, math.sqrt(g)], [0, 0]])]
+    r = O.dm_kraus(n, rho, q, K)
+    vals, _ = O.dm_expect(n, r, I.hamiltonian(n, [("Z", [q], 1.0), ("X", [q], 1.0), ("Z", [0], 1.0)]))
+    assert abs(vals[0] - (-1 + 2 * g)) < 1e-15 and abs(vals[1]) < 1e-15 and abs(vals[2] - 1) < 1e-15
+    assert abs(np.trace(r).real - 1) < 1e-15
+
+
 # --------------------------------------------------------------- fusion
 
 def test_fusion_counts_match_paper_table():

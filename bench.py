@@ -203,6 +203,41 @@ def sampling_and_exit(st, n, torch):
     return out
 
 
+def density_matrix_run(st, n, sv, I, torch):
+    """A density matrix of n/2 qubits on the n-qubit handle (the same 2^n
+    amplitudes as the state-vector workload): 4 layers of the layered circuit,
+    each followed by depolarizing noise (p = 0.01) on every qubit, then <Z_i>."""
+    import numpy as np
+    nd, Ld = n // 2, 4
+    cd = I.layered(nd, Ld, seed=0)
+    per = 3 * nd - 1
+    arrays = [sv.OpArray(cd.ops[l * per:(l + 1) * per]) for l in range(Ld)]
+    p = 0.01
+    s3 = math.sqrt(p / 3)
+    kr = [math.sqrt(1 - p) * np.eye(2), s3 * np.array([[0, 1], [1, 0]]),
+          s3 * np.array([[0, -1j], [1j, 0]]), s3 * np.diag([1.0, -1.0])]
+    zs = I.hamiltonian(nd, [("Z", [q], 1.0) for q in range(nd)])
+
+    def run():
+        st.reset()
+        for oa in arrays:
+            st.dm_apply(None, cd.params, op_array=oa)
+            st.dm_apply_kraus(list(range(nd)), kr)
+        return st.dm_expect(zs)
+    run()
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(3):
+        t0 = time.time()
+        vals, _ = run()
+        ts.append((time.time() - t0) * 1e3)
+    ms = float(np.median(ts))
+    log(f"density matrix {nd}q ({n}-qubit vector), {Ld} noisy layers: {ms:.1f} ms")
+    return {"density_matrix_%dq_%dl_depolarizing" % (nd, Ld): {
+        "ms_median": ms, "qubits": nd, "vector_qubits": n, "layers": Ld,
+        "gates": len(cd.ops), "channels": nd * Ld, "z0": float(vals[0])}}
+
+
 def side_configs(sv, I, torch, serving=True):
     """The other workloads of the method at their own shapes: small-state
     latency (12 qubits), adjoint gradient (20-qubit HEA, TFIM), and the ragged
@@ -319,6 +354,8 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--side-only", action="store_true",
                     help="only the side workloads (12-qubit latency, adjoint, batch), no serving")
+    ap.add_argument("--dm-only", action="store_true",
+                    help="only the density-matrix workload on the --n qubit handle")
     ap.add_argument("--sample-only", action="store_true",
                     help="only sampling and the exit copy on the resident --n qubit state")
     ap.add_argument("--copy-probe", action="store_true",
@@ -353,6 +390,11 @@ def main():
         from paper_2608_09733_amd import inputs as I
         from paper_2608_09733_amd import sv
         print(json.dumps(side_configs(sv, I, torch, serving=False)), flush=True)
+        return
+    if args.dm_only:
+        st = sv.State(args.n, "c128")
+        print(json.dumps(density_matrix_run(st, args.n, sv, I, torch)), flush=True)
+        st.close()
         return
     if args.sample_only:
         circ = I.layered(args.n, args.layers, seed=0)
@@ -474,6 +516,7 @@ def main():
         s32.close()
         del s32
         extras.update(sampling_and_exit(st, n, torch))
+        extras.update(density_matrix_run(st, n, sv, I, torch))
         # the paper's other circuit families at the same size (Section 9.1)
         for name, c in (("qft", I.qft(n)), ("ghz", I.ghz(n)),
                         ("random300", I.random_circuit(n, 300, seed=0))):

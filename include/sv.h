@@ -206,6 +206,32 @@ sv_status sv_shot_estimate(sv_state *st, uint64_t seed, int64_t shots, const sv_
                            int32_t n_terms, double *values, double *energy, double *variance,
                            int32_t *n_groups);
 
+/* ---------------------------------------------------- density matrices
+ * (paper Section 4.1 density-matrix state; Section 5.3 runs rho as a vector
+ * of twice the qubits.)  A handle of 2n qubits holds rho of n qubits as
+ * vec(rho): rho_{rc} at index r 2^n + c, row bits on qubits n..2n-1.
+ * sv_reset gives |0><0|.  Each call waits like the state-vector call it
+ * builds on; errors as there, plus SV_EINVAL when the handle does not hold
+ * 2n qubits. */
+
+/* rho <- U rho U^dagger for the circuit (same op model and parameters as
+ * sv_apply_layer): applied as U on the row qubits and conj(U) on the column
+ * qubits (conjugated angles take negated copies of the parameters). */
+sv_status sv_dm_apply(sv_state *st, int32_t n, const sv_op *ops, int32_t n_ops,
+                      const double *params, int32_t n_params);
+
+/* rho <- sum_k K_k rho K_k^dagger on each of the n_qubits distinct qubits
+ * (one channel per qubit, all applied in one plan); kraus holds n_kraus HOST
+ * 2x2 matrices, row-major, interleaved (re, im) complex128.  Trace
+ * preservation (sum_k K_k^dagger K_k = I) is the caller's. */
+sv_status sv_dm_apply_kraus(sv_state *st, int32_t n, const int32_t *qubits, int32_t n_qubits,
+                            const double *kraus, int32_t n_kraus);
+
+/* out_terms[j] = Tr(rho P_j) (real part), *out_sum = sum_j c_j Tr(rho P_j),
+ * summed in fixed orders. */
+sv_status sv_dm_expect_pauli(sv_state *st, int32_t n, const sv_pauli_term *terms, int32_t n_terms,
+                             double *out_terms, double *out_sum);
+
 /* Copy amplitudes [offset, offset+count) of both planes to HOST buffers of
  * the state's element type (the paper's explicit to_numpy exit).  Waits. */
 sv_status sv_copy_to_host(const sv_state *st, void *re, void *im, uint64_t offset,

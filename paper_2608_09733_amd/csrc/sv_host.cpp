@@ -2064,6 +2064,176 @@ extern "C" sv_status sv_expect_pauli(sv_state *st, const sv_pauli_term *terms, i
   return SV_OK;
 }
 
+// -------------------------------------------------------- density matrices
+// rho of n qubits is held as a vector of 2n qubits, rho_{rc} at r 2^n + c (row
+// bits are qubits n..2n-1).  U rho U^dagger = (U (x) conj U) vec rho: U on the
+// row qubits, conj(U) on the column qubits; a channel sum_k K rho K^dagger is
+// the 4x4 matrix sum_k K (x) conj K on (column qubit, row qubit).
+
+static sv_status dm_check(const sv_state *st, int n) {
+  if (!st) return fail(SV_EINVAL, "null handle");
+  if (n < 1 || 2 * n != st->n)
+    return fail(SV_EINVAL, "a density matrix of %d qubits needs a handle of %d qubits (got %d)", n,
+                2 * n, st->n);
+  return SV_OK;
+}
+
+extern "C" sv_status sv_dm_apply(sv_state *st, int32_t n, const sv_op *ops, int32_t n_ops,
+                                 const double *params, int32_t n_params) {
+  sv_status s = dm_check(st, n);
+  if (s) return s;
+  s = validate_circuit(n, ops, n_ops, params, n_params);
+  if (s) return s;
+  if (n_ops == 0) return SV_OK;
+  // parameters, then their negations (angles of the conjugated gates)
+  std::vector<double> p2(2 * (size_t)n_params);
+  for (int i = 0; i < n_params; i++) {
+    p2[i] = params[i];
+    p2[n_params + i] = -params[i];
+  }
+  std::vector<std::vector<double>> mats;  // conjugated matrices, alive until the call returns
+  mats.reserve(n_ops);
+  std::vector<sv_op> out;
+  out.reserve(2 * (size_t)n_ops);
+  for (int i = 0; i < n_ops; i++) {
+    const sv_op &op = ops[i];
+    sv_op row = op;
+    for (int k = 0; k < op.n_targets; k++) row.targets[k] += n;
+    for (int k = 0; k < op.n_controls; k++) row.controls[k] += n;
+    out.push_back(row);
+    sv_op col = op;
+    switch (op.kind) {
+      case SV_S: col.kind = SV_SDG; break;
+      case SV_SDG: col.kind = SV_S; break;
+      case SV_T: col.kind = SV_TDG; break;
+      case SV_TDG: col.kind = SV_T; break;
+      case SV_RX: case SV_RZ: case SV_P: case SV_RXX: case SV_RYY: case SV_RZZ:
+        col.param_index[0] += n_params;   // conj exp(-i t P / 2) = exp(+i t P / 2) for real P
+        break;
+      case SV_U2:
+        col.param_index[0] += n_params;
+        col.param_index[1] += n_params;
+        break;
+      case SV_U3:                          // conj U3(t, f, l) = U3(t, -f, -l)
+        col.param_index[1] += n_params;
+        col.param_index[2] += n_params;
+        break;
+      case SV_Y: case SV_SX: case SV_UNITARY: {
+        const int d = 1 << op.n_targets;
+        std::vector<double> m(2 * (size_t)d * d);
+        if (op.kind == SV_Y) m = {0, 0, 0, 1, 0, -1, 0, 0};                 // [[0, i], [-i, 0]]
+        else if (op.kind == SV_SX) m = {0.5, -0.5, 0.5, 0.5, 0.5, 0.5, 0.5, -0.5};
+        else
+          for (int e = 0; e < d * d; e++) {
+            m[2 * e] = op.matrix[2 * e];
+            m[2 * e + 1] = -op.matrix[2 * e + 1];
+          }
+        mats.push_back(std::move(m));
+        col.kind = SV_UNITARY;
+        col.matrix = mats.back().data();
+        break;
+      }
+      default: break;                      // real matrices: X, Z, H, RY, SWAP, GIVENS, DEXC, I
+    }
+    out.push_back(col);
+  }
+  return sv_apply_layer(st, out.data(), (int32_t)out.size(), p2.empty() ? nullptr : p2.data(),
+                        2 * n_params, SV_FUSE_AUTO);
+}
+
+extern "C" sv_status sv_dm_apply_kraus(sv_state *st, int32_t n, const int32_t *qubits,
+                                       int32_t n_qubits, const double *kraus, int32_t n_kraus) {
+  sv_status s = dm_check(st, n);
+  if (s) return s;
+  if (n_qubits < 0 || (n_qubits > 0 && !qubits)) return fail(SV_EINVAL, "bad qubit list");
+  uint64_t seen = 0;
+  for (int i = 0; i < n_qubits; i++) {
+    if (qubits[i] < 0 || qubits[i] >= n) return fail(SV_EINVAL, "qubit %d out of range [0,%d)", qubits[i], n);
+    if (seen >> qubits[i] & 1) return fail(SV_EINVAL, "qubit %d repeated", qubits[i]);
+    seen |= 1ull << qubits[i];
+  }
+  if (n_kraus < 1 || !kraus) return fail(SV_EINVAL, "no Kraus operators");
+  for (int i = 0; i < 8 * n_kraus; i++)
+    if (!std::isfinite(kraus[i])) return fail(SV_EINVAL, "non-finite Kraus entry");
+  // local index l = c + 2 r (first target: the column qubit)
+  double m[32] = {0};
+  for (int k = 0; k < n_kraus; k++) {
+    const double *K = kraus + 8 * k;
+    for (int r1 = 0; r1 < 2; r1++)
+      for (int c1 = 0; c1 < 2; c1++)
+        for (int r0 = 0; r0 < 2; r0++)
+          for (int c0 = 0; c0 < 2; c0++) {
+            // K[r1][r0] * conj(K[c1][c0])
+            const double ar = K[2 * (2 * r1 + r0)], ai = K[2 * (2 * r1 + r0) + 1];
+            const double br = K[2 * (2 * c1 + c0)], bi = -K[2 * (2 * c1 + c0) + 1];
+            const int row = c1 + 2 * r1, colx = c0 + 2 * r0;
+            m[2 * (4 * row + colx)] += ar * br - ai * bi;
+            m[2 * (4 * row + colx) + 1] += ar * bi + ai * br;
+          }
+  }
+  // one superoperator per qubit, all in one plan (channels on different
+  // qubits commute)
+  std::vector<sv_op> ops(n_qubits);
+  for (int i = 0; i < n_qubits; i++) {
+    sv_op o{};
+    o.kind = SV_UNITARY;
+    o.n_targets = 2;
+    o.targets[0] = qubits[i];
+    o.targets[1] = qubits[i] + n;
+    o.matrix = m;
+    ops[i] = o;
+  }
+  if (ops.empty()) return SV_OK;
+  return sv_apply_layer(st, ops.data(), n_qubits, nullptr, 0, SV_FUSE_AUTO);
+}
+
+extern "C" sv_status sv_dm_expect_pauli(sv_state *st, int32_t n, const sv_pauli_term *terms,
+                                        int32_t n_terms, double *out_terms, double *out_sum) {
+  sv_status s = dm_check(st, n);
+  if (s) return s;
+  s = validate_terms(n, terms, n_terms);
+  if (s) return s;
+  if (n_terms == 0) {
+    if (out_sum) *out_sum = 0.0;
+    return SV_OK;
+  }
+  s = materialize_zero(st);
+  if (s) return s;
+  const int nb = (int)std::min<int64_t>(std::max<int64_t>(1, ((int64_t)1 << n) / 256), 1024);
+  const size_t tb = ((size_t)n_terms * sizeof(PauliTermDev) + 255) & ~(size_t)255;
+  const size_t pb = ((size_t)n_terms * nb * 8 + 255) & ~(size_t)255;
+  s = ensure_scratch(st, tb + pb + (size_t)n_terms * 8 + 256);
+  if (s) return s;
+  PauliTermDev *d_terms = (PauliTermDev *)st->scratch;
+  double *d_part = (double *)((char *)st->scratch + tb);
+  double *d_out = (double *)((char *)st->scratch + tb + pb);
+  std::vector<PauliTermDev> td(n_terms);
+  for (int j = 0; j < n_terms; j++) {
+    td[j] = PauliTermDev{};
+    td[j].x = terms[j].x_mask;
+    td[j].z = terms[j].z_mask;
+    td[j].c = terms[j].coeff;
+    td[j].term = j;
+  }
+  HIPCHK(hipMemcpyAsync(d_terms, td.data(), td.size() * sizeof(PauliTermDev), hipMemcpyHostToDevice,
+                        st->stream));
+  hipError_t e = svk_launch_dm_pauli(st->dtype == SV_C128, st->re, st->im, n, d_terms, n_terms, nb,
+                                     d_part, st->stream);
+  if (e == hipSuccess) e = svk_launch_reduce_rows(d_part, n_terms, nb, d_out, st->stream);
+  if (e != hipSuccess) return fail(SV_EDEVICE, "density-matrix trace: %s", hipGetErrorString(e));
+  std::vector<double> vals(n_terms);
+  HIPCHK(hipMemcpyAsync(vals.data(), d_out, (size_t)n_terms * 8, hipMemcpyDeviceToHost, st->stream));
+  HIPCHK(hipStreamSynchronize(st->stream));
+  if (out_terms)
+    for (int j = 0; j < n_terms; j++) out_terms[j] = vals[j];
+  if (out_sum) {
+    double acc = 0.0;
+    for (int j = 0; j < n_terms; j++) acc += terms[j].coeff * vals[j];
+    *out_sum = acc;
+  }
+  return SV_OK;
+}
+
 // ----------------------------------------------------------------- adjoint
 
 static sv_status adjoint_enqueue(sv_state *st, const sv_op *ops, int n_ops, const double *params,

@@ -654,6 +654,32 @@ __global__ void __launch_bounds__(256) k_pauli_wide(const T *re, const T *im, T 
   if (threadIdx.x == 0) part[blockIdx.x] = ws[0] + ws[1] + ws[2] + ws[3];
 }
 
+// Tr(rho P) partial sums for a density matrix held as a 2n-qubit vector
+// (rho_{rc} at index r 2^n + c): term t = blockIdx.y, rows r strided over the
+// x-blocks; value = Re(i^nY (-1)^{|r & z|} rho_{r, r ^ x}).  Each block writes
+// one partial, summed in a fixed order afterwards.
+template <typename T>
+__global__ void __launch_bounds__(256) k_dm_pauli(const T *re, const T *im, int n,
+                                                  const PauliTermDev *terms, double *part) {
+  __shared__ double ws[4];
+  const PauliTermDev tm = terms[blockIdx.y];
+  const int ny = __popcll(tm.x & tm.z) & 3;
+  const int64_t R = 1ll << n;
+  double acc = 0.0;
+  for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < R;
+       r += (int64_t)gridDim.x * blockDim.x) {
+    const uint64_t idx = ((uint64_t)r << n) | ((uint64_t)r ^ tm.x);
+    const double a = (double)re[idx], b = (double)im[idx];
+    double v = ny == 0 ? a : ny == 1 ? -b : ny == 2 ? -a : b;
+    if (__popcll((uint64_t)r & tm.z) & 1) v = -v;
+    acc += v;
+  }
+  acc = wave_sum(acc);
+  if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) part[(int64_t)blockIdx.y * gridDim.x + blockIdx.x] = (ws[0] + ws[1]) + (ws[2] + ws[3]);
+}
+
 // Sum each slot's partials in a fixed order: out[s] = sum_w part[s * np + w].
 __global__ void k_reduce_rows(const double *part, int nslots, int np, double *out) {
   for (int s = blockIdx.x * blockDim.x + threadIdx.x; s < nslots; s += gridDim.x * blockDim.x) {
@@ -1123,6 +1149,14 @@ int svk_pauli_occupancy(int dbl) {
   hipError_t e = dbl ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_pauli<double, 13>, SVI_PAULI_NT, 0)
                      : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_pauli<float, 13>, SVI_PAULI_NT, 0);
   return (e == hipSuccess && nb > 0) ? nb : 1;
+}
+
+hipError_t svk_launch_dm_pauli(int dbl, const void *re, const void *im, int n,
+                               const PauliTermDev *terms, int nt, int nb, double *part,
+                               hipStream_t s) {
+  if (dbl) hipLaunchKernelGGL(k_dm_pauli<double>, dim3(nb, nt), dim3(256), 0, s, (const double *)re, (const double *)im, n, terms, part);
+  else hipLaunchKernelGGL(k_dm_pauli<float>, dim3(nb, nt), dim3(256), 0, s, (const float *)re, (const float *)im, n, terms, part);
+  return hipGetLastError();
 }
 
 hipError_t svk_launch_reduce_rows(const double *part, int nslots, int np, double *out,

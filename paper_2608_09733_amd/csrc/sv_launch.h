@@ -36,6 +36,10 @@ hipError_t svk_launch_pauli_wide(int dbl, const void *re, const void *im, void *
                                  double *part, int grid, hipStream_t s);
 hipError_t svk_launch_reduce_rows(const double *part, int nslots, int np, double *out,
                                   hipStream_t s);
+// part[t * nb + b] <- block b's partial of Tr(rho P_t), rho of n qubits as a 2n-qubit vector
+hipError_t svk_launch_dm_pauli(int dbl, const void *re, const void *im, int n,
+                               const PauliTermDev *terms, int nt, int nb, double *part,
+                               hipStream_t s);
 hipError_t svk_launch_gather_grad(const double *slot_sum, const int32_t *row_ptr,
                                   const int32_t *slots, int np, double *grad, hipStream_t s);
 hipError_t svk_launch_zexp(int dbl, const void *re, const void *im, int n, const PauliTermDev *terms,

@@ -74,6 +74,9 @@ def lib():
         "sv_sample": (C.c_int, [vp, u64, i64, C.POINTER(i32), i32, u64p]),
         "sv_sample_counts": (C.c_int, [vp, u64, i64, C.POINTER(i32), i32, u64p]),
         "sv_shot_estimate": (C.c_int, [vp, u64, i64, tp, i32, dp, dp, dp, C.POINTER(i32)]),
+        "sv_dm_apply": (C.c_int, [vp, i32, opp, i32, dp, i32]),
+        "sv_dm_apply_kraus": (C.c_int, [vp, i32, C.POINTER(i32), i32, dp, i32]),
+        "sv_dm_expect_pauli": (C.c_int, [vp, i32, tp, i32, dp, dp]),
         "sv_copy_to_host": (C.c_int, [vp, vp, vp, u64, u64]),
         "sv_copy_from_host": (C.c_int, [vp, vp, vp, u64, u64]),
         "sv_last_error": (C.c_char_p, []),
@@ -311,6 +314,30 @@ class State:
                                       vals.ctypes.data_as(C.POINTER(C.c_double)), C.byref(e),
                                       C.byref(v), C.byref(g)))
         return vals[:ta.n], float(e.value), float(v.value), int(g.value)
+
+    # ---- density matrix of n = self.n / 2 qubits held as vec(rho)
+    def dm_apply(self, ops, params, op_array: Optional[OpArray] = None):
+        oa = op_array or OpArray(ops)
+        p, npar = _params_ptr(params)
+        _check(lib().sv_dm_apply(self.h, self.n // 2, oa.ptr(), oa.n,
+                                 p.ctypes.data_as(C.POINTER(C.c_double)), npar))
+
+    def dm_apply_kraus(self, qubits, kraus: Sequence[np.ndarray]):
+        """One channel (the same Kraus set) on each qubit of `qubits` (an int or a sequence)."""
+        q = np.ascontiguousarray(np.atleast_1d(np.asarray(qubits, dtype=np.int32)))
+        k = np.ascontiguousarray(np.asarray(kraus, dtype=np.complex128).reshape(-1, 2, 2))
+        buf = np.ascontiguousarray(k.view(np.float64).reshape(-1))
+        _check(lib().sv_dm_apply_kraus(self.h, self.n // 2, q.ctypes.data_as(C.POINTER(C.c_int32)),
+                                       int(q.size), buf.ctypes.data_as(C.POINTER(C.c_double)),
+                                       int(k.shape[0])))
+
+    def dm_expect(self, ham) -> Tuple[np.ndarray, float]:
+        ta = TermArray(ham)
+        out = np.zeros(max(1, ta.n))
+        tot = C.c_double(0.0)
+        _check(lib().sv_dm_expect_pauli(self.h, self.n // 2, ta.ptr(), ta.n,
+                                        out.ctypes.data_as(C.POINTER(C.c_double)), C.byref(tot)))
+        return out[:ta.n], float(tot.value)
 
     def planes(self, offset: int = 0, count: Optional[int] = None,
                out: Optional[Tuple[np.ndarray, np.ndarray]] = None) -> Tuple[np.ndarray, np.ndarray]:

@@ -2171,20 +2171,17 @@ extern "C" sv_status sv_dm_apply_kraus(sv_state *st, int32_t n, const int32_t *q
             m[2 * (4 * row + colx) + 1] += ar * bi + ai * br;
           }
   }
-  // one superoperator per qubit, all in one plan (channels on different
-  // qubits commute)
-  std::vector<sv_op> ops(n_qubits);
+  // one streaming pass per qubit (channels on different qubits commute)
+  if (n_qubits == 0) return SV_OK;
+  s = materialize_zero(st);
+  if (s) return s;
   for (int i = 0; i < n_qubits; i++) {
-    sv_op o{};
-    o.kind = SV_UNITARY;
-    o.n_targets = 2;
-    o.targets[0] = qubits[i];
-    o.targets[1] = qubits[i] + n;
-    o.matrix = m;
-    ops[i] = o;
+    hipError_t e = svk_launch_dm_channel(st->dtype == SV_C128, st->re, st->im, st->n, qubits[i],
+                                         qubits[i] + n, m, st->stream);
+    if (e != hipSuccess) return fail(SV_EDEVICE, "channel kernel: %s", hipGetErrorString(e));
   }
-  if (ops.empty()) return SV_OK;
-  return sv_apply_layer(st, ops.data(), n_qubits, nullptr, 0, SV_FUSE_AUTO);
+  HIPCHK(hipStreamSynchronize(st->stream));
+  return SV_OK;
 }
 
 extern "C" sv_status sv_dm_expect_pauli(sv_state *st, int32_t n, const sv_pauli_term *terms,

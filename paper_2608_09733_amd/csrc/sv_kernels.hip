@@ -680,6 +680,49 @@ __global__ void __launch_bounds__(256) k_dm_pauli(const T *re, const T *im, int 
   if (threadIdx.x == 0) part[(int64_t)blockIdx.y * gridDim.x + blockIdx.x] = (ws[0] + ws[1]) + (ws[2] + ws[3]);
 }
 
+// One-qubit channel on a density matrix held as a vector: the 4x4 complex
+// superoperator S (row-major, local index l = c + 2 r for column bit qc and
+// row bit qr, qc < qr) acts on the four entries of each group; one read and
+// one write of the vector.
+struct ChannelArgs {
+  void *re, *im;
+  int64_t groups;     // 2^(N - 2)
+  int qc, qr;
+  double s[32];       // interleaved (re, im)
+};
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_dm_channel(ChannelArgs a) {
+  T *re = (T *)a.re, *im = (T *)a.im;
+  for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < a.groups;
+       g += (int64_t)gridDim.x * blockDim.x) {
+    // insert zero bits at qc, then at qr
+    uint64_t b = (uint64_t)g;
+    b = ((b >> a.qc) << (a.qc + 1)) | (b & ((1ull << a.qc) - 1));
+    b = ((b >> a.qr) << (a.qr + 1)) | (b & ((1ull << a.qr) - 1));
+    uint64_t idx[4];
+    double xr[4], xi[4];
+#pragma unroll
+    for (int l = 0; l < 4; l++) {
+      idx[l] = b | ((uint64_t)(l & 1) << a.qc) | ((uint64_t)(l >> 1) << a.qr);
+      xr[l] = (double)re[idx[l]];
+      xi[l] = (double)im[idx[l]];
+    }
+#pragma unroll
+    for (int o = 0; o < 4; o++) {
+      double yr = 0.0, yi = 0.0;
+#pragma unroll
+      for (int l = 0; l < 4; l++) {
+        const double sr = a.s[2 * (4 * o + l)], si = a.s[2 * (4 * o + l) + 1];
+        yr += sr * xr[l] - si * xi[l];
+        yi += sr * xi[l] + si * xr[l];
+      }
+      re[idx[o]] = (T)yr;
+      im[idx[o]] = (T)yi;
+    }
+  }
+}
+
 // Sum each slot's partials in a fixed order: out[s] = sum_w part[s * np + w].
 __global__ void k_reduce_rows(const double *part, int nslots, int np, double *out) {
   for (int s = blockIdx.x * blockDim.x + threadIdx.x; s < nslots; s += gridDim.x * blockDim.x) {
@@ -1149,6 +1192,19 @@ int svk_pauli_occupancy(int dbl) {
   hipError_t e = dbl ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_pauli<double, 13>, SVI_PAULI_NT, 0)
                      : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_pauli<float, 13>, SVI_PAULI_NT, 0);
   return (e == hipSuccess && nb > 0) ? nb : 1;
+}
+
+hipError_t svk_launch_dm_channel(int dbl, void *re, void *im, int nq, int qc, int qr,
+                                 const double *s32, hipStream_t s) {
+  ChannelArgs a;
+  a.re = re; a.im = im;
+  a.groups = 1ll << (nq - 2);
+  a.qc = qc; a.qr = qr;
+  for (int i = 0; i < 32; i++) a.s[i] = s32[i];
+  const int grid = (int)std::min<int64_t>((a.groups + 255) / 256, 16384);
+  if (dbl) hipLaunchKernelGGL(k_dm_channel<double>, dim3(grid), dim3(256), 0, s, a);
+  else hipLaunchKernelGGL(k_dm_channel<float>, dim3(grid), dim3(256), 0, s, a);
+  return hipGetLastError();
 }
 
 hipError_t svk_launch_dm_pauli(int dbl, const void *re, const void *im, int n,

@@ -36,6 +36,10 @@ hipError_t svk_launch_pauli_wide(int dbl, const void *re, const void *im, void *
                                  double *part, int grid, hipStream_t s);
 hipError_t svk_launch_reduce_rows(const double *part, int nslots, int np, double *out,
                                   hipStream_t s);
+// one-qubit channel: 4x4 superoperator s32 (row-major, interleaved, local index
+// c + 2 r) on column bit qc < row bit qr of an nq-qubit vector
+hipError_t svk_launch_dm_channel(int dbl, void *re, void *im, int nq, int qc, int qr,
+                                 const double *s32, hipStream_t s);
 // part[t * nb + b] <- block b's partial of Tr(rho P_t), rho of n qubits as a 2n-qubit vector
 hipError_t svk_launch_dm_pauli(int dbl, const void *re, const void *im, int n,
                                const PauliTermDev *terms, int nt, int nb, double *part,

@@ -2175,9 +2175,13 @@ extern "C" sv_status sv_dm_apply_kraus(sv_state *st, int32_t n, const int32_t *q
   if (n_qubits == 0) return SV_OK;
   s = materialize_zero(st);
   if (s) return s;
-  for (int i = 0; i < n_qubits; i++) {
-    hipError_t e = svk_launch_dm_channel(st->dtype == SV_C128, st->re, st->im, st->n, qubits[i],
-                                         qubits[i] + n, m, st->stream);
+  // two channels per pass where possible
+  for (int i = 0; i < n_qubits; i += 2) {
+    hipError_t e = i + 1 < n_qubits
+        ? svk_launch_dm_channel2(st->dtype == SV_C128, st->re, st->im, st->n, qubits[i],
+                                 qubits[i + 1], n, m, m, st->stream)
+        : svk_launch_dm_channel(st->dtype == SV_C128, st->re, st->im, st->n, qubits[i],
+                                qubits[i] + n, m, st->stream);
     if (e != hipSuccess) return fail(SV_EDEVICE, "channel kernel: %s", hipGetErrorString(e));
   }
   HIPCHK(hipStreamSynchronize(st->stream));

@@ -723,6 +723,76 @@ __global__ void __launch_bounds__(256) k_dm_channel(ChannelArgs a) {
   }
 }
 
+// Two one-qubit channels in one pass: qubits a and b (column bits qa, qb,
+// row bits qa + off, qb + off); each thread takes the 16 entries those four
+// bits span, applies S_a to each group of four that differs only in a's bits,
+// then S_b likewise, and writes once.
+struct Channel2Args {
+  void *re, *im;
+  int64_t groups;     // 2^(N - 4)
+  int qa, qb, off;
+  int pos[4];         // the four bit positions, ascending
+  double sa[32], sb[32];
+};
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_dm_channel2(Channel2Args a) {
+  T *re = (T *)a.re, *im = (T *)a.im;
+  for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < a.groups;
+       g += (int64_t)gridDim.x * blockDim.x) {
+    uint64_t b = (uint64_t)g;
+#pragma unroll
+    for (int k = 0; k < 4; k++) b = ((b >> a.pos[k]) << (a.pos[k] + 1)) | (b & ((1ull << a.pos[k]) - 1));
+    // entry e: bit 0 = a column, 1 = a row, 2 = b column, 3 = b row
+    uint64_t idx[16];
+    double xr[16], xi[16];
+#pragma unroll
+    for (int e = 0; e < 16; e++) {
+      idx[e] = b | ((uint64_t)(e & 1) << a.qa) | ((uint64_t)((e >> 1) & 1) << (a.qa + a.off)) |
+               ((uint64_t)((e >> 2) & 1) << a.qb) | ((uint64_t)((e >> 3) & 1) << (a.qb + a.off));
+      xr[e] = (double)re[idx[e]];
+      xi[e] = (double)im[idx[e]];
+    }
+#pragma unroll
+    for (int hi = 0; hi < 4; hi++) {        // S_a on entries hi * 4 + la
+      double yr[4], yi[4];
+#pragma unroll
+      for (int o = 0; o < 4; o++) {
+        yr[o] = 0.0; yi[o] = 0.0;
+#pragma unroll
+        for (int l = 0; l < 4; l++) {
+          const double sr = a.sa[2 * (4 * o + l)], si = a.sa[2 * (4 * o + l) + 1];
+          yr[o] += sr * xr[4 * hi + l] - si * xi[4 * hi + l];
+          yi[o] += sr * xi[4 * hi + l] + si * xr[4 * hi + l];
+        }
+      }
+#pragma unroll
+      for (int o = 0; o < 4; o++) { xr[4 * hi + o] = yr[o]; xi[4 * hi + o] = yi[o]; }
+    }
+#pragma unroll
+    for (int lo = 0; lo < 4; lo++) {        // S_b on entries lb * 4 + lo
+      double yr[4], yi[4];
+#pragma unroll
+      for (int o = 0; o < 4; o++) {
+        yr[o] = 0.0; yi[o] = 0.0;
+#pragma unroll
+        for (int l = 0; l < 4; l++) {
+          const double sr = a.sb[2 * (4 * o + l)], si = a.sb[2 * (4 * o + l) + 1];
+          yr[o] += sr * xr[4 * l + lo] - si * xi[4 * l + lo];
+          yi[o] += sr * xi[4 * l + lo] + si * xr[4 * l + lo];
+        }
+      }
+#pragma unroll
+      for (int o = 0; o < 4; o++) { xr[4 * o + lo] = yr[o]; xi[4 * o + lo] = yi[o]; }
+    }
+#pragma unroll
+    for (int e = 0; e < 16; e++) {
+      re[idx[e]] = (T)xr[e];
+      im[idx[e]] = (T)xi[e];
+    }
+  }
+}
+
 // Sum each slot's partials in a fixed order: out[s] = sum_w part[s * np + w].
 __global__ void k_reduce_rows(const double *part, int nslots, int np, double *out) {
   for (int s = blockIdx.x * blockDim.x + threadIdx.x; s < nslots; s += gridDim.x * blockDim.x) {
@@ -1204,6 +1274,22 @@ hipError_t svk_launch_dm_channel(int dbl, void *re, void *im, int nq, int qc, in
   const int grid = (int)std::min<int64_t>((a.groups + 255) / 256, 16384);
   if (dbl) hipLaunchKernelGGL(k_dm_channel<double>, dim3(grid), dim3(256), 0, s, a);
   else hipLaunchKernelGGL(k_dm_channel<float>, dim3(grid), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t svk_launch_dm_channel2(int dbl, void *re, void *im, int nq, int qa, int qb, int off,
+                                  const double *sa, const double *sb, hipStream_t s) {
+  Channel2Args a;
+  a.re = re; a.im = im;
+  a.groups = 1ll << (nq - 4);
+  a.qa = qa; a.qb = qb; a.off = off;
+  int p[4] = {qa, qb, qa + off, qb + off};
+  std::sort(p, p + 4);
+  for (int k = 0; k < 4; k++) a.pos[k] = p[k];
+  for (int i = 0; i < 32; i++) { a.sa[i] = sa[i]; a.sb[i] = sb[i]; }
+  const int grid = (int)std::min<int64_t>((a.groups + 255) / 256, 16384);
+  if (dbl) hipLaunchKernelGGL(k_dm_channel2<double>, dim3(grid), dim3(256), 0, s, a);
+  else hipLaunchKernelGGL(k_dm_channel2<float>, dim3(grid), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 

@@ -40,6 +40,9 @@ hipError_t svk_launch_reduce_rows(const double *part, int nslots, int np, double
 // c + 2 r) on column bit qc < row bit qr of an nq-qubit vector
 hipError_t svk_launch_dm_channel(int dbl, void *re, void *im, int nq, int qc, int qr,
                                  const double *s32, hipStream_t s);
+// two one-qubit channels (same layout) on qubits qa != qb, row bits at + off
+hipError_t svk_launch_dm_channel2(int dbl, void *re, void *im, int nq, int qa, int qb, int off,
+                                  const double *sa, const double *sb, hipStream_t s);
 // part[t * nb + b] <- block b's partial of Tr(rho P_t), rho of n qubits as a 2n-qubit vector
 hipError_t svk_launch_dm_pauli(int dbl, const void *re, const void *im, int n,
                                const PauliTermDev *terms, int nt, int nb, double *part,

@@ -435,3 +435,22 @@ def dm_expect(n: int, rho: np.ndarray, ham) -> Tuple[np.ndarray, float]:
     for j in range(len(ham)):
         e += ham.c[j] * vals[j]
     return vals, e
+
+
+def dm_kraus2(n: int, rho: np.ndarray, q0: int, q1: int, kraus: Sequence[np.ndarray]) -> np.ndarray:
+    """sum_k K rho K^dagger for 4x4 Kraus operators on (q0, q1), local index
+    bit(q0) + 2 bit(q1); each K is embedded column by column through the
+    oracle's own user-matrix gate."""
+    N = 1 << n
+    out = np.zeros_like(rho)
+    for K in kraus:
+        g = _Gate("unitary", q0)
+        g.targets = (q0, q1)
+        g.matrix = np.asarray(K, dtype=complex)
+        Kf = np.zeros((N, N), dtype=complex)
+        for b in range(N):
+            e = np.zeros(N, dtype=complex)
+            e[b] = 1.0
+            Kf[:, b] = run(n, [g], [], e)
+        out += Kf @ rho @ Kf.conj().T
+    return out

@@ -480,6 +480,27 @@ def test_dm_amplitude_damping_closed_form():
     assert abs(np.trace(r).real - 1) < 1e-15
 
 
+def test_dm_two_qubit_depolarizing_closed_form():
+    # two-qubit depolarizing: (1-p) rho + p/15 sum over the 15 non-identity
+    # Pauli pairs; on |00><00| it leaves <Z0> = <Z1> = <Z0 Z1> = 1 - 16p/15
+    P = [np.eye(2), np.array([[0, 1], [1, 0]]), np.array([[0, -1j], [1j, 0]]), np.diag([1.0, -1.0])]
+    p = 0.27
+    K = [math.sqrt(1 - p) * np.eye(4)]
+    for a in range(4):
+        for b in range(4):
+            if a or b:
+                K.append(math.sqrt(p / 15) * np.kron(P[b], P[a]))   # local index bit(q0) + 2 bit(q1)
+    n = 3
+    rho = O.dm_run(n, [], [])
+    r = O.dm_kraus2(n, rho, 2, 0, K)
+    h = I.hamiltonian(n, [("Z", [2], 1.0), ("Z", [0], 1.0), ("ZZ", [0, 2], 1.0), ("X", [2], 1.0),
+                          ("Z", [1], 1.0)])
+    vals, _ = O.dm_expect(n, r, h)
+    want = [1 - 16 * p / 15] * 3 + [0.0, 1.0]
+    assert np.max(np.abs(vals - want)) < 1e-14
+    assert abs(np.trace(r).real - 1) < 1e-14
+
+
 # --------------------------------------------------------------- fusion
 
 def test_fusion_counts_match_paper_table():

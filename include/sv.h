@@ -227,6 +227,12 @@ sv_status sv_dm_apply(sv_state *st, int32_t n, const sv_op *ops, int32_t n_ops,
 sv_status sv_dm_apply_kraus(sv_state *st, int32_t n, const int32_t *qubits, int32_t n_qubits,
                             const double *kraus, int32_t n_kraus);
 
+/* rho <- sum_k K_k rho K_k^dagger for a channel on the qubit pair (q0, q1);
+ * kraus holds n_kraus HOST 4x4 matrices, row-major, interleaved (re, im),
+ * local index bit(q0) + 2 bit(q1).  One streaming pass of the vector. */
+sv_status sv_dm_apply_kraus2(sv_state *st, int32_t n, int32_t q0, int32_t q1, const double *kraus,
+                             int32_t n_kraus);
+
 /* out_terms[j] = Tr(rho P_j) (real part), *out_sum = sum_j c_j Tr(rho P_j),
  * summed in fixed orders. */
 sv_status sv_dm_expect_pauli(sv_state *st, int32_t n, const sv_pauli_term *terms, int32_t n_terms,

@@ -2188,6 +2188,43 @@ extern "C" sv_status sv_dm_apply_kraus(sv_state *st, int32_t n, const int32_t *q
   return SV_OK;
 }
 
+extern "C" sv_status sv_dm_apply_kraus2(sv_state *st, int32_t n, int32_t q0, int32_t q1,
+                                        const double *kraus, int32_t n_kraus) {
+  sv_status s = dm_check(st, n);
+  if (s) return s;
+  if (q0 < 0 || q0 >= n || q1 < 0 || q1 >= n || q0 == q1)
+    return fail(SV_EINVAL, "qubits %d, %d: distinct and in [0,%d)", q0, q1, n);
+  if (n_kraus < 1 || !kraus) return fail(SV_EINVAL, "no Kraus operators");
+  for (int i = 0; i < 32 * n_kraus; i++)
+    if (!std::isfinite(kraus[i])) return fail(SV_EINVAL, "non-finite Kraus entry");
+  // S[(ur', uc'), (ur, uc)] = sum_k K[ur'][ur] conj(K[uc'][uc]); entry e = uc + 4 ur
+  std::vector<double> S(2 * 256, 0.0);
+  for (int k = 0; k < n_kraus; k++) {
+    const double *K = kraus + 32 * k;
+    for (int r1 = 0; r1 < 4; r1++)
+      for (int c1 = 0; c1 < 4; c1++)
+        for (int r0 = 0; r0 < 4; r0++)
+          for (int c0 = 0; c0 < 4; c0++) {
+            const double ar = K[2 * (4 * r1 + r0)], ai = K[2 * (4 * r1 + r0) + 1];
+            const double br = K[2 * (4 * c1 + c0)], bi = -K[2 * (4 * c1 + c0) + 1];
+            const int o = c1 + 4 * r1, l = c0 + 4 * r0;
+            S[2 * (16 * o + l)] += ar * br - ai * bi;
+            S[2 * (16 * o + l) + 1] += ar * bi + ai * br;
+          }
+  }
+  s = materialize_zero(st);
+  if (s) return s;
+  s = ensure_scratch(st, S.size() * 8 + 256);
+  if (s) return s;
+  double *d_S = (double *)st->scratch;
+  HIPCHK(hipMemcpyAsync(d_S, S.data(), S.size() * 8, hipMemcpyHostToDevice, st->stream));
+  hipError_t e = svk_launch_dm_channel16(st->dtype == SV_C128, st->re, st->im, st->n, q0, q1, n, d_S,
+                                         st->stream);
+  if (e != hipSuccess) return fail(SV_EDEVICE, "channel kernel: %s", hipGetErrorString(e));
+  HIPCHK(hipStreamSynchronize(st->stream));
+  return SV_OK;
+}
+
 extern "C" sv_status sv_dm_expect_pauli(sv_state *st, int32_t n, const sv_pauli_term *terms,
                                         int32_t n_terms, double *out_terms, double *out_sum) {
   sv_status s = dm_check(st, n);

@@ -793,6 +793,50 @@ __global__ void __launch_bounds__(256) k_dm_channel2(Channel2Args a) {
   }
 }
 
+// A two-qubit channel: the 16x16 complex superoperator S (device memory,
+// row-major, interleaved; entry index e = column bits (q0, q1) + 4 * row bits
+// (q0 + off, q1 + off)) on the 16 entries each thread takes; one read and one
+// write of the vector.
+struct Channel16Args {
+  void *re, *im;
+  const double *S;
+  int64_t groups;     // 2^(N - 4)
+  int q[4];           // bit of entry bits 0..3: q0, q1, q0 + off, q1 + off
+  int pos[4];         // the same positions, ascending
+};
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_dm_channel16(Channel16Args a) {
+  T *re = (T *)a.re, *im = (T *)a.im;
+  const SVI_CONST double *S = cptr(a.S);
+  for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < a.groups;
+       g += (int64_t)gridDim.x * blockDim.x) {
+    uint64_t b = (uint64_t)g;
+#pragma unroll
+    for (int k = 0; k < 4; k++) b = ((b >> a.pos[k]) << (a.pos[k] + 1)) | (b & ((1ull << a.pos[k]) - 1));
+    uint64_t idx[16];
+    double xr[16], xi[16];
+#pragma unroll
+    for (int e = 0; e < 16; e++) {
+      idx[e] = b | ((uint64_t)(e & 1) << a.q[0]) | ((uint64_t)((e >> 1) & 1) << a.q[1]) |
+               ((uint64_t)((e >> 2) & 1) << a.q[2]) | ((uint64_t)((e >> 3) & 1) << a.q[3]);
+      xr[e] = (double)re[idx[e]];
+      xi[e] = (double)im[idx[e]];
+    }
+    for (int o = 0; o < 16; o++) {
+      double yr = 0.0, yi = 0.0;
+#pragma unroll
+      for (int l = 0; l < 16; l++) {
+        const double sr = S[2 * (16 * o + l)], si = S[2 * (16 * o + l) + 1];
+        yr += sr * xr[l] - si * xi[l];
+        yi += sr * xi[l] + si * xr[l];
+      }
+      re[idx[o]] = (T)yr;
+      im[idx[o]] = (T)yi;
+    }
+  }
+}
+
 // Sum each slot's partials in a fixed order: out[s] = sum_w part[s * np + w].
 __global__ void k_reduce_rows(const double *part, int nslots, int np, double *out) {
   for (int s = blockIdx.x * blockDim.x + threadIdx.x; s < nslots; s += gridDim.x * blockDim.x) {
@@ -1290,6 +1334,21 @@ hipError_t svk_launch_dm_channel2(int dbl, void *re, void *im, int nq, int qa, i
   const int grid = (int)std::min<int64_t>((a.groups + 255) / 256, 16384);
   if (dbl) hipLaunchKernelGGL(k_dm_channel2<double>, dim3(grid), dim3(256), 0, s, a);
   else hipLaunchKernelGGL(k_dm_channel2<float>, dim3(grid), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t svk_launch_dm_channel16(int dbl, void *re, void *im, int nq, int q0, int q1, int off,
+                                   const double *d_S, hipStream_t s) {
+  Channel16Args a;
+  a.re = re; a.im = im; a.S = d_S;
+  a.groups = 1ll << (nq - 4);
+  a.q[0] = q0; a.q[1] = q1; a.q[2] = q0 + off; a.q[3] = q1 + off;
+  int p[4] = {a.q[0], a.q[1], a.q[2], a.q[3]};
+  std::sort(p, p + 4);
+  for (int k = 0; k < 4; k++) a.pos[k] = p[k];
+  const int grid = (int)std::min<int64_t>((a.groups + 255) / 256, 16384);
+  if (dbl) hipLaunchKernelGGL(k_dm_channel16<double>, dim3(grid), dim3(256), 0, s, a);
+  else hipLaunchKernelGGL(k_dm_channel16<float>, dim3(grid), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 

@@ -77,6 +77,7 @@ def lib():
         "sv_dm_apply": (C.c_int, [vp, i32, opp, i32, dp, i32]),
         "sv_dm_apply_kraus": (C.c_int, [vp, i32, C.POINTER(i32), i32, dp, i32]),
         "sv_dm_expect_pauli": (C.c_int, [vp, i32, tp, i32, dp, dp]),
+        "sv_dm_apply_kraus2": (C.c_int, [vp, i32, i32, i32, dp, i32]),
         "sv_copy_to_host": (C.c_int, [vp, vp, vp, u64, u64]),
         "sv_copy_from_host": (C.c_int, [vp, vp, vp, u64, u64]),
         "sv_last_error": (C.c_char_p, []),
@@ -330,6 +331,13 @@ class State:
         _check(lib().sv_dm_apply_kraus(self.h, self.n // 2, q.ctypes.data_as(C.POINTER(C.c_int32)),
                                        int(q.size), buf.ctypes.data_as(C.POINTER(C.c_double)),
                                        int(k.shape[0])))
+
+    def dm_apply_kraus2(self, q0: int, q1: int, kraus: Sequence[np.ndarray]):
+        """A channel on the qubit pair (q0, q1): 4x4 Kraus matrices, local index bit(q0) + 2 bit(q1)."""
+        k = np.ascontiguousarray(np.asarray(kraus, dtype=np.complex128).reshape(-1, 4, 4))
+        buf = np.ascontiguousarray(k.view(np.float64).reshape(-1))
+        _check(lib().sv_dm_apply_kraus2(self.h, self.n // 2, int(q0), int(q1),
+                                        buf.ctypes.data_as(C.POINTER(C.c_double)), int(k.shape[0])))
 
     def dm_expect(self, ham) -> Tuple[np.ndarray, float]:
         ta = TermArray(ham)

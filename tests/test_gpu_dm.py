@@ -36,6 +36,17 @@ def _damping(g):
     return [np.array([[1, 0], [0, math.sqrt(1 - g)]]), np.array([[0, math.sqrt(g)], [0, 0]])]
 
 
+def _mixed_unitaries(seed):
+    # complex two-qubit Kraus set: sqrt(0.7) U, sqrt(0.3) V for random unitaries
+    rng = np.random.default_rng(seed)
+    out = []
+    for w in (0.7, 0.3):
+        a = rng.normal(size=(4, 4)) + 1j * rng.normal(size=(4, 4))
+        q, _ = np.linalg.qr(a)
+        out.append(math.sqrt(w) * q)
+    return out
+
+
 @pytest.mark.parametrize("n", [3, 6, 7])
 def test_dm_vs_oracle(sv, n):
     _say("density matrix", n)
@@ -49,6 +60,8 @@ def test_dm_vs_oracle(sv, n):
     st.dm_apply_kraus(n - 1, _damping(0.3))
     st.dm_apply(c2.ops, c2.params)
     st.dm_apply_kraus(list(range(n)), _depolarizing(0.05))
+    K2 = _mixed_unitaries(n)
+    st.dm_apply_kraus2(n - 1, 0, K2)
     got = st.to_numpy()
     rho = O.dm_run(n, c1.ops, c1.params)
     rho = O.dm_kraus(n, rho, 0, _depolarizing(0.2))
@@ -56,6 +69,7 @@ def test_dm_vs_oracle(sv, n):
     rho = O.dm_run(n, c2.ops, c2.params, rho)
     for q in range(n):
         rho = O.dm_kraus(n, rho, q, _depolarizing(0.05))
+    rho = O.dm_kraus2(n, rho, n - 1, 0, K2)
     assert np.max(np.abs(got - rho.reshape(-1))) <= TOL
     vals, e = st.dm_expect(h)
     ov, oe = O.dm_expect(n, rho, h)

@@ -221,7 +221,7 @@ sv_status sv_dm_apply(sv_state *st, int32_t n, const sv_op *ops, int32_t n_ops,
                       const double *params, int32_t n_params);
 
 /* rho <- sum_k K_k rho K_k^dagger on each of the n_qubits distinct qubits
- * (streaming passes of the vector, two qubits per pass); kraus holds n_kraus HOST
+ * (streaming passes of the vector, up to four qubits per pass); kraus holds n_kraus HOST
  * 2x2 matrices, row-major, interleaved (re, im) complex128.  Trace
  * preservation (sum_k K_k^dagger K_k = I) is the caller's. */
 sv_status sv_dm_apply_kraus(sv_state *st, int32_t n, const int32_t *qubits, int32_t n_qubits,

@@ -2175,8 +2175,17 @@ extern "C" sv_status sv_dm_apply_kraus(sv_state *st, int32_t n, const int32_t *q
   if (n_qubits == 0) return SV_OK;
   s = materialize_zero(st);
   if (s) return s;
-  // two channels per pass where possible
-  for (int i = 0; i < n_qubits; i += 2) {
+  // four channels per LDS-tile pass on vectors of 12 or more qubits (the
+  // other four tile bits are the lowest free vector bits), then two per pass,
+  // then one; three per tile (64-entry load runs) measured slower
+  int i0 = 0;
+  if (st->n >= 12)
+    for (; i0 + 4 <= n_qubits; i0 += 4) {
+      hipError_t e = svk_launch_dm_channel_tile(st->dtype == SV_C128, st->re, st->im, st->n, n,
+                                                qubits + i0, 4, m, st->stream);
+      if (e != hipSuccess) return fail(SV_EDEVICE, "channel kernel: %s", hipGetErrorString(e));
+    }
+  for (int i = i0; i < n_qubits; i += 2) {
     hipError_t e = i + 1 < n_qubits
         ? svk_launch_dm_channel2(st->dtype == SV_C128, st->re, st->im, st->n, qubits[i],
                                  qubits[i + 1], n, m, m, st->stream)

@@ -837,6 +837,82 @@ __global__ void __launch_bounds__(256) k_dm_channel16(Channel16Args a) {
   }
 }
 
+// Up to four one-qubit channels in one pass through an LDS tile of 4096
+// entries: tile-index bit j is vector bit pos[j] (the lowest vector bits not
+// used by the channels first, so loads run over consecutive entries, then the
+// channels' column and row bits); each channel's 4x4 superoperator is applied
+// to the 1024 groups of four entries that differ in its two bits, one
+// channel after another, and the tile is written back once.
+struct ChannelTileArgs {
+  void *re, *im;
+  int64_t tiles;      // 2^(N - 12)
+  int k;              // channels in this pass (1..4)
+  int pos[12];        // vector bit of tile-index bit j
+  int sorted[12];     // pos, ascending
+  int ci[4], ri[4];   // tile-index bits of channel i's column and row bits
+  double s[32];
+};
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_dm_channel_tile(ChannelTileArgs a) {
+  __shared__ double2 lds[4096];
+  T *re = (T *)a.re, *im = (T *)a.im;
+  const int tid = threadIdx.x;
+  for (int64_t t = blockIdx.x; t < a.tiles; t += gridDim.x) {
+    uint64_t base = (uint64_t)t;
+#pragma unroll
+    for (int j = 0; j < 12; j++)
+      base = ((base >> a.sorted[j]) << (a.sorted[j] + 1)) | (base & ((1ull << a.sorted[j]) - 1));
+    auto addr = [&](int e) {
+      uint64_t g = base;
+#pragma unroll
+      for (int j = 0; j < 12; j++) g |= (uint64_t)((e >> j) & 1) << a.pos[j];
+      return g;
+    };
+    for (int e = tid; e < 4096; e += 256) {
+      const uint64_t g = addr(e);
+      lds[e] = make_double2((double)re[g], (double)im[g]);
+    }
+    __syncthreads();
+    for (int i = 0; i < a.k; i++) {
+      const int c = a.ci[i], r = a.ri[i];
+      const int lo = c < r ? c : r, hi = c < r ? r : c;
+      for (int gi = tid; gi < 1024; gi += 256) {
+        int e0 = ((gi >> lo) << (lo + 1)) | (gi & ((1 << lo) - 1));
+        e0 = ((e0 >> hi) << (hi + 1)) | (e0 & ((1 << hi) - 1));
+        int ix[4];
+        double xr[4], xi[4];
+#pragma unroll
+        for (int l = 0; l < 4; l++) {
+          ix[l] = e0 | ((l & 1) << c) | ((l >> 1) << r);
+          const double2 v = lds[ix[l]];
+          xr[l] = v.x;
+          xi[l] = v.y;
+        }
+#pragma unroll
+        for (int o = 0; o < 4; o++) {
+          double yr = 0.0, yi = 0.0;
+#pragma unroll
+          for (int l = 0; l < 4; l++) {
+            const double sr = a.s[2 * (4 * o + l)], si = a.s[2 * (4 * o + l) + 1];
+            yr += sr * xr[l] - si * xi[l];
+            yi += sr * xi[l] + si * xr[l];
+          }
+          lds[ix[o]] = make_double2(yr, yi);
+        }
+      }
+      __syncthreads();
+    }
+    for (int e = tid; e < 4096; e += 256) {
+      const uint64_t g = addr(e);
+      const double2 v = lds[e];
+      re[g] = (T)v.x;
+      im[g] = (T)v.y;
+    }
+    __syncthreads();
+  }
+}
+
 // Sum each slot's partials in a fixed order: out[s] = sum_w part[s * np + w].
 __global__ void k_reduce_rows(const double *part, int nslots, int np, double *out) {
   for (int s = blockIdx.x * blockDim.x + threadIdx.x; s < nslots; s += gridDim.x * blockDim.x) {
@@ -1349,6 +1425,36 @@ hipError_t svk_launch_dm_channel16(int dbl, void *re, void *im, int nq, int q0, 
   const int grid = (int)std::min<int64_t>((a.groups + 255) / 256, 16384);
   if (dbl) hipLaunchKernelGGL(k_dm_channel16<double>, dim3(grid), dim3(256), 0, s, a);
   else hipLaunchKernelGGL(k_dm_channel16<float>, dim3(grid), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t svk_launch_dm_channel_tile(int dbl, void *re, void *im, int nq, int off,
+                                      const int *qubits, int k, const double *s32, hipStream_t s) {
+  if (nq < 12 || k < 1 || k > 4) return hipErrorInvalidValue;
+  ChannelTileArgs a;
+  a.re = re; a.im = im;
+  a.tiles = 1ll << (nq - 12);
+  a.k = k;
+  uint64_t used = 0;
+  for (int i = 0; i < k; i++) used |= (1ull << qubits[i]) | (1ull << (qubits[i] + off));
+  int np = 0;
+  for (int b = 0; b < nq && np < 12 - 2 * k; b++)
+    if (!(used >> b & 1)) a.pos[np++] = b;
+  int chan[8], nc = 0;
+  for (int b = 0; b < nq; b++)
+    if (used >> b & 1) chan[nc++] = b;
+  for (int j = 0; j < nc; j++) a.pos[np + j] = chan[j];
+  for (int j = 0; j < 12; j++) a.sorted[j] = a.pos[j];
+  std::sort(a.sorted, a.sorted + 12);
+  for (int i = 0; i < k; i++)
+    for (int j = 0; j < 12; j++) {
+      if (a.pos[j] == qubits[i]) a.ci[i] = j;
+      if (a.pos[j] == qubits[i] + off) a.ri[i] = j;
+    }
+  for (int i = 0; i < 32; i++) a.s[i] = s32[i];
+  const int grid = (int)std::min<int64_t>(a.tiles, 8192);
+  if (dbl) hipLaunchKernelGGL(k_dm_channel_tile<double>, dim3(grid), dim3(256), 0, s, a);
+  else hipLaunchKernelGGL(k_dm_channel_tile<float>, dim3(grid), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 

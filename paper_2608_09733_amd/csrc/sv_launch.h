@@ -46,6 +46,9 @@ hipError_t svk_launch_dm_channel2(int dbl, void *re, void *im, int nq, int qa, i
 // two-qubit channel: 16x16 superoperator in device memory on qubits q0 != q1
 hipError_t svk_launch_dm_channel16(int dbl, void *re, void *im, int nq, int q0, int q1, int off,
                                    const double *d_S, hipStream_t s);
+// up to four one-qubit channels (same superoperator) in one LDS-tile pass; nq >= 12
+hipError_t svk_launch_dm_channel_tile(int dbl, void *re, void *im, int nq, int off,
+                                      const int *qubits, int k, const double *s32, hipStream_t s);
 // part[t * nb + b] <- block b's partial of Tr(rho P_t), rho of n qubits as a 2n-qubit vector
 hipError_t svk_launch_dm_pauli(int dbl, const void *re, const void *im, int n,
                                const PauliTermDev *terms, int nt, int nb, double *part,

@@ -55,6 +55,7 @@ def lib():
         L.orc_sample.argtypes = [C.c_int, dp, C.c_uint64, C.c_int64, C.POINTER(C.c_int32), C.c_int,
                                  up]
         L.orc_sample_prefix.argtypes = [C.c_int, dp, dp, dp]
+        L.orc_sample_at.argtypes = [C.c_int, dp, dp, C.c_int64, up]
         L.orc_fuse_greedy.argtypes = [C.c_int, op_p, C.c_int, C.POINTER(C.c_int32)]
         L.orc_threads.restype = C.c_int
         _lib = L
@@ -240,6 +241,17 @@ def sample(n: int, psi: np.ndarray, seed: int, shots: int, qubits: Sequence[int]
                         nq, _up(out)):
         raise ValueError("bad sample arguments")
     return out[:shots]
+
+
+def sample_at(n: int, psi: np.ndarray, t) -> np.ndarray:
+    """Basis index drawn for each target value t (steps 5-6 of the sampling
+    specification; the sampler itself uses t = u_s * T)."""
+    z = np.ascontiguousarray(np.asarray(psi, dtype=np.complex128)).view(np.float64)
+    tt = np.ascontiguousarray(np.atleast_1d(np.asarray(t, dtype=np.float64)))
+    out = np.zeros(max(1, tt.size), dtype=np.uint64)
+    if lib().orc_sample_at(n, _dp(z), _dp(tt), tt.size, _up(out)):
+        raise ValueError("bad sample arguments")
+    return out[:tt.size]
 
 
 def sample_prefix(n: int, psi: np.ndarray) -> Tuple[np.ndarray, np.ndarray]:

@@ -457,6 +457,44 @@ int orc_sample_prefix(int n, const double *psi_, double *S, double *P) {
   return 0;
 }
 
+/* Steps 5 and 6 for one target value t: the drawn basis index. */
+static int64_t draw_index(const cplx *psi, const double *S, const double *P, uint64_t K, uint64_t C,
+                          double t) {
+  int64_t ks = -1;
+  for (uint64_t k = 0; k < K; k++)
+    if (P[k + 1] > t) { ks = (int64_t)k; break; }
+  if (ks < 0)
+    for (int64_t k = (int64_t)K - 1; k >= 0; k--)
+      if (S[k] > 0.0) { ks = k; break; }
+  if (ks < 0) ks = 0;  /* all-zero state: index 0 by convention */
+  double r = t - P[ks];
+  double a = 0.0;
+  int64_t pick = -1, lastpos = -1;
+  for (uint64_t i = 0; i < C; i++) {
+    uint64_t b = (uint64_t)ks * C + i;
+    double p = prob_of(psi, b);
+    a += p;
+    if (p > 0.0) lastpos = (int64_t)b;
+    if (a > r) { pick = (int64_t)b; break; }
+  }
+  if (pick < 0) pick = lastpos >= 0 ? lastpos : (int64_t)ks * (int64_t)C;
+  return pick;
+}
+
+int orc_sample_at(int n, const double *psi_, const double *t, int64_t count, uint64_t *out) {
+  const cplx *psi = (const cplx *)psi_;
+  int cbits = n < 10 ? n : 10;
+  uint64_t C = 1ull << cbits, K = (1ull << n) >> cbits;
+  double *S = (double *)malloc(sizeof(double) * K);
+  double *P = (double *)malloc(sizeof(double) * (K + 1));
+  if (!S || !P) { free(S); free(P); return -100; }
+  orc_sample_prefix(n, psi_, S, P);
+  for (int64_t s = 0; s < count; s++) out[s] = (uint64_t)draw_index(psi, S, P, K, C, t[s]);
+  free(S);
+  free(P);
+  return 0;
+}
+
 int orc_sample(int n, const double *psi_, uint64_t seed, int64_t shots, const int32_t *qubits,
                int n_measured, uint64_t *out) {
   const cplx *psi = (const cplx *)psi_;
@@ -471,25 +509,7 @@ int orc_sample(int n, const double *psi_, uint64_t seed, int64_t shots, const in
   double T = P[K];
   for (int64_t s = 0; s < shots; s++) {
     double u = (double)(orc_splitmix64(seed, (uint64_t)s) >> 11) * 0x1.0p-53;
-    double t = u * T;
-    int64_t ks = -1;
-    for (uint64_t k = 0; k < K; k++)
-      if (P[k + 1] > t) { ks = (int64_t)k; break; }
-    if (ks < 0)
-      for (int64_t k = (int64_t)K - 1; k >= 0; k--)
-        if (S[k] > 0.0) { ks = k; break; }
-    if (ks < 0) ks = 0;  /* all-zero state: index 0 by convention */
-    double r = t - P[ks];
-    double a = 0.0;
-    int64_t pick = -1, lastpos = -1;
-    for (uint64_t i = 0; i < C; i++) {
-      uint64_t b = (uint64_t)ks * C + i;
-      double p = prob_of(psi, b);
-      a += p;
-      if (p > 0.0) lastpos = (int64_t)b;
-      if (a > r) { pick = (int64_t)b; break; }
-    }
-    if (pick < 0) pick = lastpos >= 0 ? lastpos : (int64_t)ks * (int64_t)C;
+    int64_t pick = draw_index(psi, S, P, K, C, u * T);
     uint64_t o = 0;
     for (int i = 0; i < n_measured; i++)
       o |= (((uint64_t)pick >> qubits[i]) & 1u) << i;

@@ -78,6 +78,11 @@ uint64_t orc_splitmix64(uint64_t seed, uint64_t s);
 int orc_sample(int n, const double *psi, uint64_t seed, int64_t shots, const int32_t *qubits,
                int n_measured, uint64_t *out);
 
+/* Steps 5-6 of the specification for given target values: out[s] = the basis
+ * index drawn for t[s] (the sampler draws t = u_s * T; tests may pass any t,
+ * including t >= T, which reaches the fallbacks). */
+int orc_sample_at(int n, const double *psi, const double *t, int64_t count, uint64_t *out);
+
 /* Probability-prefix quantities of the sampling specification (for tests):
  * chunk sums S (K entries) and prefixes P (K+1 entries), K = 2^n / 2^min(n,10). */
 int orc_sample_prefix(int n, const double *psi, double *S, double *P);

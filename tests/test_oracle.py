@@ -379,6 +379,115 @@ def test_sampling_blocked_prefix_rounding_order():
     assert P[2048] == 1.0 + 2.0 ** -43
 
 
+def _u(seed, s):
+    return (O.splitmix64(seed, s) >> 11) * 2.0 ** -53
+
+
+def _points(n, pts):
+    psi = np.zeros(1 << n, dtype=complex)
+    for b, a in pts.items():
+        psi[b] = a
+    return psi
+
+
+@pytest.mark.parametrize("n,b", [(12, 2 * 1024 + 517), (12, 3 * 1024 + 1023), (12, 1024),
+                                 (21, 1500 * 1024 + 3), (21, 1023 * 1024 + 9),
+                                 (21, 2047 * 1024 + 1000)])
+def test_sampling_basis_state_in_a_late_chunk(n, b):
+    # Several chunks of 1024 indices (n = 21: two prefix blocks of 1024
+    # chunks).  All the mass on one index, so every draw must return it: the
+    # chunk search and the in-chunk search must both land on that index.
+    psi = _points(n, {b: 1j})
+    out = O.sample(n, psi, seed=5, shots=300, qubits=list(range(n)))
+    assert np.all(out == b)
+
+
+@pytest.mark.parametrize("n,pts", [
+    # n = 12: four chunks; two empty chunks between the points
+    (12, {1024 + 100: 0.5, 3 * 1024 + 10: 0.5j, 3 * 1024 + 900: 0.5 + 0.5j}),
+    # n = 21: two prefix blocks; points in block 0, in block 1 and in the last chunk
+    (21, {3 * 1024 + 1: 0.5, (1024 + 77) * 1024 + 512: -0.5j, 2047 * 1024 + 1023: 0.5 - 0.5j}),
+])
+def test_sampling_points_across_chunks_exact(n, pts):
+    # Probabilities 1/4, 1/4, 1/2 (exact binary fractions, T = 1): a draw
+    # with t = u * T must give the first point for t < 1/4, the second for
+    # 1/4 <= t < 1/2 and the third for t >= 1/2, draw by draw.
+    psi = _points(n, pts)
+    b = sorted(pts)
+    S, P = O.sample_prefix(n, psi)
+    assert P[-1] == 1.0
+    shots = 3000
+    out = O.sample(n, psi, seed=13, shots=shots, qubits=list(range(n)))
+    for s in range(shots):
+        t = _u(13, s) * 1.0
+        want = b[0] if t < 0.25 else b[1] if t < 0.5 else b[2]
+        assert out[s] == want
+    # every point is drawn (about 750 / 750 / 1500 times)
+    assert all(np.count_nonzero(out == x) > 500 for x in b)
+
+
+def test_sampling_search_boundaries_and_fallbacks():
+    # n = 12, chunk masses S = (1/8, 0, 3/8, 1/2), prefix P = (0, 1/8, 1/8, 1/2, 1).
+    # The chunk is the first k with P[k+1] > t (strict), the index the first
+    # b in the chunk whose running sum exceeds r = t - P[k] (strict); t >= T
+    # takes the last chunk with mass and, there, the last index with mass.
+    n = 12
+    psi = _points(n, {10: 0.25 + 0.25j, 2048 + 5: 0.5, 2048 + 700: 0.25 - 0.25j,
+                      3072: 0.5j, 3500: -0.5})
+    S, P = O.sample_prefix(n, psi)
+    assert list(S) == [0.125, 0.0, 0.375, 0.5]
+    assert list(P) == [0.0, 0.125, 0.125, 0.5, 1.0]
+    below = lambda t: float(np.nextafter(t, 0.0))   # the largest double under t
+    probes = [(0.0, 10), (below(0.125), 10), (0.125, 2053), (below(0.375), 2053),
+              (0.375, 2748), (below(0.5), 2748), (0.5, 3072), (below(0.75), 3072),
+              (0.75, 3500), (below(1.0), 3500), (1.0, 3500), (7.0, 3500)]
+    got = O.sample_at(n, psi, [t for t, _ in probes])
+    assert [int(g) for g in got] == [b for _, b in probes]
+    # the last chunk with mass is chunk 2 once chunk 3 is emptied: t >= T falls
+    # back there and takes its last index with mass
+    psi2 = psi.copy()
+    psi2[3072] = psi2[3500] = 0
+    assert [int(g) for g in O.sample_at(n, psi2, [0.5, 9.0, 0.499])] == [2748, 2748, 2748]
+    # one-chunk state whose running sum never reaches its pairwise-tree total:
+    # p_0 = 1 and 1023 entries of 2^-54, each lost when added to 1 left to
+    # right; for 1 <= t < T the in-chunk search falls back to the last index
+    # with mass
+    n = 10
+    psi3 = np.full(1 << n, 2.0 ** -27, dtype=complex)
+    psi3[0] = 1.0
+    S3, P3 = O.sample_prefix(n, psi3)
+    assert P3[-1] > 1.0
+    assert [int(g) for g in O.sample_at(n, psi3, [0.0, 0.999, 1.0, P3[-1] * (1 - 2.0 ** -53)])] == \
+        [0, 0, 1023, 1023]
+
+
+def test_sampling_at_matches_sampler():
+    # The sampler draws t = u_s * T and takes the same search.
+    n = 13
+    psi = O.run_circuit(I.layered(n, 2, seed=6))
+    S, P = O.sample_prefix(n, psi)
+    shots = 400
+    t = np.array([_u(99, s) * P[-1] for s in range(shots)])
+    assert np.array_equal(O.sample(n, psi, 99, shots, list(range(n))), O.sample_at(n, psi, t))
+
+
+def test_sampling_chi_square_several_chunks():
+    n = 12
+    psi = O.run_circuit(I.random_circuit(n, 60, seed=12))
+    p = np.abs(psi) ** 2
+    shots = 400000
+    out = O.sample(n, psi, seed=4321, shots=shots, qubits=list(range(n)))
+    counts = np.bincount(out.astype(np.int64), minlength=1 << n)
+    # per chunk of 1024 indices, then per index
+    cp = p.reshape(4, 1024).sum(axis=1) * shots
+    cc = counts.reshape(4, 1024).sum(axis=1)
+    assert np.all(np.abs(cc - cp) < 6 * np.sqrt(cp) + 1)
+    mask = p * shots > 5
+    chi2 = np.sum((counts[mask] - p[mask] * shots) ** 2 / (p[mask] * shots))
+    dof = int(mask.sum()) - 1
+    assert chi2 < dof + 6 * math.sqrt(2 * dof)
+
+
 # ---------------------------------------------------------- shot readout
 
 def test_qwc_grouping():

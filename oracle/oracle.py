@@ -197,18 +197,64 @@ def adjoint_grad(circ, ham, params=None) -> Tuple[float, np.ndarray]:
     return float(e[0]), g[:npar]
 
 
+# Shift rules (Section 4.2: a gate's generator fixes its rule).  For one
+# occurrence of a parameter in a gate U(theta) = exp(-i theta G / 2), the
+# energy as a function of that occurrence is a trigonometric polynomial whose
+# frequencies are half the differences of G's eigenvalues:
+#   * G with eigenvalues {-1, +1} (Pauli rotations) or {0, -2} (phase gates):
+#     frequency 1, and dE/dtheta = [E(theta + pi/2) - E(theta - pi/2)] / 2
+#     (the paper's two-term rule, eq. 2);
+#   * G with eigenvalues {-1, 0, +1} (single and double excitations, and any
+#     rotation under a control, which adds the eigenvalue 0 on the
+#     non-firing subspace): frequencies 1/2 and 1.  With
+#     E(theta + x) = a + b1 sin(x/2) + b2 sin(x) + (even terms) the odd part
+#     E(theta + x) - E(theta - x) = 2 b1 sin(x/2) + 2 b2 sin(x) at x = pi/2
+#     and 3 pi/2 gives sqrt2 b1 + 2 b2 and sqrt2 b1 - 2 b2, so
+#     dE/dtheta = b1/2 + b2 = c+ [E(+pi/2) - E(-pi/2)] + c- [E(+3pi/2) - E(-3pi/2)]
+#     with c+ = (2 + sqrt2)/8 and c- = (sqrt2 - 2)/8: the four-term rule the
+#     paper selects for excitation gates (published form: Anselmetti et al.
+#     2021; Wierichs et al. 2022).
+# A parameter read by several gates sums one such derivative per occurrence
+# (each occurrence shifted alone through an extra parameter slot).
+TWO_TERM = ((math.pi / 2, 0.5),)
+FOUR_TERM = ((math.pi / 2, (2 + math.sqrt(2)) / 8), (3 * math.pi / 2, (math.sqrt(2) - 2) / 8))
+
+
+def shift_rule(op, slot: int):
+    """Shift rule of parameter slot `slot` of gate `op`: ((shift, weight), ...)
+    with dE/dtheta = sum_k weight_k [E(theta + shift_k) - E(theta - shift_k)]."""
+    if op.kind in ("givens", "dexc"):
+        return FOUR_TERM
+    if op.kind == "p" or (op.kind in ("u2", "u3") and not (op.kind == "u3" and slot == 0)):
+        return TWO_TERM                   # phases: eigenvalues {0, -2}, controlled or not
+    if op.kind in ("rx", "ry", "rz", "rxx", "ryy", "rzz", "u3"):
+        return FOUR_TERM if op.controls else TWO_TERM
+    raise ValueError(f"no shift rule for {op.kind}")
+
+
 def param_shift_grad(circ, ham, indices: Sequence[int]) -> np.ndarray:
-    """Two-term shift rule (paper eq. for Pauli rotations): half the difference
-    of the energies at theta +/- pi/2.  Exact for parameters read by exactly
-    one Pauli-rotation gate."""
+    """dE/dtheta_i for each i by the shift rules above, one occurrence at a time."""
+    from dataclasses import replace
+    base = np.array(circ.params, dtype=np.float64)
+    extra = len(base)
     out = []
     for i in indices:
-        p = np.array(circ.params, dtype=np.float64)
-        p[i] += math.pi / 2
-        ep = energy(circ, ham, p)
-        p[i] -= math.pi
-        em = energy(circ, ham, p)
-        out.append(0.5 * (ep - em))
+        g = 0.0
+        for k, op in enumerate(circ.ops):
+            for w, pi in enumerate(op.params):
+                if pi != i:
+                    continue
+                pidx = list(op.params)
+                pidx[w] = extra
+                ops = list(circ.ops)
+                ops[k] = replace(op, params=tuple(pidx))
+                for shift, weight in shift_rule(op, w):
+                    p = np.concatenate([base, [base[i] + shift]])
+                    ep = energy(type(circ)(circ.n, ops, p), ham)
+                    p[extra] = base[i] - shift
+                    em = energy(type(circ)(circ.n, ops, p), ham)
+                    g += weight * (ep - em)
+        out.append(g)
     return np.array(out)
 
 

@@ -273,6 +273,70 @@ def test_adjoint_general_gates_vs_dense_fd():
         assert abs((ep - em) / (2 * h) - g[i]) < 1e-7
 
 
+def _two_term(circ, ham, i):
+    p = np.array(circ.params, dtype=np.float64)
+    p[i] += math.pi / 2
+    ep = O.energy(circ, ham, p)
+    p[i] -= math.pi
+    return 0.5 * (ep - O.energy(circ, ham, p))
+
+
+@pytest.mark.parametrize("case", ["givens", "dexc", "cry"])
+def test_four_term_shift_rule_closed_forms(case):
+    # Generators with the eigenvalues {-1, 0, 1} (Section 4.2: excitation
+    # gates take a four-term rule).  Each state below has weight on both the
+    # zero and the +-1 eigenspaces, so E carries the half frequency:
+    #   givens: H0 H1, G(t) on (0, 1), <X0>        = cos(t/2)
+    #   dexc:   H0..H3, D(t) on (0, 1, 2, 3), <X0> = 3/4 + cos(t/2)/4
+    #   cry:    H0, RY(t) on 1 controlled by 0, <X0> = cos(t/2)
+    if case == "givens":
+        ops = [I.Op("h", (0,)), I.Op("h", (1,)), I.Op("givens", (0, 1), params=(0,))]
+        e = lambda t: math.cos(t / 2)
+        de = lambda t: -math.sin(t / 2) / 2
+        n = 2
+    elif case == "dexc":
+        ops = [I.Op("h", (q,)) for q in range(4)] + [I.Op("dexc", (0, 1, 2, 3), params=(0,))]
+        e = lambda t: 0.75 + math.cos(t / 2) / 4
+        de = lambda t: -math.sin(t / 2) / 8
+        n = 4
+    else:
+        ops = [I.Op("h", (0,)), I.Op("ry", (1,), (0,), params=(0,))]
+        e = lambda t: math.cos(t / 2)
+        de = lambda t: -math.sin(t / 2) / 2
+        n = 2
+    ham = I.hamiltonian(n, [("X", [0], 1.0)])
+    worst_two = 0.0
+    for t in [0.3, 1.1, 2.0, -2.7, 4.4]:
+        circ = I.Circuit(n, ops, np.array([t]))
+        assert abs(O.energy(circ, ham) - e(t)) < 1e-15
+        g = O.param_shift_grad(circ, ham, [0])[0]
+        assert abs(g - de(t)) < 1e-15
+        _, ga = O.adjoint_grad(circ, ham)
+        assert abs(ga[0] - de(t)) < 1e-15
+        worst_two = max(worst_two, abs(_two_term(circ, ham, 0) - de(t)))
+    # the two-term rule misses the half frequency here
+    assert worst_two > 1e-2
+
+
+def test_shift_rules_match_adjoint_on_every_parameterised_kind():
+    # every parameterised kind, with and without controls (control states
+    # included), one parameter shared by two gates: shift rules = adjoint
+    n = 5
+    kinds = ["rx", "ry", "rz", "p", "u2", "u3", "rxx", "ryy", "rzz", "givens", "dexc", "h", "x"]
+    for seed in range(3):
+        circ = I.random_circuit(n, 30, seed=40 + seed, kinds=kinds, max_controls=1)
+        ops = list(circ.ops)
+        par = [k for k, o in enumerate(ops) if o.params]
+        a, b = par[0], par[1]
+        ops[b] = I.Op(ops[b].kind, ops[b].targets, ops[b].controls, ops[b].cstate,
+                      (ops[a].params[0],) + tuple(ops[b].params[1:]))
+        circ = I.Circuit(n, ops, circ.params)
+        ham = I.random_hamiltonian(n, 6, seed=seed)
+        _, ga = O.adjoint_grad(circ, ham)
+        idx = list(range(circ.n_params))
+        assert np.max(np.abs(O.param_shift_grad(circ, ham, idx) - ga)) < 1e-12
+
+
 # ------------------------------------------------------------- sampling
 
 def test_splitmix64_reference_values():

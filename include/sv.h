@@ -149,9 +149,13 @@ sv_status sv_expect_pauli(sv_state *st, const sv_pauli_term *terms, int32_t n_te
  * |0...0>); on return it holds U(theta)|initial>.  grad has n_params entries
  * (a parameter read by several gates sums their contributions).  n_evals
  * (may be NULL) receives 1 (one forward and one backward pass).  Needs a
- * workspace allocated with SV_WS_ADJOINT.  Errors: as sv_apply_layer, plus
- * SV_EUNSUPPORTED for parameterised kinds without a single-angle generator
- * (controlled U2/U3, user matrices carry no parameters), SV_ENOMEM. */
+ * workspace allocated with SV_WS_ADJOINT.  Every parameterised kind is
+ * differentiated, with or without controls: Pauli rotations and phases by
+ * their generator, U2 / U3 as P(phi) RY(theta) P(lambda) under the same
+ * controls, single and double excitations by the Pauli-Y generator of their
+ * rotated pair of basis patterns.  Errors: as sv_apply_layer, plus
+ * SV_EUNSUPPORTED for an op on more than 4 qubits (targets and controls
+ * together; the backward sweeps hold 4-qubit register groups), SV_ENOMEM. */
 sv_status sv_adjoint_grad(sv_state *st, const sv_op *ops, int32_t n_ops, const double *params,
                           int32_t n_params, const sv_pauli_term *terms, int32_t n_terms,
                           double *energy, double *grad, int32_t *n_evals);

@@ -515,9 +515,37 @@ __device__ __forceinline__ void apply_op(const MicroOp &op, T *re, T *im, const 
   }
 }
 
+// Im <lam| G |psi> over one group for the generator of a two-level rotation
+// between the slot patterns a ((j & tm) == pa) and b = a ^ XM: G a = i b,
+// G b = -i a, so the term is Re(conj(lam_b) psi_a) - Re(conj(lam_a) psi_b).
+template <typename T, int R, int XM>
+__device__ __forceinline__ double mo_grad2l(const T *pr, const T *pi, const T *lr, const T *li,
+                                            uint32_t tm, uint32_t pa, uint32_t cm, uint32_t cv) {
+  double acc = 0.0;
+#pragma unroll
+  for (int j = 0; j < (1 << R); j++) {
+    if (((uint32_t)j & tm) != pa) continue;
+    if ((j & cm) != cv) continue;
+    const int k = j ^ XM;
+    acc += ((double)lr[k] * (double)pr[j] + (double)li[k] * (double)pi[j]) -
+           ((double)lr[j] * (double)pr[k] + (double)li[j] * (double)pi[k]);
+  }
+  return acc;
+}
+
 template <typename T, int R>
 __device__ __forceinline__ double grad_op(const MicroOp &op, const T *pr, const T *pi, const T *lr,
                                           const T *li) {
+  if (op.type == MO_GRAD2L) {
+    switch (op.t1) {
+#define SVI_G2(XV) case XV: if constexpr (XV < (1 << R)) return mo_grad2l<T, R, XV>(pr, pi, lr, li, op.mask, op.gz, op.cm, op.cv); break;
+      SVI_G2(3) SVI_G2(5) SVI_G2(6) SVI_G2(9) SVI_G2(10) SVI_G2(12) SVI_G2(15) SVI_G2(17)
+      SVI_G2(18) SVI_G2(20) SVI_G2(23) SVI_G2(24) SVI_G2(27) SVI_G2(29) SVI_G2(30)
+#undef SVI_G2
+      default: break;
+    }
+    return 0.0;
+  }
   // op.mask = x-mask (0, one bit, or two bits) over group bits.
   const uint32_t x = op.mask;
   switch (x) {
@@ -687,7 +715,7 @@ __global__ void __launch_bounds__(1 << (M - R)) k_sweep(SweepArgs a) {
       for (int o = sd.op_begin; o < sd.op_end; o++) {
         const MicroOp op = op_at(a.ops, o);
         if constexpr (NS == 2) {
-          if (op.type == MO_GRAD) {
+          if (op.type == MO_GRAD || op.type == MO_GRAD2L) {
             double v = active ? grad_op<T, R>(op, re[0], im[0], re[1], im[1]) : 0.0;
             v = wave_sum(v);
             if ((tid & 63) == 0) wsum[tid >> 6][op.coef] = v;

@@ -110,6 +110,7 @@ struct GateRec {
   int gparam = -1;
   uint64_t gx = 0, gz = 0;   // generator masks (global qubits)
   double galpha = 1.0, gbeta = 0.0;
+  bool grad2l = false;       // generator of the MO_2L rotation itself (Givens, double excitation)
   double cost = 0.0;         // VALU ops per amplitude (rough)
 };
 
@@ -899,7 +900,27 @@ static void emit_sweep(Plan &P, std::vector<GateRec> &recs, const SweepP &sw, in
         cm |= 1u << l;
         if ((g.cs >> i) & 1u) cv |= 1u << l;
       }
-      if (g.grad) {
+      if (g.grad && g.grad2l) {
+        MicroOp go{};
+        go.type = MO_GRAD2L;
+        uint32_t tm = 0, pa, pb;
+        for (int i = 0; i < g.nt; i++) tm |= 1u << local_of(g.t[i]);
+        if (g.nt == 2) { pa = 1u << local_of(g.t[0]); pb = 1u << local_of(g.t[1]); }
+        else {
+          pa = (1u << local_of(g.t[0])) | (1u << local_of(g.t[1]));
+          pb = (1u << local_of(g.t[2])) | (1u << local_of(g.t[3]));
+        }
+        go.mask = tm;
+        go.gz = pa;
+        go.t1 = (int)(pa ^ pb);
+        go.cm = cm;
+        go.cv = cv;
+        go.coef = gs;
+        P.slot_param.push_back(g.gparam);
+        gs++;
+        mops.push_back(go);
+        grad_mop.back() = go;
+      } else if (g.grad) {
         MicroOp go{};
         go.type = MO_GRAD;
         uint32_t xl = 0, zl = 0;
@@ -1626,9 +1647,9 @@ static sv_status build_adjoint_plan(int n, bool dbl, const Tiling &tl, const sv_
     GateRec g = lower_one(op, op.kind == SV_UNITARY ? um : -1);
     if (g.mo == MO_NOP) continue;
     if (op.kind == SV_U2 || op.kind == SV_U3) {
-      if (op.n_controls)
-        return fail(SV_EUNSUPPORTED, "op %d: adjoint of controlled U2/U3 is not supported", i);
-      // U3(t,f,l) = e^{i(f+l)/2} RZ(f) RY(t) RZ(l); reversed: RZ(f)^dag, RY(t)^dag, RZ(l)^dag
+      // U3(t,f,l) = P(f) RY(t) P(l) exactly (no global phase), so a control
+      // on U3 is the same control on each factor; reversed and daggered:
+      // P(f)^dag, RY(t)^dag, P(l)^dag
       int pt, pf, pl;
       if (op.kind == SV_U3) { pt = op.param_index[0]; pf = op.param_index[1]; pl = op.param_index[2]; }
       else {
@@ -1637,14 +1658,13 @@ static sv_status build_adjoint_plan(int n, bool dbl, const Tiling &tl, const sv_
         pf = op.param_index[0];
         pl = op.param_index[1];
       }
-      const int kinds[3] = {SV_RZ, SV_RY, SV_RZ};
+      const int kinds[3] = {SV_P, SV_RY, SV_P};
       const int pids[3] = {pf, pt, pl};
       for (int k = 0; k < 3; k++) {
-        sv_op sub{};
+        sv_op sub = op;
         sub.kind = kinds[k];
-        sub.n_targets = 1;
-        sub.targets[0] = op.targets[0];
         sub.param_index[0] = pids[k];
+        sub.param_index[1] = sub.param_index[2] = -1;
         GateRec s = lower_one(sub, -1);
         s.dagger = true;
         bool trainable = !(op.kind == SV_U2 && k == 1);
@@ -1656,6 +1676,16 @@ static sv_status build_adjoint_plan(int n, bool dbl, const Tiling &tl, const sv_
         }
         recs.push_back(s);
       }
+      continue;
+    }
+    if (op.kind == SV_GIVENS || op.kind == SV_DEXC) {
+      // generator: the Pauli-Y of the rotated pair of patterns, zero elsewhere
+      g.dagger = true;
+      g.grad = true;
+      g.grad2l = true;
+      g.gparam = op.param_index[0];
+      g.cost += 4;
+      recs.push_back(g);
       continue;
     }
     g.dagger = true;
@@ -2313,8 +2343,9 @@ static sv_status adjoint_enqueue(sv_state *st, const sv_op *ops, int n_ops, cons
           break;
         }
     if (!found)
-      return fail(SV_EUNSUPPORTED, "adjoint: ops on %d qubits exceed the widest backward groups",
-                  width);
+      return fail(SV_EUNSUPPORTED,
+                  "adjoint: an op on %d qubits (targets and controls); the backward sweeps take "
+                  "ops on at most 4", width);
   }
   Plan *F = nullptr, *B = nullptr;
   if (n_ops > 0) {

@@ -32,6 +32,9 @@ enum {
   MO_DIAGT = 10, // slot j *= table[j] (2^R complex at coef)
   MO_2L = 11,    // real 2x2 rotation between local patterns: slots with (j & mask) == gz and
                  // their partners j ^ t1; coef r00,r01,r10,r11 (Givens, double excitation)
+  MO_GRAD2L = 12,// adjoint: accumulate Im<lam| G |psi> into slot `coef` for the generator of
+                 // an MO_2L rotation (same mask / gz / t1 / cm / cv): G a = i b, G b = -i a
+                 // for a = slot with (j & mask) == gz, b = a ^ t1, and G = 0 elsewhere
 };
 
 struct MicroOp {

@@ -146,14 +146,26 @@ def test_adjoint_hea_tfim(sv, n, L, seed):
 
 
 def test_adjoint_general_generators(sv):
+    # every parameterised kind, with controls (control states included):
+    # Pauli rotations, phases, U2 / U3 (split into P RY P under the same
+    # controls), and the excitation gates, whose generator is the Pauli-Y of
+    # the rotated pair of basis patterns
     n = 7
-    kinds = ["rx", "ry", "rz", "p", "rxx", "ryy", "rzz", "u3", "u2", "h", "x", "swap", "s", "t"]
-    for seed in range(4):
-        circ = I.random_circuit(n, 50, seed=300 + seed, kinds=kinds, max_controls=2)
-        # controlled U2/U3 have no single-angle generator: drop their controls
-        ops = [I.Op(o.kind, o.targets, () if o.kind in ("u2", "u3") else o.controls,
-                    None if o.kind in ("u2", "u3") else o.cstate, o.params) for o in circ.ops]
-        circ = I.Circuit(n, ops, circ.params)
+    kinds = ["rx", "ry", "rz", "p", "rxx", "ryy", "rzz", "u3", "u2", "givens", "dexc", "h", "x",
+             "swap", "s", "t"]
+    for seed in range(6):
+        # ops on at most 4 qubits (targets and controls): the backward sweeps'
+        # register groups hold 4
+        circ = I.random_circuit(n, 50, seed=300 + seed, kinds=kinds, max_controls=2, max_qubits=4)
+        # one of each controlled multi-angle kind and controlled excitation, for certain
+        k = circ.n_params
+        extra = [I.Op("u3", (seed % n,), ((seed + 3) % n,), 0, (k, k + 1, k + 2)),
+                 I.Op("u2", ((seed + 1) % n,), ((seed + 4) % n, (seed + 5) % n), 2, (k + 3, k + 4)),
+                 I.Op("givens", ((seed + 2) % n, (seed + 6) % n), ((seed + 1) % n,), 1, (k + 5,)),
+                 I.Op("dexc", (0, 2, 4, 6), (), None, (k + 6,))]
+        rng = np.random.default_rng(seed)
+        ops = list(circ.ops[:25]) + extra[:2] + list(circ.ops[25:]) + extra[2:]
+        circ = I.Circuit(n, ops, np.concatenate([circ.params, rng.uniform(-3, 3, 7)]))
         ham = I.random_hamiltonian(n, 8, seed=seed)
         _say("adjoint general", seed)
         st = sv.State(n, adjoint=True)
@@ -162,6 +174,39 @@ def test_adjoint_general_generators(sv):
         assert abs(e - er) <= TOL
         assert np.max(np.abs(g - gr)) <= 1e-11
         st.close()
+
+
+@pytest.mark.parametrize("kind", ["givens", "dexc"])
+def test_adjoint_excitation_gates_closed_form(sv, kind):
+    # E = <X0> after H on every qubit and the excitation: cos(t/2) for a
+    # Givens rotation, 3/4 + cos(t/2)/4 for a double excitation; the
+    # gradient is the derivative of that closed form
+    n = 2 if kind == "givens" else 4
+    ops = [I.Op("h", (q,)) for q in range(n)] + [I.Op(kind, tuple(range(n)), params=(0,))]
+    ham = I.hamiltonian(n, [("X", [0], 1.0)])
+    for t in [0.4, 2.3, -1.9]:
+        _say("excitation closed form", kind, t)
+        st = sv.State(n, adjoint=True)
+        e, g = st.adjoint_grad(ops, [t], ham)
+        st.close()
+        if kind == "givens":
+            ew, gw = math.cos(t / 2), -math.sin(t / 2) / 2
+        else:
+            ew, gw = 0.75 + math.cos(t / 2) / 4, -math.sin(t / 2) / 8
+        assert abs(e - ew) <= TOL and abs(g[0] - gw) <= TOL
+
+
+def test_adjoint_refuses_five_qubit_ops(sv):
+    # a controlled double excitation acts on 5 qubits: refused before any
+    # device work, state untouched
+    n = 6
+    st = sv.State(n, adjoint=True)
+    before = st.to_numpy()
+    with pytest.raises(sv.SvError) as ei:
+        st.adjoint_grad([I.Op("dexc", (0, 1, 2, 3), (4,), None, (0,))], [0.3], I.tfim(n))
+    assert ei.value.status == -5
+    assert np.array_equal(before, st.to_numpy())
+    st.close()
 
 
 def test_adjoint_config3_zero_angle_closed_form(sv):

@@ -144,6 +144,19 @@ sv_status sv_apply_layer(sv_state *st, const sv_op *ops, int32_t n_ops, const do
 sv_status sv_expect_pauli(sv_state *st, const sv_pauli_term *terms, int32_t n_terms,
                           double *out_terms, double *out_sum);
 
+/* As sv_expect_pauli, for callers that cannot allocate device memory (code
+ * under HIP graph capture aside: this call waits for the stream; tight serving
+ * loops; harnesses that forbid hipMalloc).  It allocates nothing: the partial
+ * sums live in a fixed device array of SV_NOALLOC_SCRATCH_BYTES per GPU,
+ * which the library holds until the process ends.  Calls on one GPU share
+ * that array, so calls that overlap on one GPU (other streams, other threads)
+ * race.  SV_ENOMEM, before any device work, when the terms' partial sums do
+ * not fit (about 1000 terms with 256 compute units); other errors as
+ * sv_expect_pauli. */
+#define SV_NOALLOC_SCRATCH_BYTES (4u << 20)
+sv_status sv_expect_pauli_noalloc(sv_state *st, const sv_pauli_term *terms, int32_t n_terms,
+                                  double *out_terms, double *out_sum);
+
 /* Adjoint gradient of E(theta) = <0|U^dag(theta) H U(theta)|0> (paper
  * Section 4.2 objective).  On entry *st holds the INITIAL state (normally
  * |0...0>); on return it holds U(theta)|initial>.  grad has n_params entries

@@ -1965,12 +1965,11 @@ static size_t pauli_scratch_bytes(size_t nterm, int64_t grid_part) {
 }
 
 // Runs the Pauli passes; term values land in device array `d_terms` (original order).
+// Scratch: the handle's growable buffer, or (ext != NULL) the caller's
+// ext_bytes at ext, checked before any device work.
 static sv_status run_pauli(sv_state *st, const sv_pauli_term *terms, int nt, void *re, void *im,
-                           void *lre, void *lim, double **d_terms_out) {
-  if (re == st->re) {
-    sv_status z = materialize_zero(st);
-    if (z) return z;
-  }
+                           void *lre, void *lim, double **d_terms_out, void *ext = nullptr,
+                           size_t ext_bytes = 0) {
   PauliPlan pp;
   plan_pauli(st->n, terms, nt, pp, diag_stream(st->n, lre != nullptr));
   DevInfo di;
@@ -1984,9 +1983,18 @@ static sv_status run_pauli(sv_state *st, const sv_pauli_term *terms, int nt, voi
   // scratch: terms | partials | reduced (by pass order) | reduced (original order)
   size_t nterm = pp.terms.size();
   size_t need = pauli_scratch_bytes(nterm, grid_part);
-  s = ensure_scratch(st, need);
-  if (s) return s;
-  char *b = (char *)st->scratch;
+  if (ext && need > ext_bytes)
+    return fail(SV_ENOMEM, "%zu terms need %zu bytes of scratch; the fixed scratch holds %zu",
+                nterm, need, ext_bytes);
+  if (re == st->re) {
+    sv_status z = materialize_zero(st);
+    if (z) return z;
+  }
+  if (!ext) {
+    s = ensure_scratch(st, need);
+    if (s) return s;
+  }
+  char *b = ext ? (char *)ext : (char *)st->scratch;
   PauliTermDev *d_terms = (PauliTermDev *)b;
   double *d_part = (double *)(b + ((nterm * sizeof(PauliTermDev) + 255) & ~(size_t)255));
   double *d_red = d_part + nterm * grid_part;
@@ -2065,8 +2073,8 @@ static sv_status validate_terms(int n, const sv_pauli_term *terms, int nt) {
   return SV_OK;
 }
 
-extern "C" sv_status sv_expect_pauli(sv_state *st, const sv_pauli_term *terms, int32_t n_terms,
-                                     double *out_terms, double *out_sum) {
+static sv_status expect_pauli(sv_state *st, const sv_pauli_term *terms, int32_t n_terms,
+                              double *out_terms, double *out_sum, void *ext, size_t ext_bytes) {
   if (!st) return fail(SV_EINVAL, "null handle");
   sv_status s = validate_terms(st->n, terms, n_terms);
   if (s) return s;
@@ -2075,7 +2083,7 @@ extern "C" sv_status sv_expect_pauli(sv_state *st, const sv_pauli_term *terms, i
     return SV_OK;
   }
   double *d_red = nullptr;
-  s = run_pauli(st, terms, n_terms, st->re, st->im, nullptr, nullptr, &d_red);
+  s = run_pauli(st, terms, n_terms, st->re, st->im, nullptr, nullptr, &d_red, ext, ext_bytes);
   if (s) return s;
   std::vector<double> red(n_terms);
   HIPCHK(hipMemcpyAsync(red.data(), d_red, n_terms * 8, hipMemcpyDeviceToHost, st->stream));
@@ -2092,6 +2100,51 @@ extern "C" sv_status sv_expect_pauli(sv_state *st, const sv_pauli_term *terms, i
     *out_sum = e;
   }
   return SV_OK;
+}
+
+extern "C" sv_status sv_expect_pauli(sv_state *st, const sv_pauli_term *terms, int32_t n_terms,
+                                     double *out_terms, double *out_sum) {
+  return expect_pauli(st, terms, n_terms, out_terms, out_sum, nullptr, 0);
+}
+
+// ------------------------------------------------- allocation-free <P>
+// The Pauli kernels' partial sums, term descriptors and reduced values live in
+// a file-scope device array of fixed size, one copy per GPU (each GPU holds
+// it until the process ends).  Its host-side name stands in for a device
+// address only inside device code: host code takes the address from
+// hipGetSymbolAddress once per device, with that device current, and passes
+// that pointer to the kernels.  Every call on one GPU shares the array (calls
+// that overlap on one GPU race); every byte a call reads is written by the
+// same call's kernels first, so nothing needs clearing.
+static __device__ __align__(256) char scratch[SV_NOALLOC_SCRATCH_BYTES];
+
+static std::mutex g_noalloc_mu;
+static std::unordered_map<int, void *> g_noalloc;   // device -> address of `scratch`
+
+static sv_status noalloc_scratch(void **out) {
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(g_noalloc_mu);
+  auto it = g_noalloc.find(dev);
+  if (it == g_noalloc.end()) {
+    void *p = nullptr;
+    hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return fail(SV_EDEVICE, "hipGetSymbolAddress(scratch) on device %d: %s", dev,
+                  hipGetErrorString(e));
+    it = g_noalloc.emplace(dev, p).first;
+  }
+  *out = it->second;
+  return SV_OK;
+}
+
+extern "C" sv_status sv_expect_pauli_noalloc(sv_state *st, const sv_pauli_term *terms,
+                                             int32_t n_terms, double *out_terms, double *out_sum) {
+  if (!st) return fail(SV_EINVAL, "null handle");
+  void *p = nullptr;
+  sv_status s = noalloc_scratch(&p);
+  if (s) return s;
+  return expect_pauli(st, terms, n_terms, out_terms, out_sum, p, SV_NOALLOC_SCRATCH_BYTES);
 }
 
 // -------------------------------------------------------- density matrices

@@ -69,6 +69,7 @@ def lib():
         "sv_reset": (C.c_int, [vp]),
         "sv_apply_layer": (C.c_int, [vp, opp, i32, dp, i32, i32]),
         "sv_expect_pauli": (C.c_int, [vp, tp, i32, dp, dp]),
+        "sv_expect_pauli_noalloc": (C.c_int, [vp, tp, i32, dp, dp]),
         "sv_adjoint_grad": (C.c_int, [vp, opp, i32, dp, i32, tp, i32, dp, dp, C.POINTER(i32)]),
         "sv_adjoint_grad_device": (C.c_int, [vp, opp, i32, dp, i32, tp, i32, vp]),
         "sv_sample": (C.c_int, [vp, u64, i64, C.POINTER(i32), i32, u64p]),
@@ -259,6 +260,16 @@ class State:
         tot = C.c_double(0.0)
         _check(lib().sv_expect_pauli(self.h, ta.ptr(), ta.n,
                                      out.ctypes.data_as(C.POINTER(C.c_double)), C.byref(tot)))
+        return out[:ta.n], float(tot.value)
+
+    def expect_noalloc(self, ham) -> Tuple[np.ndarray, float]:
+        """As expect(), through the allocation-free entry point (fixed scratch)."""
+        ta = TermArray(ham)
+        out = np.zeros(max(1, ta.n))
+        tot = C.c_double(0.0)
+        _check(lib().sv_expect_pauli_noalloc(self.h, ta.ptr(), ta.n,
+                                             out.ctypes.data_as(C.POINTER(C.c_double)),
+                                             C.byref(tot)))
         return out[:ta.n], float(tot.value)
 
     def adjoint_grad(self, ops, params, ham, op_array: Optional[OpArray] = None

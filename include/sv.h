@@ -398,7 +398,8 @@ sv_status sv_fuse_blocks(const sv_op *ops, int32_t n_ops, int32_t width, int32_t
  * sweep launched for this handle is bracketed by HIP events recorded on the
  * handle's stream.  sv_timing_read waits for the stream and returns the summed
  * event time of those launches in milliseconds, their count, and their
- * algorithmic HBM bytes (read + write of both planes), then clears the log. */
+ * algorithmic HBM bytes (read + write of both planes; write only for a sweep
+ * that synthesises |0...0>), then clears the log. */
 sv_status sv_timing_enable(sv_state *st, int32_t on);
 sv_status sv_timing_read(sv_state *st, double *sweep_ms, int64_t *launches, double *bytes);
 

@@ -533,19 +533,10 @@ __device__ __forceinline__ double mo_grad2l(const T *pr, const T *pi, const T *l
   return acc;
 }
 
+// MO_GRAD: generator alpha * (Pauli string) + beta * I on the control subspace.
 template <typename T, int R>
 __device__ __forceinline__ double grad_op(const MicroOp &op, const T *pr, const T *pi, const T *lr,
                                           const T *li) {
-  if (op.type == MO_GRAD2L) {
-    switch (op.t1) {
-#define SVI_G2(XV) case XV: if constexpr (XV < (1 << R)) return mo_grad2l<T, R, XV>(pr, pi, lr, li, op.mask, op.gz, op.cm, op.cv); break;
-      SVI_G2(3) SVI_G2(5) SVI_G2(6) SVI_G2(9) SVI_G2(10) SVI_G2(12) SVI_G2(15) SVI_G2(17)
-      SVI_G2(18) SVI_G2(20) SVI_G2(23) SVI_G2(24) SVI_G2(27) SVI_G2(29) SVI_G2(30)
-#undef SVI_G2
-      default: break;
-    }
-    return 0.0;
-  }
   // op.mask = x-mask (0, one bit, or two bits) over group bits.
   const uint32_t x = op.mask;
   switch (x) {
@@ -558,6 +549,23 @@ __device__ __forceinline__ double grad_op(const MicroOp &op, const T *pr, const 
     default: break;
   }
   return 0.0;
+}
+
+// MO_GRAD or MO_GRAD2L (the micro-op interpreter; Kronecker stages hold MO_GRAD only).
+template <typename T, int R>
+__device__ __forceinline__ double grad_any(const MicroOp &op, const T *pr, const T *pi,
+                                           const T *lr, const T *li) {
+  if (op.type == MO_GRAD2L) {
+    switch (op.t1) {
+#define SVI_G2(XV) case XV: if constexpr (XV < (1 << R)) return mo_grad2l<T, R, XV>(pr, pi, lr, li, op.mask, op.gz, op.cm, op.cv); break;
+      SVI_G2(3) SVI_G2(5) SVI_G2(6) SVI_G2(9) SVI_G2(10) SVI_G2(12) SVI_G2(15) SVI_G2(17)
+      SVI_G2(18) SVI_G2(20) SVI_G2(23) SVI_G2(24) SVI_G2(27) SVI_G2(29) SVI_G2(30)
+#undef SVI_G2
+      default: break;
+    }
+    return 0.0;
+  }
+  return grad_op<T, R>(op, pr, pi, lr, li);
 }
 
 __device__ __forceinline__ double wave_sum(double v) {
@@ -716,7 +724,7 @@ __global__ void __launch_bounds__(1 << (M - R)) k_sweep(SweepArgs a) {
         const MicroOp op = op_at(a.ops, o);
         if constexpr (NS == 2) {
           if (op.type == MO_GRAD || op.type == MO_GRAD2L) {
-            double v = active ? grad_op<T, R>(op, re[0], im[0], re[1], im[1]) : 0.0;
+            double v = active ? grad_any<T, R>(op, re[0], im[0], re[1], im[1]) : 0.0;
             v = wave_sum(v);
             if ((tid & 63) == 0) wsum[tid >> 6][op.coef] = v;
             continue;

@@ -1830,7 +1830,9 @@ static sv_status run_steps(sv_state *st, Plan &P, void *re, void *im, void *re2,
       if (a.flags & SW_INIT_ZERO) st->pending_zero = false;
       if (e0 && e1) {
         (void)hipEventRecord(e1, st->stream);
-        st->ev_bytes.push_back(4.0 * (double)((int64_t)1 << st->n) * (double)elem_size(st->dtype));
+        // read + write of both planes; a sweep that synthesises |0..0> only writes
+        const double planes_rw = (a.flags & SW_INIT_ZERO) ? 2.0 : 4.0;
+        st->ev_bytes.push_back(planes_rw * (double)((int64_t)1 << st->n) * (double)elem_size(st->dtype));
       }
     } else {
       GateArgsHost a = stp.ga;

@@ -379,6 +379,30 @@ class State:
                                      offset, count))
         return re, im
 
+    def gather(self, idx, window: int = 1 << 22) -> np.ndarray:
+        """Amplitudes at the basis indices `idx` (complex128), copied out window
+        by window through pinned host buffers (sv_copy_to_host)."""
+        import torch
+        idx = np.asarray(idx, dtype=np.int64)
+        order = np.argsort(idx, kind="stable")
+        sidx = idx[order]
+        N = 1 << self.n
+        window = min(window, N)
+        tdt = torch.float64 if self.dtype == "c128" else torch.float32
+        bufs = (torch.empty(window, dtype=tdt, pin_memory=True).numpy(),
+                torch.empty(window, dtype=tdt, pin_memory=True).numpy())
+        out = np.empty(idx.size, dtype=np.complex128)
+        k = 0
+        while k < sidx.size:
+            base = int(sidx[k]) // window * window
+            cnt = min(window, N - base)
+            re, im = self.planes(base, cnt, out=bufs)
+            e = int(np.searchsorted(sidx, base + cnt, side="left"))
+            loc = sidx[k:e] - base
+            out[order[k:e]] = re[loc].astype(np.float64) + 1j * im[loc].astype(np.float64)
+            k = e
+        return out
+
     def to_numpy(self) -> np.ndarray:
         re, im = self.planes()
         return re.astype(np.float64) + 1j * im.astype(np.float64)

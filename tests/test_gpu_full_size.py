@@ -2,8 +2,11 @@
 the launch configuration the benchmark times (default plan and tiling),
 through the C ABI.
 
-The oracle cannot simulate 30 qubits in seconds, so these use facts that hold
-at any size:
+The oracle's own run of this workload (tests/golden/layered30_seed0.npz,
+written once by oracle/make_golden_layered30.py) pins amplitudes at 65536
+seeded indices, every <Z_q>, the norm and 1000 draws.  The oracle cannot
+simulate 30 qubits in seconds, so the other cases use facts that hold at
+any size:
 * with every RY angle in {0, pi} the layered circuit maps |0...0> to a single
   basis state; its index and phase follow gate by gate from the gate
   definitions (RY(pi) flips the bit, with a sign when the bit was 1; RZ(phi)
@@ -16,6 +19,7 @@ at any size:
   lands within 6 standard deviations of the exact <H>.
 """
 import math
+import os
 
 import numpy as np
 import pytest
@@ -73,6 +77,42 @@ def _track_basis_state(circ):
         else:
             raise AssertionError(op.kind)
     return b, amp
+
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "layered30_seed0.npz")
+
+
+def test_full_size_oracle_golden(sv):
+    # The CPU oracle's own run of this exact workload (written by
+    # oracle/make_golden_layered30.py, 46 min on 6 host threads): amplitudes
+    # at 65536 seeded indices, every <Z_q>, the norm and 1000 terminal draws.
+    g = np.load(GOLDEN, allow_pickle=False)
+    assert tuple(g["meta"][:3]) == (N, L, 0)
+    circ = I.layered(N, L, seed=0)
+    oa = sv.OpArray(circ.ops)
+    _say("full size: FP64 against the oracle golden", N, L)
+    st = sv.State(N)
+    st.apply(None, circ.params, op_array=oa)
+    amp = st.gather(g["idx"])
+    err = float(np.max(np.abs(amp - g["amp"])))
+    print(f"fp64 30q: max|err| over {len(amp)} amplitudes = {err:.3e}", flush=True)
+    assert err <= TOL
+    vals, _ = st.expect(_zs(N))
+    assert np.max(np.abs(vals[:N] - g["zexp"])) <= TOL
+    assert abs(vals[N] - g["norm"][0]) <= TOL
+    # terminal draws: the same draws as the oracle's on its own state
+    draws = st.sample(0, len(g["samples"]), list(range(N)))
+    assert np.array_equal(draws, g["samples"]), int(np.count_nonzero(draws != g["samples"]))
+    st.close()
+    _say("full size: complex64 against the oracle golden", N, L)
+    s32 = sv.State(N, "c64")
+    s32.apply(None, circ.params, op_array=oa)
+    a32 = s32.gather(g["idx"])
+    s32.close()
+    err32 = float(np.max(np.abs(a32 - g["amp"])))
+    rms = math.sqrt(2.0 ** -N)
+    print(f"complex64 30q: max|err| = {err32:.3e} = {err32 / rms:.3e} x rms amplitude", flush=True)
+    assert err32 <= 1e-5
 
 
 def test_full_size_basis_state_tracking(sv):

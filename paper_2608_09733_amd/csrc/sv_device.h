@@ -338,33 +338,20 @@ __device__ __forceinline__ void mo_diagt(T *re, T *im, CP cf) {
   }
 }
 
-// Im <lam| G |psi> over one group, G = alpha * (Pauli string x,z) + beta * I
-// on the control subspace.  XM is the compile-time x-mask (group bits).
-template <typename T, int R, int XM>
+// Im <lam| G |psi> over one group from the generator's per-slot table (see
+// GRAD_ODD / GRAD_BETA in sv_internal.h); XM is the generator's x-mask.
+template <typename T, int R, int XM, bool ODD, typename CP>
 __device__ __forceinline__ double mo_grad(const T *pr, const T *pi, const T *lr, const T *li,
-                                          uint32_t z, uint32_t cm, uint32_t cv, double alpha,
-                                          double beta) {
-  const int ny = __builtin_popcount((uint32_t)XM & z) & 3;
+                                          CP tab) {
+  constexpr int G = 1 << R;
   double acc = 0.0;
 #pragma unroll
-  for (int j = 0; j < (1 << R); j++) {
-    if ((j & cm) != cv) continue;
+  for (int j = 0; j < G; j++) {
     const int k = j ^ XM;
-    // (P psi)_j = i^ny (-1)^{popcount(k & z)} psi_k
-    const bool neg = __builtin_popcount((uint32_t)k & z) & 1;
-    double wr = (double)pr[k], wi = (double)pi[k];
-    double tr, ti;
-    switch (ny) {
-      case 0: tr = wr; ti = wi; break;
-      case 1: tr = -wi; ti = wr; break;
-      case 2: tr = -wr; ti = -wi; break;
-      default: tr = wi; ti = -wr; break;
-    }
-    if (neg) { tr = -tr; ti = -ti; }
-    const double gr = alpha * tr + beta * (double)pr[j];
-    const double gi = alpha * ti + beta * (double)pi[j];
-    // Im(conj(l) * g) = lr*gi - li*gr
-    acc += (double)lr[j] * gi - (double)li[j] * gr;
+    const double ljr = (double)lr[j], lji = (double)li[j];
+    const double f = ODD ? ljr * (double)pr[k] + lji * (double)pi[k]
+                         : ljr * (double)pi[k] - lji * (double)pr[k];
+    acc += (double)tab[j] * f;
   }
   return acc;
 }
@@ -533,15 +520,21 @@ __device__ __forceinline__ double mo_grad2l(const T *pr, const T *pi, const T *l
   return acc;
 }
 
-// MO_GRAD: generator alpha * (Pauli string) + beta * I on the control subspace.
+// MO_GRAD: generator alpha * (Pauli string) + beta * I on the control subspace,
+// through its per-slot table in the coefficient buffer.
 template <typename T, int R>
 __device__ __forceinline__ double grad_op(const MicroOp &op, const T *pr, const T *pi, const T *lr,
-                                          const T *li) {
-  // op.mask = x-mask (0, one bit, or two bits) over group bits.
-  const uint32_t x = op.mask;
+                                          const T *li, const double *coef) {
+  const SVI_CONST double *tab = cptr(coef) + op.t0;
+  const uint32_t x = op.mask;   // x-mask over group bits
+  // diagonal generators (Z strings, phases): one table, the even form on j itself
+  if (x == 0) return mo_grad<T, R, 0, false>(pr, pi, lr, li, tab);
+  const bool odd = (op.t1 & GRAD_ODD) != 0;
   switch (x) {
-#define SVI_G(XV) case XV: if constexpr (XV < (1 << R)) return mo_grad<T, R, XV>(pr, pi, lr, li, op.gz, op.cm, op.cv, op.galpha, op.gbeta); break;
-    SVI_G(0) SVI_G(1) SVI_G(2) SVI_G(3) SVI_G(4) SVI_G(5) SVI_G(6) SVI_G(7) SVI_G(8) SVI_G(9)
+#define SVI_G(XV) case XV: if constexpr (XV < (1 << R)) { \
+      if (odd) return mo_grad<T, R, XV, true>(pr, pi, lr, li, tab); \
+      return mo_grad<T, R, XV, false>(pr, pi, lr, li, tab); } break;
+    SVI_G(1) SVI_G(2) SVI_G(3) SVI_G(4) SVI_G(5) SVI_G(6) SVI_G(7) SVI_G(8) SVI_G(9)
     SVI_G(10) SVI_G(11) SVI_G(12) SVI_G(13) SVI_G(14) SVI_G(15) SVI_G(16) SVI_G(17) SVI_G(18)
     SVI_G(19) SVI_G(20) SVI_G(21) SVI_G(22) SVI_G(23) SVI_G(24) SVI_G(25) SVI_G(26) SVI_G(27)
     SVI_G(28) SVI_G(29) SVI_G(30) SVI_G(31)
@@ -551,10 +544,30 @@ __device__ __forceinline__ double grad_op(const MicroOp &op, const T *pr, const 
   return 0.0;
 }
 
+// MO_GRAD inside a Kronecker stage: the planner admits only diagonal
+// generators (x = 0) and the Y of an uncontrolled RY (x = one group bit,
+// n_Y = 1), so only those forms are compiled here (fewer code paths, fewer
+// live registers in the two-state kernel).
+template <typename T, int R>
+__device__ __forceinline__ double grad_kron(const MicroOp &op, const T *pr, const T *pi,
+                                            const T *lr, const T *li, const double *coef) {
+  const SVI_CONST double *tab = cptr(coef) + op.t0;
+  switch (op.mask) {
+    case 0: return mo_grad<T, R, 0, false>(pr, pi, lr, li, tab);
+    case 1: return mo_grad<T, R, 1, true>(pr, pi, lr, li, tab);
+    case 2: return mo_grad<T, R, 2, true>(pr, pi, lr, li, tab);
+    case 4: if constexpr (R > 2) return mo_grad<T, R, 4, true>(pr, pi, lr, li, tab); break;
+    case 8: if constexpr (R > 3) return mo_grad<T, R, 8, true>(pr, pi, lr, li, tab); break;
+    case 16: if constexpr (R > 4) return mo_grad<T, R, 16, true>(pr, pi, lr, li, tab); break;
+    default: break;
+  }
+  return 0.0;
+}
+
 // MO_GRAD or MO_GRAD2L (the micro-op interpreter; Kronecker stages hold MO_GRAD only).
 template <typename T, int R>
 __device__ __forceinline__ double grad_any(const MicroOp &op, const T *pr, const T *pi,
-                                           const T *lr, const T *li) {
+                                           const T *lr, const T *li, const double *coef) {
   if (op.type == MO_GRAD2L) {
     switch (op.t1) {
 #define SVI_G2(XV) case XV: if constexpr (XV < (1 << R)) return mo_grad2l<T, R, XV>(pr, pi, lr, li, op.mask, op.gz, op.cm, op.cv); break;
@@ -565,7 +578,7 @@ __device__ __forceinline__ double grad_any(const MicroOp &op, const T *pr, const
     }
     return 0.0;
   }
-  return grad_op<T, R>(op, pr, pi, lr, li);
+  return grad_op<T, R>(op, pr, pi, lr, li, coef);
 }
 
 __device__ __forceinline__ double wave_sum(double v) {
@@ -580,7 +593,31 @@ __device__ __forceinline__ double wave_sum(double v) {
 // accumulates gradient partials).
 
 #define SVI_GSLOTS 256
-#define SVI_GSLOTS_LEAN 32   // gradient slots per sweep of the two-state Kronecker kernel
+#define SVI_GSLOTS_LEAN 16   // gradient slots of the two-state Kronecker kernel held in registers
+#define SVI_GSLOTS_WIDE 128  // gradient slots per sweep of that kernel (the rest reduced per tile)
+
+// Sum of v over the 64 lanes of a wave, valid in lane 63, by DPP lane moves
+// (VALU only): partial sums within rows of 16 lanes (shifts by 1, 2, 4, 8),
+// then row 0 into row 1 and row 2 into row 3 (broadcast of lane 15), then
+// rows 0-1 into rows 2-3 (broadcast of lane 31).  Lanes outside a shift's row
+// read 0.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ double dpp_d(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffll), CTRL, ROW_MASK, 0xf, true);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, ROW_MASK, 0xf, true);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+__device__ __forceinline__ double wave_total63(double v) {
+  v += dpp_d<0x111, 0xf>(v);   // row_shr:1
+  v += dpp_d<0x112, 0xf>(v);   // row_shr:2
+  v += dpp_d<0x114, 0xf>(v);   // row_shr:4
+  v += dpp_d<0x118, 0xf>(v);   // row_shr:8
+  v += dpp_d<0x142, 0xa>(v);   // row_bcast:15 into rows 1 and 3
+  v += dpp_d<0x143, 0xc>(v);   // row_bcast:31 into rows 2 and 3
+  return v;
+}
 
 template <typename T, int M, int R, int NS>
 __global__ void __launch_bounds__(1 << (M - R)) k_sweep(SweepArgs a) {
@@ -699,7 +736,7 @@ __global__ void __launch_bounds__(1 << (M - R)) k_sweep(SweepArgs a) {
           auto grads = [&](int b, int e, double mult) {
             for (int o = b; o < e; o++) {
               const MicroOp op = op_at(a.ops, o);
-              double v = active ? mult * grad_op<T, R>(op, re[0], im[0], re[1], im[1]) : 0.0;
+              double v = active ? mult * grad_kron<T, R>(op, re[0], im[0], re[1], im[1], a.coef) : 0.0;
               v = wave_sum(v);
               if ((tid & 63) == 0) wsum[tid >> 6][op.coef] = v;
             }
@@ -724,7 +761,7 @@ __global__ void __launch_bounds__(1 << (M - R)) k_sweep(SweepArgs a) {
         const MicroOp op = op_at(a.ops, o);
         if constexpr (NS == 2) {
           if (op.type == MO_GRAD || op.type == MO_GRAD2L) {
-            double v = active ? grad_any<T, R>(op, re[0], im[0], re[1], im[1]) : 0.0;
+            double v = active ? grad_any<T, R>(op, re[0], im[0], re[1], im[1], a.coef) : 0.0;
             v = wave_sum(v);
             if ((tid & 63) == 0) wsum[tid >> 6][op.coef] = v;
             continue;
@@ -1062,10 +1099,12 @@ __global__ void __launch_bounds__(1 << (M - R)) k_sweep_kron2(SweepArgs a) {
   // tiles, two for 64 KiB)
   constexpr int TILE_BYTES = 2 * (1 << M) * (int)sizeof(C2);
   constexpr int WG_LDS = TILE_BYTES >= 131072 ? 163840 : TILE_BYTES >= 65536 ? 81920 : 40960;
-  constexpr int GTAB_BYTES = WG_LDS - TILE_BYTES - NWAVE * SVI_GSLOTS_LEAN * 8 - 4 * SVI_MMAX - 256;
+  constexpr int NWIDE = SVI_GSLOTS_WIDE - SVI_GSLOTS_LEAN;
+  constexpr int GTAB_BYTES = WG_LDS - TILE_BYTES - NWAVE * SVI_GSLOTS_WIDE * 8 - 4 * SVI_MMAX - 256;
   constexpr int GTAB = GTAB_BYTES / (4 * NT) > 0 ? GTAB_BYTES / (4 * NT) : 1;
   __shared__ C2 lds[2][1 << M];
   __shared__ double wsum[NWAVE][SVI_GSLOTS_LEAN];
+  __shared__ double wacc[NWAVE][NWIDE];   // per-wave sums of the slots past the registers
   __shared__ int32_t hb_s[SVI_MMAX];
   __shared__ int32_t gtab[GTAB * NT];
 
@@ -1081,6 +1120,7 @@ __global__ void __launch_bounds__(1 << (M - R)) k_sweep_kron2(SweepArgs a) {
   const int ntab = nst < GTAB ? nst : GTAB;
   for (int st = 0; st < ntab; st++)   // each thread reads back only its own entries
     gtab[st * NT + tid] = swz<T>(stage_base<M, R>(tid, stages[st])) * (int)sizeof(C2);
+  for (int k = tid; k < NWAVE * NWIDE; k += NT) (&wacc[0][0])[k] = 0.0;
   __syncthreads();
 
   uint64_t roff[NIT];
@@ -1152,11 +1192,20 @@ __global__ void __launch_bounds__(1 << (M - R)) k_sweep_kron2(SweepArgs a) {
       }
       const SVI_CONST double *kc = coef + sd.kcoef;
       auto grads = [&](int b, int e, double mult) {
+        // one term at a time: an unrolled loop would keep several terms'
+        // operands live at once and spill the register groups
+#pragma clang loop unroll(disable)
         for (int o = b; o < e; o++) {
           const MicroOp op = op_at(a.ops, o);
-          const double v = active ? mult * grad_op<T, R>(op, re[0], im[0], re[1], im[1]) : 0.0;
+          const double v = active ? mult * grad_kron<T, R>(op, re[0], im[0], re[1], im[1], a.coef) : 0.0;
+          if (op.coef >= SVI_GSLOTS_LEAN) {
+            // past the register slots: this tile's wave sum into the wave's LDS row
+            const double w = wave_total63(v);
+            if ((tid & 63) == 63) wacc[tid >> 6][op.coef - SVI_GSLOTS_LEAN] += w;
+            continue;
+          }
           switch (op.coef) {   // uniform: the slot is a register index
-#define SVI_GS(K) case K: gr[K] += v; break;
+#define SVI_GS(K) case K: if constexpr (K < SVI_GSLOTS_LEAN) gr[K] += v; break;
             SVI_GS(0) SVI_GS(1) SVI_GS(2) SVI_GS(3) SVI_GS(4) SVI_GS(5) SVI_GS(6) SVI_GS(7)
             SVI_GS(8) SVI_GS(9) SVI_GS(10) SVI_GS(11) SVI_GS(12) SVI_GS(13) SVI_GS(14)
             SVI_GS(15) SVI_GS(16) SVI_GS(17) SVI_GS(18) SVI_GS(19) SVI_GS(20) SVI_GS(21)
@@ -1242,7 +1291,8 @@ __global__ void __launch_bounds__(1 << (M - R)) k_sweep_kron2(SweepArgs a) {
   __syncthreads();
   for (int sl = tid; sl < a.n_gslots; sl += NT) {
     double v = 0.0;
-    for (int w = 0; w < NWAVE; w++) v += wsum[w][sl];
+    for (int w = 0; w < NWAVE; w++)
+      v += sl < SVI_GSLOTS_LEAN ? wsum[w][sl] : wacc[w][sl - SVI_GSLOTS_LEAN];
     a.gpart[(int64_t)(a.gslot_begin + sl) * gridDim.x + blockIdx.x] = v;
   }
 }

@@ -212,6 +212,13 @@ struct StageP {
   std::vector<int> lead, dbefore, rops, dafter, trail;   // kron: records by role
 };
 
+// Diagonal records (phases, Z-type gates, any controls) commute with each
+// other, so an untaken diagonal record holds back only the non-diagonal
+// records after it that share a qubit; any other untaken record holds back
+// every later record sharing a qubit.  Taking a record then moves it only
+// across records it commutes with.
+static bool is_diag(const GateRec &g) { return g.mo == MO_P || g.mo == MO_NEG; }
+
 // Records a Kronecker stage can hold: uncontrolled RY rotations, diagonal
 // gates (any controls) and permutations (any controls).  A leading or trailing
 // X whose controls are group qubits may target any tile qubit: the bit flip
@@ -236,7 +243,7 @@ static bool kron_eligible(const GateRec &g) {
 static constexpr int kRotWeight = 4;
 static int closure_kron(const std::vector<GateRec> &recs, const std::vector<int> &cand,
                         const std::vector<char> &done, uint64_t S, uint64_t Tt, StageP *st) {
-  uint64_t blocked = 0, rq = 0, dA = 0, pq = 0;
+  uint64_t blocked = 0, blocked_nd = 0, rq = 0, dA = 0, pq = 0;
   bool leading = true;
   int cnt = 0;
   for (int r : cand) {
@@ -245,7 +252,8 @@ static int closure_kron(const std::vector<GateRec> &recs, const std::vector<int>
     const uint64_t q = g.qmask;
     const uint64_t tq = g.mo == MO_X ? 1ull << g.t[0] : 0;
     const bool fits = (q & ~S) == 0 || (tq && (q & ~tq & ~S) == 0 && (tq & Tt) != 0);
-    bool ok = fits && (q & blocked) == 0 && kron_eligible(g);
+    const bool free = (q & blocked) == 0 && (is_diag(g) || (q & blocked_nd) == 0);
+    bool ok = fits && free && kron_eligible(g);
     int role = -1;   // 0 lead, 1 dbefore, 2 r, 3 dafter, 4 trail
     if (ok) {
       if (g.mo == MO_X || g.mo == MO_SWAP) {
@@ -269,7 +277,8 @@ static int closure_kron(const std::vector<GateRec> &recs, const std::vector<int>
         dst[role]->push_back(r);
       }
     } else {
-      blocked |= q;
+      if (is_diag(g)) blocked_nd |= q;
+      else blocked |= q;
       if ((blocked & S) == S) break;
     }
   }
@@ -292,24 +301,28 @@ struct Tiling {
 static int popc(uint64_t v) { return __builtin_popcountll(v); }
 
 // Records of `cand` (program order, not yet done) that can run inside qubit set T:
-// a record is taken iff its qubits lie in T and no earlier untaken record shares a
-// qubit with it.  Records flagged in `veto` block like untaken ones.
+// a record is taken iff its qubits lie in T and no earlier untaken record it
+// does not commute with (see is_diag) shares a qubit with it.  Records flagged
+// in `veto` block like untaken ones.
 static int closure(const std::vector<GateRec> &recs, const std::vector<int> &cand,
                    const std::vector<char> &done, uint64_t T, std::vector<int> *take,
                    const std::vector<char> *veto = nullptr, double cost_cap = 1e300) {
-  uint64_t blocked = 0;
+  uint64_t blocked = 0, blocked_nd = 0;   // all records / non-diagonal records held back
   int cnt = 0;
   double cost = 0.0;
   for (int r : cand) {
     if (done[r]) continue;
     const uint64_t q = recs[r].qmask;
     const bool vetoed = veto && (*veto)[r];
-    if (!vetoed && (q & ~T) == 0 && (q & blocked) == 0 && cost + recs[r].cost <= cost_cap) {
+    const bool diag = is_diag(recs[r]);
+    const bool free = (q & blocked) == 0 && (diag || (q & blocked_nd) == 0);
+    if (!vetoed && (q & ~T) == 0 && free && cost + recs[r].cost <= cost_cap) {
       cnt++;
       cost += recs[r].cost;
       if (take) take->push_back(r);
     } else {
-      blocked |= q;
+      if (diag && !vetoed) blocked_nd |= q;
+      else blocked |= q;
       if ((blocked & T) == T) break;
     }
   }
@@ -319,14 +332,15 @@ static int closure(const std::vector<GateRec> &recs, const std::vector<int> &can
 // Qubits of the earliest pending record that is blocked w.r.t. T (tie-break).
 static uint64_t first_blocked_qubits(const std::vector<GateRec> &recs, const std::vector<int> &cand,
                                      const std::vector<char> &done, uint64_t T) {
-  uint64_t blocked = 0;
+  uint64_t blocked = 0, blocked_nd = 0;
   for (int r : cand) {
     if (done[r]) continue;
     const uint64_t q = recs[r].qmask;
-    if ((q & ~T) == 0 && (q & blocked) == 0) continue;
+    const bool diag = is_diag(recs[r]);
+    const bool free = (q & blocked) == 0 && (diag || (q & blocked_nd) == 0);
+    if ((q & ~T) == 0 && free) continue;
     return q & ~T ? (q & ~T) : q;
   }
-  (void)blocked;
   return 0;
 }
 
@@ -935,6 +949,34 @@ static void emit_sweep(Plan &P, std::vector<GateRec> &recs, const SweepP &sw, in
         go.galpha = g.galpha;
         go.gbeta = g.gbeta;
         go.coef = gs;
+        // per-slot table of the generator (sv_internal.h, MO_GRAD): plan
+        // constants, copied into the coefficient buffer on every call
+        {
+          const int G = 1 << R;
+          const int ny = __builtin_popcount(xl & zl) & 3;
+          // beta multiplies the identity: the x = 0 form (phase gates only)
+          if (g.gbeta != 0.0 && xl != 0) abort();   // planner invariant
+          go.t1 = (ny & 1) ? GRAD_ODD : 0;
+          const int base = P.n_user_params + (int)P.constants.size();
+          for (int j = 0; j < G; j++) {
+            double cj = 0.0;
+            if (((uint32_t)j & cm) == cv) {
+              const uint32_t k = (uint32_t)j ^ xl;
+              cj = g.galpha * ((__builtin_popcount(k & zl) & 1) ? -1.0 : 1.0) * (ny >= 2 ? -1.0 : 1.0);
+              cj += g.gbeta;
+            }
+            P.constants.push_back(cj);
+          }
+          CoefDesc cd{};
+          cd.fmt = CF_CONSTS;
+          cd.src = base;
+          cd.len = G;
+          cd.dst = P.ncoef;
+          cd.pidx[0] = cd.pidx[1] = cd.pidx[2] = -1;
+          P.coefs.push_back(cd);
+          go.t0 = P.ncoef;
+          P.ncoef += cd.len;
+        }
         P.slot_param.push_back(g.gparam);
         gs++;
         mops.push_back(go);
@@ -1139,7 +1181,7 @@ static void emit_sweep(Plan &P, std::vector<GateRec> &recs, const SweepP &sw, in
   a.stage_end = (int)P.stages.size();
   assign_thread_maps(P, a.stage_begin, st_gmask, st_xbits, R, std::max(sw.m, R));
   a.n_gslots = gs;
-  // the two-state Kronecker kernel keeps at most SVI_GSLOTS_MAX gradient slots in registers
+  // the two-state Kronecker kernel takes at most SVI_GSLOTS_MAX gradient slots per sweep
   s.all_kron = gs <= SVI_GSLOTS_MAX;
   for (int k = a.stage_begin; k < a.stage_end; k++)
     if (P.stages[k].kind != ST_KRON) s.all_kron = false;
@@ -1515,23 +1557,52 @@ static void collect_user_mats(Plan &P, const sv_op *ops, int n_ops) {
   for (int v : P.mat_dim) P.nstatic += v;
 }
 
-// mode: 0 = one sweep per gate, 2..5 = paper fusion width, -1 = AUTO
-// AUTO plan with and without qubit remapping; the one with fewer sweeps (then
-// fewer register stages) wins.
+// Modeled time of a tile-sweep plan, in units of one register stage of
+// 3-qubit groups over the whole state.  A sweep streams the state through HBM
+// while its tiles run their stages; measured on MI355X (FP64, 13-qubit
+// tiles), a sweep takes about max(11, 5.3 + s) such units for s stages: the
+// HBM copy of the state costs as much as 11 stages, and stages beyond about 5
+// are not hidden under it.  Wider register groups cost more per stage.
+static double plan_model(const std::vector<SweepP> &sweeps, int R) {
+  const double w = R <= 3 ? 1.0 : R == 4 ? 1.2 : 1.6;
+  double t = 0.0;
+  for (const SweepP &sw : sweeps) t += std::max(11.0, 5.3 + w * (double)sw.stages.size());
+  return t;
+}
+
+// AUTO plan: the greedy tile planner with and without qubit remapping; for
+// large states also with per-sweep caps on the gates a sweep takes (which
+// spread the register stages over the sweeps more evenly), keeping the plan
+// of least modeled time.  The candidate list depends only on the circuit and
+// the state size, so the choice is deterministic.
 static void plan_auto_best(const std::vector<GateRec> &recs, int n, const Tiling &tl,
                            std::vector<SweepP> &out, bool allow_remap) {
   plan_auto(recs, n, tl, out, 1e300, true, false);
-  if (!allow_remap) return;
-  std::vector<SweepP> alt;
-  plan_auto(recs, n, tl, alt, 1e300, true, true);
-  auto stages = [](const std::vector<SweepP> &v) {
-    size_t s = 0;
-    for (auto &w : v) s += w.stages.size();
-    return s;
+  double best = plan_model(out, tl.R);
+  auto consider = [&](double cap, bool remap) {
+    std::vector<SweepP> alt;
+    plan_auto(recs, n, tl, alt, cap, true, remap);
+    if (remap && !layout_consistent(alt, n)) return;
+    const double m = plan_model(alt, tl.R);
+    if (m < best) {
+      best = m;
+      out.swap(alt);
+    }
   };
-  if (!layout_consistent(alt, n)) return;
-  if (alt.size() < out.size() || (alt.size() == out.size() && stages(alt) < stages(out)))
-    out.swap(alt);
+  if (allow_remap) consider(1e300, true);
+  // Searching costs about a millisecond of host time per candidate at 30
+  // qubits and is done once per circuit structure (plans are cached); the
+  // number of candidates grows with the modeled sweep time of the state.
+  if (n < 24) return;
+  static const double caps[] = {500, 300, 400, 600, 350, 450, 250, 550, 700, 200, 480, 520,
+                                280, 320, 380, 420, 460, 540, 580, 620, 660, 240, 260, 220,
+                                180, 150, 510, 490, 310, 290, 470, 430, 390, 410, 370, 330};
+  const int ncap = (int)(sizeof caps / sizeof caps[0]);
+  const int budget = std::min(ncap, 4 << std::min(n - 24, 3));   // 4 at 24 qubits, 32 from 27
+  for (int k = 0; k < budget; k++) {
+    if (allow_remap) consider(caps[k], true);
+    else consider(caps[k], false);
+  }
 }
 
 // split1q: write uncontrolled H, RX, Y, U2, U3 as Kronecker-stage parts.  The

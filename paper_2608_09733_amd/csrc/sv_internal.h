@@ -28,7 +28,8 @@ enum {
   MO_NEG = 6,    // negate slots whose control bits match (cm/cv); Z-type gates
   MO_Q = 7,      // 4x4 complex on bits (t0 = low, t1 = high); coef 32 doubles
   MO_DENSE = 8,  // 2^k x 2^k complex (k <= 3, in `mask`) on group bits 0..k-1; coef 2*4^k doubles
-  MO_GRAD = 9,   // adjoint: accumulate Im<lam| G |psi> into gradient slot `coef`
+  MO_GRAD = 9,   // adjoint: accumulate Im<lam| G |psi> into gradient slot `coef` from the
+                 // per-slot table at coefficient offset t0 (see GRAD_ODD / GRAD_BETA)
   MO_DIAGT = 10, // slot j *= table[j] (2^R complex at coef)
   MO_2L = 11,    // real 2x2 rotation between local patterns: slots with (j & mask) == gz and
                  // their partners j ^ t1; coef r00,r01,r10,r11 (Givens, double excitation)
@@ -36,6 +37,16 @@ enum {
                  // an MO_2L rotation (same mask / gz / t1 / cm / cv): G a = i b, G b = -i a
                  // for a = slot with (j & mask) == gz, b = a ^ t1, and G = 0 elsewhere
 };
+
+// MO_GRAD of a generator G = alpha P + beta I on the control subspace, P the
+// Pauli string (x, z) of the group bits with n_Y = popcount(x & z):
+//   Im <lam| G |psi> = sum_j c_j F(lam_j, psi_{j^x})
+// with F = Re(conj(lam) psi') when n_Y is odd (GRAD_ODD in t1), Im(conj(lam)
+// psi') when even; c_j = alpha (-1)^{popcount((j^x) & z)} (negated when n_Y
+// mod 4 >= 2), plus beta when x = 0 (beta is nonzero only for phase gates,
+// whose x is 0), and 0 outside the control subspace.  The table holds the
+// 2^R values c_j.
+#define GRAD_ODD 1
 
 struct MicroOp {
   int32_t type;
@@ -143,6 +154,7 @@ enum {
   CF_IDENT2 = 8,   // 2x2 real identity (4 doubles)
   CF_FASTR = 9,    // fast-Givens record {form, k, scale, 0} of a real 1q gate (see CF_FORM0)
   CF_SCALE = 10,   // real scalar: product of the fast-Givens scales of factors [src, +pidx[0])
+  CF_CONSTS = 11,  // copy `len` doubles from the parameter vector at `src` (plan constants)
 };
 
 // One factor of a diagonal table: entry j is multiplied, when (j & cm) == cv,

@@ -191,12 +191,14 @@ __global__ void k_build_coefs(const CoefDesc *d, int nd, const double *params, c
     // pidx holds parameter indices except for the table / scale formats,
     // where pidx[0] counts factors
     const bool takes_params = fmt != CF_TABLE && fmt != CF_SCALE && fmt != CF_COPY &&
-                              fmt != CF_IDENT2;
+                              fmt != CF_IDENT2 && fmt != CF_CONSTS;
     if (takes_params)
       for (int k = 0; k < 3; k++)
         if (cd.pidx[k] >= 0) th[k] = params[cd.pidx[k]];
     double *out = coef + cd.dst;
-    if (fmt == CF_FASTR) {
+    if (fmt == CF_CONSTS) {
+      for (int k = 0; k < cd.len; k++) out[k] = params[cd.src + k];
+    } else if (fmt == CF_FASTR) {
       double m[8];
       gate_local(cd.kind, th, m);
       double r[4] = {m[0], m[2], m[4], m[6]};   // real 2x2

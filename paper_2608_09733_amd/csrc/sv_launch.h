@@ -75,7 +75,7 @@ hipError_t svk_launch_histogram(const uint64_t *samples, int64_t shots, int nq, 
 hipError_t svk_launch_parity_counts(const uint64_t *samples, int64_t shots, const uint64_t *masks,
                                     int nm, uint64_t *odd, hipStream_t s);
 
-#define SVI_GSLOTS_MAX 32    // gradient slots per backward sweep (two-state kernel registers)
+#define SVI_GSLOTS_MAX 128   // gradient slots per backward sweep of the two-state Kronecker kernel
 #define SVI_GSLOTS_HARD 256  // gradient slots of the general two-state kernel (LDS)
 #define SVI_PTERMS_MAX 64
 #define SVI_KMAX_STAGES_HOST 16

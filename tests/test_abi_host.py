@@ -186,10 +186,30 @@ def test_kronecker_stages_take_ladder_cnots_with_outside_targets(sv):
     n, L = 30, 20
     ops = I.layered_structure(n, L)
     sweeps, stages = sv.plan_stats(n, ops, -1, 13, 5, 3)
-    assert sweeps == 30
+    assert sweeps <= 30
     assert n * L / stages >= 2.3, stages
     sweeps4, stages4 = sv.plan_stats(n, ops, -1, 13, 5, 4)
     assert n * L / stages4 >= 3.0, stages4
+
+
+def test_plan_search_beats_greedy_on_headline(sv):
+    # the AUTO planner keeps, among the greedy plan and capped variants, the
+    # one of least modeled sweep time: on the 30-qubit headline circuit it
+    # takes fewer sweeps and fewer register stages than the plain greedy plan
+    # (30 sweeps, 250 stages)
+    ops = I.layered_structure(30, 20)
+    sweeps, stages = sv.plan_stats(30, ops, -1, 13, 5, 3)
+    assert sweeps <= 27 and stages <= 245, (sweeps, stages)
+
+
+def test_diagonal_gates_commute_in_the_planner(sv):
+    # the CZ ring of the hardware-efficient ansatz is diagonal: its gates
+    # commute with each other, so the planner may take a later one before an
+    # earlier one that must wait for its tile; the 26-qubit, 10-layer ansatz
+    # fits in 7 sweeps (29 when the ring is ordered gate by gate)
+    ops = I.hea_structure(26, 10)
+    sweeps, _ = sv.plan_stats(26, ops, -1, 13, 5, 3)
+    assert sweeps <= 8, sweeps
 
 
 def test_default_tiling_query(sv):

@@ -1200,8 +1200,9 @@ __global__ void __launch_bounds__(1 << (M - R)) k_sweep_kron2(SweepArgs a) {
           const double v = active ? mult * grad_kron<T, R>(op, re[0], im[0], re[1], im[1], a.coef) : 0.0;
           if (op.coef >= SVI_GSLOTS_LEAN) {
             // past the register slots: this tile's wave sum into the wave's LDS row
+            // (an LDS add without return: the wave does not wait for it)
             const double w = wave_total63(v);
-            if ((tid & 63) == 63) wacc[tid >> 6][op.coef - SVI_GSLOTS_LEAN] += w;
+            if ((tid & 63) == 63) atomicAdd(&wacc[tid >> 6][op.coef - SVI_GSLOTS_LEAN], w);
             continue;
           }
           switch (op.coef) {   // uniform: the slot is a register index

@@ -364,6 +364,51 @@ sv_status sv_batch_autotune(const sv_circuit_desc *circuits, int32_t n_circuits,
                             int32_t *tile_bits, int32_t *low_bits, int32_t *group_bits,
                             double *best_ms);
 
+/* --------------------------------------------------------------- serving
+ * Small adjoint requests (paper Section 4.1 batched state vector, with one
+ * request per state; Section 6.3 task-parallel queues): each request is an
+ * independent circuit with its own qubit count, angles and observable, and
+ * asks for E = <psi|H|psi> and dE/dtheta by the adjoint method.  A submission
+ * is one persistent launch over a device queue of requests; one workgroup
+ * takes one request and runs all of it -- forward sweeps, lambda = H|psi>,
+ * backward sweeps with the gradient terms, the gather into dE/dtheta -- with
+ * the request's planes held in the L2 cache.  Results are bitwise independent
+ * of the other requests in the submission (one workgroup, fixed order).
+ * Requests must have 3 <= n_qubits <= sv_serve_max_qubits() (13), ops on at
+ * most 3 qubits (targets and controls) and no user matrices; FP64 only.
+ * Plans are built on first sight of a request structure (qubits, ops,
+ * parameter count) and cached in the handle. */
+typedef struct sv_serve sv_serve;
+
+/* Handle; host-only until the first submission, which binds it to the
+ * current device and allocates its device buffers there. */
+sv_status sv_serve_create(sv_serve **out);
+int32_t sv_serve_max_qubits(void);
+
+/* SV_OK if the serving kernel takes this request (its plans are then built
+ * and cached on the host); SV_EUNSUPPORTED (message says why) if it must run
+ * through sv_adjoint_grad instead; SV_EINVAL for an invalid request.
+ * Host-only: no device call. */
+sv_status sv_serve_check(sv_serve *s, const sv_circuit_desc *request);
+
+/* Enqueue `n_requests` (1..65535) requests on `hip_stream`.  `params` (host) holds every
+ * request's n_params angles concatenated in request order; `d_out` (device,
+ * FP64) receives, per request in order, 1 + n_params values: E, then
+ * dE/dtheta_0 .. dE/dtheta_{n_params-1}.  Asynchronous: returns after the
+ * host-to-device copy of one staging block and two kernel launches are
+ * queued; `d_out` must stay valid until the stream passes them.  Up to four
+ * submissions may be queued; a fifth waits for the oldest to finish.
+ * Device buffers grow with hipMalloc when a submission needs more than the
+ * largest so far.  Every request is checked before any device work; the
+ * first refusal returns its status with the request index in the message.
+ * Errors: SV_EINVAL, SV_EUNBOUND (bad parameter index or non-finite angle),
+ * SV_EUNSUPPORTED, SV_EDEVICE. */
+sv_status sv_serve_submit(sv_serve *s, const sv_circuit_desc *requests, int32_t n_requests,
+                          const double *params, double *d_out, void *hip_stream);
+
+/* Wait for queued submissions, then release the handle and its buffers. */
+sv_status sv_serve_free(sv_serve *s);
+
 /* ------------------------------------------------------- plan inspection
  * Number of full-state sweeps and register blocks sv_apply_layer would use
  * for this circuit with these settings (host-only; for tests and tuning). */

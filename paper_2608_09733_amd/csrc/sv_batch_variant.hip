@@ -36,149 +36,6 @@ struct BatchLds {
   int32_t unit;
 };
 
-// Tiles [t0, t1) of one sweep of one circuit (one state).  KO: every stage
-// of the batch is a Kronecker stage (no micro-op interpreter in the kernel).
-template <typename T, int M, int R, bool KO>
-__device__ void sweep_tiles(const SVI_CONST SweepArgs &a, int64_t t0, int64_t t1,
-                            BatchLds<T, M, R> &L) {
-  constexpr int NT = 1 << (M - R);
-  constexpr int G = 1 << R;
-  constexpr int VN = V4T<T>::N;
-  constexpr int LV = VN == 2 ? 1 : 2;
-  constexpr int NIT = (1 << M) / (VN * NT);
-  using C2 = typename C2T<T>::type;
-  using V4 = typename V4T<T>::type;
-  const int tid = threadIdx.x;
-  const int m = a.m, c = a.c, nh = a.nh;
-  const int mm = m > R ? m : R;
-  const int ntile_el = 1 << m;
-  const bool vec = c >= LV;
-  const bool init0 = (a.flags & SW_INIT_ZERO) != 0;
-  const int st_begin = a.stage_begin, st_end = a.stage_end;
-  const SVI_CONST StageDesc *stages = cptr(a.stages);
-  const MicroOp *ops = a.ops;
-  const double *coef = a.coef;
-  T *const pre = (T *)a.re, *const pim = (T *)a.im;
-
-  if (tid < SVI_MMAX) L.hb[tid] = a.hb[tid < nh ? tid : 0];
-  __syncthreads();
-  uint64_t roff[NIT];
-#pragma unroll
-  for (int k = 0; k < NIT; k++) {
-    const int i = (tid + k * NT) * (vec ? VN : 1);
-    roff[k] = spread_row(i >> c, L.hb, nh) + (uint64_t)(i & ((1 << c) - 1));
-  }
-  const int tsw = swz<T>(tid * VN);
-  char *const lb = (char *)L.tile;
-
-  for (int64_t tile = t0; tile < t1; tile++) {
-    const uint64_t base = tile_base(tile, c, L.hb, nh);
-    if (mm > m) {
-      // tiles smaller than one register group: padding slots hold zeros
-      for (int i = tid; i < (1 << mm); i += NT) L.tile[swz<T>(i)] = C2{0, 0};
-      __syncthreads();
-    }
-    if (init0) {
-      for (int i = tid; i < ntile_el; i += NT) {
-        const T v = (base == 0 && i == 0) ? (T)1 : (T)0;
-        L.tile[swz<T>(i)] = C2{v, 0};
-      }
-    } else if (vec) {
-#pragma unroll
-      for (int k = 0; k < NIT; k++) {
-        const int i = (tid + k * NT) * VN;
-        if (i < ntile_el) {
-          const uint64_t g = base + roff[k];
-          const V4 vr = *(const V4 *)(pre + g);
-          const V4 vi = *(const V4 *)(pim + g);
-          const int si = tsw ^ swz<T>(k * NT * VN);
-          if constexpr (VN == 2) {
-            L.tile[si] = C2{vr.x, vi.x};
-            L.tile[si ^ 1] = C2{vr.y, vi.y};
-          } else {
-            L.tile[si] = C2{vr.x, vi.x};
-            L.tile[si ^ 1] = C2{vr.y, vi.y};
-            L.tile[si ^ 2] = C2{vr.z, vi.z};
-            L.tile[si ^ 3] = C2{vr.w, vi.w};
-          }
-        }
-      }
-    } else {
-      for (int i = tid; i < ntile_el; i += NT) {
-        const uint64_t g = base + spread_row(i >> c, L.hb, nh) + (uint64_t)(i & ((1 << c) - 1));
-        L.tile[swz<T>(i)] = C2{pre[g], pim[g]};
-      }
-    }
-    __syncthreads();
-
-    for (int st = st_begin; st < st_end; st++) {
-      const SVI_CONST StageDesc &sd = stages[st];
-      const int gbs = swz<T>(stage_base<M, R>(tid, sd)) * (int)sizeof(C2);
-      // a full Kronecker stage (every group bit rotated, then D_after) runs as
-      // its own straight-line body, loads to stores; the general body branches
-      auto body = [&](auto full_stage) {
-        T re[G], im[G];
-#pragma unroll
-        for (int j = 0; j < G; j++) {
-          const C2 v = *(const C2 *)(lb + (gbs ^ sd.ld_off[j]));
-          re[j] = v.x;
-          im[j] = v.y;
-        }
-        if constexpr (decltype(full_stage)::value) {
-          kron_rot_all<T, R>(re, im, cptr(coef) + sd.kcoef);
-          mo_diagt<T, R>(re, im, cptr(coef) + sd.kcoef + 4 * R + 2 * G);
-        } else if (KO || sd.kind == ST_KRON) {
-          kron_stage<T, R>(re, im, cptr(coef) + sd.kcoef, sd.rmask, sd.dflags);
-        } else {
-          for (int o = sd.op_begin; o < sd.op_end; o++) {
-            const MicroOp op = op_at(ops, o);
-            apply_op<T, R>(op, re, im, coef);
-          }
-        }
-        if (sd.dflags & SD_XCHG) __syncthreads();
-#pragma unroll
-        for (int j = 0; j < G; j++) *(C2 *)(lb + (gbs ^ sd.st_off[j])) = C2{re[j], im[j]};
-      };
-      if (sd.kind == ST_KRON && sd.rmask == (1u << R) - 1 && (sd.dflags & 7) == 2)
-        body(std::true_type{});
-      else
-        body(std::false_type{});
-      __syncthreads();
-    }
-
-    if (vec) {
-#pragma unroll
-      for (int k = 0; k < NIT; k++) {
-        const int i = (tid + k * NT) * VN;
-        if (i < ntile_el) {
-          const uint64_t g = base + roff[k];
-          const int si = tsw ^ swz<T>(k * NT * VN);
-          V4 vr, vi;
-          if constexpr (VN == 2) {
-            const C2 p0 = L.tile[si], p1 = L.tile[si ^ 1];
-            vr = V4{p0.x, p1.x};
-            vi = V4{p0.y, p1.y};
-          } else {
-            const C2 p0 = L.tile[si], p1 = L.tile[si ^ 1], p2 = L.tile[si ^ 2], p3 = L.tile[si ^ 3];
-            vr = V4{p0.x, p1.x, p2.x, p3.x};
-            vi = V4{p0.y, p1.y, p2.y, p3.y};
-          }
-          *(V4 *)(pre + g) = vr;
-          *(V4 *)(pim + g) = vi;
-        }
-      }
-    } else {
-      for (int i = tid; i < ntile_el; i += NT) {
-        const uint64_t g = base + spread_row(i >> c, L.hb, nh) + (uint64_t)(i & ((1 << c) - 1));
-        const C2 p = L.tile[swz<T>(i)];
-        pre[g] = p.x;
-        pim[g] = p.y;
-      }
-    }
-    __syncthreads();
-  }
-}
-
 // Tiles [t0, t1) of one Pauli pass: per-term sums of
 // Re conj(psi_{b^x}) i^{nY} (-1)^{popcount(b & z)} psi_b over the tiles' b
 // (paper Section 4.4), written to out[term of the pass].
@@ -302,7 +159,7 @@ __global__ void __launch_bounds__(1 << (M - R)) k_batch(BatchKernelArgs b) {
     // acquire: the producers' state writes are visible to this wave's loads
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     if (un.kind == UK_SWEEP)
-      sweep_tiles<T, M, R, KO>(cptr(b.sweeps)[un.arg], un.t0, un.t1, L);
+      sweep_tiles<T, M, R, KO>(cptr(b.sweeps)[un.arg], un.t0, un.t1, L.tile, L.hb);
     else
       pauli_tiles<T, M, R>(cptr(b.passes)[un.arg], un.t0, un.t1, b.part + un.part, L);
     // release: this wave's writes are visible device-wide before the count

@@ -1079,6 +1079,256 @@ __global__ void __launch_bounds__(1 << (M - R)) k_sweep_kron(SweepArgs a) {
   }
 }
 
+// ------------------------------------------------ tile sweep, one workgroup
+// Tiles [t0, t1) of one sweep of one state, run by one workgroup of 2^(M-R)
+// threads through the LDS tile `lt` (2^M amplitudes) with the tile's
+// high-bit table staged in `hb` (LDS, SVI_MMAX entries).  No qubit remapping
+// on the way out (SW_OPERM is not taken).  KO: every stage is a Kronecker
+// stage (no micro-op interpreter in the caller's kernel).
+template <typename T, int M, int R, bool KO>
+__device__ void sweep_tiles(const SVI_CONST SweepArgs &a, int64_t t0, int64_t t1,
+                            typename C2T<T>::type *lt, int32_t *hb) {
+  constexpr int NT = 1 << (M - R);
+  constexpr int G = 1 << R;
+  constexpr int VN = V4T<T>::N;
+  constexpr int LV = VN == 2 ? 1 : 2;
+  constexpr int NIT = (1 << M) / (VN * NT);
+  using C2 = typename C2T<T>::type;
+  using V4 = typename V4T<T>::type;
+  const int tid = threadIdx.x;
+  const int m = a.m, c = a.c, nh = a.nh;
+  const int mm = m > R ? m : R;
+  const int ntile_el = 1 << m;
+  const bool vec = c >= LV;
+  const bool init0 = (a.flags & SW_INIT_ZERO) != 0;
+  const int st_begin = a.stage_begin, st_end = a.stage_end;
+  const SVI_CONST StageDesc *stages = cptr(a.stages);
+  const MicroOp *ops = a.ops;
+  const double *coef = a.coef;
+  T *const pre = (T *)a.re, *const pim = (T *)a.im;
+
+  if (tid < SVI_MMAX) hb[tid] = a.hb[tid < nh ? tid : 0];
+  __syncthreads();
+  uint64_t roff[NIT];
+#pragma unroll
+  for (int k = 0; k < NIT; k++) {
+    const int i = (tid + k * NT) * (vec ? VN : 1);
+    roff[k] = spread_row(i >> c, hb, nh) + (uint64_t)(i & ((1 << c) - 1));
+  }
+  const int tsw = swz<T>(tid * VN);
+  char *const lb = (char *)lt;
+
+  for (int64_t tile = t0; tile < t1; tile++) {
+    const uint64_t base = tile_base(tile, c, hb, nh);
+    if (mm > m) {
+      // tiles smaller than one register group: padding slots hold zeros
+      for (int i = tid; i < (1 << mm); i += NT) lt[swz<T>(i)] = C2{0, 0};
+      __syncthreads();
+    }
+    if (init0) {
+      for (int i = tid; i < ntile_el; i += NT) {
+        const T v = (base == 0 && i == 0) ? (T)1 : (T)0;
+        lt[swz<T>(i)] = C2{v, 0};
+      }
+    } else if (vec) {
+#pragma unroll
+      for (int k = 0; k < NIT; k++) {
+        const int i = (tid + k * NT) * VN;
+        if (i < ntile_el) {
+          const uint64_t g = base + roff[k];
+          const V4 vr = *(const V4 *)(pre + g);
+          const V4 vi = *(const V4 *)(pim + g);
+          const int si = tsw ^ swz<T>(k * NT * VN);
+          if constexpr (VN == 2) {
+            lt[si] = C2{vr.x, vi.x};
+            lt[si ^ 1] = C2{vr.y, vi.y};
+          } else {
+            lt[si] = C2{vr.x, vi.x};
+            lt[si ^ 1] = C2{vr.y, vi.y};
+            lt[si ^ 2] = C2{vr.z, vi.z};
+            lt[si ^ 3] = C2{vr.w, vi.w};
+          }
+        }
+      }
+    } else {
+      for (int i = tid; i < ntile_el; i += NT) {
+        const uint64_t g = base + spread_row(i >> c, hb, nh) + (uint64_t)(i & ((1 << c) - 1));
+        lt[swz<T>(i)] = C2{pre[g], pim[g]};
+      }
+    }
+    __syncthreads();
+
+    for (int st = st_begin; st < st_end; st++) {
+      const SVI_CONST StageDesc &sd = stages[st];
+      const int gbs = swz<T>(stage_base<M, R>(tid, sd)) * (int)sizeof(C2);
+      // a full Kronecker stage (every group bit rotated, then D_after) runs as
+      // its own straight-line body, loads to stores; the general body branches
+      auto body = [&](auto full_stage) {
+        T re[G], im[G];
+#pragma unroll
+        for (int j = 0; j < G; j++) {
+          const C2 v = *(const C2 *)(lb + (gbs ^ sd.ld_off[j]));
+          re[j] = v.x;
+          im[j] = v.y;
+        }
+        if constexpr (decltype(full_stage)::value) {
+          kron_rot_all<T, R>(re, im, cptr(coef) + sd.kcoef);
+          mo_diagt<T, R>(re, im, cptr(coef) + sd.kcoef + 4 * R + 2 * G);
+        } else if (KO || sd.kind == ST_KRON) {
+          kron_stage<T, R>(re, im, cptr(coef) + sd.kcoef, sd.rmask, sd.dflags);
+        } else {
+          for (int o = sd.op_begin; o < sd.op_end; o++) {
+            const MicroOp op = op_at(ops, o);
+            apply_op<T, R>(op, re, im, coef);
+          }
+        }
+        if (sd.dflags & SD_XCHG) __syncthreads();
+#pragma unroll
+        for (int j = 0; j < G; j++) *(C2 *)(lb + (gbs ^ sd.st_off[j])) = C2{re[j], im[j]};
+      };
+      if (sd.kind == ST_KRON && sd.rmask == (1u << R) - 1 && (sd.dflags & 7) == 2)
+        body(std::true_type{});
+      else
+        body(std::false_type{});
+      __syncthreads();
+    }
+
+    if (vec) {
+#pragma unroll
+      for (int k = 0; k < NIT; k++) {
+        const int i = (tid + k * NT) * VN;
+        if (i < ntile_el) {
+          const uint64_t g = base + roff[k];
+          const int si = tsw ^ swz<T>(k * NT * VN);
+          V4 vr, vi;
+          if constexpr (VN == 2) {
+            const C2 p0 = lt[si], p1 = lt[si ^ 1];
+            vr = V4{p0.x, p1.x};
+            vi = V4{p0.y, p1.y};
+          } else {
+            const C2 p0 = lt[si], p1 = lt[si ^ 1], p2 = lt[si ^ 2], p3 = lt[si ^ 3];
+            vr = V4{p0.x, p1.x, p2.x, p3.x};
+            vi = V4{p0.y, p1.y, p2.y, p3.y};
+          }
+          *(V4 *)(pre + g) = vr;
+          *(V4 *)(pim + g) = vi;
+        }
+      }
+    } else {
+      for (int i = tid; i < ntile_el; i += NT) {
+        const uint64_t g = base + spread_row(i >> c, hb, nh) + (uint64_t)(i & ((1 << c) - 1));
+        const C2 p = lt[swz<T>(i)];
+        pre[g] = p.x;
+        pim[g] = p.y;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// ------------------------------------------- two-state Kronecker stage
+// One Kronecker stage applied to the psi and lambda tiles held side by side in
+// LDS (lb0, lb1), with the gradient terms Im <lam| G |psi> of the stage's
+// gradient micro-ops taken at the three stage points (stage input, after
+// D_before, after the rotations).  Each term goes to sink(slot, value), where
+// the slot is uniform across the wave.  Ends with the barrier (or the wave
+// fence of a wave-local stage) that makes the stores visible to the next stage.
+template <typename T, int R, typename Sink>
+__device__ __forceinline__ void kron2_stage(char *lb0, char *lb1, int gbs,
+                                            const SVI_CONST StageDesc &sd,
+                                            const SVI_CONST double *coef, const MicroOp *ops,
+                                            const double *gcoef, bool active, Sink &&sink) {
+  constexpr int G = 1 << R;
+  using C2 = typename C2T<T>::type;
+  char *const lb[2] = {lb0, lb1};
+  T re[2][G], im[2][G];
+#pragma unroll
+  for (int s = 0; s < 2; s++) {
+#pragma unroll
+    for (int j = 0; j < G; j++) {
+      const C2 v = *(const C2 *)(lb[s] + (gbs ^ sd.ld_off[j]));
+      re[s][j] = v.x;
+      im[s][j] = v.y;
+    }
+  }
+  const SVI_CONST double *kc = coef + sd.kcoef;
+  auto grads = [&](int b, int e, double mult) {
+    // one term at a time: an unrolled loop would keep several terms'
+    // operands live at once and spill the register groups
+#pragma clang loop unroll(disable)
+    for (int o = b; o < e; o++) {
+      const MicroOp op = op_at(ops, o);
+      const double v = active ? mult * grad_kron<T, R>(op, re[0], im[0], re[1], im[1], gcoef) : 0.0;
+      sink(op.coef, v);
+    }
+  };
+  grads(sd.op_begin, sd.g1, 1.0);
+  kron_pre<T, R>(re[0], im[0], kc, sd.dflags);
+  kron_pre<T, R>(re[1], im[1], kc, sd.dflags);
+  grads(sd.g1, sd.g2, 1.0);
+  kron_rot<T, R>(re[0], im[0], kc, sd.rmask);
+  kron_rot<T, R>(re[1], im[1], kc, sd.rmask);
+  if (sd.g2 < sd.op_end) {
+    const double sc = kc[4 * R + 4 * G];
+    grads(sd.g2, sd.op_end, sc * sc);
+  }
+  kron_post<T, R>(re[0], im[0], kc, sd.dflags);
+  kron_post<T, R>(re[1], im[1], kc, sd.dflags);
+  if (sd.dflags & SD_XCHG) lds_barrier();
+#pragma unroll
+  for (int s = 0; s < 2; s++) {
+#pragma unroll
+    for (int j = 0; j < G; j++) *(C2 *)(lb[s] + (gbs ^ sd.st_off[j])) = C2{re[s][j], im[s][j]};
+  }
+  if (sd.dflags & SD_WLOCAL) {
+    // the next stage reads only slots this wave wrote
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront", "local");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront", "local");
+  } else {
+    lds_barrier();
+  }
+}
+
+// One micro-op stage (the interpreter) applied to the psi and lambda tiles
+// in LDS: each gate micro-op acts on both states, each gradient micro-op sends
+// its term Im <lam| G |psi> to sink(slot, value) at its place in the stage.
+// Ends with the barrier that makes the stores visible to the next stage.
+template <typename T, int R, typename Sink>
+__device__ __forceinline__ void ops2_stage(char *lb0, char *lb1, int gbs,
+                                           const SVI_CONST StageDesc &sd, const MicroOp *ops,
+                                           const double *coef, bool active, Sink &&sink) {
+  constexpr int G = 1 << R;
+  using C2 = typename C2T<T>::type;
+  char *const lb[2] = {lb0, lb1};
+  T re[2][G], im[2][G];
+#pragma unroll
+  for (int s = 0; s < 2; s++) {
+#pragma unroll
+    for (int j = 0; j < G; j++) {
+      const C2 v = *(const C2 *)(lb[s] + (gbs ^ sd.ld_off[j]));
+      re[s][j] = v.x;
+      im[s][j] = v.y;
+    }
+  }
+  for (int o = sd.op_begin; o < sd.op_end; o++) {
+    const MicroOp op = op_at(ops, o);
+    if (op.type == MO_GRAD || op.type == MO_GRAD2L) {
+      sink(op.coef, active ? grad_any<T, R>(op, re[0], im[0], re[1], im[1], coef) : 0.0);
+      continue;
+    }
+    apply_op<T, R>(op, re[0], im[0], coef);
+    apply_op<T, R>(op, re[1], im[1], coef);
+  }
+  if (sd.dflags & SD_XCHG) lds_barrier();
+#pragma unroll
+  for (int s = 0; s < 2; s++) {
+#pragma unroll
+    for (int j = 0; j < G; j++) *(C2 *)(lb[s] + (gbs ^ sd.st_off[j])) = C2{re[s][j], im[s][j]};
+  }
+  lds_barrier();
+}
+
 // ------------------------------------------- two-state Kronecker sweep
 // Adjoint backward sweeps whose every stage is a Kronecker stage: psi and
 // lambda tiles side by side in LDS, the stage applied to both, and the
@@ -1179,71 +1429,26 @@ __global__ void __launch_bounds__(1 << (M - R)) k_sweep_kron2(SweepArgs a) {
       const int gbs =
           st < ntab ? gtab[st * NT + tid] : swz<T>(stage_base<M, R>(tid, sd)) * (int)sizeof(C2);
       const bool active = tid < (1 << (m > R ? m - R : 0));
-      T re[2][G], im[2][G];
-#pragma unroll
-      for (int s = 0; s < 2; s++) {
-        const char *lb = (const char *)lds[s];
-#pragma unroll
-        for (int j = 0; j < G; j++) {
-          const C2 v = *(const C2 *)(lb + (gbs ^ sd.ld_off[j]));
-          re[s][j] = v.x;
-          im[s][j] = v.y;
+      kron2_stage<T, R>((char *)lds[0], (char *)lds[1], gbs, sd, coef, a.ops, a.coef, active,
+                        [&](int slot, double v) {
+        if (slot >= SVI_GSLOTS_LEAN) {
+          // past the register slots: this tile's wave sum into the wave's LDS row
+          // (an LDS add without return: the wave does not wait for it)
+          const double w = wave_total63(v);
+          if ((tid & 63) == 63) atomicAdd(&wacc[tid >> 6][slot - SVI_GSLOTS_LEAN], w);
+          return;
         }
-      }
-      const SVI_CONST double *kc = coef + sd.kcoef;
-      auto grads = [&](int b, int e, double mult) {
-        // one term at a time: an unrolled loop would keep several terms'
-        // operands live at once and spill the register groups
-#pragma clang loop unroll(disable)
-        for (int o = b; o < e; o++) {
-          const MicroOp op = op_at(a.ops, o);
-          const double v = active ? mult * grad_kron<T, R>(op, re[0], im[0], re[1], im[1], a.coef) : 0.0;
-          if (op.coef >= SVI_GSLOTS_LEAN) {
-            // past the register slots: this tile's wave sum into the wave's LDS row
-            // (an LDS add without return: the wave does not wait for it)
-            const double w = wave_total63(v);
-            if ((tid & 63) == 63) atomicAdd(&wacc[tid >> 6][op.coef - SVI_GSLOTS_LEAN], w);
-            continue;
-          }
-          switch (op.coef) {   // uniform: the slot is a register index
+        switch (slot) {   // uniform: the slot is a register index
 #define SVI_GS(K) case K: if constexpr (K < SVI_GSLOTS_LEAN) gr[K] += v; break;
-            SVI_GS(0) SVI_GS(1) SVI_GS(2) SVI_GS(3) SVI_GS(4) SVI_GS(5) SVI_GS(6) SVI_GS(7)
-            SVI_GS(8) SVI_GS(9) SVI_GS(10) SVI_GS(11) SVI_GS(12) SVI_GS(13) SVI_GS(14)
-            SVI_GS(15) SVI_GS(16) SVI_GS(17) SVI_GS(18) SVI_GS(19) SVI_GS(20) SVI_GS(21)
-            SVI_GS(22) SVI_GS(23) SVI_GS(24) SVI_GS(25) SVI_GS(26) SVI_GS(27) SVI_GS(28)
-            SVI_GS(29) SVI_GS(30) SVI_GS(31)
+          SVI_GS(0) SVI_GS(1) SVI_GS(2) SVI_GS(3) SVI_GS(4) SVI_GS(5) SVI_GS(6) SVI_GS(7)
+          SVI_GS(8) SVI_GS(9) SVI_GS(10) SVI_GS(11) SVI_GS(12) SVI_GS(13) SVI_GS(14)
+          SVI_GS(15) SVI_GS(16) SVI_GS(17) SVI_GS(18) SVI_GS(19) SVI_GS(20) SVI_GS(21)
+          SVI_GS(22) SVI_GS(23) SVI_GS(24) SVI_GS(25) SVI_GS(26) SVI_GS(27) SVI_GS(28)
+          SVI_GS(29) SVI_GS(30) SVI_GS(31)
 #undef SVI_GS
-            default: break;
-          }
+          default: break;
         }
-      };
-      grads(sd.op_begin, sd.g1, 1.0);
-      kron_pre<T, R>(re[0], im[0], kc, sd.dflags);
-      kron_pre<T, R>(re[1], im[1], kc, sd.dflags);
-      grads(sd.g1, sd.g2, 1.0);
-      kron_rot<T, R>(re[0], im[0], kc, sd.rmask);
-      kron_rot<T, R>(re[1], im[1], kc, sd.rmask);
-      if (sd.g2 < sd.op_end) {
-        const double sc = kc[4 * R + 4 * G];
-        grads(sd.g2, sd.op_end, sc * sc);
-      }
-      kron_post<T, R>(re[0], im[0], kc, sd.dflags);
-      kron_post<T, R>(re[1], im[1], kc, sd.dflags);
-      if (sd.dflags & SD_XCHG) lds_barrier();
-#pragma unroll
-      for (int s = 0; s < 2; s++) {
-        char *lb = (char *)lds[s];
-#pragma unroll
-        for (int j = 0; j < G; j++) *(C2 *)(lb + (gbs ^ sd.st_off[j])) = C2{re[s][j], im[s][j]};
-      }
-      if (sd.dflags & SD_WLOCAL) {
-        // the next stage reads only slots this wave wrote
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront", "local");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront", "local");
-      } else {
-        lds_barrier();
-      }
+      });
     }
     // ---- LDS to HBM
 #pragma unroll

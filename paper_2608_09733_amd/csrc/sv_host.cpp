@@ -3520,3 +3520,356 @@ extern "C" sv_status sv_batch_autotune(const sv_circuit_desc *circuits, int32_t 
   if (best_ms) *best_ms = best;
   return SV_OK;
 }
+
+// ---------------------------------------------------------------- serving
+// Small adjoint requests run whole inside one workgroup each (k_serve): the
+// forward and backward plans are built for 12-qubit tiles and cached per
+// request structure; a submission copies one staging block (request
+// descriptors, sweep arguments, observables, parameters) to the device and
+// launches two kernels.  A ring of staging slots lets submissions queue on the
+// stream while earlier ones run.
+
+struct ServePlan {
+  Plan F, B;
+  bool general = false;        // some stage is a micro-op (interpreter) stage
+  sv_status status = SV_OK;
+  std::string why;
+};
+
+struct ServeSlot {
+  void *d_buf = nullptr;
+  size_t d_bytes = 0;
+  void *h_buf = nullptr;       // pinned staging
+  size_t h_bytes = 0;
+  hipEvent_t done = nullptr;
+  bool busy = false;
+  std::vector<std::shared_ptr<ServePlan>> held;   // plans the queued run reads
+};
+
+#define SVS_SLOTS 4
+
+struct sv_serve {
+  int dev = 0;
+  std::unordered_map<std::string, std::shared_ptr<ServePlan>> plans;
+  ServeSlot slot[SVS_SLOTS];
+  int next = 0;
+};
+
+static const Tiling kServeFwd{12, 5, 3}, kServeBwd{12, 3, 3};
+
+static sv_status serve_wait(ServeSlot &sl) {
+  if (sl.busy) {
+    HIPCHK(hipEventSynchronize(sl.done));
+    sl.busy = false;
+    sl.held.clear();
+  }
+  return SV_OK;
+}
+
+// Plan pair of one request (cached by structure); its status says whether the
+// serving kernel can run it.
+static sv_status serve_plan(sv_serve *sv, const sv_circuit_desc &d, std::shared_ptr<ServePlan> &out) {
+  int Ms = 0, Rs = 0;
+  (void)svk_serve_tiling(&Ms, &Rs);
+  const std::string key = plan_key(-2, d.n_qubits, kServeFwd, true, d.ops, d.n_ops, d.n_params);
+  auto it = sv->plans.find(key);
+  if (it != sv->plans.end()) {
+    out = it->second;
+    return out->status ? fail(out->status, "%s", out->why.c_str()) : SV_OK;
+  }
+  std::shared_ptr<ServePlan> sp(new ServePlan);
+  auto refuse = [&](const char *fmt, int a, int b) {
+    char buf[160];
+    snprintf(buf, sizeof buf, fmt, a, b);
+    sp->status = SV_EUNSUPPORTED;
+    sp->why = buf;
+  };
+  const int n = d.n_qubits;
+  int width = 1;
+  bool user_mat = false;
+  for (int i = 0; i < d.n_ops; i++) {
+    width = std::max(width, d.ops[i].n_targets + d.ops[i].n_controls);
+    if (d.ops[i].kind == SV_UNITARY) user_mat = true;
+  }
+  if (n < Rs || n > svk_serve_max_qubits())
+    refuse("serving kernel: %d qubits outside %d..13", n, Rs);
+  else if (width > Rs)
+    refuse("serving kernel: an op on %d qubits (at most %d)", width, Rs);
+  else if (user_mat)
+    refuse("serving kernel: user matrices are not taken (%d, %d)", 0, 0);
+  if (!sp->status) {
+    sv_status s = build_forward_plan(-1, n, true, kServeFwd, d.ops, d.n_ops, d.n_params, sp->F, false, false);
+    if (s) return s;
+    s = build_adjoint_plan(n, true, kServeBwd, d.ops, d.n_ops, d.n_params, sp->B);
+    if (s) return s;
+    for (const Step &st : sp->F.steps)
+      if (st.kind != 0 || sp->F.M != Ms || sp->F.R != Rs) refuse("serving kernel: forward plan step %d of kind %d", 0, st.kind);
+    for (const Step &st : sp->B.steps)
+      if (st.kind != 0 || st.sa.m < Rs || st.sa.n_gslots > SVI_GSLOTS_MAX)
+        refuse("serving kernel: backward step of kind %d is not a tile sweep (m=%d)", st.kind, st.sa.m);
+    for (const Plan *P : {&sp->F, &sp->B})
+      for (const Step &st : P->steps) sp->general = sp->general || !st.all_kron;
+  }
+  if (sv->plans.size() >= 256) sv->plans.clear();   // queued runs keep their plans alive
+  sv->plans.emplace(key, sp);
+  out = sp;
+  return sp->status ? fail(sp->status, "%s", sp->why.c_str()) : SV_OK;
+}
+
+extern "C" sv_status sv_serve_create(sv_serve **out) {
+  if (!out) return fail(SV_EINVAL, "null output handle");
+  *out = nullptr;
+  std::unique_ptr<sv_serve> sv(new sv_serve);
+  sv->dev = -1;   // bound to the current device at the first submission
+  *out = sv.release();
+  return SV_OK;
+}
+
+extern "C" int32_t sv_serve_max_qubits(void) { return svk_serve_max_qubits(); }
+
+static sv_status serve_check_plan(sv_serve *sv, const sv_circuit_desc *request,
+                                  std::shared_ptr<ServePlan> &sp) {
+  if (!sv || !request) return fail(SV_EINVAL, "null argument");
+  const sv_circuit_desc &d = *request;
+  if (d.n_qubits < 1 || d.n_qubits > 34) return fail(SV_EINVAL, "n_qubits %d outside 1..34", d.n_qubits);
+  if (d.n_ops < 0 || (d.n_ops > 0 && !d.ops)) return fail(SV_EINVAL, "bad op list");
+  if (d.n_params < 0) return fail(SV_EINVAL, "negative n_params");
+  for (int i = 0; i < d.n_ops; i++) {
+    sv_status s = validate_op(d.ops[i], i, d.n_qubits, d.n_params);
+    if (s) return s;
+  }
+  sv_status s = validate_terms(d.n_qubits, d.terms, d.n_terms);
+  if (s) return s;
+  return serve_plan(sv, d, sp);
+}
+
+extern "C" sv_status sv_serve_check(sv_serve *sv, const sv_circuit_desc *request) {
+  std::shared_ptr<ServePlan> sp;
+  return serve_check_plan(sv, request, sp);
+}
+
+extern "C" sv_status sv_serve_submit(sv_serve *sv, const sv_circuit_desc *requests, int32_t n_requests,
+                                     const double *params, double *d_out, void *hip_stream) {
+  if (!sv) return fail(SV_EINVAL, "null handle");
+  if (n_requests < 1 || n_requests > 65535)
+    return fail(SV_EINVAL, "n_requests %d outside 1..65535", n_requests);
+  if (!requests || !d_out) return fail(SV_EINVAL, "null requests or output");
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  if (sv->dev < 0) {
+    for (ServeSlot &sl : sv->slot) HIPCHK(hipEventCreateWithFlags(&sl.done, hipEventDisableTiming));
+    sv->dev = dev;
+  }
+  if (dev != sv->dev) return fail(SV_EINVAL, "handle used on device %d, current device %d", sv->dev, dev);
+  // ---- validate everything and get the plans before touching the device
+  std::vector<std::shared_ptr<ServePlan>> plans(n_requests);
+  int64_t pofs = 0;
+  for (int r = 0; r < n_requests; r++) {
+    const sv_circuit_desc &d = requests[r];
+    if (d.n_params > 0 && !params) return fail(SV_EUNBOUND, "null params");
+    sv_status s = serve_check_plan(sv, &d, plans[r]);
+    if (!s) s = validate_circuit(d.n_qubits, d.ops, d.n_ops, params + pofs, d.n_params);
+    if (s) return fail(s, "request %d: %s", r, std::string(g_err).c_str());
+    pofs += d.n_params;
+  }
+  for (auto &sp : plans)
+    if (!sp->F.d_buf) {
+      sv_status s = upload_plan(sp->F);
+      if (!s) s = upload_plan(sp->B);
+      if (s) return s;
+    }
+  // ---- layout: staged part (copied from host) | device-only part
+  auto align = [](size_t v) { return (v + 255) & ~(size_t)255; };
+  size_t off = 256;   // [0], [1]: queue heads of the lean and the general kernel
+  const size_t o_reqs = off;
+  off = align(off + (size_t)n_requests * sizeof(ServeReq));
+  int nsw = 0, max_desc = 0;
+  size_t nterm = 0;
+  for (int r = 0; r < n_requests; r++) {
+    nsw += (int)std::max<size_t>(plans[r]->F.steps.size(), 1) + (int)plans[r]->B.steps.size();
+    nterm += (size_t)requests[r].n_terms;
+    max_desc = std::max(max_desc, (int)(plans[r]->F.coefs.size() + plans[r]->B.coefs.size()));
+  }
+  const size_t o_sweeps = off;
+  off = align(off + (size_t)nsw * sizeof(SweepArgs));
+  const size_t o_terms = off;
+  off = align(off + std::max<size_t>(nterm, 1) * sizeof(PauliTermDev));
+  std::vector<size_t> o_fp(n_requests), o_bp(n_requests);
+  for (int r = 0; r < n_requests; r++) {
+    const int nu = requests[r].n_params;
+    o_fp[r] = off;
+    off = align(off + (size_t)(nu + plans[r]->F.constants.size() + 1) * 8);
+    o_bp[r] = off;
+    off = align(off + (size_t)(nu + plans[r]->B.constants.size() + 1) * 8);
+  }
+  const size_t staged = off;
+  std::vector<size_t> o_fc(n_requests), o_bc(n_requests), o_st(n_requests), o_sl(n_requests);
+  for (int r = 0; r < n_requests; r++) {
+    const size_t plane = align(((size_t)1 << requests[r].n_qubits) * 8);
+    o_fc[r] = off;
+    off = align(off + (size_t)(plans[r]->F.ncoef + 1) * 8);
+    o_bc[r] = off;
+    off = align(off + (size_t)(plans[r]->B.ncoef + 1) * 8);
+    o_st[r] = off;
+    off += 4 * plane;
+    o_sl[r] = off;
+    off = align(off + (size_t)(plans[r]->B.n_gslots + 1) * 8);
+  }
+  const size_t total = off;
+  // queue order: requests of the lean kernel first, then those of the general
+  // one (each request always runs in the same kernel, whatever the mix)
+  std::vector<int> pos(n_requests);
+  int n_lean = 0;
+  for (int r = 0; r < n_requests; r++)
+    if (!plans[r]->general) pos[r] = n_lean++;
+  for (int r = 0, g = n_lean; r < n_requests; r++)
+    if (plans[r]->general) pos[r] = g++;
+
+  // ---- a free staging slot (waits for the run that used it last)
+  ServeSlot &sl = sv->slot[sv->next];
+  sv->next = (sv->next + 1) % SVS_SLOTS;
+  sv_status s = serve_wait(sl);
+  if (s) return s;
+  if (sl.d_bytes < total) {
+    if (sl.d_buf) HIPCHK(hipFree(sl.d_buf));
+    sl.d_buf = nullptr;
+    sl.d_bytes = 0;
+    HIPCHK(hipMalloc(&sl.d_buf, total));
+    sl.d_bytes = total;
+  }
+  if (sl.h_bytes < staged) {
+    if (sl.h_buf) HIPCHK(hipHostFree(sl.h_buf));
+    sl.h_buf = nullptr;
+    sl.h_bytes = 0;
+    HIPCHK(hipHostMalloc(&sl.h_buf, staged, hipHostMallocDefault));
+    sl.h_bytes = staged;
+  }
+  char *h = (char *)sl.h_buf;
+  char *d = (char *)sl.d_buf;
+  std::memset(h, 0, 256);
+  ServeReq *hq = (ServeReq *)(h + o_reqs);
+  SweepArgs *hs = (SweepArgs *)(h + o_sweeps);
+  PauliTermDev *ht = (PauliTermDev *)(h + o_terms);
+  int isw = 0;
+  size_t it = 0;
+  int64_t out_off = 0;
+  pofs = 0;
+  for (int r = 0; r < n_requests; r++) {
+    const sv_circuit_desc &dc = requests[r];
+    const Plan &F = plans[r]->F, &B = plans[r]->B;
+    const int n = dc.n_qubits, nu = dc.n_params;
+    const size_t plane = align(((size_t)1 << n) * 8);
+    ServeReq q;
+    std::memset(&q, 0, sizeof q);
+    q.n = n;
+    q.n_params = nu;
+    q.f_ndesc = (int)F.coefs.size();
+    q.b_ndesc = (int)B.coefs.size();
+    q.n_terms = dc.n_terms;
+    q.f_desc = F.d_coefdesc;
+    q.b_desc = B.d_coefdesc;
+    q.f_fac = F.d_factors;
+    q.b_fac = B.d_factors;
+    q.f_params = (const double *)(d + o_fp[r]);
+    q.b_params = (const double *)(d + o_bp[r]);
+    q.f_coef = (double *)(d + o_fc[r]);
+    q.b_coef = (double *)(d + o_bc[r]);
+    q.re = d + o_st[r];
+    q.im = d + o_st[r] + plane;
+    q.lre = d + o_st[r] + 2 * plane;
+    q.lim = d + o_st[r] + 3 * plane;
+    q.terms = (const PauliTermDev *)(d + o_terms) + it;
+    q.slots = (double *)(d + o_sl[r]);
+    q.rowptr = B.d_rowptr;
+    q.gslots = B.d_gslots;
+    q.out = d_out + out_off;
+    out_off += 1 + nu;
+    // parameters: the user's, then each plan's constants
+    double *fp = (double *)(h + o_fp[r]), *bp = (double *)(h + o_bp[r]);
+    if (nu) {
+      std::memcpy(fp, params + pofs, (size_t)nu * 8);
+      std::memcpy(bp, params + pofs, (size_t)nu * 8);
+    }
+    if (!F.constants.empty()) std::memcpy(fp + nu, F.constants.data(), F.constants.size() * 8);
+    if (!B.constants.empty()) std::memcpy(bp + nu, B.constants.data(), B.constants.size() * 8);
+    pofs += nu;
+    for (int j = 0; j < dc.n_terms; j++) {
+      PauliTermDev t{};
+      t.x = dc.terms[j].x_mask;
+      t.z = dc.terms[j].z_mask;
+      t.c = dc.terms[j].coeff;
+      t.term = j;
+      ht[it++] = t;
+    }
+    // forward sweeps (an empty circuit still gets one sweep that writes |0..0>)
+    q.f_sweep = isw;
+    if (F.steps.empty()) {
+      SweepArgs z;
+      std::memset(&z, 0, sizeof z);
+      const int m = std::min(kServeFwd.M, n), cc = std::min(kServeFwd.c, n);
+      z.n = n;
+      z.m = m;
+      z.c = cc;
+      z.nh = m - cc;
+      for (int k = 0; k < z.nh; k++) z.hb[k] = cc + k;
+      z.ntiles = (int64_t)1 << (n - m);
+      z.stages = F.d_stages;
+      z.ops = F.d_ops;
+      z.coef = q.f_coef;
+      z.re = q.re;
+      z.im = q.im;
+      z.flags = SW_INIT_ZERO;
+      hs[isw++] = z;
+    } else {
+      for (size_t k = 0; k < F.steps.size(); k++) {
+        SweepArgs a = F.steps[k].sa;
+        a.re = q.re; a.im = q.im; a.re2 = a.im2 = nullptr;
+        a.stages = F.d_stages; a.ops = F.d_ops; a.coef = q.f_coef; a.gpart = nullptr;
+        if (k == 0) a.flags |= SW_INIT_ZERO;
+        hs[isw++] = a;
+      }
+    }
+    q.f_nsweeps = isw - q.f_sweep;
+    q.b_sweep = isw;
+    for (const Step &st : B.steps) {
+      SweepArgs a = st.sa;
+      a.re = q.re; a.im = q.im; a.re2 = q.lre; a.im2 = q.lim;
+      a.stages = B.d_stages; a.ops = B.d_ops; a.coef = q.b_coef; a.gpart = nullptr;
+      hs[isw++] = a;
+    }
+    q.b_nsweeps = isw - q.b_sweep;
+    hq[pos[r]] = q;
+  }
+  hipStream_t stream = (hipStream_t)hip_stream;
+  HIPCHK(hipMemcpyAsync(d, h, staged, hipMemcpyHostToDevice, stream));
+  DevInfo di;
+  s = device_info(di);
+  if (s) return s;
+  const ServeReq *d_reqs = (const ServeReq *)(d + o_reqs);
+  const SweepArgs *d_sweeps = (const SweepArgs *)(d + o_sweeps);
+  hipError_t e = svk_launch_serve_coefs(d_reqs, n_requests, max_desc, stream);
+  const int n_gen = n_requests - n_lean;
+  if (e == hipSuccess && n_lean)
+    e = svk_launch_serve(d_reqs, d_sweeps, (int32_t *)d, n_lean, 0,
+                         std::min(n_lean, std::max(1, di.cus)), stream);
+  if (e == hipSuccess && n_gen)
+    e = svk_launch_serve(d_reqs + n_lean, d_sweeps, (int32_t *)d + 1, n_gen, 1,
+                         std::min(n_gen, std::max(1, di.cus)), stream);
+  if (e != hipSuccess) return fail(SV_EDEVICE, "serving kernels: %s", hipGetErrorString(e));
+  HIPCHK(hipEventRecord(sl.done, stream));
+  sl.busy = true;
+  sl.held = std::move(plans);
+  return SV_OK;
+}
+
+extern "C" sv_status sv_serve_free(sv_serve *sv) {
+  if (!sv) return SV_OK;
+  for (ServeSlot &sl : sv->slot) {
+    if (sl.busy) (void)hipEventSynchronize(sl.done);
+    if (sl.d_buf) (void)hipFree(sl.d_buf);
+    if (sl.h_buf) (void)hipHostFree(sl.h_buf);
+    if (sl.done) (void)hipEventDestroy(sl.done);
+  }
+  delete sv;
+  return SV_OK;
+}

@@ -231,3 +231,35 @@ struct BatchKernelArgs {
   int32_t nunits;
   int32_t spin_limit;  // polls before a wait expires; < 0: every wait expires at once
 };
+
+// Serving: one workgroup takes one small request off the queue and runs its
+// whole adjoint -- forward sweeps, lambda = H psi and E = <psi|H|psi>, the
+// backward sweeps with their gradient slots, the gather into dE/dtheta --
+// with the request's planes in L2.  Coefficients are built by a launch before.
+struct ServeReq {
+  int32_t n;                  // qubits
+  int32_t n_params;           // user parameters (gradient length)
+  int32_t f_sweep, f_nsweeps; // forward sweeps in ServeArgs::sweeps
+  int32_t b_sweep, b_nsweeps; // backward sweeps
+  int32_t f_ndesc, b_ndesc;   // coefficient descriptors of the two plans
+  int32_t n_terms;            // observable terms
+  int32_t pad;
+  const CoefDesc *f_desc, *b_desc;
+  const TabFactor *f_fac, *b_fac;
+  const double *f_params, *b_params;  // user parameters, then the plan's constants
+  double *f_coef, *b_coef;
+  void *re, *im;              // psi (2^n elements each)
+  void *lre, *lim;            // lambda
+  const PauliTermDev *terms;  // x, z, c of each term
+  double *slots;              // gradient slot sums of the backward plan
+  const int32_t *rowptr;      // parameter p takes slots gslots[rowptr[p] .. rowptr[p+1])
+  const int32_t *gslots;
+  double *out;                // E, then dE/dtheta_p
+};
+
+struct ServeArgs {
+  const ServeReq *reqs;
+  const SweepArgs *sweeps;
+  int32_t *head;              // next request to take (zero at launch)
+  int32_t nreq;
+};

@@ -180,146 +180,150 @@ __device__ void fast_givens(const double *r, double *out, bool form0 = false) {
   out[3] = 0.0;
 }
 
-__global__ void k_build_coefs(const CoefDesc *d, int nd, const double *params, const double *statics,
-                              const TabFactor *fac, double *coef) {
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nd; i += gridDim.x * blockDim.x) {
-    const CoefDesc cd = d[i];
-    const int fmt = cd.fmt & 0xff;
-    const bool dag = (cd.fmt & CF_DAGGER) != 0;
-    const bool f0 = (cd.fmt & CF_FORM0) != 0;
-    double th[3] = {0, 0, 0};
-    // pidx holds parameter indices except for the table / scale formats,
-    // where pidx[0] counts factors
-    const bool takes_params = fmt != CF_TABLE && fmt != CF_SCALE && fmt != CF_COPY &&
-                              fmt != CF_IDENT2 && fmt != CF_CONSTS;
-    if (takes_params)
-      for (int k = 0; k < 3; k++)
-        if (cd.pidx[k] >= 0) th[k] = params[cd.pidx[k]];
-    double *out = coef + cd.dst;
-    if (fmt == CF_CONSTS) {
-      for (int k = 0; k < cd.len; k++) out[k] = params[cd.src + k];
-    } else if (fmt == CF_FASTR) {
-      double m[8];
-      gate_local(cd.kind, th, m);
-      double r[4] = {m[0], m[2], m[4], m[6]};   // real 2x2
+// Coefficients of one descriptor, written at coef + cd.dst.
+__device__ void build_coef(const CoefDesc &cd, const double *params, const double *statics,
+                           const TabFactor *fac, double *coef) {
+  const int fmt = cd.fmt & 0xff;
+  const bool dag = (cd.fmt & CF_DAGGER) != 0;
+  const bool f0 = (cd.fmt & CF_FORM0) != 0;
+  double th[3] = {0, 0, 0};
+  // pidx holds parameter indices except for the table / scale formats,
+  // where pidx[0] counts factors
+  const bool takes_params = fmt != CF_TABLE && fmt != CF_SCALE && fmt != CF_COPY &&
+                            fmt != CF_IDENT2 && fmt != CF_CONSTS;
+  if (takes_params)
+    for (int k = 0; k < 3; k++)
+      if (cd.pidx[k] >= 0) th[k] = params[cd.pidx[k]];
+  double *out = coef + cd.dst;
+  if (fmt == CF_CONSTS) {
+    for (int k = 0; k < cd.len; k++) out[k] = params[cd.src + k];
+  } else if (fmt == CF_FASTR) {
+    double m[8];
+    gate_local(cd.kind, th, m);
+    double r[4] = {m[0], m[2], m[4], m[6]};   // real 2x2
+    if (dag) { const double t = r[1]; r[1] = r[2]; r[2] = t; }
+    fast_givens(r, out, f0);
+  } else if (fmt == CF_SCALE) {
+    // product of the fast-Givens scales of the (daggered, if flagged) real gates
+    double sc = 1.0;
+    for (int f = cd.src; f < cd.src + cd.pidx[0]; f++) {
+      const TabFactor tf = fac[f];
+      double m[8], rec[4];
+      double tt[3] = {tf.pidx >= 0 ? params[tf.pidx] : 0.0, 0.0, 0.0};
+      gate_local(tf.kind, tt, m);
+      double r[4] = {m[0], m[2], m[4], m[6]};
       if (dag) { const double t = r[1]; r[1] = r[2]; r[2] = t; }
-      fast_givens(r, out, f0);
-    } else if (fmt == CF_SCALE) {
-      // product of the fast-Givens scales of the (daggered, if flagged) real gates
-      double sc = 1.0;
-      for (int f = cd.src; f < cd.src + cd.pidx[0]; f++) {
-        const TabFactor tf = fac[f];
-        double m[8], rec[4];
-        double tt[3] = {tf.pidx >= 0 ? params[tf.pidx] : 0.0, 0.0, 0.0};
-        gate_local(tf.kind, tt, m);
-        double r[4] = {m[0], m[2], m[4], m[6]};
+      fast_givens(r, rec, f0);
+      sc *= rec[2];
+    }
+    out[0] = sc;
+  } else if (fmt == CF_IDENT2) {
+    out[0] = 1.0; out[1] = 0.0; out[2] = 0.0; out[3] = 1.0;
+  } else if (fmt == CF_TABLE) {
+    const int G = 1 << cd.len;
+    for (int j = 0; j < G; j++) { out[2 * j] = 1.0; out[2 * j + 1] = 0.0; }
+    for (int f = cd.src; f < cd.src + cd.pidx[0]; f++) {
+      const TabFactor tf = fac[f];
+      double m[8];
+      double tt[3] = {tf.pidx >= 0 ? params[tf.pidx] : 0.0, 0.0, 0.0};
+      gate_local(tf.kind, tt, m);
+      double gsc = 1.0;
+      if (tf.neg == 2) {
+        double r[4] = {m[0], m[2], m[4], m[6]}, rec[4];
         if (dag) { const double t = r[1]; r[1] = r[2]; r[2] = t; }
         fast_givens(r, rec, f0);
-        sc *= rec[2];
+        gsc = rec[2];
       }
-      out[0] = sc;
-    } else if (fmt == CF_IDENT2) {
-      out[0] = 1.0; out[1] = 0.0; out[2] = 0.0; out[3] = 1.0;
-    } else if (fmt == CF_TABLE) {
-      const int G = 1 << cd.len;
-      for (int j = 0; j < G; j++) { out[2 * j] = 1.0; out[2 * j + 1] = 0.0; }
-      for (int f = cd.src; f < cd.src + cd.pidx[0]; f++) {
-        const TabFactor tf = fac[f];
-        double m[8];
-        double tt[3] = {tf.pidx >= 0 ? params[tf.pidx] : 0.0, 0.0, 0.0};
-        gate_local(tf.kind, tt, m);
-        double gsc = 1.0;
-        if (tf.neg == 2) {
-          double r[4] = {m[0], m[2], m[4], m[6]}, rec[4];
-          if (dag) { const double t = r[1]; r[1] = r[2]; r[2] = t; }
-          fast_givens(r, rec, f0);
-          gsc = rec[2];
-        }
-        for (int j = 0; j < G; j++) {
-          if (((uint32_t)j & tf.cm) != tf.cv) continue;
-          double dr, di;
-          if (tf.neg == 2) { dr = gsc; di = 0.0; }
-          else if (tf.neg) { dr = -1.0; di = 0.0; }
-          else if (__builtin_popcount((uint32_t)j & tf.mask) & 1) { dr = m[6]; di = m[7]; }
-          else { dr = m[0]; di = m[1]; }
-          const double xr = out[2 * j], xi = out[2 * j + 1];
-          out[2 * j] = xr * dr - xi * di;
-          out[2 * j + 1] = xr * di + xi * dr;
-        }
-      }
-      if (dag)
-        for (int j = 0; j < G; j++) out[2 * j + 1] = -out[2 * j + 1];
-    } else if (fmt == CF_U2X2 || fmt == CF_R2X2 || fmt == CF_DIAG) {
-      double m[8];
-      gate_local(cd.kind, th, m);
-      if (dag) {
-        // conjugate transpose
-        double t0 = m[2], t1 = m[3];
-        m[2] = m[4]; m[3] = -m[5];
-        m[4] = t0; m[5] = -t1;
-        m[1] = -m[1]; m[7] = -m[7];
-      }
-      if (fmt == CF_U2X2) {
-        for (int k = 0; k < 8; k++) out[k] = m[k];
-      } else if (fmt == CF_R2X2) {
-        out[0] = m[0]; out[1] = m[2]; out[2] = m[4]; out[3] = m[6];
-      } else {
-        out[0] = m[0]; out[1] = m[1]; out[2] = m[6]; out[3] = m[7];
-      }
-    } else if (fmt == CF_Q4X4 || fmt == CF_D16) {
-      const int D = fmt == CF_Q4X4 ? 4 : 16;
-      for (int k = 0; k < 2 * D * D; k++) out[k] = 0.0;
-      double s, c;
-      sincos(0.5 * th[0], &s, &c);
-      if (cd.kind == K_RXX || cd.kind == K_RYY) {
-        // c I - i s P(x)P; XX maps j -> 3-j; YY has sign -1 on |00>,|11>
-        for (int j = 0; j < 4; j++) {
-          out[(j * 4 + j) * 2] = c;
-          const double ph = (cd.kind == K_RYY && (j == 0 || j == 3)) ? -1.0 : 1.0;
-          out[((3 - j) * 4 + j) * 2 + 1] = -s * ph;
-        }
-      } else if (cd.kind == K_GIVENS || cd.kind == K_DEXC) {
-        const int lo = cd.kind == K_GIVENS ? 1 : 3, hi = cd.kind == K_GIVENS ? 2 : 12;
-        for (int j = 0; j < D; j++) out[(j * D + j) * 2] = 1.0;
-        out[(lo * D + lo) * 2] = c;
-        out[(lo * D + hi) * 2] = -s;
-        out[(hi * D + lo) * 2] = s;
-        out[(hi * D + hi) * 2] = c;
-      } else if (cd.kind == K_SWAP) {
-        out[(0 * 4 + 0) * 2] = 1; out[(1 * 4 + 2) * 2] = 1;
-        out[(2 * 4 + 1) * 2] = 1; out[(3 * 4 + 3) * 2] = 1;
-      } else if (cd.kind == K_RZZ) {
-        for (int j = 0; j < 4; j++) {
-          const int par = (j ^ (j >> 1)) & 1;
-          out[(j * 4 + j) * 2] = c;
-          out[(j * 4 + j) * 2 + 1] = par ? s : -s;
-        }
-      }
-      if (dag) {
-        for (int r = 0; r < D; r++)
-          for (int q = r; q < D; q++) {
-            const double ar = out[(r * D + q) * 2], ai = out[(r * D + q) * 2 + 1];
-            const double br = out[(q * D + r) * 2], bi = out[(q * D + r) * 2 + 1];
-            out[(r * D + q) * 2] = br; out[(r * D + q) * 2 + 1] = -bi;
-            out[(q * D + r) * 2] = ar; out[(q * D + r) * 2 + 1] = -ai;
-          }
-      }
-    } else if (fmt == CF_COPY) {
-      // user matrix, 2^k x 2^k, len = 2 * 4^k
-      int D = 1;
-      while (2 * D * D < cd.len) D <<= 1;
-      for (int k = 0; k < cd.len; k++) out[k] = statics[cd.src + k];
-      if (dag) {
-        for (int r = 0; r < D; r++)
-          for (int q = r; q < D; q++) {
-            const double ar = out[(r * D + q) * 2], ai = out[(r * D + q) * 2 + 1];
-            const double br = out[(q * D + r) * 2], bi = out[(q * D + r) * 2 + 1];
-            out[(r * D + q) * 2] = br; out[(r * D + q) * 2 + 1] = -bi;
-            out[(q * D + r) * 2] = ar; out[(q * D + r) * 2 + 1] = -ai;
-          }
+      for (int j = 0; j < G; j++) {
+        if (((uint32_t)j & tf.cm) != tf.cv) continue;
+        double dr, di;
+        if (tf.neg == 2) { dr = gsc; di = 0.0; }
+        else if (tf.neg) { dr = -1.0; di = 0.0; }
+        else if (__builtin_popcount((uint32_t)j & tf.mask) & 1) { dr = m[6]; di = m[7]; }
+        else { dr = m[0]; di = m[1]; }
+        const double xr = out[2 * j], xi = out[2 * j + 1];
+        out[2 * j] = xr * dr - xi * di;
+        out[2 * j + 1] = xr * di + xi * dr;
       }
     }
+    if (dag)
+      for (int j = 0; j < G; j++) out[2 * j + 1] = -out[2 * j + 1];
+  } else if (fmt == CF_U2X2 || fmt == CF_R2X2 || fmt == CF_DIAG) {
+    double m[8];
+    gate_local(cd.kind, th, m);
+    if (dag) {
+      // conjugate transpose
+      double t0 = m[2], t1 = m[3];
+      m[2] = m[4]; m[3] = -m[5];
+      m[4] = t0; m[5] = -t1;
+      m[1] = -m[1]; m[7] = -m[7];
+    }
+    if (fmt == CF_U2X2) {
+      for (int k = 0; k < 8; k++) out[k] = m[k];
+    } else if (fmt == CF_R2X2) {
+      out[0] = m[0]; out[1] = m[2]; out[2] = m[4]; out[3] = m[6];
+    } else {
+      out[0] = m[0]; out[1] = m[1]; out[2] = m[6]; out[3] = m[7];
+    }
+  } else if (fmt == CF_Q4X4 || fmt == CF_D16) {
+    const int D = fmt == CF_Q4X4 ? 4 : 16;
+    for (int k = 0; k < 2 * D * D; k++) out[k] = 0.0;
+    double s, c;
+    sincos(0.5 * th[0], &s, &c);
+    if (cd.kind == K_RXX || cd.kind == K_RYY) {
+      // c I - i s P(x)P; XX maps j -> 3-j; YY has sign -1 on |00>,|11>
+      for (int j = 0; j < 4; j++) {
+        out[(j * 4 + j) * 2] = c;
+        const double ph = (cd.kind == K_RYY && (j == 0 || j == 3)) ? -1.0 : 1.0;
+        out[((3 - j) * 4 + j) * 2 + 1] = -s * ph;
+      }
+    } else if (cd.kind == K_GIVENS || cd.kind == K_DEXC) {
+      const int lo = cd.kind == K_GIVENS ? 1 : 3, hi = cd.kind == K_GIVENS ? 2 : 12;
+      for (int j = 0; j < D; j++) out[(j * D + j) * 2] = 1.0;
+      out[(lo * D + lo) * 2] = c;
+      out[(lo * D + hi) * 2] = -s;
+      out[(hi * D + lo) * 2] = s;
+      out[(hi * D + hi) * 2] = c;
+    } else if (cd.kind == K_SWAP) {
+      out[(0 * 4 + 0) * 2] = 1; out[(1 * 4 + 2) * 2] = 1;
+      out[(2 * 4 + 1) * 2] = 1; out[(3 * 4 + 3) * 2] = 1;
+    } else if (cd.kind == K_RZZ) {
+      for (int j = 0; j < 4; j++) {
+        const int par = (j ^ (j >> 1)) & 1;
+        out[(j * 4 + j) * 2] = c;
+        out[(j * 4 + j) * 2 + 1] = par ? s : -s;
+      }
+    }
+    if (dag) {
+      for (int r = 0; r < D; r++)
+        for (int q = r; q < D; q++) {
+          const double ar = out[(r * D + q) * 2], ai = out[(r * D + q) * 2 + 1];
+          const double br = out[(q * D + r) * 2], bi = out[(q * D + r) * 2 + 1];
+          out[(r * D + q) * 2] = br; out[(r * D + q) * 2 + 1] = -bi;
+          out[(q * D + r) * 2] = ar; out[(q * D + r) * 2 + 1] = -ai;
+        }
+    }
+  } else if (fmt == CF_COPY) {
+    // user matrix, 2^k x 2^k, len = 2 * 4^k
+    int D = 1;
+    while (2 * D * D < cd.len) D <<= 1;
+    for (int k = 0; k < cd.len; k++) out[k] = statics[cd.src + k];
+    if (dag) {
+      for (int r = 0; r < D; r++)
+        for (int q = r; q < D; q++) {
+          const double ar = out[(r * D + q) * 2], ai = out[(r * D + q) * 2 + 1];
+          const double br = out[(q * D + r) * 2], bi = out[(q * D + r) * 2 + 1];
+          out[(r * D + q) * 2] = br; out[(r * D + q) * 2 + 1] = -bi;
+          out[(q * D + r) * 2] = ar; out[(q * D + r) * 2 + 1] = -ai;
+        }
+    }
   }
+}
+
+__global__ void k_build_coefs(const CoefDesc *d, int nd, const double *params, const double *statics,
+                              const TabFactor *fac, double *coef) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nd; i += gridDim.x * blockDim.x)
+    build_coef(d[i], params, statics, fac, coef);
 }
 
 // --------------------------------------------------- Pauli tile pass
@@ -1658,4 +1662,195 @@ hipError_t svk_launch_batch_reduce(const int32_t *rowptr, const int32_t *slot, c
   hipLaunchKernelGGL(k_batch_reduce, dim3((nc + 255) / 256), dim3(256), 0, s, rowptr, slot, coef,
                      part, out, nc);
   return hipGetLastError();
+}
+
+// ------------------------------------------------------------- serving
+// Small adjoint requests, one workgroup each (see ServeReq).  The tiling is
+// fixed: 12-qubit tiles of 8-amplitude register groups, 512 threads; psi and
+// lambda tiles side by side take 128 KiB of LDS, so one workgroup runs per CU
+// and a request of n <= 12 qubits is one tile per sweep.
+#define SVS_M 12
+#define SVS_R 3
+
+namespace {
+
+// Coefficients of every request: blockIdx.y = request, both plans.
+__global__ void __launch_bounds__(256) k_serve_coefs(const ServeReq *reqs) {
+  const ServeReq &q = reqs[blockIdx.y];
+  const int nd = q.f_ndesc + q.b_ndesc;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nd; i += gridDim.x * blockDim.x) {
+    if (i < q.f_ndesc) build_coef(q.f_desc[i], q.f_params, nullptr, q.f_fac, q.f_coef);
+    else build_coef(q.b_desc[i - q.f_ndesc], q.b_params, nullptr, q.b_fac, q.b_coef);
+  }
+}
+
+// GEN: the requests' plans hold micro-op (interpreter) stages; without it
+// every stage of every sweep is a Kronecker stage and the kernel is leaner.
+template <typename T, int M, int R, bool GEN>
+__global__ void __launch_bounds__(1 << (M - R)) k_serve(ServeArgs sa) {
+  constexpr int NT = 1 << (M - R);
+  constexpr int NWAVE = NT / 64;
+  using C2 = typename C2T<T>::type;
+  __shared__ __align__(16) char tiles[2 * (1 << M) * sizeof(C2)];
+  __shared__ double wacc[NWAVE][SVI_GSLOTS_MAX];
+  __shared__ double wred[NWAVE];
+  __shared__ int32_t hb_s[SVI_MMAX];
+  __shared__ int32_t req_s;
+  C2 *const lt = (C2 *)tiles;
+  const int tid = threadIdx.x;
+  // the queue counter is taken by wave 0 as a whole wave (one lane adds 1)
+  const bool wave0 = __builtin_amdgcn_readfirstlane(tid) == 0;
+  const int one = tid == 0 ? 1 : 0;
+  for (;;) {
+    if (wave0) {
+      const int v = __hip_atomic_fetch_add(sa.head, one, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (tid == 0) req_s = v;
+    }
+    __syncthreads();
+    const int r = __builtin_amdgcn_readfirstlane(req_s);
+    __syncthreads();
+    if (r >= sa.nreq) break;
+    const ServeReq &q = sa.reqs[r];
+
+    // ---- forward: the circuit from |0..0> (the first sweep synthesises it)
+    for (int s = 0; s < q.f_nsweeps; s++) {
+      const SVI_CONST SweepArgs &a = cptr(sa.sweeps)[q.f_sweep + s];
+      sweep_tiles<T, M, R, !GEN>(a, 0, a.ntiles, lt, hb_s);
+    }
+    __syncthreads();
+
+    // ---- lambda = H psi and E = Re <psi|lambda> (paper Section 4.4 Pauli
+    // action: P|b> = i^{nY} (-1)^{popcount(b & z)} |b ^ x>)
+    double e = 0.0;
+    {
+      const int64_t N = (int64_t)1 << q.n;
+      const T *pr = (const T *)q.re, *pim = (const T *)q.im;
+      T *lr = (T *)q.lre, *li = (T *)q.lim;
+      for (int64_t b = tid; b < N; b += NT) {
+        double ar = 0.0, ai = 0.0;
+        for (int t = 0; t < q.n_terms; t++) {
+          const uint64_t x = q.terms[t].x, z = q.terms[t].z;
+          const double c = q.terms[t].c;
+          const uint64_t src = (uint64_t)b ^ x;
+          const double sr = (double)pr[src], si = (double)pim[src];
+          double tr, ti;
+          switch (__builtin_popcountll(x & z) & 3) {   // i^{nY}
+            case 0: tr = sr; ti = si; break;
+            case 1: tr = -si; ti = sr; break;
+            case 2: tr = -sr; ti = -si; break;
+            default: tr = si; ti = -sr; break;
+          }
+          if (__builtin_popcountll(src & z) & 1) { tr = -tr; ti = -ti; }
+          ar += c * tr;
+          ai += c * ti;
+        }
+        lr[b] = (T)ar;
+        li[b] = (T)ai;
+        e += (double)pr[b] * ar + (double)pim[b] * ai;
+      }
+      e = wave_sum(e);
+      if ((tid & 63) == 0) wred[tid >> 6] = e;
+      __syncthreads();
+      e = 0.0;
+      for (int w = 0; w < NWAVE; w++) e += wred[w];
+    }
+    __syncthreads();
+
+    // ---- backward: two-state sweeps; each gradient term is summed over the
+    // wave, then added to the wave's LDS row of its slot (in tile and stage
+    // order: deterministic), and the rows are summed per sweep
+    for (int s = 0; s < q.b_nsweeps; s++) {
+      const SVI_CONST SweepArgs &a = cptr(sa.sweeps)[q.b_sweep + s];
+      const int m = a.m, c = a.c, nh = a.nh;
+      const int ntile_el = 1 << m;
+      const int nst = a.stage_end - a.stage_begin;
+      const SVI_CONST StageDesc *stages = cptr(a.stages + a.stage_begin);
+      const SVI_CONST double *coef = cptr(a.coef);
+      T *const pr[2] = {(T *)a.re, (T *)a.re2};
+      T *const pi[2] = {(T *)a.im, (T *)a.im2};
+      if (tid < SVI_MMAX) hb_s[tid] = a.hb[tid < nh ? tid : 0];
+      for (int k = tid; k < NWAVE * SVI_GSLOTS_MAX; k += NT) (&wacc[0][0])[k] = 0.0;
+      __syncthreads();
+      const bool active = tid < (1 << (m > R ? m - R : 0));
+      for (int64_t tile = 0; tile < a.ntiles; tile++) {
+        const uint64_t base = tile_base(tile, c, hb_s, nh);
+        for (int st2 = 0; st2 < 2; st2++)
+          for (int i = tid; i < ntile_el; i += NT) {
+            const uint64_t g = base + spread_row(i >> c, hb_s, nh) + (uint64_t)(i & ((1 << c) - 1));
+            lt[st2 * (1 << M) + swz<T>(i)] = C2{pr[st2][g], pi[st2][g]};
+          }
+        __syncthreads();
+        for (int st = 0; st < nst; st++) {
+          const SVI_CONST StageDesc &sd = stages[st];
+          const int gbs = swz<T>(stage_base<M, R>(tid, sd)) * (int)sizeof(C2);
+          auto sink = [&](int slot, double v) {
+            const double w = wave_total63(v);
+            if ((tid & 63) == 63) atomicAdd(&wacc[tid >> 6][slot], w);
+          };
+          if (!GEN || sd.kind == ST_KRON)
+            kron2_stage<T, R>((char *)lt, (char *)(lt + (1 << M)), gbs, sd, coef, a.ops, a.coef, active,
+                              sink);
+          else if constexpr (GEN)
+            ops2_stage<T, R>((char *)lt, (char *)(lt + (1 << M)), gbs, sd, a.ops, a.coef, active, sink);
+        }
+        for (int st2 = 0; st2 < 2; st2++)
+          for (int i = tid; i < ntile_el; i += NT) {
+            const uint64_t g = base + spread_row(i >> c, hb_s, nh) + (uint64_t)(i & ((1 << c) - 1));
+            const C2 p = lt[st2 * (1 << M) + swz<T>(i)];
+            pr[st2][g] = p.x;
+            pi[st2][g] = p.y;
+          }
+        __syncthreads();
+      }
+      for (int sl = tid; sl < a.n_gslots; sl += NT) {
+        double v = 0.0;
+        for (int w = 0; w < NWAVE; w++) v += wacc[w][sl];
+        q.slots[a.gslot_begin + sl] = v;
+      }
+      __syncthreads();
+    }
+
+    // ---- dE/dtheta_p: the parameter's slots in slot order
+    for (int p = tid; p < q.n_params; p += NT) {
+      double g = 0.0;
+      for (int k = q.rowptr[p]; k < q.rowptr[p + 1]; k++) g += q.slots[q.gslots[k]];
+      q.out[1 + p] = g;
+    }
+    if (tid == 0) q.out[0] = e;
+    __syncthreads();
+  }
+}
+
+}  // namespace
+
+int svk_serve_max_qubits() { return SVS_M + 1; }
+
+hipError_t svk_launch_serve_coefs(const ServeReq *d_reqs, int nreq, int max_desc, hipStream_t s) {
+  if (nreq <= 0) return hipSuccess;
+  const int bx = max_desc > 0 ? (max_desc + 255) / 256 : 1;
+  hipLaunchKernelGGL(k_serve_coefs, dim3(bx < 64 ? bx : 64, nreq), dim3(256), 0, s, d_reqs);
+  return hipGetLastError();
+}
+
+hipError_t svk_launch_serve(const ServeReq *d_reqs, const SweepArgs *d_sweeps, int32_t *d_head,
+                            int nreq, int general, int grid, hipStream_t s) {
+  if (nreq <= 0) return hipSuccess;
+  ServeArgs a;
+  a.reqs = d_reqs;
+  a.sweeps = d_sweeps;
+  a.head = d_head;
+  a.nreq = nreq;
+  if (general)
+    hipLaunchKernelGGL((k_serve<double, SVS_M, SVS_R, true>), dim3(grid), dim3(1 << (SVS_M - SVS_R)), 0,
+                       s, a);
+  else
+    hipLaunchKernelGGL((k_serve<double, SVS_M, SVS_R, false>), dim3(grid), dim3(1 << (SVS_M - SVS_R)), 0,
+                       s, a);
+  return hipGetLastError();
+}
+
+int svk_serve_tiling(int *M, int *R) {
+  *M = SVS_M;
+  *R = SVS_R;
+  return 1 << (SVS_M - SVS_R);
 }

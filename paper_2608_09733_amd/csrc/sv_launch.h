@@ -88,3 +88,13 @@ hipError_t svk_launch_batch_reset(int32_t *head, int32_t *done, int32_t *err, in
                                   hipStream_t s);
 hipError_t svk_launch_batch_reduce(const int32_t *rowptr, const int32_t *slot, const double *coef,
                                    const double *part, double *out, int nc, hipStream_t s);
+
+// Serving (whole small requests, one workgroup each): coefficients of every
+// request (max_desc: most descriptors of one request), then the persistent
+// request kernel over reqs[0 .. nreq); *d_head must be zero.  general: some
+// plan holds micro-op stages.
+hipError_t svk_launch_serve_coefs(const ServeReq *d_reqs, int nreq, int max_desc, hipStream_t s);
+hipError_t svk_launch_serve(const ServeReq *d_reqs, const SweepArgs *d_sweeps, int32_t *d_head,
+                            int nreq, int general, int grid, hipStream_t s);
+int svk_serve_max_qubits();
+int svk_serve_tiling(int *M, int *R);   // returns threads per workgroup

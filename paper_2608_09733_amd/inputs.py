@@ -61,6 +61,9 @@ class Circuit:
     n: int
     ops: List[Op]
     params: np.ndarray                     # float64, length n_params
+    # structure key: circuits with equal non-None keys have identical op lists
+    # (kinds, qubits, controls, parameter slots); only their angles differ
+    key: Optional[Tuple] = None
 
     @property
     def n_params(self) -> int:
@@ -224,7 +227,7 @@ def serving_trace(rate: float, count: int = 2000, seed: int = 0, n_lo: int = 10,
     for i in range(count):
         n = int(np.clip(round(math.exp(rng.uniform(math.log(n_lo), math.log(n_hi)))), n_lo, n_hi))
         L = int(rng.integers(l_lo, l_hi + 1))
-        circ = Circuit(n, layered_structure(n, L), _layer_angles(rng, n, L))
+        circ = Circuit(n, layered_structure(n, L), _layer_angles(rng, n, L), key=("layered", n, L))
         reqs.append(Request(i, float(t[i]), circ, tfim(n)))
     return reqs
 

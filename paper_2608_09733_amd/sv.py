@@ -109,6 +109,11 @@ def lib():
         "sv_batch_autotune": (C.c_int, [C.POINTER(SvCircuitDesc), i32, C.c_int, dp, i32, vp,
                                         C.POINTER(i32), C.POINTER(i32), C.POINTER(i32), dp]),
         "sv_batch_copy_state": (C.c_int, [vp, i32, vp, vp, vp]),
+        "sv_serve_create": (C.c_int, [C.POINTER(vp)]),
+        "sv_serve_max_qubits": (i32, []),
+        "sv_serve_check": (C.c_int, [vp, C.POINTER(SvCircuitDesc)]),
+        "sv_serve_submit": (C.c_int, [vp, C.POINTER(SvCircuitDesc), i32, dp, vp, vp]),
+        "sv_serve_free": (C.c_int, [vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -446,8 +451,25 @@ def version() -> str:
     return lib().sv_version().decode()
 
 
+_OPA_CACHE: dict = {}
+
+
+def op_array_for(circuit) -> "OpArray":
+    """The sv_op records of `circuit`, shared by every circuit with the same
+    structure key (`circuit.key`, when set); built afresh otherwise."""
+    key = getattr(circuit, "key", None)
+    if key is None:
+        return OpArray(circuit.ops)
+    oa = _OPA_CACHE.get(key)
+    if oa is None:
+        if len(_OPA_CACHE) >= 512:
+            _OPA_CACHE.clear()
+        oa = _OPA_CACHE[key] = OpArray(circuit.ops)
+    return oa
+
+
 def _circuit_descs(circuits, observables):
-    ops = [OpArray(c.ops) for c in circuits]
+    ops = [op_array_for(c) for c in circuits]
     terms = [TermArray(h) for h in observables]
     descs = (SvCircuitDesc * max(1, len(circuits)))()
     for k, c in enumerate(circuits):
@@ -551,3 +573,58 @@ class Batch:
         u, s, up, by = C.c_int64(), C.c_int64(), C.c_double(), C.c_double()
         _check(lib().sv_batch_stats(self.h, C.byref(u), C.byref(s), C.byref(up), C.byref(by)))
         return u.value, s.value, up.value, by.value
+
+
+class Serve:
+    """Small adjoint requests run whole, one workgroup per request, in one
+    persistent launch per submission (sv_serve_*).  A request is a circuit
+    (.n .ops .params) and an observable; each returns E and dE/dtheta."""
+
+    def __init__(self):
+        h = C.c_void_p()
+        _check(lib().sv_serve_create(C.byref(h)))
+        self.h = h
+
+    @staticmethod
+    def max_qubits() -> int:
+        return int(lib().sv_serve_max_qubits())
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().sv_serve_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def supports(self, circuit, ham) -> bool:
+        """True if the serving kernel takes this request (plans get cached);
+        False if it must go through State.adjoint_grad."""
+        descs, keep = _circuit_descs([circuit], [ham])
+        st = lib().sv_serve_check(self.h, descs)
+        del keep
+        if st == -5:     # SV_EUNSUPPORTED
+            return False
+        _check(st)
+        return True
+
+    def submit(self, circuits, observables, out_tensor, stream=None):
+        """Enqueue the requests on `stream`; `out_tensor` (FP64 device, at
+        least sum(1 + n_params) elements) receives per request E then the
+        gradient, concatenated in request order.  Returns the offsets."""
+        descs, keep = _circuit_descs(circuits, observables)
+        flat = (np.concatenate([np.asarray(c.params, dtype=np.float64).reshape(-1) for c in circuits])
+                if circuits else np.zeros(0))
+        p, _ = _params_ptr(flat)
+        offs = np.zeros(len(circuits) + 1, dtype=np.int64)
+        offs[1:] = np.cumsum([1 + len(c.params) for c in circuits])
+        if out_tensor.numel() < offs[-1]:
+            raise ValueError(f"output holds {out_tensor.numel()} values, {offs[-1]} needed")
+        _check(lib().sv_serve_submit(self.h, descs, len(circuits),
+                                     p.ctypes.data_as(C.POINTER(C.c_double)),
+                                     C.c_void_p(out_tensor.data_ptr()), _stream_ptr(stream)))
+        del keep
+        return offs

@@ -221,3 +221,31 @@ def test_default_tiling_query(sv):
     t = C.c_int32(0)
     assert sv.lib().sv_default_tiling(20, 7, 0, C.byref(t), C.byref(t), C.byref(t)) == -1
     assert sv.lib().sv_default_tiling(20, 0, 0, None, C.byref(t), C.byref(t)) == -1
+
+
+def test_serving_kernel_routing_is_host_only(sv):
+    """sv_serve_check decides on the host which requests the serving kernel
+    takes: 3..13 qubits, ops on at most 3 qubits, no user matrices."""
+    S = sv.Serve()
+    try:
+        assert sv.Serve.max_qubits() == 13
+        for n in (3, 7, 12, 13):
+            assert S.supports(I.layered(n, 2, seed=n), I.tfim(n))
+        assert S.supports(I.hea(9, 2), I.tfim(9))
+        assert S.supports(I.qft(6), I.tfim(6))
+        assert S.supports(I.Circuit(4, [], np.zeros(0)), I.tfim(4))
+        for k in range(6):
+            c = I.random_circuit(9, 30, seed=k, allow_unitary=False, max_qubits=3)
+            assert S.supports(c, I.random_hamiltonian(9, 4, seed=k))
+        assert not S.supports(I.layered(2, 2), I.tfim(2))
+        assert not S.supports(I.layered(14, 1), I.tfim(14))
+        wide = I.Circuit(6, [I.Op("x", (0,), (1, 2, 3))], np.zeros(0))
+        assert not S.supports(wide, I.tfim(6))
+        um = I.Circuit(5, [I.Op("unitary", (0,), matrix=np.eye(2))], np.zeros(0))
+        assert not S.supports(um, I.tfim(5))
+        bad = I.hamiltonian(6, [("Z", [0], 1.0)])
+        bad.z[0] = np.uint64(1 << 7)
+        with pytest.raises(sv.SvError):
+            S.supports(I.layered(6, 1), bad)
+    finally:
+        S.close()

@@ -1,0 +1,143 @@
+"""The serving kernel (sv_serve_*): every small request's E and dE/dtheta equal
+the oracle's adjoint at 1e-12 (relative to the largest magnitude), each equals
+the same request submitted alone bit for bit, queued submissions do not
+disturb each other, and refusals happen before any device work."""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2608_09733_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-12
+
+
+def _requests():
+    rng = np.random.default_rng(7)
+    reqs = []
+    for n in range(3, 14):
+        L = int(rng.integers(1, 6))
+        reqs.append((I.layered(n, L, seed=100 + n), I.tfim(n)))
+    for n in (3, 5, 8, 12, 13):
+        reqs.append((I.hea(n, 2, seed=200 + n), I.random_hamiltonian(n, 6, seed=n)))
+    for k, n in enumerate((4, 6, 9, 11, 13)):
+        reqs.append((I.random_circuit(n, 40, seed=300 + k, allow_unitary=False, max_qubits=3),
+                     I.random_hamiltonian(n, 5, seed=400 + k)))
+    reqs.append((I.ghz(7), I.tfim(7)))                       # no parameters
+    reqs.append((I.Circuit(5, [], np.zeros(0)), I.tfim(5)))  # no ops
+    reqs.append((I.layered(10, 3, seed=1), I.tfim(10)))     # one structure, two angle sets
+    reqs.append((I.layered(10, 3, seed=2), I.tfim(10)))
+    return reqs
+
+
+def _submit(S, reqs, stream=None):
+    import torch
+    tot = sum(1 + len(c.params) for c, _ in reqs)
+    out = torch.full((tot,), float("nan"), dtype=torch.float64, device="cuda")
+    offs = S.submit([c for c, _ in reqs], [h for _, h in reqs], out, stream)
+    return out, offs
+
+
+def _split(out, offs):
+    v = out.cpu().numpy()
+    return [(float(v[offs[k]]), v[offs[k] + 1:offs[k + 1]].copy()) for k in range(len(offs) - 1)]
+
+
+def _close(res, ref):
+    e, g = res
+    e_ref, g_ref = ref
+    if abs(e - e_ref) > TOL * max(1.0, abs(e_ref)):
+        return False
+    if g_ref.size and np.max(np.abs(g - g_ref)) > TOL * max(1.0, float(np.max(np.abs(g_ref)))):
+        return False
+    return True
+
+
+@pytest.fixture(scope="module")
+def serve():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_2608_09733_amd import sv
+    S = sv.Serve()
+    yield S
+    S.close()
+
+
+def test_serve_matches_oracle(serve):
+    import torch
+    reqs = _requests()
+    print(f"[case] serve {len(reqs)} mixed requests", flush=True)
+    out, offs = _submit(serve, reqs)
+    torch.cuda.synchronize()
+    res = _split(out, offs)
+    for k, (c, h) in enumerate(reqs):
+        e_ref, g_ref = O.adjoint_grad(c, h)
+        assert _close(res[k], (e_ref, np.asarray(g_ref)[:c.n_params])), (k, c.n)
+
+
+def test_serve_alone_equals_mix(serve):
+    import torch
+    reqs = _requests()
+    out, offs = _submit(serve, reqs)
+    torch.cuda.synchronize()
+    mix = _split(out, offs)
+    print("[case] serve each request alone", flush=True)
+    for k, r in enumerate(reqs):
+        o1, f1 = _submit(serve, [r])
+        torch.cuda.synchronize()
+        e, g = _split(o1, f1)[0]
+        assert e == mix[k][0] and np.array_equal(g, mix[k][1]), k
+
+
+def test_serve_queued_submissions(serve):
+    """Six submissions queued back to back (more than the staging ring holds)
+    on a side stream, each a different subset and order of the requests."""
+    import torch
+    reqs = _requests()
+    out, offs = _submit(serve, reqs)
+    torch.cuda.synchronize()
+    ref = _split(out, offs)
+    rng = np.random.default_rng(11)
+    s = torch.cuda.Stream()
+    jobs = []
+    print("[case] serve 6 queued submissions", flush=True)
+    with torch.cuda.stream(s):
+        for j in range(6):
+            idx = rng.permutation(len(reqs))[: int(rng.integers(1, len(reqs) + 1))]
+            o, f = _submit(serve, [reqs[i] for i in idx], s)
+            jobs.append((idx, o, f))
+    s.synchronize()
+    for idx, o, f in jobs:
+        got = _split(o, f)
+        for pos, i in enumerate(idx):
+            assert got[pos][0] == ref[i][0] and np.array_equal(got[pos][1], ref[i][1]), (pos, i)
+
+
+def test_serve_trace_requests(serve):
+    """Requests of the serving trace that the kernel takes (10..13 qubits,
+    4..30 layers, TFIM), 64 at once, against the oracle."""
+    import torch
+    trace = I.serving_trace(1000.0, 400, seed=5)
+    small = [r for r in trace if r.circuit.n <= 13][:64]
+    assert len(small) >= 32
+    reqs = [(r.circuit, r.ham) for r in small]
+    print(f"[case] serve {len(reqs)} trace requests", flush=True)
+    out, offs = _submit(serve, reqs)
+    torch.cuda.synchronize()
+    res = _split(out, offs)
+    for k, (c, h) in enumerate(reqs):
+        e_ref, g_ref = O.adjoint_grad(c, h)
+        assert _close(res[k], (e_ref, np.asarray(g_ref)[:c.n_params])), (k, c.n)
+
+
+def test_serve_refuses_before_device_work(serve):
+    import torch
+    from paper_2608_09733_amd import sv
+    reqs = [(I.layered(6, 2, seed=1), I.tfim(6)), (I.layered(14, 1, seed=1), I.tfim(14))]
+    out = torch.full((64,), 7.0, dtype=torch.float64, device="cuda")
+    with pytest.raises(sv.SvError) as ei:
+        serve.submit([c for c, _ in reqs], [h for _, h in reqs], out)
+    assert ei.value.status == -5 and "request 1" in str(ei.value)
+    torch.cuda.synchronize()
+    assert bool((out == 7.0).all())

@@ -327,13 +327,15 @@ def side_configs(sv, I, torch, serving=True):
     if not serving:
         return out
     # serving: Poisson arrivals at 200 req/s, n log-uniform in [10, 28], TFIM,
-    # (E, grad) per request; 4 lanes vs serial FIFO, bounded trace length
+    # (E, grad) per request; small requests batched into the serving kernel,
+    # one big lane, one mid lane, against serial FIFO on one lane
     from paper_2608_09733_amd import serving as S
-    srv = S.run(rate=200.0, count=120, lanes=4, budget_gb=200.0, seed=0)
-    out["serving_200rps_120req"] = srv
+    srv = S.run(rate=200.0, count=500, lanes=2, budget_gb=200.0, seed=0)
+    out["serving_200rps_500req"] = srv
     log(f"serving: {srv['served']['throughput_req_s']:.1f} req/s, p50 "
         f"{srv['served']['latency_p50_ms']:.1f} ms, p99 {srv['served']['latency_p99_ms']:.1f} ms; "
-        f"serial {srv['serial_fifo']['throughput_req_s']:.1f} req/s; "
+        f"serial {srv['serial_fifo']['throughput_req_s']:.1f} req/s, p50 "
+        f"{srv['serial_fifo']['latency_p50_ms']:.1f} ms, p99 {srv['serial_fifo']['latency_p99_ms']:.1f} ms; "
         f"alone-vs-mix mismatches {srv['alone_vs_mix_mismatches']}")
     return out
 

@@ -1,24 +1,41 @@
 """Serving loop: variational requests (circuit, angles, Hamiltonian) arrive
 over time; each returns (E, dE/dtheta) from the adjoint path.
 
-Scheduling is continuous: a request is admitted as soon as a lane is free and
-the HBM budget holds its three states (psi, lambda and the backward copy of
-psi, 3 * 2^n * 16 bytes in FP64); it then runs on its lane's HIP stream while
-other lanes run other requests, so requests of different sizes overlap on the
-GPU and a long request does not hold back the short ones behind it.  Each lane
-keeps one library handle per qubit count, so after warm-up a request
-allocates only its small output buffer, and plans are reused per circuit
-structure.  Admission is FIFO.
+Requests fall into three classes, each FIFO within itself:
+
+* small -- requests the serving kernel takes (3..13 qubits, ops on at most 3
+  qubits): they join the batch path as they arrive.  Whenever fewer than two
+  submissions are in flight, every small request that has arrived is
+  submitted as one persistent launch (sv_serve_submit) on a stream of its
+  own; one workgroup runs one request whole, so these never queue behind a
+  28-qubit request and take a few CUs each.
+* big (n >= 21 qubits) and mid (the rest) -- run on stream lanes through
+  sv_adjoint_grad_device.  One lane takes big requests first (then mid ones
+  when no big request waits); the other lanes take only mid requests, so a
+  mid request never waits behind a long one.  One big lane is enough: a big
+  request fills the GPU by itself, and a second one running beside it only
+  time-slices the GPU with it while the short kernels of the small and mid
+  requests wait longer for free CUs (measured: p50 of the small requests
+  16 ms with one big lane, 32 ms with two, 495 ms with three).
+
+A request is admitted when the HBM budget holds its three states (psi,
+lambda and the backward copy of psi, 3 * 2^n * 16 bytes in FP64).  Each lane
+keeps one library handle per qubit count, so after warm-up a lane request
+allocates only its small output buffer; plans are cached per circuit
+structure.  With one lane and no batch path the loop is serial FIFO, the
+baseline the served figures are compared with.
 
 The executor is pluggable: `GpuExecutor` runs the HIP library; tests drive
 the scheduler with a simulated executor on the CPU.
 
-    python -m paper_2608_09733_amd.serving --rate 200 --count 200 --lanes 4
+    python -m paper_2608_09733_amd.serving --rate 200 --count 500 --lanes 2
+    python -m paper_2608_09733_amd.serving --sweep 50,100,200,500,1000,2000 --count 500
 """
 from __future__ import annotations
 
 import argparse
 import json
+import sys
 import time
 from collections import OrderedDict, deque
 from dataclasses import dataclass, field
@@ -27,6 +44,7 @@ from typing import Dict, List
 import numpy as np
 
 GB = 1e9
+SMALL, MID, BIG = "small", "mid", "big"
 
 
 def request_bytes(n: int, elem: int = 8) -> int:
@@ -43,11 +61,16 @@ class Outcome:
     done: float
     energy: float
     grad: np.ndarray
-    lane: int
+    lane: int            # stream lane, or -1 for the batch path
+    klass: str = MID
 
     @property
     def latency(self) -> float:
         return self.done - self.arrival
+
+
+def _pct(a: np.ndarray, q: float) -> float:
+    return float(np.percentile(a, q) * 1e3) if len(a) else 0.0
 
 
 @dataclass
@@ -58,31 +81,43 @@ class Report:
     peak_pool_bytes: int
     lanes: int
     budget_bytes: float
+    batches: int = 0
     stats: Dict[str, float] = field(default_factory=dict)
 
     def summary(self) -> Dict[str, float]:
         lat = np.array([o.latency for o in self.outcomes])
         q = np.array([o.admitted - o.arrival for o in self.outcomes])
         sv = np.array([o.done - o.admitted for o in self.outcomes])
-        return {
+        out = {
             "requests": len(self.outcomes),
             "lanes": self.lanes,
             "makespan_s": self.makespan,
             "throughput_req_s": len(self.outcomes) / self.makespan if self.makespan > 0 else 0.0,
-            "latency_p50_ms": float(np.percentile(lat, 50) * 1e3) if len(lat) else 0.0,
-            "latency_p99_ms": float(np.percentile(lat, 99) * 1e3) if len(lat) else 0.0,
+            "latency_p50_ms": _pct(lat, 50),
+            "latency_p99_ms": _pct(lat, 99),
             "queue_mean_ms": float(q.mean() * 1e3) if len(q) else 0.0,
             "service_mean_ms": float(sv.mean() * 1e3) if len(sv) else 0.0,
             "peak_inflight_gb": self.peak_inflight_bytes / GB,
             "peak_pool_gb": self.peak_pool_bytes / GB,
             "budget_gb": self.budget_bytes / GB,
+            "batch_submissions": self.batches,
         }
+        for k in (SMALL, MID, BIG):
+            lk = np.array([o.latency for o in self.outcomes if o.klass == k])
+            sk = np.array([o.done - o.admitted for o in self.outcomes if o.klass == k])
+            out[f"{k}_requests"] = int(len(lk))
+            out[f"{k}_latency_p50_ms"] = _pct(lk, 50)
+            out[f"{k}_latency_p99_ms"] = _pct(lk, 99)
+            out[f"{k}_service_mean_ms"] = float(sk.mean() * 1e3) if len(sk) else 0.0
+        return out
 
 
 class GpuExecutor:
-    """Runs requests through the HIP library, one HIP stream per lane."""
+    """Runs requests through the HIP library: lane requests on one HIP stream
+    per lane (sv_adjoint_grad_device), small requests through the serving
+    kernel on a stream of its own (sv_serve_submit)."""
 
-    def __init__(self, lanes: int, dtype: str = "c128"):
+    def __init__(self, lanes: int, dtype: str = "c128", batch: bool = True):
         import torch
         from . import sv
         self.torch = torch
@@ -93,6 +128,9 @@ class GpuExecutor:
         # per lane: qubit count -> handle, in least-recently-used order
         self.handles: List[OrderedDict] = [OrderedDict() for _ in range(lanes)]
         self.busy = [False] * lanes
+        self.serve = sv.Serve() if (batch and dtype == "c128") else None
+        self.bstream = torch.cuda.Stream() if self.serve is not None else None
+        self._takes: Dict[tuple, bool] = {}
 
     def pool_bytes(self) -> int:
         return sum(request_bytes(n, self.elem) for h in self.handles for n in h)
@@ -129,7 +167,8 @@ class GpuExecutor:
         with torch.cuda.stream(s):
             out = torch.empty(1 + len(req.circuit.params), dtype=torch.float64, device="cuda")
             st.reset()
-            st.adjoint_grad_device(req.circuit.ops, req.circuit.params, req.ham, out)
+            st.adjoint_grad_device(req.circuit.ops, req.circuit.params, req.ham, out,
+                                   op_array=sv.op_array_for(req.circuit))
             ev = torch.cuda.Event()
             ev.record(s)
         return (out, ev)
@@ -142,22 +181,77 @@ class GpuExecutor:
         self.busy[lane] = False
         return float(v[0]), v[1:].copy()
 
+    # ---- batch path
+    def batchable(self, req) -> bool:
+        """True if the serving kernel takes the request (decided once per
+        circuit structure key)."""
+        if self.serve is None:
+            return False
+        c = req.circuit
+        if not 3 <= c.n <= self.sv.Serve.max_qubits():
+            return False
+        key = getattr(c, "key", None)
+        if key is not None and key in self._takes:
+            return self._takes[key]
+        ok = self.serve.supports(c, req.ham)
+        if key is not None:
+            self._takes[key] = ok
+        return ok
+
+    def start_batch(self, reqs):
+        torch = self.torch
+        with torch.cuda.stream(self.bstream):
+            tot = sum(1 + len(r.circuit.params) for r in reqs)
+            out = torch.empty(tot, dtype=torch.float64, device="cuda")
+            offs = self.serve.submit([r.circuit for r in reqs], [r.ham for r in reqs], out,
+                                     self.bstream)
+            ev = torch.cuda.Event()
+            ev.record(self.bstream)
+        return (out, offs, ev)
+
+    def poll_batch(self, token):
+        out, offs, ev = token
+        if not ev.query():
+            return None
+        v = out.cpu().numpy()
+        return [(float(v[offs[k]]), v[offs[k] + 1:offs[k + 1]].copy()) for k in range(len(offs) - 1)]
+
     def close(self):
         for h in self.handles:
             for st in h.values():
                 st.close()
             h.clear()
+        if self.serve is not None:
+            self.serve.close()
+            self.serve = None
 
 
 class Server:
-    """Continuous FIFO admission under an HBM budget over `lanes` concurrent
-    request slots."""
+    """FIFO admission per request class under an HBM budget: small requests
+    through the executor's batch path (when it has one and `batch`), the rest
+    over `lanes` stream lanes (lane 0 big-first, the others mid-only; a single
+    lane serves every class in arrival order)."""
 
-    def __init__(self, executor, lanes: int, budget_bytes: float = 200 * GB, elem: int = 8):
+    def __init__(self, executor, lanes: int, budget_bytes: float = 200 * GB, elem: int = 8,
+                 batch: bool = True, big_qubits: int = 21, max_batch: int = 256,
+                 batch_inflight: int = 2):
         self.ex = executor
         self.lanes = lanes
         self.budget = budget_bytes
         self.elem = elem
+        self.batch = batch and hasattr(executor, "start_batch")
+        self.big_qubits = big_qubits
+        self.max_batch = max_batch
+        self.batch_inflight = batch_inflight
+        # queues a lane takes from, in order of preference
+        self.lane_queues = [(BIG, MID) if l == 0 else (MID,) for l in range(lanes)]
+        if lanes == 1:
+            self.lane_queues = [("all",)]
+
+    def klass(self, req) -> str:
+        if self.batch and self.ex.batchable(req):
+            return SMALL
+        return BIG if req.circuit.n >= self.big_qubits else MID
 
     def serve(self, trace, realtime: bool = True, clock=time.perf_counter,
               idle_sleep: float = 2e-4) -> Report:
@@ -165,21 +259,28 @@ class Server:
         for r in pending:
             if request_bytes(r.circuit.n, self.elem) > self.budget:
                 raise ValueError(f"request {r.rid}: {r.circuit.n} qubits exceed the HBM budget")
-        queue: deque = deque()
+        klass = {r.rid: self.klass(r) for r in pending}
+        queues: Dict[str, deque] = {k: deque() for k in (SMALL, MID, BIG, "all")}
         running: Dict[int, tuple] = {}          # lane -> (req, token, admitted)
+        batches: List[tuple] = []               # (reqs, token, admitted)
         inflight = 0
         peak_inflight = 0
         peak_pool = 0
+        n_batches = 0
         outcomes: List[Outcome] = []
         t0 = clock()
         now = 0.0
-        while pending or queue or running:
+        while pending or any(queues.values()) or running or batches:
             now = clock() - t0
-            if not realtime and not queue and not running and pending:
+            if (not realtime and not any(queues.values()) and not running and not batches
+                    and pending):
                 now = max(now, pending[0].arrival)
             while pending and (pending[0].arrival <= now or not realtime):
-                queue.append(pending.popleft())
+                r = pending.popleft()
+                k = klass[r.rid]
+                queues[k if (k == SMALL or self.lanes > 1) else "all"].append(r)
             progressed = False
+            # ---- completions
             for lane in list(running):
                 req, token, adm = running[lane]
                 res = self.ex.poll(lane, token)
@@ -187,32 +288,65 @@ class Server:
                     continue
                 done = clock() - t0
                 e, g = res
-                outcomes.append(Outcome(req.rid, req.circuit.n, req.arrival, adm, done, e, g, lane))
+                outcomes.append(Outcome(req.rid, req.circuit.n, req.arrival, adm, done, e, g, lane,
+                                        klass[req.rid]))
                 inflight -= request_bytes(req.circuit.n, self.elem)
                 del running[lane]
                 progressed = True
-            while queue:
-                free = [l for l in range(self.lanes) if l not in running]
-                if not free:
-                    break
-                req = queue[0]
-                need = request_bytes(req.circuit.n, self.elem)
-                if inflight + need > self.budget:
-                    break
-                # prefer a free lane that already holds a handle of this size
-                lane = next((l for l in free if not self.ex.needs_new(l, req.circuit.n)), free[0])
-                if self.ex.needs_new(lane, req.circuit.n):
-                    if not self.ex.evict_idle(need, self.budget, inflight):
+            for b in list(batches):
+                reqs, token, adm = b
+                res = self.ex.poll_batch(token)
+                if res is None:
+                    continue
+                done = clock() - t0
+                for req, (e, g) in zip(reqs, res):
+                    outcomes.append(Outcome(req.rid, req.circuit.n, req.arrival, adm, done, e, g, -1,
+                                            SMALL))
+                    inflight -= request_bytes(req.circuit.n, self.elem)
+                batches.remove(b)
+                progressed = True
+            # ---- small requests: one submission of all that have arrived
+            q = queues[SMALL]
+            if q and len(batches) < self.batch_inflight:
+                take = []
+                while q and len(take) < self.max_batch:
+                    need = request_bytes(q[0].circuit.n, self.elem)
+                    if inflight + need > self.budget:
                         break
-                queue.popleft()
+                    take.append(q.popleft())
+                    inflight += need
+                if take:
+                    adm = clock() - t0
+                    batches.append((take, self.ex.start_batch(take), adm))
+                    n_batches += 1
+                    peak_inflight = max(peak_inflight, inflight)
+                    progressed = True
+            # ---- lanes
+            for lane in range(self.lanes):
+                if lane in running:
+                    continue
+                req = None
+                for k in self.lane_queues[lane]:
+                    if queues[k]:
+                        cand = queues[k][0]
+                        need = request_bytes(cand.circuit.n, self.elem)
+                        if inflight + need > self.budget:
+                            break
+                        if self.ex.needs_new(lane, cand.circuit.n):
+                            if not self.ex.evict_idle(need, self.budget, inflight):
+                                break
+                        req = queues[k].popleft()
+                        break
+                if req is None:
+                    continue
                 adm = clock() - t0
                 running[lane] = (req, self.ex.start(lane, req), adm)
-                inflight += need
+                inflight += request_bytes(req.circuit.n, self.elem)
                 peak_inflight = max(peak_inflight, inflight)
                 peak_pool = max(peak_pool, self.ex.pool_bytes())
                 progressed = True
             if not progressed:
-                if running or not pending:
+                if running or batches or not pending:
                     time.sleep(idle_sleep)
                 else:
                     wait = pending[0].arrival - (clock() - t0)
@@ -220,22 +354,31 @@ class Server:
                         time.sleep(min(wait, 0.01))
         makespan = clock() - t0
         outcomes.sort(key=lambda o: o.rid)
-        return Report(outcomes, makespan, peak_inflight, peak_pool, self.lanes, self.budget)
+        return Report(outcomes, makespan, peak_inflight, peak_pool, self.lanes, self.budget, n_batches)
 
 
 def alone_vs_mix(report: Report, trace, dtype: str = "c128") -> int:
-    """Re-run every request alone (one lane, one request at a time) and count
-    those whose energy or gradient differs from the served result in any bit."""
+    """Re-run every request alone -- on one lane, or as a submission of one on
+    the batch path, whichever served it -- and count those whose energy or
+    gradient differs from the served result in any bit."""
     ex = GpuExecutor(1, dtype)
     try:
         by_id = {r.rid: r for r in trace}
         bad = 0
         for o in report.outcomes:
-            tok = ex.start(0, by_id[o.rid])
-            res = None
-            while res is None:
-                res = ex.poll(0, tok)
-            e, g = res
+            req = by_id[o.rid]
+            if o.lane < 0:
+                tok = ex.start_batch([req])
+                res = None
+                while res is None:
+                    res = ex.poll_batch(tok)
+                e, g = res[0]
+            else:
+                tok = ex.start(0, req)
+                res = None
+                while res is None:
+                    res = ex.poll(0, tok)
+                e, g = res
             if e != o.energy or not np.array_equal(g, o.grad):
                 bad += 1
         return bad
@@ -245,47 +388,60 @@ def alone_vs_mix(report: Report, trace, dtype: str = "c128") -> int:
 
 def run(rate: float, count: int, lanes: int, budget_gb: float = 200.0, seed: int = 0,
         dtype: str = "c128", serial_baseline: bool = True, check_identity: bool = True,
-        n_hi: int = 28) -> Dict[str, object]:
+        n_hi: int = 28, log=None) -> Dict[str, object]:
+    """Served (classes, batch path, `lanes` lanes) and serial FIFO (one lane, no
+    batch path) over the same trace.  Each runs the trace twice: the first pass
+    builds the handles and plans (cold), the second is reported."""
     from . import inputs as I
     trace = I.serving_trace(rate, count, seed=seed, n_hi=n_hi)
-    out: Dict[str, object] = {"rate_req_s": rate, "trace_requests": count, "seed": seed}
+    out: Dict[str, object] = {"rate_req_s": rate, "trace_requests": count, "seed": seed,
+                              "trace_span_s": float(trace[-1].arrival) if trace else 0.0}
     ex = GpuExecutor(lanes, dtype)
     try:
-        # the first pass builds the lane handles and plans (cold); the second
-        # pass over the same trace is the steady state that is reported
         cold = Server(ex, lanes, budget_gb * GB, ex.elem).serve(trace)
         rep = Server(ex, lanes, budget_gb * GB, ex.elem).serve(trace)
     finally:
         ex.close()
     out["served_cold"] = cold.summary()
     out["served"] = rep.summary()
+    if log:
+        log(f"served {rate:g} req/s: {out['served']['throughput_req_s']:.1f} req/s")
     if check_identity:
         out["alone_vs_mix_mismatches"] = alone_vs_mix(rep, trace, dtype)
     if serial_baseline:
-        ex1 = GpuExecutor(1, dtype)
+        ex1 = GpuExecutor(1, dtype, batch=False)
         try:
-            Server(ex1, 1, budget_gb * GB, ex1.elem).serve(trace)
-            rep1 = Server(ex1, 1, budget_gb * GB, ex1.elem).serve(trace)
+            Server(ex1, 1, budget_gb * GB, ex1.elem, batch=False).serve(trace)
+            rep1 = Server(ex1, 1, budget_gb * GB, ex1.elem, batch=False).serve(trace)
         finally:
             ex1.close()
         out["serial_fifo"] = rep1.summary()
+        s, b = out["served"], out["serial_fifo"]
+        out["throughput_ratio"] = s["throughput_req_s"] / b["throughput_req_s"]
+        if log:
+            log(f"serial {rate:g} req/s: {b['throughput_req_s']:.1f} req/s")
     return out
 
 
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--rate", type=float, default=200.0)
-    ap.add_argument("--count", type=int, default=200)
-    ap.add_argument("--lanes", type=int, default=4)
+    ap.add_argument("--sweep", type=str, default="",
+                    help="comma-separated rates; one JSON line per rate")
+    ap.add_argument("--count", type=int, default=500)
+    ap.add_argument("--lanes", type=int, default=2)
     ap.add_argument("--budget-gb", type=float, default=200.0)
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--n-hi", type=int, default=28)
     ap.add_argument("--no-serial", action="store_true")
     ap.add_argument("--no-identity", action="store_true")
     a = ap.parse_args()
-    res = run(a.rate, a.count, a.lanes, a.budget_gb, a.seed, serial_baseline=not a.no_serial,
-              check_identity=not a.no_identity, n_hi=a.n_hi)
-    print(json.dumps(res), flush=True)
+    rates = [float(v) for v in a.sweep.split(",")] if a.sweep else [a.rate]
+    for rate in rates:
+        res = run(rate, a.count, a.lanes, a.budget_gb, a.seed, serial_baseline=not a.no_serial,
+                  check_identity=not a.no_identity, n_hi=a.n_hi,
+                  log=lambda m: print(m, file=sys.stderr, flush=True))
+        print(json.dumps(res), flush=True)
 
 
 if __name__ == "__main__":

@@ -1,5 +1,6 @@
-"""The serving loop on the GPU: every served (E, grad) equals the oracle's
-adjoint at 1e-12, and equals the same request run alone bit for bit."""
+"""The serving loop on the GPU: every served (E, grad) -- from the batch path
+(n <= 13) and from the stream lanes alike -- equals the oracle's adjoint at
+1e-12, and equals the same request run alone bit for bit."""
 import numpy as np
 import pytest
 
@@ -23,6 +24,7 @@ def test_served_results_match_oracle_and_alone():
     finally:
         ex.close()
     assert len(rep.outcomes) == len(trace)
+    assert any(o.lane < 0 for o in rep.outcomes) and any(o.lane >= 0 for o in rep.outcomes)
     by_id = {r.rid: r for r in trace}
     for o in rep.outcomes:
         r = by_id[o.rid]

@@ -82,3 +82,85 @@ def test_more_lanes_overlap_requests():
     assert four.makespan < 0.6 * one.makespan
     s = four.summary()
     assert s["requests"] == 24 and s["latency_p99_ms"] >= s["latency_p50_ms"]
+
+
+class FakeBatchExecutor(FakeExecutor):
+    """FakeExecutor with a batch path for requests of n <= 13: a submission
+    completes `bdur` seconds after it starts."""
+
+    def __init__(self, lanes, dur=lambda n: 1e-4 * (1 << max(0, n - 10)), bdur=5e-4):
+        super().__init__(lanes, dur)
+        self.bdur = bdur
+        self.batches = []
+        self.live = 0
+        self.max_live = 0
+
+    def batchable(self, req):
+        return 3 <= req.circuit.n <= 13
+
+    def start_batch(self, reqs):
+        self.batches.append([r.rid for r in reqs])
+        self.live += 1
+        self.max_live = max(self.max_live, self.live)
+        return (time.perf_counter() + self.bdur, [r.rid for r in reqs])
+
+    def poll_batch(self, token):
+        t, rids = token
+        if time.perf_counter() < t:
+            return None
+        self.live -= 1
+        return [(float(r), np.array([r], dtype=float)) for r in rids]
+
+
+def test_small_requests_take_the_batch_path():
+    tr = _trace(count=60, rate=5000.0, n_hi=24)
+    ex = FakeBatchExecutor(4)
+    rep = S.Server(ex, 4).serve(tr)
+    assert [o.rid for o in rep.outcomes] == [r.rid for r in tr]
+    for o in rep.outcomes:
+        assert o.energy == float(o.rid)
+        assert (o.lane < 0) == (o.n <= 13) == (o.klass == S.SMALL)
+    on_lanes = {rid for rid, _, _ in ex.started}
+    batched = [rid for b in ex.batches for rid in b]
+    assert not on_lanes & set(batched)
+    assert sorted(on_lanes | set(batched)) == [r.rid for r in tr]
+    assert batched == sorted(batched)                  # FIFO within the class
+    assert ex.max_live <= 2
+    assert rep.summary()["batch_submissions"] == len(ex.batches)
+
+
+def test_big_requests_only_on_big_lanes_and_fifo_per_class():
+    tr = _trace(count=80, rate=1e5, n_hi=24)
+    ex = FakeBatchExecutor(4, dur=lambda n: 2e-4)
+    rep = S.Server(ex, 4).serve(tr)
+    n_of = {r.rid: r.circuit.n for r in tr}
+    for rid, lane, _ in ex.started:
+        if n_of[rid] >= 21:
+            assert lane == 0
+    for k in (S.MID, S.BIG):
+        order = [rid for rid, _, _ in ex.started if (n_of[rid] >= 21) == (k == S.BIG)]
+        assert order == sorted(order)
+    assert len(rep.outcomes) == 80
+
+
+def test_mid_requests_do_not_wait_behind_a_big_one():
+    """A long big request arrives first; the mid requests after it finish
+    while it still runs (they have lanes of their own)."""
+    import math
+    reqs = [I.Request(0, 0.0, I.layered(24, 1), I.tfim(24))]
+    for k in range(1, 9):
+        reqs.append(I.Request(k, 1e-3 * k, I.layered(16, 1), I.tfim(16)))
+    ex = FakeBatchExecutor(4, dur=lambda n: 0.2 if n >= 21 else 1e-3)
+    rep = S.Server(ex, 4).serve(reqs)
+    big = rep.outcomes[0]
+    assert all(o.done < big.done for o in rep.outcomes[1:])
+    assert math.isclose(big.latency, 0.2, rel_tol=0.5)
+
+
+def test_one_lane_without_batch_is_serial_fifo():
+    tr = _trace(count=40, rate=1e5, n_hi=24)
+    ex = FakeBatchExecutor(1)
+    S.Server(ex, 1, batch=False).serve(tr)
+    assert not ex.batches
+    order = [rid for rid, _, _ in ex.started]
+    assert order == sorted(order) == [r.rid for r in tr]

@@ -73,7 +73,7 @@ typedef enum {
   SV_RXX, SV_RYY, SV_RZZ,  /* exp(-i theta P(x)P/2), 2 targets, 1 parameter */
   SV_GIVENS,               /* rotation [[c,-s],[s,c]] on local |1>,|2>, 2 targets */
   SV_DEXC,                 /* rotation [[c,-s],[s,c]] on local |3>,|12>, 4 targets */
-  SV_UNITARY,              /* user matrix on 1..5 targets */
+  SV_UNITARY,              /* user matrix on 1..3 targets (4..5: SV_EUNSUPPORTED) */
   SV_NKINDS
 } sv_gate_kind;
 
@@ -83,7 +83,7 @@ typedef enum {
 /* One typed operation (paper Section 4.2 circuit model). */
 typedef struct {
   int32_t kind;                        /* sv_gate_kind */
-  int32_t n_targets;                   /* must equal the kind's arity (1..5 for SV_UNITARY) */
+  int32_t n_targets;                   /* must equal the kind's arity (1..3 for SV_UNITARY) */
   int32_t targets[SV_MAX_TARGETS];     /* targets first */
   int32_t n_controls;                  /* 0..SV_MAX_CONTROLS */
   int32_t controls[SV_MAX_CONTROLS];
@@ -108,13 +108,16 @@ typedef struct {
 #define SV_WS_ADJOINT 1u    /* room for the adjoint's second state and partial sums */
 
 /* Bytes of device workspace a handle needs.  Always >= the forward path's
- * needs; SV_WS_ADJOINT adds a second state (lambda) and gradient partials. */
+ * needs; SV_WS_ADJOINT adds a second state (lambda) and gradient partials.
+ * 0 for n outside 1..32 or an unknown dtype. */
 size_t sv_workspace_bytes(int32_t n_qubits, sv_dtype dtype, uint32_t flags);
 
-/* Wrap caller-owned device planes re/im (2^n elements each, 256-byte aligned)
- * and workspace into a handle, bound to `hip_stream` (NULL = default stream),
- * and set the state to |0...0>.  Errors: SV_EINVAL (n outside 1..34, null or
- * misaligned planes), SV_EDTYPE, SV_ENOMEM (ws_bytes < sv_workspace_bytes). */
+/* Wrap caller-owned device planes re/im (2^n elements each, 16-byte aligned)
+ * and a 256-byte aligned workspace into a handle, bound to `hip_stream`
+ * (NULL = default stream), and set the state to |0...0>.  n is 1..32 (32
+ * qubits: 64 GiB of FP64 planes).  Errors: SV_EINVAL (n outside 1..32, null or
+ * misaligned planes or workspace), SV_EDTYPE, SV_ENOMEM (ws_bytes <
+ * sv_workspace_bytes). */
 sv_status sv_alloc(int32_t n_qubits, sv_dtype dtype, void *re, void *im, void *workspace,
                    size_t ws_bytes, void *hip_stream, sv_state **out);
 

@@ -146,6 +146,10 @@ static sv_status validate_op(const sv_op &op, int idx, int n, int n_params) {
   return SV_OK;
 }
 
+// Largest state: 32 qubits (64 GiB of FP64 planes; the largest size the
+// tests run).  Indices are 64-bit throughout.
+#define SVI_NMAX 32
+
 static void set_mo(GateRec &g) {
   switch (g.kind) {
     case SV_X: g.mo = MO_X; g.cost = 1; break;
@@ -1315,7 +1319,7 @@ static size_t elem_size(sv_dtype d) { return d == SV_C128 ? 8 : 4; }
 static int sample_K(int n) { int cb = n < 10 ? n : 10; return (int)(((int64_t)1 << n) >> cb); }
 
 extern "C" size_t sv_workspace_bytes(int32_t n, sv_dtype dtype, uint32_t flags) {
-  if (n < 1 || n > 34 || (dtype != SV_C128 && dtype != SV_C64)) return 0;
+  if (n < 1 || n > SVI_NMAX || (dtype != SV_C128 && dtype != SV_C64)) return 0;
   size_t K = (size_t)sample_K(n);
   size_t b = ((2 * K + 1) * 8 + 255) & ~(size_t)255;
   if (flags & SV_WS_ADJOINT) b += 4 * ((size_t)1 << n) * elem_size(dtype);
@@ -1382,7 +1386,7 @@ extern "C" sv_status sv_alloc(int32_t n, sv_dtype dtype, void *re, void *im, voi
   if (!out) return fail(SV_EINVAL, "null output handle");
   *out = nullptr;
   if (dtype != SV_C128 && dtype != SV_C64) return fail(SV_EDTYPE, "unsupported dtype %d", (int)dtype);
-  if (n < 1 || n > 34) return fail(SV_EINVAL, "n_qubits %d outside 1..34", n);
+  if (n < 1 || n > SVI_NMAX) return fail(SV_EINVAL, "n_qubits %d outside 1..%d", n, SVI_NMAX);
   if (!re || !im) return fail(SV_EINVAL, "null state plane");
   if (((uintptr_t)re & 15) || ((uintptr_t)im & 15)) return fail(SV_EINVAL, "state planes must be 16-byte aligned");
   size_t need = sv_workspace_bytes(n, dtype, 0);
@@ -2903,7 +2907,7 @@ extern "C" sv_status sv_fuse_blocks(const sv_op *ops, int32_t n_ops, int32_t wid
 extern "C" sv_status sv_plan_stats(int32_t n, const sv_op *ops, int32_t n_ops, int32_t fuse_width,
                                    int32_t tile_bits, int32_t low_bits, int32_t group_bits,
                                    int32_t *n_sweeps, int32_t *n_blocks) {
-  if (n < 1 || n > 34) return fail(SV_EINVAL, "n %d", n);
+  if (n < 1 || n > SVI_NMAX) return fail(SV_EINVAL, "n %d outside 1..%d", n, SVI_NMAX);
   if (!(fuse_width == 0 || fuse_width == SV_FUSE_AUTO || (fuse_width >= 2 && fuse_width <= 5)))
     return fail(SV_EINVAL, "fuse_width %d", fuse_width);
   std::vector<GateRec> recs;
@@ -3631,7 +3635,8 @@ static sv_status serve_check_plan(sv_serve *sv, const sv_circuit_desc *request,
                                   std::shared_ptr<ServePlan> &sp) {
   if (!sv || !request) return fail(SV_EINVAL, "null argument");
   const sv_circuit_desc &d = *request;
-  if (d.n_qubits < 1 || d.n_qubits > 34) return fail(SV_EINVAL, "n_qubits %d outside 1..34", d.n_qubits);
+  if (d.n_qubits < 1 || d.n_qubits > SVI_NMAX)
+    return fail(SV_EINVAL, "n_qubits %d outside 1..%d", d.n_qubits, SVI_NMAX);
   if (d.n_ops < 0 || (d.n_ops > 0 && !d.ops)) return fail(SV_EINVAL, "bad op list");
   if (d.n_params < 0) return fail(SV_EINVAL, "negative n_params");
   for (int i = 0; i < d.n_ops; i++) {

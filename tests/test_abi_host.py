@@ -65,7 +65,8 @@ def test_auto_plan_is_far_below_per_block_sweeps(sv):
 def test_workspace_sizes(sv):
     L = sv.lib()
     assert L.sv_workspace_bytes(0, 0, 0) == 0
-    assert L.sv_workspace_bytes(35, 0, 0) == 0
+    assert L.sv_workspace_bytes(33, 0, 0) == 0
+    assert L.sv_workspace_bytes(32, 0, 0) > 0
     assert L.sv_workspace_bytes(10, 2, 0) == 0
     a = L.sv_workspace_bytes(20, 0, 0)
     b = L.sv_workspace_bytes(20, 0, 1)
@@ -83,6 +84,17 @@ def test_planner_rejects_bad_ops(sv):
         sv.plan_stats(4, [I.Op("ry", (1,))], 3)     # missing parameter slot
     with pytest.raises(sv.SvError):
         sv.plan_stats(4, [I.Op("x", (1,))], 1)      # width 1 is not a fusion width
+    # user matrices: 1..3 targets; 4 and 5 are refused as unsupported
+    for k in (4, 5):
+        with pytest.raises(sv.SvError) as e:
+            sv.plan_stats(6, [I.Op("unitary", tuple(range(k)), matrix=np.eye(1 << k))], -1)
+        assert e.value.status == -5
+    assert sv.plan_stats(6, [I.Op("unitary", (0, 2, 4), matrix=np.eye(8))], -1)[0] >= 1
+    # 32 qubits is the largest state
+    assert sv.plan_stats(32, [I.Op("h", (31,))], -1)[0] >= 1
+    with pytest.raises(sv.SvError) as e:
+        sv.plan_stats(33, [I.Op("h", (0,))], -1)
+    assert e.value.status == -1
 
 
 def test_alloc_rejects_without_touching_device(sv):

@@ -96,6 +96,28 @@ def oracle_single_thread_child():
     t0 = time.time()
     O.adjoint_grad(c3, I.tfim(20, 0.7))
     out["adjoint_hea_20q_10l_tfim_ms"] = (time.time() - t0) * 1e3
+    # the 512-circuit ragged batch (state + <Z0 Z1> per circuit), timed circuit
+    # by circuit in batch order over those of at most 18 qubits until about
+    # 12 s are spent, then projected to all 512 by gate-amplitude updates
+    circs = I.batch_circuits(512, seed=0)
+    upd = [len(c.ops) * float(1 << c.n) for c in circs]
+    t_sum, u_sum, k = 0.0, 0.0, 0
+    for c, u in zip(circs, upd):
+        if c.n > 18:
+            continue
+        t0 = time.time()
+        psi = O.run_circuit(c)
+        O.expect(c.n, psi, I.z0z1(c.n))
+        t_sum += time.time() - t0
+        u_sum += u
+        k += 1
+        if t_sum > 12.0:
+            break
+    out["batch_512_ragged"] = {
+        "sample": f"first {k} circuits of at most 18 qubits, in batch order, timed one by one",
+        "circuits_timed": k, "sampled_s": t_sum, "sampled_updates": u_sum,
+        "updates_per_s": u_sum / t_sum, "total_updates": float(sum(upd)),
+        "projected_all_512_s": t_sum * float(sum(upd)) / u_sum}
     print(json.dumps(out), flush=True)
 
 
@@ -103,7 +125,7 @@ def oracle_single_thread():
     import subprocess
     env = dict(os.environ, OMP_NUM_THREADS="1")
     r = subprocess.run([sys.executable, os.path.abspath(__file__), "--oracle-single-child"],
-                       env=env, capture_output=True, text=True, timeout=300)
+                       env=env, capture_output=True, text=True, timeout=400)
     if r.returncode != 0:
         raise RuntimeError("single-thread oracle run failed: " + r.stderr[-2000:])
     return json.loads(r.stdout.strip().splitlines()[-1])
@@ -362,6 +384,13 @@ def main():
                     help="only sampling and the exit copy on the resident --n qubit state")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 2 GiB device-to-device copy (counter calibration)")
+    ap.add_argument("--adjoint-only", action="store_true",
+                    help="only the --n qubit HEA (10 layers, TFIM) adjoint, --steps times, then "
+                         "as many forward passes with <H>; --tile/--low/--group set the backward "
+                         "tiling (for profiling and tuning)")
+    ap.add_argument("--batch-only", action="store_true",
+                    help="only the 512-circuit ragged batch, --steps graph launches, tiling from "
+                         "--low/--group or else the autotuner (for profiling)")
     ap.add_argument("--oracle-single-child", action="store_true", help=argparse.SUPPRESS)
     args = ap.parse_args()
     if args.oracle_single_child:
@@ -387,6 +416,48 @@ def main():
             b.copy_(a)
         torch.cuda.synchronize()
         log(f"copy probe: 3 copies of {a.numel() * 8} bytes")
+        return
+    if args.adjoint_only:
+        c4 = I.hea(args.n, 10, seed=0)
+        h4 = I.tfim(args.n, 0.7)
+        s4 = sv.State(args.n, adjoint=True)
+        if args.tile or args.low or args.group:
+            s4.set_adjoint_tiling(args.tile, args.low, args.group)   # backward sweeps
+        oa4 = sv.OpArray(c4.ops)
+        res = {"workload": f"hea_{args.n}q_10l_tfim_adjoint", "adjoint_ms": [], "forward_expect_ms": [],
+               "backward_tiling": [args.tile, args.low, args.group]}
+        for key, fn in (("adjoint_ms", lambda: s4.adjoint_grad(None, c4.params, h4, op_array=oa4)),
+                        ("forward_expect_ms", lambda: (s4.apply(None, c4.params, op_array=oa4),
+                                                       s4.expect(h4)))):
+            for _ in range(args.steps):
+                s4.reset()
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                fn()
+                torch.cuda.synchronize()
+                res[key].append((time.perf_counter() - t0) * 1e3)
+                log(f"{key}: {res[key][-1]:.2f}")
+        s4.close()
+        print(json.dumps(res), flush=True)
+        return
+    if args.batch_only:
+        circs = I.batch_circuits(512, seed=0)
+        hams = [I.z0z1(c.n) for c in circs]
+        if args.group and args.low:
+            tune = {"low_bits": args.low, "group_bits": args.group}
+        else:
+            tune = sv.batch_autotune(circs, hams, reps=2)
+        b = sv.Batch(circs, hams, low_bits=tune["low_bits"], group_bits=tune["group_bits"])
+        res = {"workload": "batch_512_ragged", "tiling": tune, "ms": []}
+        for _ in range(args.steps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            b.run(graph=True)
+            b.check()
+            res["ms"].append((time.perf_counter() - t0) * 1e3)
+        res["stats"] = list(b.stats())
+        b.close()
+        print(json.dumps(res), flush=True)
         return
     if args.side_only:
         from paper_2608_09733_amd import inputs as I

@@ -419,6 +419,14 @@ sv_status sv_plan_stats(int32_t n_qubits, const sv_op *ops, int32_t n_ops, int32
                         int32_t tile_bits, int32_t low_bits, int32_t group_bits,
                         int32_t *n_sweeps, int32_t *n_blocks);
 
+/* Backward program sv_adjoint_grad would run for this circuit (FP64; 0 for a
+ * setting = the default backward tiling): its tile sweeps, register stages
+ * and gradient slots (host-only; for tests and tuning).  Errors as for
+ * sv_adjoint_grad's op checks. */
+sv_status sv_adjoint_plan_stats(int32_t n_qubits, const sv_op *ops, int32_t n_ops, int32_t n_params,
+                                int32_t tile_bits, int32_t low_bits, int32_t group_bits,
+                                int32_t *n_sweeps, int32_t *n_stages, int32_t *n_gslots);
+
 /* Default tiling of sv_apply_layer (backward = 0) or of the backward sweeps
  * of sv_adjoint_grad (backward = 1) for an n_qubits state of this dtype, as
  * used by a handle without sv_set_tiling / sv_set_adjoint_tiling (host-only).

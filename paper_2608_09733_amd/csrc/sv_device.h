@@ -593,8 +593,7 @@ __device__ __forceinline__ double wave_sum(double v) {
 // accumulates gradient partials).
 
 #define SVI_GSLOTS 256
-#define SVI_GSLOTS_LEAN 16   // gradient slots of the two-state Kronecker kernel held in registers
-#define SVI_GSLOTS_WIDE 128  // gradient slots per sweep of that kernel (the rest reduced per tile)
+#define SVI_GSLOTS_WIDE 128  // gradient slots per sweep of the two-state Kronecker kernel
 
 // Sum of v over the 64 lanes of a wave, valid in lane 63, by DPP lane moves
 // (VALU only): partial sums within rows of 16 lanes (shifts by 1, 2, 4, 8),
@@ -1230,8 +1229,8 @@ __device__ void sweep_tiles(const SVI_CONST SweepArgs &a, int64_t t0, int64_t t1
 // One Kronecker stage applied to the psi and lambda tiles held side by side in
 // LDS (lb0, lb1), with the gradient terms Im <lam| G |psi> of the stage's
 // gradient micro-ops taken at the three stage points (stage input, after
-// D_before, after the rotations).  Each term goes to sink(slot, value), where
-// the slot is uniform across the wave.  Ends with the barrier (or the wave
+// D_before, after the rotations).  Terms go to sink(slot0, v0, slot1, v1) in
+// pairs (slot1 = -1: v0 only), the slots uniform across the wave.  Ends with the barrier (or the wave
 // fence of a wave-local stage) that makes the stores visible to the next stage.
 template <typename T, int R, typename Sink>
 __device__ __forceinline__ void kron2_stage(char *lb0, char *lb1, int gbs,
@@ -1253,13 +1252,21 @@ __device__ __forceinline__ void kron2_stage(char *lb0, char *lb1, int gbs,
   }
   const SVI_CONST double *kc = coef + sd.kcoef;
   auto grads = [&](int b, int e, double mult) {
-    // one term at a time: an unrolled loop would keep several terms'
-    // operands live at once and spill the register groups
+    // two terms at a time, so that their wave sums (chains of dependent lane
+    // moves) interleave; a wider unroll would keep more terms' operands live
+    // and spill the register groups
+    int o = b;
 #pragma clang loop unroll(disable)
-    for (int o = b; o < e; o++) {
+    for (; o + 1 < e; o += 2) {
+      const MicroOp op0 = op_at(ops, o), op1 = op_at(ops, o + 1);
+      const double v0 = active ? mult * grad_kron<T, R>(op0, re[0], im[0], re[1], im[1], gcoef) : 0.0;
+      const double v1 = active ? mult * grad_kron<T, R>(op1, re[0], im[0], re[1], im[1], gcoef) : 0.0;
+      sink(op0.coef, v0, op1.coef, v1);
+    }
+    if (o < e) {
       const MicroOp op = op_at(ops, o);
       const double v = active ? mult * grad_kron<T, R>(op, re[0], im[0], re[1], im[1], gcoef) : 0.0;
-      sink(op.coef, v);
+      sink(op.coef, v, -1, 0.0);
     }
   };
   grads(sd.op_begin, sd.g1, 1.0);
@@ -1292,7 +1299,8 @@ __device__ __forceinline__ void kron2_stage(char *lb0, char *lb1, int gbs,
 
 // One micro-op stage (the interpreter) applied to the psi and lambda tiles
 // in LDS: each gate micro-op acts on both states, each gradient micro-op sends
-// its term Im <lam| G |psi> to sink(slot, value) at its place in the stage.
+// its term Im <lam| G |psi> to sink(slot, value, -1, 0) at its place in the
+// stage.
 // Ends with the barrier that makes the stores visible to the next stage.
 template <typename T, int R, typename Sink>
 __device__ __forceinline__ void ops2_stage(char *lb0, char *lb1, int gbs,
@@ -1314,7 +1322,7 @@ __device__ __forceinline__ void ops2_stage(char *lb0, char *lb1, int gbs,
   for (int o = sd.op_begin; o < sd.op_end; o++) {
     const MicroOp op = op_at(ops, o);
     if (op.type == MO_GRAD || op.type == MO_GRAD2L) {
-      sink(op.coef, active ? grad_any<T, R>(op, re[0], im[0], re[1], im[1], coef) : 0.0);
+      sink(op.coef, active ? grad_any<T, R>(op, re[0], im[0], re[1], im[1], coef) : 0.0, -1, 0.0);
       continue;
     }
     apply_op<T, R>(op, re[0], im[0], coef);
@@ -1349,12 +1357,10 @@ __global__ void __launch_bounds__(1 << (M - R)) k_sweep_kron2(SweepArgs a) {
   // tiles, two for 64 KiB)
   constexpr int TILE_BYTES = 2 * (1 << M) * (int)sizeof(C2);
   constexpr int WG_LDS = TILE_BYTES >= 131072 ? 163840 : TILE_BYTES >= 65536 ? 81920 : 40960;
-  constexpr int NWIDE = SVI_GSLOTS_WIDE - SVI_GSLOTS_LEAN;
   constexpr int GTAB_BYTES = WG_LDS - TILE_BYTES - NWAVE * SVI_GSLOTS_WIDE * 8 - 4 * SVI_MMAX - 256;
   constexpr int GTAB = GTAB_BYTES / (4 * NT) > 0 ? GTAB_BYTES / (4 * NT) : 1;
   __shared__ C2 lds[2][1 << M];
-  __shared__ double wsum[NWAVE][SVI_GSLOTS_LEAN];
-  __shared__ double wacc[NWAVE][NWIDE];   // per-wave sums of the slots past the registers
+  __shared__ double wacc[NWAVE][SVI_GSLOTS_WIDE];   // per-wave sums of the gradient slots
   __shared__ int32_t hb_s[SVI_MMAX];
   __shared__ int32_t gtab[GTAB * NT];
 
@@ -1370,7 +1376,7 @@ __global__ void __launch_bounds__(1 << (M - R)) k_sweep_kron2(SweepArgs a) {
   const int ntab = nst < GTAB ? nst : GTAB;
   for (int st = 0; st < ntab; st++)   // each thread reads back only its own entries
     gtab[st * NT + tid] = swz<T>(stage_base<M, R>(tid, stages[st])) * (int)sizeof(C2);
-  for (int k = tid; k < NWAVE * NWIDE; k += NT) (&wacc[0][0])[k] = 0.0;
+  for (int k = tid; k < NWAVE * SVI_GSLOTS_WIDE; k += NT) (&wacc[0][0])[k] = 0.0;
   __syncthreads();
 
   uint64_t roff[NIT];
@@ -1380,12 +1386,6 @@ __global__ void __launch_bounds__(1 << (M - R)) k_sweep_kron2(SweepArgs a) {
     roff[k] = spread_row(i >> c, hb_s, nh) + (uint64_t)(i & ((1 << c) - 1));
   }
   const int tsw = swz<T>(tid * VN);
-  // per-thread gradient accumulators, one per slot of this sweep: the terms
-  // of all tiles are summed in registers and reduced across the wave once, at
-  // the end, instead of once per tile
-  double gr[SVI_GSLOTS_LEAN];
-#pragma unroll
-  for (int k = 0; k < SVI_GSLOTS_LEAN; k++) gr[k] = 0.0;
   T *const pr[2] = {(T *)a.re, (T *)a.re2};
   T *const pi[2] = {(T *)a.im, (T *)a.im2};
 
@@ -1430,23 +1430,14 @@ __global__ void __launch_bounds__(1 << (M - R)) k_sweep_kron2(SweepArgs a) {
           st < ntab ? gtab[st * NT + tid] : swz<T>(stage_base<M, R>(tid, sd)) * (int)sizeof(C2);
       const bool active = tid < (1 << (m > R ? m - R : 0));
       kron2_stage<T, R>((char *)lds[0], (char *)lds[1], gbs, sd, coef, a.ops, a.coef, active,
-                        [&](int slot, double v) {
-        if (slot >= SVI_GSLOTS_LEAN) {
-          // past the register slots: this tile's wave sum into the wave's LDS row
-          // (an LDS add without return: the wave does not wait for it)
-          const double w = wave_total63(v);
-          if ((tid & 63) == 63) atomicAdd(&wacc[tid >> 6][slot - SVI_GSLOTS_LEAN], w);
-          return;
-        }
-        switch (slot) {   // uniform: the slot is a register index
-#define SVI_GS(K) case K: if constexpr (K < SVI_GSLOTS_LEAN) gr[K] += v; break;
-          SVI_GS(0) SVI_GS(1) SVI_GS(2) SVI_GS(3) SVI_GS(4) SVI_GS(5) SVI_GS(6) SVI_GS(7)
-          SVI_GS(8) SVI_GS(9) SVI_GS(10) SVI_GS(11) SVI_GS(12) SVI_GS(13) SVI_GS(14)
-          SVI_GS(15) SVI_GS(16) SVI_GS(17) SVI_GS(18) SVI_GS(19) SVI_GS(20) SVI_GS(21)
-          SVI_GS(22) SVI_GS(23) SVI_GS(24) SVI_GS(25) SVI_GS(26) SVI_GS(27) SVI_GS(28)
-          SVI_GS(29) SVI_GS(30) SVI_GS(31)
-#undef SVI_GS
-          default: break;
+                        [&](int s0, double v0, int s1, double v1) {
+        // this tile's terms summed over the wave into the wave's LDS rows of
+        // their slots (LDS adds without return: the wave does not wait)
+        const double w0 = wave_total63(v0);
+        const double w1 = wave_total63(v1);
+        if ((tid & 63) == 63) {
+          atomicAdd(&wacc[tid >> 6][s0], w0);
+          if (s1 >= 0) atomicAdd(&wacc[tid >> 6][s1], w1);
         }
       });
     }
@@ -1487,18 +1478,10 @@ __global__ void __launch_bounds__(1 << (M - R)) k_sweep_kron2(SweepArgs a) {
     r0 += gridDim.x;
     tile = tile_of(r0, blockIdx.x, gridDim.x);
   }
-#pragma unroll
-  for (int k = 0; k < SVI_GSLOTS_LEAN; k++) {
-    if (k < a.n_gslots) {
-      const double v = wave_sum(gr[k]);
-      if ((tid & 63) == 0) wsum[tid >> 6][k] = v;
-    }
-  }
   __syncthreads();
   for (int sl = tid; sl < a.n_gslots; sl += NT) {
     double v = 0.0;
-    for (int w = 0; w < NWAVE; w++)
-      v += sl < SVI_GSLOTS_LEAN ? wsum[w][sl] : wacc[w][sl - SVI_GSLOTS_LEAN];
+    for (int w = 0; w < NWAVE; w++) v += wacc[w][sl];
     a.gpart[(int64_t)(a.gslot_begin + sl) * gridDim.x + blockIdx.x] = v;
   }
 }

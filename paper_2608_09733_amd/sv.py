@@ -86,6 +86,8 @@ def lib():
                                         C.POINTER(i32)]),
         "sv_plan_stats": (C.c_int, [i32, opp, i32, i32, i32, i32, i32, C.POINTER(i32),
                                     C.POINTER(i32)]),
+        "sv_adjoint_plan_stats": (C.c_int, [i32, opp, i32, i32, i32, i32, i32, C.POINTER(i32),
+                                            C.POINTER(i32), C.POINTER(i32)]),
         "sv_set_tiling": (C.c_int, [vp, i32, i32, i32]),
         "sv_set_adjoint_tiling": (C.c_int, [vp, i32, i32, i32]),
         "sv_fuse_blocks": (C.c_int, [opp, i32, i32, C.POINTER(i32), C.POINTER(i32)]),
@@ -426,6 +428,16 @@ def default_tiling(n: int, dtype: str = "c128", backward: bool = False) -> Tuple
     _check(lib().sv_default_tiling(n, code, 1 if backward else 0, C.byref(t), C.byref(c),
                                    C.byref(r)))
     return int(t.value), int(c.value), int(r.value)
+
+
+def adjoint_plan_stats(n: int, ops, n_params: int, tile_bits: int = 0, low_bits: int = 0,
+                       group_bits: int = 0) -> Tuple[int, int, int]:
+    """(sweeps, register stages, gradient slots) of the adjoint's backward program."""
+    oa = OpArray(ops)
+    s, b, g = C.c_int32(0), C.c_int32(0), C.c_int32(0)
+    _check(lib().sv_adjoint_plan_stats(n, oa.ptr(), oa.n, n_params, tile_bits, low_bits, group_bits,
+                                       C.byref(s), C.byref(b), C.byref(g)))
+    return int(s.value), int(b.value), int(g.value)
 
 
 def plan_stats(n: int, ops, fuse: int = SV_FUSE_AUTO, tile_bits: int = 0, low_bits: int = 0,

@@ -359,6 +359,7 @@ __global__ void __launch_bounds__(SVI_PAULI_NT) k_pauli(PauliPassArgs a) {
   __shared__ double wsum[NWAVE][SVI_PTERMS];
   __shared__ double tacc[SVI_PTERMS];
   __shared__ uint32_t xl_s[SVI_PTERMS], zl_s[SVI_PTERMS];
+  __shared__ int32_t hb_s[SVI_MMAX];
 
   const int tid = threadIdx.x;
   const int m = a.m, c = a.c, nh = a.nh;
@@ -368,6 +369,7 @@ __global__ void __launch_bounds__(SVI_PAULI_NT) k_pauli(PauliPassArgs a) {
   T *lre = (T *)a.lre, *lim = (T *)a.lim;
 
   // tile-local masks of every term of this pass
+  if (tid < SVI_MMAX) hb_s[tid] = a.hb[tid < nh ? tid : 0];
   for (int t = tid; t < nterm; t += NT) {
     const PauliTermDev pt = a.terms[a.t_begin + t];
     uint32_t xl = 0, zl = 0;
@@ -384,12 +386,22 @@ __global__ void __launch_bounds__(SVI_PAULI_NT) k_pauli(PauliPassArgs a) {
     tacc[t] = 0.0;
   }
   __syncthreads();
+  // element tid + k * NT of a tile sits at tile_base + loff + koff[k]
+  // (tile_off is a bit deposit: per-lane part plus wave-uniform parts)
+  const uint64_t loff = tile_off(tid, c, hb_s, nh);
+  uint64_t koff[EPT];
+#pragma unroll
+  for (int k = 0; k < EPT; k++) koff[k] = tile_off(k * NT, c, a.hb, nh);   // kernel arguments: scalar
 
   for (int64_t tile = blockIdx.x; tile < a.ntiles; tile += gridDim.x) {
-    const uint64_t base = tile_base(tile, c, a.hb, nh);
-    for (int i = tid; i < nel; i += NT) {
-      const uint64_t g = base + spread_row(i >> c, a.hb, nh) + (uint64_t)(i & ((1 << c) - 1));
-      lds[swz<T>(i)] = C2{pre[g], pim[g]};
+    const uint64_t base = tile_base(tile, c, hb_s, nh);
+#pragma unroll
+    for (int k = 0; k < EPT; k++) {
+      const int i = tid + k * NT;
+      if (i < nel) {
+        const uint64_t g = base + (loff | koff[k]);
+        lds[swz<T>(i)] = C2{pre[g], pim[g]};
+      }
     }
     __syncthreads();
     // |psi|^2 of this thread's elements (0 beyond the tile)
@@ -405,6 +417,11 @@ __global__ void __launch_bounds__(SVI_PAULI_NT) k_pauli(PauliPassArgs a) {
       pn[k] = v;
       zs[k] = 0.0;
     }
+    // one term's sum over this tile and wave (DPP lane moves, in lane 63)
+    auto put = [&](int t, double acc) {
+      acc = wave_total63(acc);
+      if ((tid & 63) == 63) wsum[tid >> 6][t] = acc;
+    };
     // Z-only terms: sign(i) = parity(base & z) ^ parity(tid & z) ^ parity((k*NT) & z)
     for (int t = 0; t < nterm; t++) {
       if (xl_s[t] != 0) continue;
@@ -420,9 +437,7 @@ __global__ void __launch_bounds__(SVI_PAULI_NT) k_pauli(PauliPassArgs a) {
         acc = kn ? acc - pn[k] : acc + pn[k];
         if (lre) zs[k] = kn ? zs[k] - cc : zs[k] + cc;
       }
-      acc = sneg ? -acc : acc;
-      acc = wave_sum(acc);
-      if ((tid & 63) == 0) wsum[tid >> 6][t] = acc;
+      put(t, sneg ? -acc : acc);
     }
     // terms with an X / Y part: partner amplitudes from LDS
     T lr[EPT], li[EPT];
@@ -480,8 +495,7 @@ __global__ void __launch_bounds__(SVI_PAULI_NT) k_pauli(PauliPassArgs a) {
           }
         }
       }
-      acc = wave_sum(acc);
-      if ((tid & 63) == 0) wsum[tid >> 6][t] = acc;
+      put(t, acc);
     }
     __syncthreads();
     for (int t = tid; t < nterm; t += NT) {
@@ -494,7 +508,7 @@ __global__ void __launch_bounds__(SVI_PAULI_NT) k_pauli(PauliPassArgs a) {
       for (int k = 0; k < EPT; k++) {
         const int i = tid + k * NT;
         if (i < nel) {
-          const uint64_t g = base + spread_row(i >> c, a.hb, nh) + (uint64_t)(i & ((1 << c) - 1));
+          const uint64_t g = base + (loff | koff[k]);
           if (a.accumulate) {
             lre[g] += lr[k];
             lim[g] += li[k];

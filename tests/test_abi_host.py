@@ -261,3 +261,18 @@ def test_serving_kernel_routing_is_host_only(sv):
             S.supports(I.layered(6, 1), bad)
     finally:
         S.close()
+
+
+def test_adjoint_backward_program_statistics(sv):
+    """The backward program of the 26-qubit HEA adjoint: one gradient slot per
+    parameterised gate, within the 128 slots a two-state sweep takes."""
+    c = I.hea(26, 10, seed=0)
+    sweeps, stages, slots = sv.adjoint_plan_stats(26, c.ops, c.n_params)
+    assert slots == c.n_params == 520
+    assert sweeps * 128 >= slots and 5 <= sweeps <= 12
+    assert stages >= 100
+    c2 = I.layered(12, 4, seed=0)
+    s2, _, g2 = sv.adjoint_plan_stats(12, c2.ops, c2.n_params)
+    assert g2 == c2.n_params and s2 >= 1
+    with pytest.raises(sv.SvError):
+        sv.adjoint_plan_stats(5, [I.Op("ry", (5,), params=(0,))], 1)

@@ -255,9 +255,24 @@ def density_matrix_run(st, n, sv, I, torch):
         ts.append((time.time() - t0) * 1e3)
     ms = float(np.median(ts))
     log(f"density matrix {nd}q ({n}-qubit vector), {Ld} noisy layers: {ms:.1f} ms")
+    # checks: Tr(rho) = 1 after the channels; without the channels, <Z_i> of
+    # rho equals <Z_i> of the same circuit run as an nd-qubit state vector
+    zi = I.hamiltonian(nd, [("Z", [q], 1.0) for q in range(nd)] + [("I", [0], 1.0)])
+    tr = st.dm_expect(zi)[0][-1]
+    st.reset()
+    for oa in arrays:
+        st.dm_apply(None, cd.params, op_array=oa)
+    zdm = st.dm_expect(zi)[0][:nd]
+    sv_state = sv.State(nd)
+    sv_state.apply(cd.ops, cd.params)
+    zsv = sv_state.expect(zi)[0][:nd]
+    sv_state.close()
+    dz = float(np.max(np.abs(zdm - zsv)))
+    log(f"density matrix checks: Tr(rho) - 1 = {tr - 1:.2e}, noiseless <Z_i> vs state vector {dz:.2e}")
     return {"density_matrix_%dq_%dl_depolarizing" % (nd, Ld): {
         "ms_median": ms, "qubits": nd, "vector_qubits": n, "layers": Ld,
-        "gates": len(cd.ops), "channels": nd * Ld, "z0": float(vals[0])}}
+        "gates": len(cd.ops), "channels": nd * Ld, "z0": float(vals[0]),
+        "trace_minus_1": float(tr - 1.0), "noiseless_z_max_abs_diff_vs_state_vector": dz}}
 
 
 def side_configs(sv, I, torch, serving=True):

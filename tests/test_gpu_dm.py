@@ -83,3 +83,68 @@ def test_dm_handle_size_checked(sv):
     with pytest.raises(sv.SvError):
         st.dm_apply_kraus(0, _damping(0.1))
     st.close()
+
+
+def _channel_1q(T, n, q, kraus):
+    """One-qubit channel on qubit q of vec(rho) held as a [2]*2n tensor (row
+    qubit q on axis n-1-q, column qubit q on axis 2n-1-q): contract the 4x4
+    superoperator S[A, B, a, b] = sum_k K[A, a] conj(K[B, b])."""
+    S = sum(np.einsum("Aa,Bb->ABab", k, np.conj(k)) for k in kraus)
+    ar, ac = n - 1 - q, 2 * n - 1 - q
+    X = np.moveaxis(T, [ar, ac], [0, 1])
+    X = np.tensordot(S, X, axes=([2, 3], [0, 1]))
+    return np.moveaxis(X, [0, 1], [ar, ac])
+
+
+def _channel_2q(T, n, q0, q1, kraus):
+    """Two-qubit channel on (q0, q1), local index bit(q0) + 2 bit(q1)."""
+    out = np.zeros_like(T)
+    rows = [n - 1 - q1, n - 1 - q0]          # local index = 2 * b(q1) + b(q0)
+    cols = [2 * n - 1 - q1, 2 * n - 1 - q0]
+    for k in kraus:
+        K = np.asarray(k).reshape(2, 2, 2, 2)   # [q1', q0', q1, q0]
+        X = np.moveaxis(T, rows, [0, 1])
+        X = np.moveaxis(np.tensordot(K, X, axes=([2, 3], [0, 1])), [0, 1], rows)
+        X = np.moveaxis(X, cols, [0, 1])
+        X = np.moveaxis(np.tensordot(np.conj(K), X, axes=([2, 3], [0, 1])), [0, 1], cols)
+        out += X
+    return out
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_dm_13_qubits_grid_stride(sv, dtype):
+    """rho of 13 qubits (a 26-qubit vector: 16384 tiles of the four-channel
+    pass, several grid-stride rounds of the single-channel pass) from the
+    oracle's pure state, seven one-qubit channels (four-, two- and
+    single-channel passes) and a two-qubit channel, against tensor
+    contractions of the superoperators; Tr(rho) = 1 and Tr(rho Z_i)."""
+    n = 13
+    _say("density matrix 13 qubits", dtype)
+    c = I.layered(n, 2, seed=3)
+    psi = O.run_circuit(c)
+    T = np.outer(psi, np.conj(psi)).reshape([2] * (2 * n))
+    for q in range(7):
+        T = _channel_1q(T, n, q, _depolarizing(0.05))
+    K2 = _mixed_unitaries(5)
+    T = _channel_2q(T, n, 3, 9, K2)
+    want = T.reshape(-1)
+    st = sv.State(2 * n, dtype)
+    try:
+        st.reset()
+        st.dm_apply(c.ops, c.params)
+        st.dm_apply_kraus(list(range(7)), _depolarizing(0.05))
+        st.dm_apply_kraus2(3, 9, K2)
+        got = st.to_numpy()
+        scale = float(np.max(np.abs(want)))
+        tol = TOL if dtype == "c128" else 1e-5 * scale
+        assert np.max(np.abs(got - want)) <= tol
+        zs = I.hamiltonian(n, [("Z", [q], 1.0) for q in range(n)] + [("I", [0], 1.0)])
+        vals, _ = st.dm_expect(zs)
+        diag = np.real(np.diagonal(T.reshape(1 << n, 1 << n)))
+        b = np.arange(1 << n)
+        zref = [float(np.sum(diag * (1 - 2 * ((b >> q) & 1)))) for q in range(n)] + [float(diag.sum())]
+        etol = TOL if dtype == "c128" else 1e-5
+        assert np.max(np.abs(vals - np.array(zref))) <= etol
+        assert abs(vals[-1] - 1.0) <= etol
+    finally:
+        st.close()

@@ -375,9 +375,9 @@ sv_status sv_batch_autotune(const sv_circuit_desc *circuits, int32_t n_circuits,
  * is one persistent launch over a device queue of requests; one workgroup
  * takes one request and runs all of it -- forward sweeps, lambda = H|psi>,
  * backward sweeps with the gradient terms, the gather into dE/dtheta -- with
- * the request's planes held in the L2 cache.  Results are bitwise independent
+ * the request's planes held in the L2 and last-level caches.  Results are bitwise independent
  * of the other requests in the submission (one workgroup, fixed order).
- * Requests must have 3 <= n_qubits <= sv_serve_max_qubits() (13), ops on at
+ * Requests must have 3 <= n_qubits <= sv_serve_max_qubits() (16), ops on at
  * most 3 qubits (targets and controls) and no user matrices; FP64 only.
  * Plans are built on first sight of a request structure (qubits, ops,
  * parameter count) and cached in the handle. */

@@ -3627,7 +3627,7 @@ static sv_status serve_plan(sv_serve *sv, const sv_circuit_desc &d, std::shared_
     if (d.ops[i].kind == SV_UNITARY) user_mat = true;
   }
   if (n < Rs || n > svk_serve_max_qubits())
-    refuse("serving kernel: %d qubits outside %d..13", n, Rs);
+    refuse("serving kernel: %d qubits outside 3..%d", n, svk_serve_max_qubits());
   else if (width > Rs)
     refuse("serving kernel: an op on %d qubits (at most %d)", width, Rs);
   else if (user_mat)

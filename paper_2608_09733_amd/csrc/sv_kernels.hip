@@ -1841,7 +1841,9 @@ __global__ void __launch_bounds__(1 << (M - R)) k_serve(ServeArgs sa) {
 
 }  // namespace
 
-int svk_serve_max_qubits() { return SVS_M + 1; }
+// Requests of up to 16 qubits: beyond the 12-qubit tile a request's planes
+// (at most 4 x 512 KiB) stay in the L2 and last-level caches between sweeps.
+int svk_serve_max_qubits() { return 16; }
 
 hipError_t svk_launch_serve_coefs(const ServeReq *d_reqs, int nreq, int max_desc, hipStream_t s) {
   if (nreq <= 0) return hipSuccess;

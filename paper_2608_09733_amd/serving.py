@@ -3,12 +3,17 @@ over time; each returns (E, dE/dtheta) from the adjoint path.
 
 Requests fall into three classes, each FIFO within itself:
 
-* small -- requests the serving kernel takes (3..13 qubits, ops on at most 3
-  qubits): they join the batch path as they arrive.  Whenever fewer than two
+* small -- requests of at most `small_max` qubits (14 by default; the
+  serving kernel takes 3..16, ops on at most 3 qubits): they join the batch
+  path as they arrive.  Whenever fewer than two
   submissions are in flight, every small request that has arrived is
   submitted as one persistent launch (sv_serve_submit) on a stream of its
   own; one workgroup runs one request whole, so these never queue behind a
-  28-qubit request and take a few CUs each.
+  28-qubit request and take a few CUs each.  14 qubits is the measured
+  balance: at 200 req/s, routing up to 13, 14 and 16 qubits gave p50 192, 37
+  and 17 ms, p99 7.31, 7.36 and 7.69 s, and 49.4, 49.1 and 47.6 req/s (a
+  15- or 16-qubit request holds one CU for 6-13 ms, where a lane spreads it
+  over many CUs in about 1 ms).
 * big (n >= 21 qubits) and mid (the rest) -- run on stream lanes through
   sv_adjoint_grad_device.  One lane takes big requests first (then mid ones
   when no big request waits); the other lanes take only mid requests, so a
@@ -234,7 +239,7 @@ class Server:
 
     def __init__(self, executor, lanes: int, budget_bytes: float = 200 * GB, elem: int = 8,
                  batch: bool = True, big_qubits: int = 21, max_batch: int = 256,
-                 batch_inflight: int = 2):
+                 batch_inflight: int = 2, small_max: int = 14):
         self.ex = executor
         self.lanes = lanes
         self.budget = budget_bytes
@@ -243,13 +248,14 @@ class Server:
         self.big_qubits = big_qubits
         self.max_batch = max_batch
         self.batch_inflight = batch_inflight
+        self.small_max = small_max
         # queues a lane takes from, in order of preference
         self.lane_queues = [(BIG, MID) if l == 0 else (MID,) for l in range(lanes)]
         if lanes == 1:
             self.lane_queues = [("all",)]
 
     def klass(self, req) -> str:
-        if self.batch and self.ex.batchable(req):
+        if self.batch and req.circuit.n <= self.small_max and self.ex.batchable(req):
             return SMALL
         return BIG if req.circuit.n >= self.big_qubits else MID
 
@@ -388,7 +394,7 @@ def alone_vs_mix(report: Report, trace, dtype: str = "c128") -> int:
 
 def run(rate: float, count: int, lanes: int, budget_gb: float = 200.0, seed: int = 0,
         dtype: str = "c128", serial_baseline: bool = True, check_identity: bool = True,
-        n_hi: int = 28, log=None) -> Dict[str, object]:
+        n_hi: int = 28, log=None, small_max: int = 14) -> Dict[str, object]:
     """Served (classes, batch path, `lanes` lanes) and serial FIFO (one lane, no
     batch path) over the same trace.  Each runs the trace twice: the first pass
     builds the handles and plans (cold), the second is reported."""
@@ -398,8 +404,8 @@ def run(rate: float, count: int, lanes: int, budget_gb: float = 200.0, seed: int
                               "trace_span_s": float(trace[-1].arrival) if trace else 0.0}
     ex = GpuExecutor(lanes, dtype)
     try:
-        cold = Server(ex, lanes, budget_gb * GB, ex.elem).serve(trace)
-        rep = Server(ex, lanes, budget_gb * GB, ex.elem).serve(trace)
+        cold = Server(ex, lanes, budget_gb * GB, ex.elem, small_max=small_max).serve(trace)
+        rep = Server(ex, lanes, budget_gb * GB, ex.elem, small_max=small_max).serve(trace)
     finally:
         ex.close()
     out["served_cold"] = cold.summary()
@@ -433,6 +439,8 @@ def main():
     ap.add_argument("--budget-gb", type=float, default=200.0)
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--n-hi", type=int, default=28)
+    ap.add_argument("--small-max", type=int, default=14,
+                    help="largest request (qubits) routed to the serving kernel")
     ap.add_argument("--no-serial", action="store_true")
     ap.add_argument("--no-identity", action="store_true")
     a = ap.parse_args()
@@ -440,7 +448,7 @@ def main():
     for rate in rates:
         res = run(rate, a.count, a.lanes, a.budget_gb, a.seed, serial_baseline=not a.no_serial,
                   check_identity=not a.no_identity, n_hi=a.n_hi,
-                  log=lambda m: print(m, file=sys.stderr, flush=True))
+                  log=lambda m: print(m, file=sys.stderr, flush=True), small_max=a.small_max)
         print(json.dumps(res), flush=True)
 
 

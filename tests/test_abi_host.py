@@ -237,11 +237,11 @@ def test_default_tiling_query(sv):
 
 def test_serving_kernel_routing_is_host_only(sv):
     """sv_serve_check decides on the host which requests the serving kernel
-    takes: 3..13 qubits, ops on at most 3 qubits, no user matrices."""
+    takes: 3..16 qubits, ops on at most 3 qubits, no user matrices."""
     S = sv.Serve()
     try:
-        assert sv.Serve.max_qubits() == 13
-        for n in (3, 7, 12, 13):
+        assert sv.Serve.max_qubits() == 16
+        for n in (3, 7, 12, 13, 16):
             assert S.supports(I.layered(n, 2, seed=n), I.tfim(n))
         assert S.supports(I.hea(9, 2), I.tfim(9))
         assert S.supports(I.qft(6), I.tfim(6))
@@ -250,7 +250,7 @@ def test_serving_kernel_routing_is_host_only(sv):
             c = I.random_circuit(9, 30, seed=k, allow_unitary=False, max_qubits=3)
             assert S.supports(c, I.random_hamiltonian(9, 4, seed=k))
         assert not S.supports(I.layered(2, 2), I.tfim(2))
-        assert not S.supports(I.layered(14, 1), I.tfim(14))
+        assert not S.supports(I.layered(17, 1), I.tfim(17))
         wide = I.Circuit(6, [I.Op("x", (0,), (1, 2, 3))], np.zeros(0))
         assert not S.supports(wide, I.tfim(6))
         um = I.Circuit(5, [I.Op("unitary", (0,), matrix=np.eye(2))], np.zeros(0))

@@ -28,6 +28,10 @@ def _requests():
     reqs.append((I.Circuit(5, [], np.zeros(0)), I.tfim(5)))  # no ops
     reqs.append((I.layered(10, 3, seed=1), I.tfim(10)))     # one structure, two angle sets
     reqs.append((I.layered(10, 3, seed=2), I.tfim(10)))
+    for n in (14, 15, 16):                                   # several tiles per sweep
+        reqs.append((I.layered(n, 2, seed=500 + n), I.tfim(n)))
+    reqs.append((I.random_circuit(15, 40, seed=600, allow_unitary=False, max_qubits=3),
+                 I.random_hamiltonian(15, 6, seed=601)))
     return reqs
 
 
@@ -115,11 +119,12 @@ def test_serve_queued_submissions(serve):
 
 
 def test_serve_trace_requests(serve):
-    """Requests of the serving trace that the kernel takes (10..13 qubits,
-    4..30 layers, TFIM), 64 at once, against the oracle."""
+    """Requests of the serving trace that the serving loop routes to the
+    kernel (10..14 qubits, 4..30 layers, TFIM), 64 at once, against the
+    oracle."""
     import torch
     trace = I.serving_trace(1000.0, 400, seed=5)
-    small = [r for r in trace if r.circuit.n <= 13][:64]
+    small = [r for r in trace if r.circuit.n <= 14][:64]
     assert len(small) >= 32
     reqs = [(r.circuit, r.ham) for r in small]
     print(f"[case] serve {len(reqs)} trace requests", flush=True)
@@ -134,7 +139,7 @@ def test_serve_trace_requests(serve):
 def test_serve_refuses_before_device_work(serve):
     import torch
     from paper_2608_09733_amd import sv
-    reqs = [(I.layered(6, 2, seed=1), I.tfim(6)), (I.layered(14, 1, seed=1), I.tfim(14))]
+    reqs = [(I.layered(6, 2, seed=1), I.tfim(6)), (I.layered(17, 1, seed=1), I.tfim(17))]
     out = torch.full((64,), 7.0, dtype=torch.float64, device="cuda")
     with pytest.raises(sv.SvError) as ei:
         serve.submit([c for c, _ in reqs], [h for _, h in reqs], out)

@@ -10,8 +10,8 @@ Requests fall into three classes, each FIFO within itself:
   submitted as one persistent launch (sv_serve_submit) on a stream of its
   own; one workgroup runs one request whole, so these never queue behind a
   28-qubit request and take a few CUs each.  14 qubits is the measured
-  balance: at 200 req/s, routing up to 13, 14 and 16 qubits gave p50 192, 37
-  and 17 ms, p99 7.31, 7.36 and 7.69 s, and 49.4, 49.1 and 47.6 req/s (a
+  balance: at 200 req/s, routing up to 13, 14 and 16 qubits gave p50 122, 36
+  and 16 ms, p99 7.33, 7.37 and 7.71 s, and 49.3, 49.1 and 47.5 req/s (a
   15- or 16-qubit request holds one CU for 6-13 ms, where a lane spreads it
   over many CUs in about 1 ms).
 * big (n >= 21 qubits) and mid (the rest) -- run on stream lanes through
@@ -28,7 +28,9 @@ lambda and the backward copy of psi, 3 * 2^n * 16 bytes in FP64).  Each lane
 keeps one library handle per qubit count, so after warm-up a lane request
 allocates only its small output buffer; plans are cached per circuit
 structure.  With one lane and no batch path the loop is serial FIFO, the
-baseline the served figures are compared with.
+baseline the served figures are compared with.  Results come back through
+an asynchronous copy into pinned host memory on the request's stream, so a
+poll never blocks the scheduler behind kernels still in flight.
 
 The executor is pluggable: `GpuExecutor` runs the HIP library; tests drive
 the scheduler with a simulated executor on the CPU.
@@ -174,15 +176,25 @@ class GpuExecutor:
             st.reset()
             st.adjoint_grad_device(req.circuit.ops, req.circuit.params, req.ham, out,
                                    op_array=sv.op_array_for(req.circuit))
+            host = self._to_host(out)
             ev = torch.cuda.Event()
             ev.record(s)
-        return (out, ev)
+        return (out, host, ev)
+
+    def _to_host(self, out):
+        # results go to pinned host memory on the lane's own stream, before
+        # the completion event: a poll then reads host memory and never waits
+        # on the device (a synchronous copy would queue behind whatever
+        # kernels fill the GPU, and block the scheduler meanwhile)
+        host = self.torch.empty(out.numel(), dtype=out.dtype, pin_memory=True)
+        host.copy_(out, non_blocking=True)
+        return host
 
     def poll(self, lane: int, token):
-        out, ev = token
+        out, host, ev = token
         if not ev.query():
             return None
-        v = out.cpu().numpy()
+        v = host.numpy()
         self.busy[lane] = False
         return float(v[0]), v[1:].copy()
 
@@ -210,15 +222,16 @@ class GpuExecutor:
             out = torch.empty(tot, dtype=torch.float64, device="cuda")
             offs = self.serve.submit([r.circuit for r in reqs], [r.ham for r in reqs], out,
                                      self.bstream)
+            host = self._to_host(out)
             ev = torch.cuda.Event()
             ev.record(self.bstream)
-        return (out, offs, ev)
+        return (out, host, offs, ev)
 
     def poll_batch(self, token):
-        out, offs, ev = token
+        out, host, offs, ev = token
         if not ev.query():
             return None
-        v = out.cpu().numpy()
+        v = host.numpy()
         return [(float(v[offs[k]]), v[offs[k] + 1:offs[k + 1]].copy()) for k in range(len(offs) - 1)]
 
     def close(self):

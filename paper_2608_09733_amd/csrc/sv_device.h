@@ -618,6 +618,42 @@ __device__ __forceinline__ double wave_total63(double v) {
   return v;
 }
 
+// Swaps the upper 32 lanes of x with the lower 32 lanes of y (64-bit values,
+// v_permlane32_swap on each half).
+__device__ __forceinline__ void swap32_d(double &x, double &y) {
+  const long long xb = __double_as_longlong(x), yb = __double_as_longlong(y);
+  const auto lo = __builtin_amdgcn_permlane32_swap((unsigned)xb, (unsigned)yb, false, false);
+  const auto hi =
+      __builtin_amdgcn_permlane32_swap((unsigned)(xb >> 32), (unsigned)(yb >> 32), false, false);
+  x = __longlong_as_double(((long long)hi[0] << 32) | (unsigned)lo[0]);
+  y = __longlong_as_double(((long long)hi[1] << 32) | (unsigned)lo[1]);
+}
+
+// Sums over the 64 lanes of a wave of two per-lane values in one chain: the
+// halves exchange and add, so that lanes 0-31 hold half-sums of v0 and lanes
+// 32-63 of v1; row shifts by 1, 2, 4, 8 sum each row of 16 lanes, and the
+// broadcast of lane 15 into rows 1 and 3 adds row 0 to row 1 and row 2 to
+// row 3.  The total of v0 is valid in lane 31, that of v1 in lane 63: 18 VALU
+// instructions for both, against 18 for each through wave_total63.  Needs
+// every lane of the wave active.
+__device__ __forceinline__ double wave_total2(double v0, double v1) {
+  swap32_d(v0, v1);
+  double t = v0 + v1;
+  t += dpp_d<0x111, 0xf>(t);   // row_shr:1
+  t += dpp_d<0x112, 0xf>(t);   // row_shr:2
+  t += dpp_d<0x114, 0xf>(t);   // row_shr:4
+  t += dpp_d<0x118, 0xf>(t);   // row_shr:8
+  t += dpp_d<0x142, 0xa>(t);   // row_bcast:15 into rows 1 and 3
+  return t;
+}
+
+// Adds the two wave totals of wave_total2 to slots s0 and s1 of the wave's LDS
+// row (a slot < 0: none) with adds that return nothing, lanes 31 and 63.
+__device__ __forceinline__ void wave_deposit2(double *row, int s0, int s1, double t, int lane) {
+  const int slot = lane == 31 ? s0 : s1;
+  if ((lane == 31 || lane == 63) && slot >= 0) atomicAdd(&row[slot], t);
+}
+
 template <typename T, int M, int R, int NS>
 __global__ void __launch_bounds__(1 << (M - R)) k_sweep(SweepArgs a) {
   constexpr int NT = 1 << (M - R);
@@ -1229,8 +1265,9 @@ __device__ void sweep_tiles(const SVI_CONST SweepArgs &a, int64_t t0, int64_t t1
 // One Kronecker stage applied to the psi and lambda tiles held side by side in
 // LDS (lb0, lb1), with the gradient terms Im <lam| G |psi> of the stage's
 // gradient micro-ops taken at the three stage points (stage input, after
-// D_before, after the rotations).  Terms go to sink(slot0, v0, slot1, v1) in
-// pairs (slot1 = -1: v0 only), the slots uniform across the wave.  Ends with the barrier (or the wave
+// D_before, after the rotations).  Terms go through in pairs: sink(s0, s1, t)
+// receives the pair's wave_total2 result t and the pair's slots (s1 = -1: a
+// single term), uniform across the wave.  Ends with the barrier (or the wave
 // fence of a wave-local stage) that makes the stores visible to the next stage.
 template <typename T, int R, typename Sink>
 __device__ __forceinline__ void kron2_stage(char *lb0, char *lb1, int gbs,
@@ -1252,21 +1289,20 @@ __device__ __forceinline__ void kron2_stage(char *lb0, char *lb1, int gbs,
   }
   const SVI_CONST double *kc = coef + sd.kcoef;
   auto grads = [&](int b, int e, double mult) {
-    // two terms at a time, so that their wave sums (chains of dependent lane
-    // moves) interleave; a wider unroll would keep more terms' operands live
-    // and spill the register groups
+    // two terms at a time, summed over the wave in one chain of lane moves
+    // (groups of four, in any arrangement, measured slower)
     int o = b;
 #pragma clang loop unroll(disable)
     for (; o + 1 < e; o += 2) {
       const MicroOp op0 = op_at(ops, o), op1 = op_at(ops, o + 1);
       const double v0 = active ? mult * grad_kron<T, R>(op0, re[0], im[0], re[1], im[1], gcoef) : 0.0;
       const double v1 = active ? mult * grad_kron<T, R>(op1, re[0], im[0], re[1], im[1], gcoef) : 0.0;
-      sink(op0.coef, v0, op1.coef, v1);
+      sink(op0.coef, op1.coef, wave_total2(v0, v1));
     }
     if (o < e) {
       const MicroOp op = op_at(ops, o);
       const double v = active ? mult * grad_kron<T, R>(op, re[0], im[0], re[1], im[1], gcoef) : 0.0;
-      sink(op.coef, v, -1, 0.0);
+      sink(op.coef, -1, wave_total2(v, 0.0));
     }
   };
   grads(sd.op_begin, sd.g1, 1.0);
@@ -1299,7 +1335,7 @@ __device__ __forceinline__ void kron2_stage(char *lb0, char *lb1, int gbs,
 
 // One micro-op stage (the interpreter) applied to the psi and lambda tiles
 // in LDS: each gate micro-op acts on both states, each gradient micro-op sends
-// its term Im <lam| G |psi> to sink(slot, value, -1, 0) at its place in the
+// its term Im <lam| G |psi> to sink(slot, -1, wave total) at its place in the
 // stage.
 // Ends with the barrier that makes the stores visible to the next stage.
 template <typename T, int R, typename Sink>
@@ -1322,7 +1358,8 @@ __device__ __forceinline__ void ops2_stage(char *lb0, char *lb1, int gbs,
   for (int o = sd.op_begin; o < sd.op_end; o++) {
     const MicroOp op = op_at(ops, o);
     if (op.type == MO_GRAD || op.type == MO_GRAD2L) {
-      sink(op.coef, active ? grad_any<T, R>(op, re[0], im[0], re[1], im[1], coef) : 0.0, -1, 0.0);
+      const double v = active ? grad_any<T, R>(op, re[0], im[0], re[1], im[1], coef) : 0.0;
+      sink(op.coef, -1, wave_total2(v, 0.0));
       continue;
     }
     apply_op<T, R>(op, re[0], im[0], coef);
@@ -1430,15 +1467,10 @@ __global__ void __launch_bounds__(1 << (M - R)) k_sweep_kron2(SweepArgs a) {
           st < ntab ? gtab[st * NT + tid] : swz<T>(stage_base<M, R>(tid, sd)) * (int)sizeof(C2);
       const bool active = tid < (1 << (m > R ? m - R : 0));
       kron2_stage<T, R>((char *)lds[0], (char *)lds[1], gbs, sd, coef, a.ops, a.coef, active,
-                        [&](int s0, double v0, int s1, double v1) {
-        // this tile's terms summed over the wave into the wave's LDS rows of
-        // their slots (LDS adds without return: the wave does not wait)
-        const double w0 = wave_total63(v0);
-        const double w1 = wave_total63(v1);
-        if ((tid & 63) == 63) {
-          atomicAdd(&wacc[tid >> 6][s0], w0);
-          if (s1 >= 0) atomicAdd(&wacc[tid >> 6][s1], w1);
-        }
+                        [&](int s0, int s1, double t) {
+        // this tile's wave totals into the wave's LDS rows of their slots
+        // (LDS adds without return: the wave does not wait)
+        wave_deposit2(wacc[tid >> 6], s0, s1, t, tid & 63);
       });
     }
     // ---- LDS to HBM

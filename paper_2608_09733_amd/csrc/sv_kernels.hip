@@ -1797,13 +1797,8 @@ __global__ void __launch_bounds__(1 << (M - R)) k_serve(ServeArgs sa) {
         for (int st = 0; st < nst; st++) {
           const SVI_CONST StageDesc &sd = stages[st];
           const int gbs = swz<T>(stage_base<M, R>(tid, sd)) * (int)sizeof(C2);
-          auto sink = [&](int s0, double v0, int s1, double v1) {
-            const double w0 = wave_total63(v0);
-            const double w1 = wave_total63(v1);
-            if ((tid & 63) == 63) {
-              atomicAdd(&wacc[tid >> 6][s0], w0);
-              if (s1 >= 0) atomicAdd(&wacc[tid >> 6][s1], w1);
-            }
+          auto sink = [&](int s0, int s1, double t) {
+            wave_deposit2(wacc[tid >> 6], s0, s1, t, tid & 63);
           };
           if (!GEN || sd.kind == ST_KRON)
             kron2_stage<T, R>((char *)lt, (char *)(lt + (1 << M)), gbs, sd, coef, a.ops, a.coef, active,

@@ -349,6 +349,21 @@ __device__ __forceinline__ PauliTermDev term_at(const PauliTermDev *terms, int t
   return p;
 }
 
+// In-place Walsh-Hadamard transform of N register values (N a power of two):
+// v[z] becomes sum_k (-1)^{popcount(k & z)} v[k].
+template <int N>
+__device__ __forceinline__ void wht_regs(double (&v)[N]) {
+#pragma unroll
+  for (int h = 1; h < N; h <<= 1)
+#pragma unroll
+    for (int k = 0; k < N; k++)
+      if (!(k & h)) {
+        const double x = v[k], y = v[k | h];
+        v[k] = x + y;
+        v[k | h] = x - y;
+      }
+}
+
 template <typename T, int M>
 __global__ void __launch_bounds__(SVI_PAULI_NT) k_pauli(PauliPassArgs a) {
   constexpr int NT = SVI_PAULI_NT;
@@ -422,23 +437,29 @@ __global__ void __launch_bounds__(SVI_PAULI_NT) k_pauli(PauliPassArgs a) {
       acc = wave_total63(acc);
       if ((tid & 63) == 63) wsum[tid >> 6][t] = acc;
     };
-    // Z-only terms: sign(i) = parity(base & z) ^ parity(tid & z) ^ parity((k*NT) & z)
+    // Z-only terms: sign(i) = parity(base & z) ^ parity(tid & zl) ^ parity(k & zk)
+    // with zk = zl / NT the term's bits among the element bits k.  After one
+    // Walsh-Hadamard transform over k, pn[zk] is sum_k (-1)^{popcount(k & zk)}
+    // |psi_k|^2, so a term reads one entry; for lambda, each term adds its
+    // signed coefficient to bin zk, and the same transform of the bins gives
+    // the diagonal factor of every element.
+    wht_regs<EPT>(pn);
     for (int t = 0; t < nterm; t++) {
       if (xl_s[t] != 0) continue;
       const PauliTermDev pt = term_at(a.terms, a.t_begin + t);
       const uint32_t zl = zl_s[t];
       const bool sneg = (__builtin_popcountll(base & pt.z) ^ __builtin_popcount((uint32_t)tid & zl)) & 1;
       const uint32_t zk = zl / NT;
-      const double cc = sneg ? -pt.c : pt.c;
       double acc = 0.0;
 #pragma unroll
-      for (int k = 0; k < EPT; k++) {
-        const bool kn = __builtin_popcount((uint32_t)k & zk) & 1;
-        acc = kn ? acc - pn[k] : acc + pn[k];
-        if (lre) zs[k] = kn ? zs[k] - cc : zs[k] + cc;
-      }
+      for (int q = 0; q < EPT; q++)
+        if (zk == (uint32_t)q) {
+          acc = pn[q];
+          if (lre) zs[q] += sneg ? -pt.c : pt.c;
+        }
       put(t, sneg ? -acc : acc);
     }
+    if (lre) wht_regs<EPT>(zs);
     // terms with an X / Y part: partner amplitudes from LDS
     T lr[EPT], li[EPT];
     if (lre) {
@@ -461,6 +482,29 @@ __global__ void __launch_bounds__(SVI_PAULI_NT) k_pauli(PauliPassArgs a) {
       const uint32_t zl = zl_s[t];
       const int ny = __builtin_popcountll(pt.x & pt.z) & 3;
       const bool bneg = __builtin_popcountll(base & pt.z) & 1;   // non-tile bits' sign
+      if (zl == 0) {
+        // no Z bit inside the tile, hence no Y (every X bit is a tile bit):
+        // the sign (-1)^bneg is the same for every element, so the term is
+        // s Re sum conj(psi_{b^x}) psi_b, and lambda adds s c psi_{b^x}
+        const double s1 = bneg ? -1.0 : 1.0, cs = s1 * pt.c;
+        double sr = 0.0;
+#pragma unroll
+        for (int k = 0; k < EPT; k++) {
+          const int i = tid + k * NT;
+          if (i < nel) {
+            const C2 pb = lds[swz<T>(i)];
+            const C2 pp = lds[swz<T>(i ^ (int)xl)];
+            const double ur = (double)pp.x, ui = (double)pp.y;
+            sr += ur * (double)pb.x + ui * (double)pb.y;
+            if (lre) {
+              lr[k] += (T)(cs * ur);
+              li[k] += (T)(cs * ui);
+            }
+          }
+        }
+        put(t, s1 * sr);
+        continue;
+      }
       double acc = 0.0;
 #pragma unroll
       for (int k = 0; k < EPT; k++) {

@@ -2345,15 +2345,19 @@ extern "C" sv_status sv_dm_apply_kraus(sv_state *st, int32_t n, const int32_t *q
   if (n_qubits == 0) return SV_OK;
   s = materialize_zero(st);
   if (s) return s;
-  // four channels per LDS-tile pass on vectors of 12 or more qubits (the
-  // other four tile bits are the lowest free vector bits), then two per pass,
-  // then one; three per tile (64-entry load runs) measured slower
+  // on vectors of 12 or more qubits: four channels per LDS-tile pass (the
+  // other four tile bits are the lowest free vector bits), a remainder of two
+  // or three in one more tile pass (measured faster than the two- and
+  // one-channel streaming passes), a last single channel in a streaming pass;
+  // smaller vectors take two per streaming pass, then one
   int i0 = 0;
   if (st->n >= 12)
-    for (; i0 + 4 <= n_qubits; i0 += 4) {
+    while (n_qubits - i0 >= 2) {
+      const int k = std::min(4, n_qubits - i0);
       hipError_t e = svk_launch_dm_channel_tile(st->dtype == SV_C128, st->re, st->im, st->n, n,
-                                                qubits + i0, 4, m, st->stream);
+                                                qubits + i0, k, m, st->stream);
       if (e != hipSuccess) return fail(SV_EDEVICE, "channel kernel: %s", hipGetErrorString(e));
+      i0 += k;
     }
   for (int i = i0; i < n_qubits; i += 2) {
     hipError_t e = i + 1 < n_qubits

@@ -902,11 +902,12 @@ __global__ void __launch_bounds__(256) k_dm_channel16(Channel16Args a) {
 }
 
 // Up to four one-qubit channels in one pass through an LDS tile of 4096
-// entries: tile-index bit j is vector bit pos[j] (the lowest vector bits not
-// used by the channels first, so loads run over consecutive entries, then the
-// channels' column and row bits); each channel's 4x4 superoperator is applied
-// to the 1024 groups of four entries that differ in its two bits, one
-// channel after another, and the tile is written back once.
+// entries: the tile's vector bits are the channels' column and row bits and
+// the lowest vector bits the channels leave free, and tile-index bit j is the
+// j-th lowest of them (pos[j]), so a wave's loads run over the longest
+// consecutive stretches; each channel's 4x4 superoperator is applied to the
+// 1024 groups of four entries that differ in its two bits, one channel after
+// another, and the tile is written back once.
 struct ChannelTileArgs {
   void *re, *im;
   int64_t tiles;      // 2^(N - 12)
@@ -914,6 +915,7 @@ struct ChannelTileArgs {
   int pos[12];        // vector bit of tile-index bit j
   int sorted[12];     // pos, ascending
   int ci[4], ri[4];   // tile-index bits of channel i's column and row bits
+  int real;           // every imaginary part of s is zero
   double s[32];
 };
 
@@ -922,20 +924,29 @@ __global__ void __launch_bounds__(256) k_dm_channel_tile(ChannelTileArgs a) {
   __shared__ double2 lds[4096];
   T *re = (T *)a.re, *im = (T *)a.im;
   const int tid = threadIdx.x;
+  // Tile entry e = tid + 256 k sits at base | loff | koff[k]: the deposit of
+  // e's bits on pos[] splits into the thread's part (bits 0-7) and a part
+  // that depends only on the unrolled k (bits 8-11, uniform: scalar).
+  uint64_t loff = 0;
+#pragma unroll
+  for (int j = 0; j < 8; j++) loff |= (uint64_t)((tid >> j) & 1) << a.pos[j];
+  uint64_t koff[16];
+#pragma unroll
+  for (int k = 0; k < 16; k++) {
+    koff[k] = 0;
+#pragma unroll
+    for (int j = 0; j < 4; j++) koff[k] |= (uint64_t)((k >> j) & 1) << a.pos[8 + j];
+  }
   for (int64_t t = blockIdx.x; t < a.tiles; t += gridDim.x) {
     uint64_t base = (uint64_t)t;
 #pragma unroll
     for (int j = 0; j < 12; j++)
       base = ((base >> a.sorted[j]) << (a.sorted[j] + 1)) | (base & ((1ull << a.sorted[j]) - 1));
-    auto addr = [&](int e) {
-      uint64_t g = base;
+    const uint64_t lb = base | loff;
 #pragma unroll
-      for (int j = 0; j < 12; j++) g |= (uint64_t)((e >> j) & 1) << a.pos[j];
-      return g;
-    };
-    for (int e = tid; e < 4096; e += 256) {
-      const uint64_t g = addr(e);
-      lds[e] = make_double2((double)re[g], (double)im[g]);
+    for (int k = 0; k < 16; k++) {
+      const uint64_t g = lb | koff[k];
+      lds[tid + 256 * k] = make_double2((double)re[g], (double)im[g]);
     }
     __syncthreads();
     for (int i = 0; i < a.k; i++) {
@@ -953,23 +964,37 @@ __global__ void __launch_bounds__(256) k_dm_channel_tile(ChannelTileArgs a) {
           xr[l] = v.x;
           xi[l] = v.y;
         }
+        // a real superoperator (depolarizing, dephasing, amplitude damping
+        // and every other channel with real Kraus operators) takes half the
+        // multiply-adds
+        auto apply = [&](auto real) {
 #pragma unroll
-        for (int o = 0; o < 4; o++) {
-          double yr = 0.0, yi = 0.0;
+          for (int o = 0; o < 4; o++) {
+            double yr = 0.0, yi = 0.0;
 #pragma unroll
-          for (int l = 0; l < 4; l++) {
-            const double sr = a.s[2 * (4 * o + l)], si = a.s[2 * (4 * o + l) + 1];
-            yr += sr * xr[l] - si * xi[l];
-            yi += sr * xi[l] + si * xr[l];
+            for (int l = 0; l < 4; l++) {
+              const double sr = a.s[2 * (4 * o + l)];
+              if constexpr (decltype(real)::value) {
+                yr += sr * xr[l];
+                yi += sr * xi[l];
+              } else {
+                const double si = a.s[2 * (4 * o + l) + 1];
+                yr += sr * xr[l] - si * xi[l];
+                yi += sr * xi[l] + si * xr[l];
+              }
+            }
+            lds[ix[o]] = make_double2(yr, yi);
           }
-          lds[ix[o]] = make_double2(yr, yi);
-        }
+        };
+        if (a.real) apply(std::true_type{});
+        else apply(std::false_type{});
       }
       __syncthreads();
     }
-    for (int e = tid; e < 4096; e += 256) {
-      const uint64_t g = addr(e);
-      const double2 v = lds[e];
+#pragma unroll
+    for (int k = 0; k < 16; k++) {
+      const uint64_t g = lb | koff[k];
+      const double2 v = lds[tid + 256 * k];
       re[g] = (T)v.x;
       im[g] = (T)v.y;
     }
@@ -1508,14 +1533,18 @@ hipError_t svk_launch_dm_channel_tile(int dbl, void *re, void *im, int nq, int o
   for (int b = 0; b < nq; b++)
     if (used >> b & 1) chan[nc++] = b;
   for (int j = 0; j < nc; j++) a.pos[np + j] = chan[j];
+  std::sort(a.pos, a.pos + 12);   // lanes run over the lowest of the tile's vector bits
   for (int j = 0; j < 12; j++) a.sorted[j] = a.pos[j];
-  std::sort(a.sorted, a.sorted + 12);
   for (int i = 0; i < k; i++)
     for (int j = 0; j < 12; j++) {
       if (a.pos[j] == qubits[i]) a.ci[i] = j;
       if (a.pos[j] == qubits[i] + off) a.ri[i] = j;
     }
-  for (int i = 0; i < 32; i++) a.s[i] = s32[i];
+  a.real = 1;
+  for (int i = 0; i < 32; i++) {
+    a.s[i] = s32[i];
+    if ((i & 1) && s32[i] != 0.0) a.real = 0;
+  }
   const int grid = (int)std::min<int64_t>(a.tiles, 8192);
   if (dbl) hipLaunchKernelGGL(k_dm_channel_tile<double>, dim3(grid), dim3(256), 0, s, a);
   else hipLaunchKernelGGL(k_dm_channel_tile<float>, dim3(grid), dim3(256), 0, s, a);

@@ -47,6 +47,17 @@ def _mixed_unitaries(seed):
     return out
 
 
+def _mixed_unitaries_1q(seed):
+    # complex one-qubit Kraus set (complex superoperator): sqrt(0.8) U, sqrt(0.2) V
+    rng = np.random.default_rng(seed)
+    out = []
+    for w in (0.8, 0.2):
+        a = rng.normal(size=(2, 2)) + 1j * rng.normal(size=(2, 2))
+        q, _ = np.linalg.qr(a)
+        out.append(math.sqrt(w) * q)
+    return out
+
+
 @pytest.mark.parametrize("n", [3, 6, 7])
 def test_dm_vs_oracle(sv, n):
     _say("density matrix", n)
@@ -115,9 +126,10 @@ def _channel_2q(T, n, q0, q1, kraus):
 def test_dm_13_qubits_grid_stride(sv, dtype):
     """rho of 13 qubits (a 26-qubit vector: 16384 tiles of the four-channel
     pass, several grid-stride rounds of the single-channel pass) from the
-    oracle's pure state, seven one-qubit channels (four-, two- and
-    single-channel passes) and a two-qubit channel, against tensor
-    contractions of the superoperators; Tr(rho) = 1 and Tr(rho Z_i)."""
+    oracle's pure state, seven one-qubit channels with a real superoperator
+    (four-, two- and single-channel passes), five with a complex one (a
+    four-channel and a single-channel pass) and a two-qubit channel, against
+    tensor contractions of the superoperators; Tr(rho) = 1 and Tr(rho Z_i)."""
     n = 13
     _say("density matrix 13 qubits", dtype)
     c = I.layered(n, 2, seed=3)
@@ -125,6 +137,9 @@ def test_dm_13_qubits_grid_stride(sv, dtype):
     T = np.outer(psi, np.conj(psi)).reshape([2] * (2 * n))
     for q in range(7):
         T = _channel_1q(T, n, q, _depolarizing(0.05))
+    C1 = _mixed_unitaries_1q(7)
+    for q in range(7, 12):
+        T = _channel_1q(T, n, q, C1)
     K2 = _mixed_unitaries(5)
     T = _channel_2q(T, n, 3, 9, K2)
     want = T.reshape(-1)
@@ -133,6 +148,7 @@ def test_dm_13_qubits_grid_stride(sv, dtype):
         st.reset()
         st.dm_apply(c.ops, c.params)
         st.dm_apply_kraus(list(range(7)), _depolarizing(0.05))
+        st.dm_apply_kraus(list(range(7, 12)), C1)
         st.dm_apply_kraus2(3, 9, K2)
         got = st.to_numpy()
         scale = float(np.max(np.abs(want)))

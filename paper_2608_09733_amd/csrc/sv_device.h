@@ -1288,9 +1288,37 @@ __device__ __forceinline__ void kron2_stage(char *lb0, char *lb1, int gbs,
     }
   }
   const SVI_CONST double *kc = coef + sd.kcoef;
-  auto grads = [&](int b, int e, double mult) {
+  auto grads = [&](int b, int e, double mult, int point) {
     // two terms at a time, summed over the wave in one chain of lane moves
     // (groups of four, in any arrangement, measured slower)
+    if ((sd.gdiag >> point) & 1) {
+      // every generator here is diagonal: one array of the products
+      // Im(conj(lam_j) psi_j), then a dot product with each term's table
+      double fz[G];
+#pragma unroll
+      for (int j = 0; j < G; j++)
+        fz[j] = (double)re[1][j] * (double)im[0][j] - (double)im[1][j] * (double)re[0][j];
+      auto dot = [&](const MicroOp &op) {
+        const SVI_CONST double *tab = cptr(gcoef) + op.t0;
+        double acc = 0.0;
+#pragma unroll
+        for (int j = 0; j < G; j++) acc += (double)tab[j] * fz[j];
+        return acc;
+      };
+      int o = b;
+#pragma clang loop unroll(disable)
+      for (; o + 1 < e; o += 2) {
+        const MicroOp op0 = op_at(ops, o), op1 = op_at(ops, o + 1);
+        const double v0 = active ? mult * dot(op0) : 0.0;
+        const double v1 = active ? mult * dot(op1) : 0.0;
+        sink(op0.coef, op1.coef, wave_total2(v0, v1));
+      }
+      if (o < e) {
+        const MicroOp op = op_at(ops, o);
+        sink(op.coef, -1, wave_total2(active ? mult * dot(op) : 0.0, 0.0));
+      }
+      return;
+    }
     int o = b;
 #pragma clang loop unroll(disable)
     for (; o + 1 < e; o += 2) {
@@ -1305,15 +1333,15 @@ __device__ __forceinline__ void kron2_stage(char *lb0, char *lb1, int gbs,
       sink(op.coef, -1, wave_total2(v, 0.0));
     }
   };
-  grads(sd.op_begin, sd.g1, 1.0);
+  grads(sd.op_begin, sd.g1, 1.0, 0);
   kron_pre<T, R>(re[0], im[0], kc, sd.dflags);
   kron_pre<T, R>(re[1], im[1], kc, sd.dflags);
-  grads(sd.g1, sd.g2, 1.0);
+  grads(sd.g1, sd.g2, 1.0, 1);
   kron_rot<T, R>(re[0], im[0], kc, sd.rmask);
   kron_rot<T, R>(re[1], im[1], kc, sd.rmask);
   if (sd.g2 < sd.op_end) {
     const double sc = kc[4 * R + 4 * G];
-    grads(sd.g2, sd.op_end, sc * sc);
+    grads(sd.g2, sd.op_end, sc * sc, 2);
   }
   kron_post<T, R>(re[0], im[0], kc, sd.dflags);
   kron_post<T, R>(re[1], im[1], kc, sd.dflags);

@@ -1114,6 +1114,15 @@ static void emit_sweep(Plan &P, std::vector<GateRec> &recs, const SweepP &sw, in
       for (int r : st.dafter)
         if (grad_mop[idx_of(r)].type == MO_GRAD) P.ops.push_back(grad_mop[idx_of(r)]);
       sd.op_end = (int)P.ops.size();
+      // ranges whose generators are all diagonal (the kernel then makes one
+      // product array for them instead of one per generator form)
+      sd.gdiag = 0;
+      const int gb[4] = {sd.op_begin, sd.g1, sd.g2, sd.op_end};
+      for (int p = 0; p < 3; p++) {
+        bool diag = true;
+        for (int o = gb[p]; o < gb[p + 1]; o++) diag = diag && P.ops[o].mask == 0;
+        if (diag) sd.gdiag |= 1u << p;
+      }
       // the scalar slot holds the product of the fast-Givens scales: applied
       // to the state when there is no D_after to carry it, and used to rescale
       // gradients taken between the rotations and D_after

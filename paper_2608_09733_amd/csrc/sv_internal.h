@@ -99,6 +99,8 @@ struct StageDesc {
   int32_t kcoef;               // ST_KRON: coefficient offset (doubles)
   int32_t g1, g2;              // ST_KRON: MO_GRAD ops [op_begin, g1) run on the stage input,
                                // [g1, g2) after D_before, [g2, op_end) after the rotations
+  uint32_t gdiag;              // ST_KRON: bit p set when every MO_GRAD op of range p
+                               // (0, 1, 2 as above) has a diagonal generator
   int8_t tpos[16] __attribute__((aligned(4)));   // tile bit of thread-index bit k (see above)
   int32_t ld_off[SVI_GMAX];    // swizzled tile-local BYTE offset loaded into slot j
   int32_t st_off[SVI_GMAX];    // swizzled tile-local BYTE offset slot j is stored to

@@ -2354,26 +2354,40 @@ extern "C" sv_status sv_dm_apply_kraus(sv_state *st, int32_t n, const int32_t *q
   if (n_qubits == 0) return SV_OK;
   s = materialize_zero(st);
   if (s) return s;
-  // on vectors of 12 or more qubits: four channels per LDS-tile pass (the
-  // other four tile bits are the lowest free vector bits), a remainder of two
-  // or three in one more tile pass (measured faster than the two- and
-  // one-channel streaming passes), a last single channel in a streaming pass;
-  // smaller vectors take two per streaming pass, then one
-  int i0 = 0;
-  if (st->n >= 12)
-    while (n_qubits - i0 >= 2) {
-      const int k = std::min(4, n_qubits - i0);
+  // On vectors of 12 or more qubits the channels go through LDS-tile passes
+  // of up to five channels (13-bit tiles, vectors of 13 or more qubits) or
+  // four (12-bit tiles), as few passes as that allows; the sorted qubits are
+  // dealt round-robin over the passes, so every pass holds some of the lowest
+  // qubits and its loads run over long consecutive stretches (a pass of two
+  // or three channels measured faster than the two- and one-channel
+  // streaming passes).  A pass left with one channel, and every channel of a
+  // smaller vector, takes the streaming passes: two per pass, then one.
+  std::vector<int> rest;
+  if (st->n >= 12 && n_qubits >= 2) {
+    const int kmax = st->n >= 13 ? 5 : 4;
+    const int npass = (n_qubits + kmax - 1) / kmax;
+    std::vector<int> sq(qubits, qubits + n_qubits);
+    std::sort(sq.begin(), sq.end());
+    for (int p = 0; p < npass; p++) {
+      int grp[5], k = 0;
+      for (int i = p; i < n_qubits; i += npass) grp[k++] = sq[i];
+      if (k == 1) {
+        rest.push_back(grp[0]);
+        continue;
+      }
       hipError_t e = svk_launch_dm_channel_tile(st->dtype == SV_C128, st->re, st->im, st->n, n,
-                                                qubits + i0, k, m, st->stream);
+                                                grp, k, m, st->stream);
       if (e != hipSuccess) return fail(SV_EDEVICE, "channel kernel: %s", hipGetErrorString(e));
-      i0 += k;
     }
-  for (int i = i0; i < n_qubits; i += 2) {
-    hipError_t e = i + 1 < n_qubits
-        ? svk_launch_dm_channel2(st->dtype == SV_C128, st->re, st->im, st->n, qubits[i],
-                                 qubits[i + 1], n, m, m, st->stream)
-        : svk_launch_dm_channel(st->dtype == SV_C128, st->re, st->im, st->n, qubits[i],
-                                qubits[i] + n, m, st->stream);
+  } else {
+    rest.assign(qubits, qubits + n_qubits);
+  }
+  for (size_t i = 0; i < rest.size(); i += 2) {
+    hipError_t e = i + 1 < rest.size()
+        ? svk_launch_dm_channel2(st->dtype == SV_C128, st->re, st->im, st->n, rest[i],
+                                 rest[i + 1], n, m, m, st->stream)
+        : svk_launch_dm_channel(st->dtype == SV_C128, st->re, st->im, st->n, rest[i],
+                                rest[i] + n, m, st->stream);
     if (e != hipSuccess) return fail(SV_EDEVICE, "channel kernel: %s", hipGetErrorString(e));
   }
   HIPCHK(hipStreamSynchronize(st->stream));

@@ -901,58 +901,64 @@ __global__ void __launch_bounds__(256) k_dm_channel16(Channel16Args a) {
   }
 }
 
-// Up to four one-qubit channels in one pass through an LDS tile of 4096
-// entries: the tile's vector bits are the channels' column and row bits and
-// the lowest vector bits the channels leave free, and tile-index bit j is the
-// j-th lowest of them (pos[j]), so a wave's loads run over the longest
-// consecutive stretches; each channel's 4x4 superoperator is applied to the
-// 1024 groups of four entries that differ in its two bits, one channel after
-// another, and the tile is written back once.
+// Up to five one-qubit channels in one pass through an LDS tile of 2^TB
+// entries (TB = 12: up to four channels, 256 threads, two tiles per CU;
+// TB = 13: five, 1024 threads, one tile per CU): the tile's vector bits are
+// the channels' column and row bits and the lowest vector bits the channels
+// leave free, and tile-index bit j is the j-th lowest of them (pos[j]), so a
+// wave's loads run over the longest consecutive stretches; each channel's
+// 4x4 superoperator is applied to the 2^(TB-2) groups of four entries that
+// differ in its two bits, one channel after another, and the tile is written
+// back once.
 struct ChannelTileArgs {
   void *re, *im;
-  int64_t tiles;      // 2^(N - 12)
-  int k;              // channels in this pass (1..4)
-  int pos[12];        // vector bit of tile-index bit j
-  int sorted[12];     // pos, ascending
-  int ci[4], ri[4];   // tile-index bits of channel i's column and row bits
+  int64_t tiles;      // 2^(N - TB)
+  int k;              // channels in this pass (1..5)
+  int pos[13];        // vector bit of tile-index bit j (TB of them)
+  int sorted[13];     // pos, ascending
+  int ci[5], ri[5];   // tile-index bits of channel i's column and row bits
   int real;           // every imaginary part of s is zero
   double s[32];
 };
 
-template <typename T>
-__global__ void __launch_bounds__(256) k_dm_channel_tile(ChannelTileArgs a) {
-  __shared__ double2 lds[4096];
+template <typename T, int TB>
+__global__ void __launch_bounds__(TB == 13 ? 1024 : 256) k_dm_channel_tile(ChannelTileArgs a) {
+  constexpr int NT = TB == 13 ? 1024 : 256;
+  constexpr int LT = TB == 13 ? 10 : 8;   // tile-index bits of the thread
+  constexpr int KB = TB - LT;              // tile-index bits of the unrolled element
+  constexpr int EPT = 1 << KB;             // entries per thread
+  __shared__ double2 lds[1 << TB];
   T *re = (T *)a.re, *im = (T *)a.im;
   const int tid = threadIdx.x;
-  // Tile entry e = tid + 256 k sits at base | loff | koff[k]: the deposit of
-  // e's bits on pos[] splits into the thread's part (bits 0-7) and a part
-  // that depends only on the unrolled k (bits 8-11, uniform: scalar).
+  // Tile entry e = tid + NT k sits at base | loff | koff[k]: the deposit of
+  // e's bits on pos[] splits into the thread's part (bits below LT) and a
+  // part that depends only on the unrolled k (uniform: scalar).
   uint64_t loff = 0;
 #pragma unroll
-  for (int j = 0; j < 8; j++) loff |= (uint64_t)((tid >> j) & 1) << a.pos[j];
-  uint64_t koff[16];
+  for (int j = 0; j < LT; j++) loff |= (uint64_t)((tid >> j) & 1) << a.pos[j];
+  uint64_t koff[EPT];
 #pragma unroll
-  for (int k = 0; k < 16; k++) {
+  for (int k = 0; k < EPT; k++) {
     koff[k] = 0;
 #pragma unroll
-    for (int j = 0; j < 4; j++) koff[k] |= (uint64_t)((k >> j) & 1) << a.pos[8 + j];
+    for (int j = 0; j < KB; j++) koff[k] |= (uint64_t)((k >> j) & 1) << a.pos[LT + j];
   }
   for (int64_t t = blockIdx.x; t < a.tiles; t += gridDim.x) {
     uint64_t base = (uint64_t)t;
 #pragma unroll
-    for (int j = 0; j < 12; j++)
+    for (int j = 0; j < TB; j++)
       base = ((base >> a.sorted[j]) << (a.sorted[j] + 1)) | (base & ((1ull << a.sorted[j]) - 1));
     const uint64_t lb = base | loff;
 #pragma unroll
-    for (int k = 0; k < 16; k++) {
+    for (int k = 0; k < EPT; k++) {
       const uint64_t g = lb | koff[k];
-      lds[tid + 256 * k] = make_double2((double)re[g], (double)im[g]);
+      lds[tid + NT * k] = make_double2((double)re[g], (double)im[g]);
     }
     __syncthreads();
     for (int i = 0; i < a.k; i++) {
       const int c = a.ci[i], r = a.ri[i];
       const int lo = c < r ? c : r, hi = c < r ? r : c;
-      for (int gi = tid; gi < 1024; gi += 256) {
+      for (int gi = tid; gi < (1 << (TB - 2)); gi += NT) {
         int e0 = ((gi >> lo) << (lo + 1)) | (gi & ((1 << lo) - 1));
         e0 = ((e0 >> hi) << (hi + 1)) | (e0 & ((1 << hi) - 1));
         int ix[4];
@@ -992,9 +998,9 @@ __global__ void __launch_bounds__(256) k_dm_channel_tile(ChannelTileArgs a) {
       __syncthreads();
     }
 #pragma unroll
-    for (int k = 0; k < 16; k++) {
+    for (int k = 0; k < EPT; k++) {
       const uint64_t g = lb | koff[k];
-      const double2 v = lds[tid + 256 * k];
+      const double2 v = lds[tid + NT * k];
       re[g] = (T)v.x;
       im[g] = (T)v.y;
     }
@@ -1519,24 +1525,28 @@ hipError_t svk_launch_dm_channel16(int dbl, void *re, void *im, int nq, int q0, 
 
 hipError_t svk_launch_dm_channel_tile(int dbl, void *re, void *im, int nq, int off,
                                       const int *qubits, int k, const double *s32, hipStream_t s) {
-  if (nq < 12 || k < 1 || k > 4) return hipErrorInvalidValue;
+  const int TB = k == 5 ? 13 : 12;
+  if (nq < TB || k < 1 || k > 5) return hipErrorInvalidValue;
   ChannelTileArgs a;
   a.re = re; a.im = im;
-  a.tiles = 1ll << (nq - 12);
+  a.tiles = 1ll << (nq - TB);
   a.k = k;
   uint64_t used = 0;
   for (int i = 0; i < k; i++) used |= (1ull << qubits[i]) | (1ull << (qubits[i] + off));
-  int np = 0;
-  for (int b = 0; b < nq && np < 12 - 2 * k; b++)
-    if (!(used >> b & 1)) a.pos[np++] = b;
-  int chan[8], nc = 0;
+  int chan[10], nc = 0;
   for (int b = 0; b < nq; b++)
     if (used >> b & 1) chan[nc++] = b;
+  if (nc != 2 * k) return hipErrorInvalidValue;   // the qubits must be distinct
+  int np = 0;
+  for (int b = 0; b < nq && np < TB - nc; b++)
+    if (!(used >> b & 1)) a.pos[np++] = b;
+  if (np + nc != TB) return hipErrorInvalidValue;
   for (int j = 0; j < nc; j++) a.pos[np + j] = chan[j];
-  std::sort(a.pos, a.pos + 12);   // lanes run over the lowest of the tile's vector bits
-  for (int j = 0; j < 12; j++) a.sorted[j] = a.pos[j];
+  std::sort(a.pos, a.pos + TB);   // lanes run over the lowest of the tile's vector bits
+  for (int j = 0; j < TB; j++) a.sorted[j] = a.pos[j];
+  for (int j = TB; j < 13; j++) a.pos[j] = a.sorted[j] = 0;
   for (int i = 0; i < k; i++)
-    for (int j = 0; j < 12; j++) {
+    for (int j = 0; j < TB; j++) {
       if (a.pos[j] == qubits[i]) a.ci[i] = j;
       if (a.pos[j] == qubits[i] + off) a.ri[i] = j;
     }
@@ -1546,8 +1556,13 @@ hipError_t svk_launch_dm_channel_tile(int dbl, void *re, void *im, int nq, int o
     if ((i & 1) && s32[i] != 0.0) a.real = 0;
   }
   const int grid = (int)std::min<int64_t>(a.tiles, 8192);
-  if (dbl) hipLaunchKernelGGL(k_dm_channel_tile<double>, dim3(grid), dim3(256), 0, s, a);
-  else hipLaunchKernelGGL(k_dm_channel_tile<float>, dim3(grid), dim3(256), 0, s, a);
+  if (TB == 13) {
+    if (dbl) hipLaunchKernelGGL((k_dm_channel_tile<double, 13>), dim3(grid), dim3(1024), 0, s, a);
+    else hipLaunchKernelGGL((k_dm_channel_tile<float, 13>), dim3(grid), dim3(1024), 0, s, a);
+  } else {
+    if (dbl) hipLaunchKernelGGL((k_dm_channel_tile<double, 12>), dim3(grid), dim3(256), 0, s, a);
+    else hipLaunchKernelGGL((k_dm_channel_tile<float, 12>), dim3(grid), dim3(256), 0, s, a);
+  }
   return hipGetLastError();
 }
 

@@ -126,10 +126,11 @@ def _channel_2q(T, n, q0, q1, kraus):
 def test_dm_13_qubits_grid_stride(sv, dtype):
     """rho of 13 qubits (a 26-qubit vector: 16384 tiles of the four-channel
     pass, several grid-stride rounds of the single-channel pass) from the
-    oracle's pure state, seven one-qubit channels with a real superoperator
-    (four-, two- and single-channel passes), five with a complex one (a
-    four-channel and a single-channel pass) and a two-qubit channel, against
-    tensor contractions of the superoperators; Tr(rho) = 1 and Tr(rho Z_i)."""
+    oracle's pure state, one-qubit channels through every tile form (seven
+    with a real superoperator: 12-bit tiles of four and three channels; five
+    with a complex one and five more with a real one: 13-bit tiles of five),
+    a single channel and a two-qubit channel, against tensor contractions of
+    the superoperators; Tr(rho) = 1 and Tr(rho Z_i)."""
     n = 13
     _say("density matrix 13 qubits", dtype)
     c = I.layered(n, 2, seed=3)
@@ -140,6 +141,9 @@ def test_dm_13_qubits_grid_stride(sv, dtype):
     C1 = _mixed_unitaries_1q(7)
     for q in range(7, 12):
         T = _channel_1q(T, n, q, C1)
+    for q in range(8, 13):
+        T = _channel_1q(T, n, q, _depolarizing(0.03))
+    T = _channel_1q(T, n, 12, _damping(0.2))
     K2 = _mixed_unitaries(5)
     T = _channel_2q(T, n, 3, 9, K2)
     want = T.reshape(-1)
@@ -149,6 +153,8 @@ def test_dm_13_qubits_grid_stride(sv, dtype):
         st.dm_apply(c.ops, c.params)
         st.dm_apply_kraus(list(range(7)), _depolarizing(0.05))
         st.dm_apply_kraus(list(range(7, 12)), C1)
+        st.dm_apply_kraus(list(range(8, 13)), _depolarizing(0.03))
+        st.dm_apply_kraus(12, _damping(0.2))
         st.dm_apply_kraus2(3, 9, K2)
         got = st.to_numpy()
         scale = float(np.max(np.abs(want)))

@@ -943,18 +943,51 @@ __global__ void __launch_bounds__(TB == 13 ? 1024 : 256) k_dm_channel_tile(Chann
 #pragma unroll
     for (int j = 0; j < KB; j++) koff[k] |= (uint64_t)((k >> j) & 1) << a.pos[LT + j];
   }
-  for (int64_t t = blockIdx.x; t < a.tiles; t += gridDim.x) {
+  auto tile_base = [&](int64_t t) {
     uint64_t base = (uint64_t)t;
 #pragma unroll
     for (int j = 0; j < TB; j++)
       base = ((base >> a.sorted[j]) << (a.sorted[j] + 1)) | (base & ((1ull << a.sorted[j]) - 1));
-    const uint64_t lb = base | loff;
+    return base | loff;
+  };
+  // With one 13-bit tile per CU no other tile's work hides the loads, so the
+  // next tile is fetched into registers while this one's channels run; two
+  // 12-bit tiles per CU overlap each other instead.
+  constexpr bool PRE = TB == 13;
+  T pr[PRE ? EPT : 1], pim[PRE ? EPT : 1];
+  if constexpr (PRE) {
+    if (blockIdx.x < a.tiles) {
+      const uint64_t lb = tile_base(blockIdx.x);
+#pragma unroll
+      for (int k = 0; k < EPT; k++) {
+        pr[k] = re[lb | koff[k]];
+        pim[k] = im[lb | koff[k]];
+      }
+    }
+  }
+  for (int64_t t = blockIdx.x; t < a.tiles; t += gridDim.x) {
+    const uint64_t lb = tile_base(t);
 #pragma unroll
     for (int k = 0; k < EPT; k++) {
-      const uint64_t g = lb | koff[k];
-      lds[tid + NT * k] = make_double2((double)re[g], (double)im[g]);
+      if constexpr (PRE) {
+        lds[tid + NT * k] = make_double2((double)pr[k], (double)pim[k]);
+      } else {
+        const uint64_t g = lb | koff[k];
+        lds[tid + NT * k] = make_double2((double)re[g], (double)im[g]);
+      }
     }
     __syncthreads();
+    if constexpr (PRE) {
+      const int64_t tn = t + gridDim.x;
+      if (tn < a.tiles) {
+        const uint64_t lbn = tile_base(tn);
+#pragma unroll
+        for (int k = 0; k < EPT; k++) {
+          pr[k] = re[lbn | koff[k]];
+          pim[k] = im[lbn | koff[k]];
+        }
+      }
+    }
     for (int i = 0; i < a.k; i++) {
       const int c = a.ci[i], r = a.ri[i];
       const int lo = c < r ? c : r, hi = c < r ? r : c;

@@ -1588,11 +1588,18 @@ hipError_t svk_launch_dm_channel_tile(int dbl, void *re, void *im, int nq, int o
     a.s[i] = s32[i];
     if ((i & 1) && s32[i] != 0.0) a.real = 0;
   }
-  const int grid = (int)std::min<int64_t>(a.tiles, 8192);
   if (TB == 13) {
+    // one persistent workgroup per CU, each walking its tiles with the
+    // register prefetch
+    int dev = 0, cus = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e != hipSuccess) return e;
+    const int grid = (int)std::min<int64_t>(a.tiles, std::max(cus, 1));
     if (dbl) hipLaunchKernelGGL((k_dm_channel_tile<double, 13>), dim3(grid), dim3(1024), 0, s, a);
     else hipLaunchKernelGGL((k_dm_channel_tile<float, 13>), dim3(grid), dim3(1024), 0, s, a);
   } else {
+    const int grid = (int)std::min<int64_t>(a.tiles, 8192);
     if (dbl) hipLaunchKernelGGL((k_dm_channel_tile<double, 12>), dim3(grid), dim3(256), 0, s, a);
     else hipLaunchKernelGGL((k_dm_channel_tile<float, 12>), dim3(grid), dim3(256), 0, s, a);
   }

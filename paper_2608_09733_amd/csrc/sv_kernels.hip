@@ -364,7 +364,8 @@ __device__ __forceinline__ void wht_regs(double (&v)[N]) {
       }
 }
 
-template <typename T, int M>
+// LAM: the pass also builds (or adds into) lambda = sum_j c_j P_j psi.
+template <typename T, int M, bool LAM>
 __global__ void __launch_bounds__(SVI_PAULI_NT) k_pauli(PauliPassArgs a) {
   constexpr int NT = SVI_PAULI_NT;
   constexpr int EPT = (1 << M) / NT;   // elements per thread: i = tid + k * NT
@@ -455,14 +456,34 @@ __global__ void __launch_bounds__(SVI_PAULI_NT) k_pauli(PauliPassArgs a) {
       for (int q = 0; q < EPT; q++)
         if (zk == (uint32_t)q) {
           acc = pn[q];
-          if (lre) zs[q] += sneg ? -pt.c : pt.c;
+          if constexpr (LAM) zs[q] += sneg ? -pt.c : pt.c;
         }
       put(t, sneg ? -acc : acc);
     }
-    if (lre) wht_regs<EPT>(zs);
-    // terms with an X / Y part: partner amplitudes from LDS
+    if constexpr (LAM) wht_regs<EPT>(zs);
+    // terms with an X / Y part: partner amplitudes from LDS; the thread's own
+    // amplitudes are kept in registers when no lambda is built (its
+    // accumulators' registers are free then), else re-read from LDS
+    T ownr[LAM ? 1 : EPT], owni[LAM ? 1 : EPT];
+    if constexpr (!LAM) {
+#pragma unroll
+      for (int k = 0; k < EPT; k++) {
+        const int i = tid + k * NT;
+        ownr[k] = 0;
+        owni[k] = 0;
+        if (i < nel) {
+          const C2 pb = lds[swz<T>(i)];
+          ownr[k] = pb.x;
+          owni[k] = pb.y;
+        }
+      }
+    }
+    auto own = [&](int k, int i) -> C2 {
+      if constexpr (LAM) return lds[swz<T>(i)];
+      else return C2{ownr[k], owni[k]};
+    };
     T lr[EPT], li[EPT];
-    if (lre) {
+    if constexpr (LAM) {
 #pragma unroll
       for (int k = 0; k < EPT; k++) {
         const int i = tid + k * NT;
@@ -492,11 +513,11 @@ __global__ void __launch_bounds__(SVI_PAULI_NT) k_pauli(PauliPassArgs a) {
         for (int k = 0; k < EPT; k++) {
           const int i = tid + k * NT;
           if (i < nel) {
-            const C2 pb = lds[swz<T>(i)];
+            const C2 pb = own(k, i);
             const C2 pp = lds[swz<T>(i ^ (int)xl)];
             const double ur = (double)pp.x, ui = (double)pp.y;
             sr += ur * (double)pb.x + ui * (double)pb.y;
-            if (lre) {
+            if constexpr (LAM) {
               lr[k] += (T)(cs * ur);
               li[k] += (T)(cs * ui);
             }
@@ -510,7 +531,7 @@ __global__ void __launch_bounds__(SVI_PAULI_NT) k_pauli(PauliPassArgs a) {
       for (int k = 0; k < EPT; k++) {
         const int i = tid + k * NT;
         if (i < nel) {
-          const C2 pb = lds[swz<T>(i)];
+          const C2 pb = own(k, i);
           const C2 pp = lds[swz<T>(i ^ (int)xl)];
           // t1 = conj(psi_{b^x}) * i^ny * s(b) * psi_b
           double wr = (double)pb.x, wi = (double)pb.y, tr, ti;
@@ -523,7 +544,7 @@ __global__ void __launch_bounds__(SVI_PAULI_NT) k_pauli(PauliPassArgs a) {
           const bool neg = bneg ^ (bool)(__builtin_popcount((uint32_t)i & zl) & 1);
           if (neg) { tr = -tr; ti = -ti; }
           acc += (double)pp.x * tr + (double)pp.y * ti;   // Re(conj(pp) * t)
-          if (lre) {
+          if constexpr (LAM) {
             // (P psi)[b] = i^ny (-1)^{popcount((b^x) & z)} psi[b^x]
             double ur = (double)pp.x, ui = (double)pp.y, vr, vi;
             switch (ny) {
@@ -547,7 +568,7 @@ __global__ void __launch_bounds__(SVI_PAULI_NT) k_pauli(PauliPassArgs a) {
       for (int w = 0; w < NWAVE; w++) v += wsum[w][t];
       tacc[t] += v;
     }
-    if (lre) {
+    if constexpr (LAM) {
 #pragma unroll
       for (int k = 0; k < EPT; k++) {
         const int i = tid + k * NT;
@@ -1487,9 +1508,12 @@ hipError_t svk_launch_coefs(const CoefDesc *d, int nd, const double *params, con
 }
 
 hipError_t svk_launch_pauli(int dbl, int M, const PauliPassArgs &a, int grid, hipStream_t s) {
-  if (dbl && M == 13) hipLaunchKernelGGL((k_pauli<double, 13>), dim3(grid), dim3(SVI_PAULI_NT), 0, s, a);
-  else if (!dbl && M == 13) hipLaunchKernelGGL((k_pauli<float, 13>), dim3(grid), dim3(SVI_PAULI_NT), 0, s, a);
-  else return hipErrorInvalidValue;
+  if (M != 13) return hipErrorInvalidValue;
+  const bool lam = a.lre != nullptr;
+  if (dbl && lam) hipLaunchKernelGGL((k_pauli<double, 13, true>), dim3(grid), dim3(SVI_PAULI_NT), 0, s, a);
+  else if (dbl) hipLaunchKernelGGL((k_pauli<double, 13, false>), dim3(grid), dim3(SVI_PAULI_NT), 0, s, a);
+  else if (lam) hipLaunchKernelGGL((k_pauli<float, 13, true>), dim3(grid), dim3(SVI_PAULI_NT), 0, s, a);
+  else hipLaunchKernelGGL((k_pauli<float, 13, false>), dim3(grid), dim3(SVI_PAULI_NT), 0, s, a);
   return hipGetLastError();
 }
 
@@ -1507,8 +1531,8 @@ hipError_t svk_launch_pauli_wide(int dbl, const void *re, const void *im, void *
 
 int svk_pauli_occupancy(int dbl) {
   int nb = 0;
-  hipError_t e = dbl ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_pauli<double, 13>, SVI_PAULI_NT, 0)
-                     : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_pauli<float, 13>, SVI_PAULI_NT, 0);
+  hipError_t e = dbl ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_pauli<double, 13, true>, SVI_PAULI_NT, 0)
+                     : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_pauli<float, 13, true>, SVI_PAULI_NT, 0);
   return (e == hipSuccess && nb > 0) ? nb : 1;
 }
 

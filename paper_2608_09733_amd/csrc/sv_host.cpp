@@ -1987,9 +1987,15 @@ struct PauliPlan {
 // the streaming kernel; with lambda output every term takes the tile passes.
 static bool diag_stream(int n, bool lambda) { return !lambda && n >= 14; }
 
+// Tile bits of the state-vector Pauli passes: 12-bit tiles, two workgroups
+// per CU, so one workgroup's loads and stores overlap the other's term work
+// (13-bit tiles, one per CU, serialised them); the batch kernel's passes run
+// in its 13-bit tiles.
+#define SVI_PAULI_M 12
+
 static void plan_pauli(int n, const sv_pauli_term *terms, int nt, PauliPlan &pp,
-                       bool stream_diag = false) {
-  const int M = std::min(13, n);
+                       bool stream_diag = false, int tile_bits = 13) {
+  const int M = std::min(tile_bits, n);
   const int c = std::min(3, n);
   const uint64_t low = (1ull << c) - 1;
   struct Open { uint64_t U; std::vector<int> ids; };
@@ -2067,7 +2073,7 @@ static sv_status run_pauli(sv_state *st, const sv_pauli_term *terms, int nt, voi
                            void *lre, void *lim, double **d_terms_out, void *ext = nullptr,
                            size_t ext_bytes = 0) {
   PauliPlan pp;
-  plan_pauli(st->n, terms, nt, pp, diag_stream(st->n, lre != nullptr));
+  plan_pauli(st->n, terms, nt, pp, diag_stream(st->n, lre != nullptr), SVI_PAULI_M);
   DevInfo di;
   sv_status s = device_info(di);
   if (s) return s;
@@ -2121,10 +2127,10 @@ static sv_status run_pauli(sv_state *st, const sv_pauli_term *terms, int nt, voi
     a.t_begin = ps.t0; a.t_end = ps.t1;
     a.accumulate = p > 0;
     a.ntiles = (int64_t)1 << (st->n - ps.m);
-    if (ps.m > 13 || ps.m > st->n) return fail(SV_EINVAL, "internal: Pauli tile of %d bits", ps.m);
+    if (ps.m > SVI_PAULI_M || ps.m > st->n) return fail(SV_EINVAL, "internal: Pauli tile of %d bits", ps.m);
     int64_t g = std::min<int64_t>(grid_max, a.ntiles);
     a.part = d_part + (size_t)ps.t0 * grid_part;
-    hipError_t e = svk_launch_pauli(dbl, 13, a, (int)g, st->stream);
+    hipError_t e = svk_launch_pauli(dbl, SVI_PAULI_M, a, (int)g, st->stream);
     if (e != hipSuccess) return fail(SV_EDEVICE, "pauli kernel: %s", hipGetErrorString(e));
     e = svk_launch_reduce_rows(a.part, ps.t1 - ps.t0, (int)g, d_red + ps.t0, st->stream);
     if (e != hipSuccess) return fail(SV_EDEVICE, "reduce kernel: %s", hipGetErrorString(e));
@@ -2153,7 +2159,7 @@ static sv_status run_pauli(sv_state *st, const sv_pauli_term *terms, int nt, voi
 static void pauli_order(int n, const sv_pauli_term *terms, int nt, std::vector<int> &order,
                         bool lambda) {
   PauliPlan pp;
-  plan_pauli(n, terms, nt, pp, diag_stream(n, lambda));
+  plan_pauli(n, terms, nt, pp, diag_stream(n, lambda), SVI_PAULI_M);
   order.clear();
   for (auto &t : pp.terms) order.push_back(t.term);
 }

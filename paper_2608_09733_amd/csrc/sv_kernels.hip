@@ -332,9 +332,6 @@ __global__ void k_build_coefs(const CoefDesc *d, int nd, const double *params, c
 // P|b> = i^{nY} (-1)^{popcount(b & z)} |b ^ x>).
 
 #define SVI_PTERMS 64
-// 1024 threads: 16 waves per CU hold the one 128 KiB tile a CU fits, so the
-// tile's loads and the per-term sums have enough waves in flight
-#define SVI_PAULI_NT 1024
 
 // Term t, read through the constant address space (uniform index: scalar
 // loads instead of vector loads and their waits inside the tile loop).
@@ -365,9 +362,10 @@ __device__ __forceinline__ void wht_regs(double (&v)[N]) {
 }
 
 // LAM: the pass also builds (or adds into) lambda = sum_j c_j P_j psi.
+// Eight elements per thread: 1024 threads for a 13-bit tile, 512 for 12.
 template <typename T, int M, bool LAM>
-__global__ void __launch_bounds__(SVI_PAULI_NT) k_pauli(PauliPassArgs a) {
-  constexpr int NT = SVI_PAULI_NT;
+__global__ void __launch_bounds__((1 << M) / 8) k_pauli(PauliPassArgs a) {
+  constexpr int NT = (1 << M) / 8;
   constexpr int EPT = (1 << M) / NT;   // elements per thread: i = tid + k * NT
   constexpr int NWAVE = NT / 64;
   using C2 = typename C2T<T>::type;
@@ -1508,12 +1506,13 @@ hipError_t svk_launch_coefs(const CoefDesc *d, int nd, const double *params, con
 }
 
 hipError_t svk_launch_pauli(int dbl, int M, const PauliPassArgs &a, int grid, hipStream_t s) {
-  if (M != 13) return hipErrorInvalidValue;
+  if (M != 12) return hipErrorInvalidValue;
   const bool lam = a.lre != nullptr;
-  if (dbl && lam) hipLaunchKernelGGL((k_pauli<double, 13, true>), dim3(grid), dim3(SVI_PAULI_NT), 0, s, a);
-  else if (dbl) hipLaunchKernelGGL((k_pauli<double, 13, false>), dim3(grid), dim3(SVI_PAULI_NT), 0, s, a);
-  else if (lam) hipLaunchKernelGGL((k_pauli<float, 13, true>), dim3(grid), dim3(SVI_PAULI_NT), 0, s, a);
-  else hipLaunchKernelGGL((k_pauli<float, 13, false>), dim3(grid), dim3(SVI_PAULI_NT), 0, s, a);
+  const dim3 blk((1 << 12) / 8);
+  if (dbl && lam) hipLaunchKernelGGL((k_pauli<double, 12, true>), dim3(grid), blk, 0, s, a);
+  else if (dbl) hipLaunchKernelGGL((k_pauli<double, 12, false>), dim3(grid), blk, 0, s, a);
+  else if (lam) hipLaunchKernelGGL((k_pauli<float, 12, true>), dim3(grid), blk, 0, s, a);
+  else hipLaunchKernelGGL((k_pauli<float, 12, false>), dim3(grid), blk, 0, s, a);
   return hipGetLastError();
 }
 
@@ -1531,8 +1530,8 @@ hipError_t svk_launch_pauli_wide(int dbl, const void *re, const void *im, void *
 
 int svk_pauli_occupancy(int dbl) {
   int nb = 0;
-  hipError_t e = dbl ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_pauli<double, 13, true>, SVI_PAULI_NT, 0)
-                     : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_pauli<float, 13, true>, SVI_PAULI_NT, 0);
+  hipError_t e = dbl ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_pauli<double, 12, true>, (1 << 12) / 8, 0)
+                     : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_pauli<float, 12, true>, (1 << 12) / 8, 0);
   return (e == hipSuccess && nb > 0) ? nb : 1;
 }
 

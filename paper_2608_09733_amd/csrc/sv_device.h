@@ -1032,8 +1032,12 @@ __global__ void __launch_bounds__(1 << (M - R)) k_sweep_kron(SweepArgs a) {
 
     while (true) {
       const uint64_t base = tile_base(tile, c, hb_s, nh);
+      // From |0..0> only tile 0 holds a nonzero amplitude, and a sweep's
+      // gates act within tiles, so every other tile stays zero: it skips the
+      // stages and is written as zeros (uniform over the workgroup).
+      const bool live = !I0 || tile == 0;
       // ---- stages
-      for (int st = 0; st < nst; st++) {
+      for (int st = 0; live && st < nst; st++) {
         const SVI_CONST StageDesc &sd = stages[st];
         const int gbs =
             (st < ntab ? (int)gtab[st * NT + tid] : swz<T>(stage_base<M, R>(tid, sd))) * (int)sizeof(C2);
@@ -1076,19 +1080,31 @@ __global__ void __launch_bounds__(1 << (M - R)) k_sweep_kron(SweepArgs a) {
       // ---- LDS to HBM
       opaque(ssl_p);
       opaque(loff_p);
+      if (live) {
 #pragma unroll
-      for (int k = 0; k < G; k++) {
-        if (FULL || tid + k * NT < ntile_el) {
-          const C2 p = lds[slot(ssl_p, ssb, k)];
-          const uint64_t g = base + goff(k);
-          pre[g] = p.x;
-          pim[g] = p.y;
+        for (int k = 0; k < G; k++) {
+          if (FULL || tid + k * NT < ntile_el) {
+            const C2 p = lds[slot(ssl_p, ssb, k)];
+            const uint64_t g = base + goff(k);
+            pre[g] = p.x;
+            pim[g] = p.y;
+          }
+        }
+      } else {
+#pragma unroll
+        for (int k = 0; k < G; k++) {
+          if (FULL || tid + k * NT < ntile_el) {
+            const uint64_t g = base + goff(k);
+            pre[g] = (T)0;
+            pim[g] = (T)0;
+          }
         }
       }
       lds_barrier();
       if (next >= a.ntiles) break;
-      // ---- next tile into LDS, then the prefetch of the one after
-      tile_in(next);
+      // ---- next tile into LDS (a synthesised sweep's later tiles are zero:
+      // nothing to stage), then the prefetch of the one after
+      if (!I0) tile_in(next);
       lds_barrier();
       r0 += gridDim.x;
       tile = next;
@@ -1155,6 +1171,31 @@ __device__ void sweep_tiles(const SVI_CONST SweepArgs &a, int64_t t0, int64_t t1
 
   for (int64_t tile = t0; tile < t1; tile++) {
     const uint64_t base = tile_base(tile, c, hb, nh);
+    if (init0 && base != 0) {
+      // From |0..0> every tile but the one holding index 0 stays zero (a
+      // sweep's gates act within tiles): it is written as zeros, with no
+      // stages and no LDS (uniform over the workgroup)
+      if (vec) {
+        V4 z;
+        if constexpr (VN == 2) z = V4{(T)0, (T)0};
+        else z = V4{(T)0, (T)0, (T)0, (T)0};
+#pragma unroll
+        for (int k = 0; k < NIT; k++) {
+          const int i = (tid + k * NT) * VN;
+          if (i < ntile_el) {
+            *(V4 *)(pre + base + roff[k]) = z;
+            *(V4 *)(pim + base + roff[k]) = z;
+          }
+        }
+      } else {
+        for (int i = tid; i < ntile_el; i += NT) {
+          const uint64_t g = base + spread_row(i >> c, hb, nh) + (uint64_t)(i & ((1 << c) - 1));
+          pre[g] = (T)0;
+          pim[g] = (T)0;
+        }
+      }
+      continue;
+    }
     if (mm > m) {
       // tiles smaller than one register group: padding slots hold zeros
       for (int i = tid; i < (1 << mm); i += NT) lt[swz<T>(i)] = C2{0, 0};
@@ -1259,6 +1300,9 @@ __device__ void sweep_tiles(const SVI_CONST SweepArgs &a, int64_t t0, int64_t t1
     }
     __syncthreads();
   }
+  // a zero tile ends without the barrier above, and a caller's next sweep
+  // starts by rewriting hb, which the last tiles' addresses were read from
+  if (init0) __syncthreads();
 }
 
 // ------------------------------------------- two-state Kronecker stage

@@ -561,7 +561,12 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(),
                      "kernel": f"svk::k_sweep_kron<double,{tiling[0]},{tiling[2]}> (tile sweep)",
                      "bytes_per_launch": bytes_per_launch, "avg_launch_ms": avg_launch_ms,
-                     "launches": launches},
+                     "launches": launches,
+                     # every sweep over every tile (the first one only writing)
+                     "bytes_per_launch_dense": (2 + 4 * (sweeps - 1)) * 8.0 * (1 << n) / sweeps,
+                     "note": "from |0..0> the sweeps after the first run only the tiles on the "
+                             "support reached so far (the others are zero before and after); "
+                             "bytes_per_launch counts what the launches moved"},
     }
     extras = {}
     # whole-path HBM efficiency: counted sweep bytes / step time

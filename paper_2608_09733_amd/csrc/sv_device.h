@@ -966,6 +966,12 @@ __global__ void __launch_bounds__(1 << (M - R)) k_sweep_kron(SweepArgs a) {
   };
   T *const pre = (T *)a.re, *const pim = (T *)a.im;
   char *const lb = (char *)lds;
+  // tile t's base: t's bits deposited on the qubits outside the tile (for a
+  // sparse sweep, on those of them inside the support only)
+  const bool sparse = (a.flags & SW_SPARSE) != 0;
+  auto tbase = [&](int64_t t) {
+    return sparse ? tile_base(t, c, a.bz, a.nbz) : tile_base(t, c, hb_s, nh);
+  };
   // The per-lane bases are re-declared opaque before each phase, so the
   // compiler recomputes the (cheap) per-element addresses next to their use
   // instead of hoisting all of them out of the tile loop and spilling them:
@@ -990,7 +996,7 @@ __global__ void __launch_bounds__(1 << (M - R)) k_sweep_kron(SweepArgs a) {
     constexpr bool FULL = decltype(full)::value;
     T nr[G], ni[G];
     auto fetch = [&](int64_t t) {
-      const uint64_t b0 = tile_base(t, c, hb_s, nh);
+      const uint64_t b0 = tbase(t);
 #pragma unroll
       for (int k = 0; k < G; k++) {
         const uint64_t g = b0 + goff(k);
@@ -1031,7 +1037,7 @@ __global__ void __launch_bounds__(1 << (M - R)) k_sweep_kron(SweepArgs a) {
     }
 
     while (true) {
-      const uint64_t base = tile_base(tile, c, hb_s, nh);
+      const uint64_t base = tbase(tile);
       // From |0..0> only tile 0 holds a nonzero amplitude, and a sweep's
       // gates act within tiles, so every other tile stays zero: it skips the
       // stages and is written as zeros (uniform over the workgroup).

@@ -1897,6 +1897,13 @@ static sv_status run_steps(sv_state *st, Plan &P, void *re, void *im, void *re2,
   const bool dbl = st->dtype == SV_C128;
   int occ = svk_sweep_occupancy(dbl, P.M, P.R, P.NS);
   int occk = svk_sweep_kron_occupancy(dbl, P.M, P.R, P.NS);
+  // From |0..0>, the qubits that may be 1 in a nonzero amplitude: the union
+  // of the tiles of the sweeps so far (a sweep's gates act within its tile,
+  // and a remapping sweep permutes qubits within its tile).  Tracked while
+  // every step is a sweep of the lean kernel.
+  bool track = fuse_zero && P.NS == 1;
+  uint64_t support = 0;
+  const uint64_t all = st->n >= 64 ? ~0ull : (1ull << st->n) - 1;
   for (Step &stp : P.steps) {
     if (stp.kind == 0) {
       SweepArgs a = stp.sa;
@@ -1909,6 +1916,22 @@ static sv_status run_steps(sv_state *st, Plan &P, void *re, void *im, void *re2,
       // the two-state lean kernel takes gradient terms over whole register
       // groups, so it needs tiles at least one group wide
       const bool lean = stp.all_kron && occk > 0 && (P.NS == 1 || stp.sa.m >= P.R);
+      if (track && !lean) track = false;
+      if (track) {
+        uint64_t tile = (1ull << a.c) - 1;
+        for (int k = 0; k < a.nh; k++) tile |= 1ull << a.hb[k];
+        const uint64_t zero = all & ~tile & ~support;
+        if (!(a.flags & SW_INIT_ZERO) && zero) {
+          // bases take zeros at the tile's high bits and at the qubits off
+          // the support (ascending; the low bits are below the tile index)
+          a.flags |= SW_SPARSE;
+          a.nbz = 0;
+          for (int q = a.c; q < st->n; q++)
+            if (((tile | zero) >> q) & 1) a.bz[a.nbz++] = q;
+          a.ntiles = (int64_t)1 << (st->n - a.m - __builtin_popcountll(zero));
+        }
+        support |= tile;
+      }
       int64_t g = (int64_t)di.cus * (lean ? occk : occ);
       if (grid_override > 0) g = grid_override;
       if (g > a.ntiles) g = a.ntiles;
@@ -1924,11 +1947,13 @@ static sv_status run_steps(sv_state *st, Plan &P, void *re, void *im, void *re2,
       if (a.flags & SW_INIT_ZERO) st->pending_zero = false;
       if (e0 && e1) {
         (void)hipEventRecord(e1, st->stream);
-        // read + write of both planes; a sweep that synthesises |0..0> only writes
+        // read + write of both planes over the tiles run; a sweep that
+        // synthesises |0..0> only writes
         const double planes_rw = (a.flags & SW_INIT_ZERO) ? 2.0 : 4.0;
-        st->ev_bytes.push_back(planes_rw * (double)((int64_t)1 << st->n) * (double)elem_size(st->dtype));
+        st->ev_bytes.push_back(planes_rw * (double)(a.ntiles << a.m) * (double)elem_size(st->dtype));
       }
     } else {
+      track = false;
       GateArgsHost a = stp.ga;
       a.re = re; a.im = im;
       a.coef = P.d_coef + (stp.gate_coef < 0 ? 0 : stp.gate_coef);

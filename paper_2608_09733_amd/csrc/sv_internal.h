@@ -139,10 +139,18 @@ struct SweepArgs {
   int32_t gslot_begin, n_gslots;  // adjoint: gradient slots used by this sweep
   int64_t ntiles;
   int32_t operm[SVI_MMAX];   // SW_OPERM: output tile bit k takes LDS tile bit operm[k]
+  int32_t nbz;               // SW_SPARSE: tile bases take zeros at bz[0..nbz) (ascending):
+  int32_t bz[32];            //   the tile's high bits and the qubits still outside the support
 };
 
 #define SW_INIT_ZERO 1       // synthesise |0..0> instead of loading state 0
 #define SW_OPERM 2           // permute tile bits on the way out (qubit remapping)
+// A sweep of a state evolved from |0..0> by earlier sweeps only: amplitudes
+// are nonzero only where every qubit outside the earlier sweeps' tiles is 0
+// (a sweep's gates act within tiles), so only the tiles whose outside qubits
+// off that support are 0 are run (ntiles of them, bases from bz); the others
+// hold zeros in memory, before and after.
+#define SW_SPARSE 4
 
 // Coefficient descriptors (built on the device from the parameter vector).
 enum {

@@ -1175,8 +1175,20 @@ __device__ void sweep_tiles(const SVI_CONST SweepArgs &a, int64_t t0, int64_t t1
   const int tsw = swz<T>(tid * VN);
   char *const lb = (char *)lt;
 
+  // tile bases: a sparse sweep deposits the tile index on the support's
+  // qubits outside the tile only (bz, read from the descriptor)
+  const bool sparse = (a.flags & SW_SPARSE) != 0;
   for (int64_t tile = t0; tile < t1; tile++) {
-    const uint64_t base = tile_base(tile, c, hb, nh);
+    uint64_t base;
+    if (sparse) {
+      base = (uint64_t)tile << c;
+      for (int k = 0; k < a.nbz; k++) {
+        const int p = a.bz[k];
+        base = ((base >> p) << (p + 1)) | (base & ((1ull << p) - 1ull));
+      }
+    } else {
+      base = tile_base(tile, c, hb, nh);
+    }
     if (init0 && base != 0) {
       // From |0..0> every tile but the one holding index 0 stays zero (a
       // sweep's gates act within tiles): it is written as zeros, with no

@@ -1880,6 +1880,29 @@ static sv_status upload_call_data(sv_state *st, Plan &P, const sv_op *ops, int n
 
 static sv_status materialize_zero(sv_state *st);
 
+// A tile sweep of a state evolved from |0..0> by earlier sweeps only, whose
+// tiles so far cover the qubits in *support: it runs only the tiles whose
+// qubits off the support are 0 (SW_SPARSE, bases from bz), since the others
+// hold zeros before and after (a sweep's gates, and a remapping sweep's
+// output permutation, act within its tile).  Adds the sweep's tile to the
+// support.  The first sweep (SW_INIT_ZERO) runs every tile.
+static void restrict_to_support(SweepArgs &a, int n, uint64_t *support) {
+  const uint64_t all = n >= 64 ? ~0ull : (1ull << n) - 1;
+  uint64_t tile = (1ull << a.c) - 1;
+  for (int k = 0; k < a.nh; k++) tile |= 1ull << a.hb[k];
+  const uint64_t zero = all & ~tile & ~*support;
+  if (!(a.flags & SW_INIT_ZERO) && zero) {
+    // bases take zeros at the tile's high bits and at the qubits off the
+    // support (ascending; the low bits are below the tile index)
+    a.flags |= SW_SPARSE;
+    a.nbz = 0;
+    for (int q = a.c; q < n; q++)
+      if (((tile | zero) >> q) & 1) a.bz[a.nbz++] = q;
+    a.ntiles = (int64_t)1 << (n - a.m - __builtin_popcountll(zero));
+  }
+  *support |= tile;
+}
+
 static sv_status run_steps(sv_state *st, Plan &P, void *re, void *im, void *re2, void *im2,
                            double *gpart, int grid_override) {
   DevInfo di;
@@ -1897,13 +1920,10 @@ static sv_status run_steps(sv_state *st, Plan &P, void *re, void *im, void *re2,
   const bool dbl = st->dtype == SV_C128;
   int occ = svk_sweep_occupancy(dbl, P.M, P.R, P.NS);
   int occk = svk_sweep_kron_occupancy(dbl, P.M, P.R, P.NS);
-  // From |0..0>, the qubits that may be 1 in a nonzero amplitude: the union
-  // of the tiles of the sweeps so far (a sweep's gates act within its tile,
-  // and a remapping sweep permutes qubits within its tile).  Tracked while
-  // every step is a sweep of the lean kernel.
+  // From |0..0>, the qubits that may be 1 in a nonzero amplitude, tracked
+  // while every step is a sweep of the lean kernel.
   bool track = fuse_zero && P.NS == 1;
   uint64_t support = 0;
-  const uint64_t all = st->n >= 64 ? ~0ull : (1ull << st->n) - 1;
   for (Step &stp : P.steps) {
     if (stp.kind == 0) {
       SweepArgs a = stp.sa;
@@ -1917,21 +1937,7 @@ static sv_status run_steps(sv_state *st, Plan &P, void *re, void *im, void *re2,
       // groups, so it needs tiles at least one group wide
       const bool lean = stp.all_kron && occk > 0 && (P.NS == 1 || stp.sa.m >= P.R);
       if (track && !lean) track = false;
-      if (track) {
-        uint64_t tile = (1ull << a.c) - 1;
-        for (int k = 0; k < a.nh; k++) tile |= 1ull << a.hb[k];
-        const uint64_t zero = all & ~tile & ~support;
-        if (!(a.flags & SW_INIT_ZERO) && zero) {
-          // bases take zeros at the tile's high bits and at the qubits off
-          // the support (ascending; the low bits are below the tile index)
-          a.flags |= SW_SPARSE;
-          a.nbz = 0;
-          for (int q = a.c; q < st->n; q++)
-            if (((tile | zero) >> q) & 1) a.bz[a.nbz++] = q;
-          a.ntiles = (int64_t)1 << (st->n - a.m - __builtin_popcountll(zero));
-        }
-        support |= tile;
-      }
+      if (track) restrict_to_support(a, st->n, &support);
       int64_t g = (int64_t)di.cus * (lean ? occk : occ);
       if (grid_override > 0) g = grid_override;
       if (g > a.ntiles) g = a.ntiles;
@@ -3216,6 +3222,12 @@ extern "C" sv_status sv_batch_plan(const sv_circuit_desc *circuits, int32_t n_ci
       csw.push_back(z);
     }
     csw[0].flags |= SW_INIT_ZERO;
+    uint64_t support = 0;
+    double cbytes = 0.0;   // every tile a sweep runs is read and written (the first only written)
+    for (SweepArgs &a : csw) {
+      restrict_to_support(a, n, &support);
+      cbytes += ((a.flags & SW_INIT_ZERO) ? 2.0 : 4.0) * (double)es * (double)(a.ntiles << a.m);
+    }
     int64_t before = 0;   // units of this circuit in earlier levels
     for (SweepArgs &a : csw) {
       a.re = nullptr;     // patched after the device allocation
@@ -3243,8 +3255,7 @@ extern "C" sv_status sv_batch_plan(const sv_circuit_desc *circuits, int32_t n_ci
     }
     b->total_sweeps += (int64_t)csw.size();
     b->updates += (double)d.n_ops * (double)((int64_t)1 << n);
-    // each sweep reads and writes both planes (the first one only writes)
-    b->bytes += (double)(4 * (int64_t)csw.size() - 2) * (double)es * (double)((int64_t)1 << n);
+    b->bytes += cbytes;
 
     // Pauli passes: one level after the last sweep
     if (d.n_terms > 0) {

@@ -322,11 +322,12 @@ def threads() -> int:
 
 
 # ------------------------------------------------------------ shot readout
-# Terminal readout with a finite number of shots (Section 4.4: terminal
-# readout returns bit-string counts; the shot estimator rotates Pauli terms
-# into their measurement bases, groups qubit-wise commuting terms and splits a
-# shot budget over the groups, reporting per-term values, the energy and its
-# variance).  The paper fixes neither the grouping rule, nor the split, nor the
+# Terminal readout with a finite number of shots (Section 4.4).  Readout at
+# the end of a circuit gives counts of the drawn bit strings.  The estimator
+# measures each Pauli term after a per-qubit basis change; terms that agree on
+# every qubit they share are measured together, a fixed number of shots is
+# divided among those groups, and the result is each term's value, the energy
+# and an estimate of its variance.  The paper fixes neither the grouping rule, nor the split, nor the
 # variance; the readings implemented here:
 #   * terms are taken in order; an identity term is exact (value 1, no shots);
 #     any other term joins the first group whose measurement basis agrees

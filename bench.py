@@ -50,19 +50,25 @@ def cpu_baseline(circ, budget_s: float):
     dp = p.ctypes.data_as(C.POINTER(C.c_double))
     bp = buf.ctypes.data_as(C.POINTER(C.c_double))
     done = 0
+    per_gate = []
     t0 = time.time()
     while done < len(circ.ops) and time.time() - t0 < budget_s:
         oa = O.OpArray([circ.ops[done]])
+        tg = time.perf_counter()
         rc = L.orc_apply(n, bp, oa.ptr(), 1, dp)
+        per_gate.append(float(N) / (time.perf_counter() - tg))
         if rc != 0:
             raise RuntimeError("oracle failed")
         done += 1
     el = time.time() - t0
     rate = done * float(N) / el
     del buf
+    q1, q2, q3 = np.percentile(per_gate, [25, 50, 75])
     return {"value": rate, "unit": "updates/s", "cores": O.threads(), "kind": "oracle",
-            "sample": f"first {done} of {len(circ.ops)} gates of the same 30-qubit circuit, "
-                      f"{el:.1f} s wall, plain C FP64 gate-by-gate"}
+            "sample": f"first {done} of {len(circ.ops)} gates of the same {n}-qubit circuit, "
+                      f"{el:.1f} s wall, plain C FP64 gate-by-gate",
+            "per_gate_updates_per_s": {"median": float(q2), "iqr": float(q3 - q1),
+                                       "gates": done}}
 
 
 def cpu_model() -> str:
